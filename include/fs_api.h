@@ -1,0 +1,243 @@
+/*
+ * fs_api.h - C ABI of libfs: the data-parallel XOR path of an LDGM fountain
+ * erasure code (Founsure 1.0, Arslan, SoftwareX) on one AMD MI355X (gfx950).
+ *
+ * The code: k input blocks x_0..x_{k-1} and n coded blocks c_0..c_{n-1}, all
+ * of t bytes.  Coded block g is the region XOR of the d_g input blocks in its
+ * neighbour set N(g) (paper §2.2); d_g is drawn from a degree distribution
+ * (Robust Soliton, or any finite max-degree table such as the Raptor Omega of
+ * §2.2) and N(g) is drawn uniformly without replacement.  Everything follows
+ * from (k, n, distribution, seed, stripe key), so a graph is regenerable
+ * (§2.2, per-object seed).  The generator matrix B in F_2^{k x n} of
+ * Algorithms 1 and 5 has column g = indicator of N(g).
+ *
+ * Conventions shared by every call
+ *  - Payload, mask, id, flag, schedule and workspace pointers are DEVICE
+ *    pointers owned by the caller; the library never allocates on a payload
+ *    call.  Payloads are block-major: block b of a stripe starts at
+ *    base + b * t.  t must be a positive multiple of 16 and every payload base
+ *    16-byte aligned, else FS_ERR_ALIGN.
+ *  - Calls are asynchronous on the given HIP stream (0 = the null stream);
+ *    results land in device memory.  Argument errors found on the host are
+ *    returned before anything is enqueued; out-parameters are then untouched.
+ *  - Data-dependent outcomes (decode failure, a row that cannot be repaired,
+ *    a bad id inside a device array) are RESULTS written to device status
+ *    arrays, never host error codes.
+ *  - Graphs are immutable after fs_graph_build and may be used concurrently
+ *    from several streams.  Calls that share a workspace must not overlap.
+ *  - Arithmetic is bytewise XOR (GF(2)): results are exact and deterministic.
+ */
+#ifndef FS_API_H
+#define FS_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FS_API __attribute__((visibility("default")))
+
+typedef enum fs_status {
+  FS_OK = 0,
+  FS_ERR_INVALID = 1,     /* a parameter is out of range or inconsistent    */
+  FS_ERR_ALIGN = 2,       /* t % 16 != 0 or a payload base not 16-B aligned */
+  FS_ERR_NOMEM = 3,       /* host or device allocation failed (build/plan)  */
+  FS_ERR_HIP = 4,         /* a HIP runtime call failed; see fs_last_error   */
+  FS_ERR_UNSUPPORTED = 5, /* valid request this build does not handle       */
+  FS_ERR_WORKSPACE = 6    /* workspace pointer null or smaller than needed  */
+} fs_status;
+
+/* Degree distributions (paper §1 and §2.2). */
+enum {
+  FS_DIST_RSD = 0,     /* Robust Soliton (Luby): R = c ln(k/delta) sqrt(k),
+                          spike at M = clamp(floor(k/R), 1, k); needs c > 0,
+                          0 < delta < 1 and R/delta > 1                         */
+  FS_DIST_FINITE = 1,  /* finite table: weights w_1..w_dmax >= 0, normalised;
+                          degrees above k are dropped                          */
+  FS_DIST_RAPTOR = 2   /* the Raptor Omega printed in §2.2 (finite, max 65)    */
+};
+
+/* Default object seed quoted in the paper (§2.2, footnote on the seed). */
+#define FS_DEFAULT_SEED 1389488782ULL
+
+/* fs_graph_params.flags */
+enum {
+  FS_GRAPH_HOST_ONLY = 1   /* build the host arrays only (no device copy, no
+                              HIP call): for fs_graph_export on any machine  */
+};
+
+typedef struct fs_graph_params {
+  uint32_t k;              /* input blocks, >= 1                               */
+  uint32_t n;              /* coded blocks, >= 1                               */
+  uint32_t dist;           /* FS_DIST_*                                        */
+  uint32_t finite_dmax;    /* FS_DIST_FINITE: length of finite_w (>= 1)        */
+  double rsd_c;            /* FS_DIST_RSD: c                                   */
+  double rsd_delta;        /* FS_DIST_RSD: delta                               */
+  const double *finite_w;  /* FS_DIST_FINITE: host array w_1..w_dmax           */
+  uint64_t seed;           /* object seed                                      */
+  uint64_t stripe_key;     /* per-stripe key (0: one graph shared per object)  */
+  uint32_t flags;          /* FS_GRAPH_*                                       */
+  uint32_t reserved;       /* must be 0                                        */
+} fs_graph_params;
+
+typedef struct fs_graph fs_graph;   /* opaque; owns host + device CSR and CSC */
+
+/*
+ * Degree table: the integer inverse-CDF thresholds used
+ * to draw a coded row's degree.  Weights are summed in float64 in order
+ * d = 1..D into W, p_d = w_d / W, C_d is the running sum and
+ * T_d = min(2^53, floor(C_d 2^53)) for d < D, T_D = 2^53.  A 64-bit draw u
+ * gives d = min{d : (u >> 11) < T_d}.  Host-only; writes D to *D_out and, if
+ * T_out is non-null and cap >= D, T_1..T_D to T_out[0..D-1].
+ * Errors: FS_ERR_INVALID for bad parameters or cap < D with T_out non-null.
+ */
+FS_API fs_status fs_degree_table(const fs_graph_params *params, uint64_t *T_out, uint32_t cap,
+                          uint32_t *D_out);
+
+/*
+ * Build the seeded graph (§2.2 encoding step 2, "pseudo-randomly
+ * selected" neighbours).  Row j uses the stream
+ *   key = mix(mix(mix(mix(seed + G) ^ 1) ^ stripe_key) ^ j)
+ *   draw i = mix(key + (i + 1) G)  (mix: SplitMix64's output function,
+ *   G = 0x9E3779B97F4A7C15),
+ * draw 0 picks d_j by the degree table, draws 1..d_j drive Floyd's sampler
+ * (value r = k - d_j + s, v = ((draw >> 32) (r + 1)) >> 32; r if v is taken),
+ * and the row is sorted ascending.  Rows do not depend on n.
+ * Unless FS_GRAPH_HOST_ONLY, the CSR/CSC are copied to the current device on
+ * `stream` and the call returns after the copy has completed.
+ * *out receives the graph (freed with fs_graph_free).
+ * Errors: FS_ERR_INVALID (parameters, nnz >= 2^31), FS_ERR_NOMEM, FS_ERR_HIP.
+ */
+FS_API fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_graph **out);
+
+/* Sizes of a built graph (any out pointer may be null). */
+FS_API fs_status fs_graph_info(const fs_graph *g, uint32_t *k, uint32_t *n, uint64_t *nnz,
+                        uint32_t *max_degree, uint32_t *max_column_degree);
+
+/*
+ * Copy the graph to caller HOST arrays (any may be null): row_ptr[n+1] and
+ * col[nnz] (CSR by coded row, ascending within a row), col_ptr[k+1] and
+ * rowidx[nnz] (CSC by input, rows ascending within a column).
+ */
+FS_API fs_status fs_graph_export(const fs_graph *g, int32_t *row_ptr, int32_t *col,
+                          int32_t *col_ptr, int32_t *rowidx);
+
+FS_API void fs_graph_free(fs_graph *g);
+
+/*
+ * Encode (§2.2 encoding step 2): c_g = XOR_{i in N(g)} x_i for every
+ * g in [0, n).  x: device uint8[k][t]; c: device uint8[n][t] (written, not
+ * read).  x and c must not overlap.
+ */
+FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t, hipStream_t stream);
+
+/* Operations for fs_workspace_size. */
+enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
+       FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5 };
+
+/*
+ * Workspace bytes the operation needs for this graph and block size
+ * (n_items: lost rows for repair, updated ids for update; ignored otherwise).
+ */
+FS_API fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items,
+                            size_t *bytes);
+
+/*
+ * Peeling schedule Algorithm 5 (DPG) with the level-synchronous
+ * ("delayed") BP of §3.1.  With F the undecoded inputs (initially all k) and
+ * S the coded rows with erased[g] == 0, each level:
+ *   - every g in S with exactly one neighbour f(g) in F names f(g);
+ *   - each named f is decoded by its namer of least (d_g, g), d_g the
+ *     ORIGINAL degree, ties to the lower row index;
+ *   - the decoded inputs leave F.
+ * It stops when F is empty, no row names anything, or maxit levels ran
+ * (maxit == 0: no limit).
+ * Inputs : erased  device uint8[n] (non-zero = erased).
+ * Outputs: recovered device uint8[k]  (1 = decoded);
+ *          status    device int32[3]  {ok (F empty), |F|, levels L};
+ *          level_ptr device int32[k+1] (entries 0..L valid, level_ptr[0] = 0);
+ *          dp_f      device int32[k]: pairs of level l at [level_ptr[l],
+ *                    level_ptr[l+1]) by ascending f, then F ascending;
+ *          dp_g      device int32[k]: the decoding row of each pair, -1 for F.
+ * ws: FS_OP_PEEL bytes of device workspace.
+ */
+FS_API fs_status fs_peel(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered,
+                  int32_t *status, int32_t *level_ptr, int32_t *dp_f, int32_t *dp_g, void *ws,
+                  size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Replay a schedule (§3.1): level by level,
+ *   x_f = c_g XOR (XOR of x_i for i in N(g), i != f),
+ * then x_f = 0 for every f left in F.  Reads c (device uint8[n][t]), writes
+ * every block of x (device uint8[k][t]).  status/level_ptr/dp_f/dp_g are the
+ * device outputs of fs_peel for the same graph.
+ */
+FS_API fs_status fs_replay(const fs_graph *g, const void *c, const int32_t *status,
+                    const int32_t *level_ptr, const int32_t *dp_f, const int32_t *dp_g, void *x,
+                    uint64_t t, hipStream_t stream);
+
+/*
+ * Decode (Algorithms 1/5, "founsureDec"): fs_peel into the
+ * workspace then fs_replay.  A failed decode is a result: status[0] = 0,
+ * recovered[] tells which blocks of x are valid, the others are zero.
+ */
+FS_API fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uint32_t maxit,
+                    void *x, uint8_t *recovered, int32_t *status, uint64_t t, void *ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Repair (the repair engine of §2.1 / §4).  lost: device uint32[n_lost]
+ * coded rows to rebuild in place in c.
+ *   x != NULL  re-encode from resident inputs: c_j = XOR_{i in N(j)} x_i.
+ *   x == NULL  conventional repair (§4): peel + replay over the rows that are
+ *              neither erased nor lost (into the workspace), then rebuild each
+ *              lost row whose neighbours were all recovered; other lost rows
+ *              are zero-filled.  erased: device uint8[n] (may be NULL = none).
+ * repaired: device uint8[n_lost], 1 where c_j was rebuilt.
+ * status: device int32[3] {all rebuilt, rows not rebuilt, 0 or an FS_ERR_*
+ *         code for a bad lost id (>= n or repeated: nothing is written)}.
+ */
+FS_API fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *erased,
+                    const uint32_t *lost, uint32_t n_lost, uint8_t *repaired, int32_t *status,
+                    uint64_t t, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Update replace inputs ids[u] by new_blocks[u] and bring every
+ * adjacent coded block up to date by adding the delta x_old ^ x_new (the
+ * region XOR is linear, §2.2), i.e. the result equals re-encoding from
+ * scratch.  ids: device uint32[n_ids], distinct, < k; new_blocks: device
+ * uint8[n_ids][t].  x and c are updated in place.
+ * status: device int32[3] {affected coded rows, pairs (row, id), 0 or
+ *         FS_ERR_INVALID if an id is out of range or repeated, in which case
+ *         nothing is written}.
+ */
+FS_API fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *ids, uint32_t n_ids,
+                    const void *new_blocks, int32_t *status, uint64_t t, void *ws,
+                    size_t ws_bytes, hipStream_t stream);
+
+/* Tuning of the gather-XOR kernel family (encode, repair, update). */
+typedef struct fs_tune {
+  uint32_t lanes_per_row;  /* 16, 32 or 64 lanes share one coded row         */
+  uint32_t chunks;         /* 16-byte chunks per lane per slice: 1, 2 or 4   */
+  uint32_t xcd_remap;      /* 1: keep each XCD on a contiguous slice range   */
+  uint32_t nt_store;       /* 1: non-temporal stores for outputs             */
+} fs_tune;
+
+/* Override (or with NULL restore) the gather tuning used by this process. */
+FS_API fs_status fs_set_tune(const fs_tune *tune);
+FS_API fs_status fs_get_tune(fs_tune *tune);
+
+FS_API const char *fs_status_string(fs_status s);
+/* Message of the last error on the calling thread ("" if none). */
+FS_API const char *fs_last_error(void);
+/* Library version string. */
+FS_API const char *fs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FS_API_H */

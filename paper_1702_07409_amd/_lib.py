@@ -1,0 +1,245 @@
+"""ctypes binding of libfs.so: argument marshalling only.
+
+Every function here forwards to the C entry point of the same name; payloads,
+masks, ids and workspaces are torch tensors on the GPU, passed by pointer.
+Nothing is computed in Python.  If libfs.so has not been built, importing
+this module raises ImportError: there is no fallback path.
+"""
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfs.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libfs.so is not built (run python -m paper_1702_07409_amd.build)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FS_OK, FS_ERR_INVALID, FS_ERR_ALIGN, FS_ERR_NOMEM, FS_ERR_HIP, FS_ERR_UNSUPPORTED, FS_ERR_WORKSPACE = range(7)
+FS_DIST_RSD, FS_DIST_FINITE, FS_DIST_RAPTOR = 0, 1, 2
+FS_DEFAULT_SEED = 1389488782
+FS_GRAPH_HOST_ONLY = 1
+FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE = range(6)
+
+DIST_CODES = {"rsd": FS_DIST_RSD, "finite": FS_DIST_FINITE, "raptor": FS_DIST_RAPTOR}
+
+
+class fs_graph_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_uint32), ("n", ctypes.c_uint32), ("dist", ctypes.c_uint32),
+                ("finite_dmax", ctypes.c_uint32), ("rsd_c", ctypes.c_double),
+                ("rsd_delta", ctypes.c_double), ("finite_w", ctypes.POINTER(ctypes.c_double)),
+                ("seed", ctypes.c_uint64), ("stripe_key", ctypes.c_uint64),
+                ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class fs_tune(ctypes.Structure):
+    _fields_ = [("lanes_per_row", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
+                ("xcd_remap", ctypes.c_uint32), ("nt_store", ctypes.c_uint32)]
+
+
+P = ctypes.c_void_p
+U32, U64, SZ, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
+ST = ctypes.c_int
+
+_SIGS = {
+    "fs_degree_table": ([ctypes.POINTER(fs_graph_params), P, U32, ctypes.POINTER(U32)], ST),
+    "fs_graph_build": ([ctypes.POINTER(fs_graph_params), P, ctypes.POINTER(P)], ST),
+    "fs_graph_info": ([P, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U64),
+                       ctypes.POINTER(U32), ctypes.POINTER(U32)], ST),
+    "fs_graph_export": ([P, P, P, P, P], ST),
+    "fs_graph_free": ([P], None),
+    "fs_workspace_size": ([P, I32, U64, U32, ctypes.POINTER(SZ)], ST),
+    "fs_encode": ([P, P, P, U64, P], ST),
+    "fs_peel": ([P, P, U32, P, P, P, P, P, P, SZ, P], ST),
+    "fs_replay": ([P, P, P, P, P, P, P, U64, P], ST),
+    "fs_decode": ([P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
+    "fs_repair": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
+    "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
+    "fs_set_tune": ([ctypes.POINTER(fs_tune)], ST),
+    "fs_get_tune": ([ctypes.POINTER(fs_tune)], ST),
+    "fs_status_string": ([I32], ctypes.c_char_p),
+    "fs_last_error": ([], ctypes.c_char_p),
+    "fs_version": ([], ctypes.c_char_p),
+}
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+
+EXPORTED = tuple(_SIGS)
+
+
+class FsError(RuntimeError):
+    def __init__(self, status, where):
+        self.status = status
+        msg = _lib.fs_last_error().decode() or _lib.fs_status_string(status).decode()
+        super().__init__("%s: %s (%s)" % (where, _lib.fs_status_string(status).decode(), msg))
+
+
+def _check(status, where):
+    if status != FS_OK:
+        raise FsError(status, where)
+
+
+def version():
+    return _lib.fs_version().decode()
+
+
+def _ptr(t):
+    """Device pointer of a tensor (or None -> NULL)."""
+    if t is None:
+        return None
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def make_params(k, n, dist="rsd", rsd_c=0.1, rsd_delta=0.05, finite_w=(), seed=FS_DEFAULT_SEED,
+                stripe_key=0, host_only=False):
+    p = fs_graph_params()
+    p.k, p.n = k, n
+    p.dist = DIST_CODES[dist]
+    p.rsd_c, p.rsd_delta = rsd_c, rsd_delta
+    w = (ctypes.c_double * max(1, len(finite_w)))(*finite_w)
+    p.finite_dmax = len(finite_w)
+    p.finite_w = ctypes.cast(w, ctypes.POINTER(ctypes.c_double))
+    p.seed, p.stripe_key = seed, stripe_key
+    p.flags = FS_GRAPH_HOST_ONLY if host_only else 0
+    p._keep = w
+    return p
+
+
+def fs_degree_table(**kw):
+    """Thresholds T_1..T_D of the degree distribution, as a Python list."""
+    p = make_params(k=kw.pop("k"), n=kw.pop("n", 1), **kw)
+    D = U32()
+    _check(_lib.fs_degree_table(ctypes.byref(p), None, 0, ctypes.byref(D)), "fs_degree_table")
+    buf = (ctypes.c_uint64 * D.value)()
+    _check(_lib.fs_degree_table(ctypes.byref(p), buf, D.value, ctypes.byref(D)), "fs_degree_table")
+    return list(buf)
+
+
+class Graph:
+    """Owner of an fs_graph handle."""
+
+    def __init__(self, handle, params):
+        self.handle = handle
+        self.params = params
+        k, n, nnz, md, mc = U32(), U32(), U64(), U32(), U32()
+        _check(_lib.fs_graph_info(handle, ctypes.byref(k), ctypes.byref(n), ctypes.byref(nnz),
+                                  ctypes.byref(md), ctypes.byref(mc)), "fs_graph_info")
+        self.k, self.n, self.nnz = k.value, n.value, nnz.value
+        self.max_degree, self.max_column_degree = md.value, mc.value
+
+    def export(self):
+        import numpy as np
+        rp = np.zeros(self.n + 1, np.int32)
+        col = np.zeros(max(self.nnz, 1), np.int32)
+        cp = np.zeros(self.k + 1, np.int32)
+        ri = np.zeros(max(self.nnz, 1), np.int32)
+        _check(_lib.fs_graph_export(self.handle, rp.ctypes.data, col.ctypes.data, cp.ctypes.data,
+                                    ri.ctypes.data), "fs_graph_export")
+        return rp, col[:self.nnz], cp, ri[:self.nnz]
+
+    def workspace_size(self, op, t=16, n_items=0):
+        return fs_workspace_size(self, op, t, n_items)
+
+    def free(self):
+        if self.handle:
+            _lib.fs_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fs_graph_build(k, n, dist="rsd", rsd_c=0.1, rsd_delta=0.05, finite_w=(), seed=FS_DEFAULT_SEED,
+                   stripe_key=0, host_only=False, stream=None):
+    p = make_params(k, n, dist, rsd_c, rsd_delta, finite_w, seed, stripe_key, host_only)
+    h = P()
+    s = None if host_only else _stream(stream)
+    _check(_lib.fs_graph_build(ctypes.byref(p), s, ctypes.byref(h)), "fs_graph_build")
+    return Graph(h, p)
+
+
+def fs_workspace_size(g, op, t=16, n_items=0):
+    b = SZ()
+    _check(_lib.fs_workspace_size(g.handle, op, t, n_items, ctypes.byref(b)), "fs_workspace_size")
+    return b.value
+
+
+def workspace(g, op, t=16, n_items=0, device="cuda"):
+    """A device workspace tensor of the size the operation needs (torch memory)."""
+    import torch
+    nbytes = fs_workspace_size(g, op, t, n_items)
+    return torch.empty(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
+
+
+def _ws(ws):
+    if ws is None:
+        return None, 0
+    base = ws.data_ptr()
+    aligned = (base + 255) & ~255
+    return aligned, ws.numel() - (aligned - base)
+
+
+def fs_encode(g, x, c, t, stream=None):
+    _check(_lib.fs_encode(g.handle, _ptr(x), _ptr(c), t, _stream(stream)), "fs_encode")
+
+
+def fs_peel(g, erased, maxit, recovered, status, level_ptr, dp_f, dp_g, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_peel(g.handle, _ptr(erased), maxit, _ptr(recovered), _ptr(status), _ptr(level_ptr),
+                        _ptr(dp_f), _ptr(dp_g), w, wb, _stream(stream)), "fs_peel")
+
+
+def fs_replay(g, c, status, level_ptr, dp_f, dp_g, x, t, stream=None):
+    _check(_lib.fs_replay(g.handle, _ptr(c), _ptr(status), _ptr(level_ptr), _ptr(dp_f), _ptr(dp_g),
+                          _ptr(x), t, _stream(stream)), "fs_replay")
+
+
+def fs_decode(g, c, erased, maxit, x, recovered, status, t, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_decode(g.handle, _ptr(c), _ptr(erased), maxit, _ptr(x), _ptr(recovered), _ptr(status),
+                          t, w, wb, _stream(stream)), "fs_decode")
+
+
+def fs_repair(g, x, c, erased, lost, n_lost, repaired, status, t, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_repair(g.handle, _ptr(x), _ptr(c), _ptr(erased), _ptr(lost), n_lost, _ptr(repaired),
+                          _ptr(status), t, w, wb, _stream(stream)), "fs_repair")
+
+
+def fs_update(g, x, c, ids, n_ids, new_blocks, status, t, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_update(g.handle, _ptr(x), _ptr(c), _ptr(ids), n_ids, _ptr(new_blocks), _ptr(status),
+                          t, w, wb, _stream(stream)), "fs_update")
+
+
+def fs_set_tune(lanes_per_row=16, chunks=2, xcd_remap=1, nt_store=1):
+    tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store)
+    _check(_lib.fs_set_tune(ctypes.byref(tu)), "fs_set_tune")
+
+
+def fs_reset_tune():
+    _check(_lib.fs_set_tune(None), "fs_set_tune")
+
+
+def fs_get_tune():
+    tu = fs_tune()
+    _check(_lib.fs_get_tune(ctypes.byref(tu)), "fs_get_tune")
+    return dict(lanes_per_row=tu.lanes_per_row, chunks=tu.chunks, xcd_remap=tu.xcd_remap,
+                nt_store=tu.nt_store)

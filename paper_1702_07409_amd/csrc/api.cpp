@@ -1,0 +1,553 @@
+// C ABI entry points of libfs: argument checks, workspace layout, launches.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+
+#include "fs_internal.h"
+
+namespace fs {
+
+static thread_local std::string g_last_error;
+
+fs_status fail(fs_status s, const std::string &msg) {
+  g_last_error = msg;
+  return s;
+}
+void clear_error() { g_last_error.clear(); }
+
+const DeviceInfo &device_info(int dev) {
+  static std::mutex mu;
+  static DeviceInfo info[64];
+  static bool have[64] = {false};
+  std::lock_guard<std::mutex> lock(mu);
+  if (dev < 0 || dev >= 64) return info[0];
+  if (!have[dev]) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      info[dev].cu_count = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+      info[dev].max_lds_per_block = v;
+    have[dev] = true;
+  }
+  return info[dev];
+}
+
+namespace {
+
+std::mutex g_tune_mu;
+fs_tune g_tune = {16, 2, 1, 1};
+
+fs_tune current_tune() {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return g_tune;
+}
+
+bool tune_ok(const fs_tune &t) {
+  const bool lpr = t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64;
+  const bool ch = t.chunks == 1 || t.chunks == 2 || t.chunks == 4;
+  return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1;
+}
+
+fs_status check_graph(const fs_graph *g) {
+  if (!g) return fail(FS_ERR_INVALID, "graph is null");
+  if (!g->d_base) return fail(FS_ERR_INVALID, "graph was built host-only");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(FS_ERR_HIP, "hipGetDevice failed");
+  if (dev != g->device) return fail(FS_ERR_INVALID, "graph lives on another device");
+  return FS_OK;
+}
+
+fs_status check_payload(const void *p, uint64_t t, const char *name) {
+  if (t == 0 || (t & 15)) return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
+  if (!p) return fail(FS_ERR_INVALID, std::string(name) + " is null");
+  if (reinterpret_cast<uintptr_t>(p) & 15) return fail(FS_ERR_ALIGN, std::string(name) + " is not 16-byte aligned");
+  return FS_OK;
+}
+
+#define FS_TRY(expr)                  \
+  do {                                \
+    fs_status _s = (expr);            \
+    if (_s != FS_OK) return _s;       \
+  } while (0)
+
+// Schedule arrays kept in a decode workspace.
+struct SchedBufs {
+  int32_t *status, *level_ptr, *dp_f, *dp_g;
+  uint8_t *recovered;
+};
+
+void carve_sched(Carver &cv, uint32_t k, SchedBufs &s, bool with_recovered) {
+  s.status = cv.take<int32_t>(4);
+  s.level_ptr = cv.take<int32_t>((size_t)k + 1);
+  s.dp_f = cv.take<int32_t>(k);
+  s.dp_g = cv.take<int32_t>(k);
+  s.recovered = with_recovered ? cv.take<uint8_t>(k) : nullptr;
+}
+
+struct RepairBufs {
+  uint32_t *seen;
+  int32_t *flag;
+  uint8_t *erased2;
+  SchedBufs sched;
+  PeelJob peel;
+  uint8_t *x;
+};
+
+void carve_repair(Carver &cv, const fs_graph *g, uint64_t t, bool conventional, RepairBufs &b) {
+  b.seen = cv.take<uint32_t>((g->n + 31) / 32);
+  b.flag = cv.take<int32_t>(4);
+  b.erased2 = nullptr;
+  b.x = nullptr;
+  b.sched = SchedBufs{};
+  b.peel = PeelJob{};
+  if (conventional) {
+    b.erased2 = cv.take<uint8_t>(g->n);
+    carve_sched(cv, g->k, b.sched, true);
+    b.peel.k = g->k;
+    b.peel.n = g->n;
+    peel_carve(cv, b.peel);
+    b.x = cv.take<uint8_t>((size_t)g->k * t);
+  }
+}
+
+struct UpdateBufs {
+  uint32_t *seen;
+  int32_t *cnt, *arow, *aptr, *asrc, *n_aff, *flag;
+  uint8_t *delta;
+  uint32_t max_rows;
+};
+
+void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, UpdateBufs &b) {
+  const uint64_t max_pairs = (uint64_t)n_ids * g->max_cdeg;
+  b.max_rows = (uint32_t)std::min<uint64_t>(g->n, max_pairs);
+  b.seen = cv.take<uint32_t>((g->k + 31) / 32);
+  b.cnt = cv.take<int32_t>(g->n);
+  b.arow = cv.take<int32_t>(g->n);
+  b.aptr = cv.take<int32_t>((size_t)g->n + 1);
+  b.asrc = cv.take<int32_t>(std::max<uint64_t>(max_pairs, 1));
+  b.n_aff = cv.take<int32_t>(1);
+  b.flag = cv.take<int32_t>(1);
+  b.delta = cv.take<uint8_t>((size_t)n_ids * t);
+}
+
+size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) {
+  Carver cv(nullptr);
+  switch (op) {
+    case FS_OP_ENCODE: return 0;
+    case FS_OP_PEEL: {
+      PeelJob j{};
+      j.k = g->k;
+      j.n = g->n;
+      peel_carve(cv, j);
+      return cv.size();
+    }
+    case FS_OP_DECODE: {
+      SchedBufs s;
+      carve_sched(cv, g->k, s, false);
+      PeelJob j{};
+      j.k = g->k;
+      j.n = g->n;
+      peel_carve(cv, j);
+      return cv.size();
+    }
+    case FS_OP_REPAIR:
+    case FS_OP_REPAIR_CONVENTIONAL: {
+      RepairBufs b;
+      carve_repair(cv, g, t, op == FS_OP_REPAIR_CONVENTIONAL, b);
+      return cv.size();
+    }
+    case FS_OP_UPDATE: {
+      UpdateBufs b;
+      carve_update(cv, g, t, n_items, b);
+      return cv.size();
+    }
+  }
+  return 0;
+}
+
+fs_status check_ws(const fs_graph *g, int op, uint64_t t, uint32_t n_items, void *ws, size_t ws_bytes) {
+  const size_t need = workspace_bytes(g, op, t, n_items);
+  if (need == 0) return FS_OK;
+  if (!ws) return fail(FS_ERR_WORKSPACE, "workspace is null");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(FS_ERR_ALIGN, "workspace must be 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(FS_ERR_WORKSPACE, "workspace too small: need " + std::to_string(need) + " bytes");
+  return FS_OK;
+}
+
+PeelJob peel_job(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered,
+                 int32_t *status, int32_t *level_ptr, int32_t *dp_f, int32_t *dp_g) {
+  PeelJob j{};
+  j.k = g->k;
+  j.n = g->n;
+  j.row_ptr = g->d_row_ptr;
+  j.col = g->d_col;
+  j.col_ptr = g->d_col_ptr;
+  j.rowidx = g->d_rowidx;
+  j.erased = erased;
+  j.maxit = maxit;
+  j.recovered = recovered;
+  j.status = status;
+  j.level_ptr = level_ptr;
+  j.dp_f = dp_f;
+  j.dp_g = dp_g;
+  return j;
+}
+
+ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, const int32_t *status,
+                     const int32_t *level_ptr, const int32_t *dp_f, const int32_t *dp_g) {
+  ReplayJob r{};
+  r.k = g->k;
+  r.n = g->n;
+  r.row_ptr = g->d_row_ptr;
+  r.col = g->d_col;
+  r.c = static_cast<const uint8_t *>(c);
+  r.x = static_cast<uint8_t *>(x);
+  r.t = t;
+  r.status = status;
+  r.level_ptr = level_ptr;
+  r.dp_f = dp_f;
+  r.dp_g = dp_g;
+  return r;
+}
+
+}  // namespace
+}  // namespace fs
+
+using namespace fs;
+
+extern "C" {
+
+const char *fs_version(void) { return "libfs 0.1 (gfx950)"; }
+
+const char *fs_status_string(fs_status s) {
+  switch (s) {
+    case FS_OK: return "ok";
+    case FS_ERR_INVALID: return "invalid argument";
+    case FS_ERR_ALIGN: return "misaligned size or pointer";
+    case FS_ERR_NOMEM: return "out of memory";
+    case FS_ERR_HIP: return "HIP runtime error";
+    case FS_ERR_UNSUPPORTED: return "unsupported";
+    case FS_ERR_WORKSPACE: return "workspace missing or too small";
+  }
+  return "unknown status";
+}
+
+const char *fs_last_error(void) { return g_last_error.c_str(); }
+
+fs_status fs_set_tune(const fs_tune *tune) {
+  clear_error();
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  if (!tune) {
+    g_tune = fs_tune{16, 2, 1, 1};
+    return FS_OK;
+  }
+  if (!tune_ok(*tune)) return fail(FS_ERR_INVALID, "tuning out of range");
+  g_tune = *tune;
+  return FS_OK;
+}
+
+fs_status fs_get_tune(fs_tune *tune) {
+  if (!tune) return fail(FS_ERR_INVALID, "tune is null");
+  *tune = current_tune();
+  return FS_OK;
+}
+
+fs_status fs_degree_table(const fs_graph_params *params, uint64_t *T_out, uint32_t cap, uint32_t *D_out) {
+  clear_error();
+  if (!params) return fail(FS_ERR_INVALID, "params is null");
+  std::vector<double> w;
+  FS_TRY(degree_weights(*params, w));
+  std::vector<uint64_t> T;
+  degree_thresholds(w, T);
+  if (T_out && cap < T.size()) return fail(FS_ERR_INVALID, "threshold buffer too small");
+  if (D_out) *D_out = (uint32_t)T.size();
+  if (T_out) std::memcpy(T_out, T.data(), T.size() * sizeof(uint64_t));
+  return FS_OK;
+}
+
+fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_graph **out) {
+  clear_error();
+  if (!params || !out) return fail(FS_ERR_INVALID, "params and out must be non-null");
+  fs_graph *g = new (std::nothrow) fs_graph();
+  if (!g) return fail(FS_ERR_NOMEM, "host allocation failed");
+  fs_status st = build_host_graph(*params, *g);
+  if (st != FS_OK) {
+    delete g;
+    return st;
+  }
+  if (!(params->flags & FS_GRAPH_HOST_ONLY)) {
+    if (hipGetDevice(&g->device) != hipSuccess) {
+      delete g;
+      return fail(FS_ERR_HIP, "hipGetDevice failed");
+    }
+    const size_t a = ((size_t)g->n + 1) * 4, b = g->nnz * 4, c = ((size_t)g->k + 1) * 4;
+    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
+    const size_t total = up(a) + up(b) + up(c) + up(b) + 256;
+    void *base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) {
+      delete g;
+      return fail(FS_ERR_NOMEM, "device allocation for the graph failed");
+    }
+    g->d_base = base;
+    uint8_t *p = static_cast<uint8_t *>(base);
+    int32_t *rp = reinterpret_cast<int32_t *>(p);
+    int32_t *cl = reinterpret_cast<int32_t *>(p + up(a));
+    int32_t *cp = reinterpret_cast<int32_t *>(p + up(a) + up(b));
+    int32_t *ri = reinterpret_cast<int32_t *>(p + up(a) + up(b) + up(c));
+    hipError_t e = hipMemcpyAsync(rp, g->row_ptr.data(), a, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && b) e = hipMemcpyAsync(cl, g->col.data(), b, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(cp, g->col_ptr.data(), c, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess && b) e = hipMemcpyAsync(ri, g->rowidx.data(), b, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      hipFree(base);
+      delete g;
+      return fail(FS_ERR_HIP, std::string("graph upload: ") + hipGetErrorString(e));
+    }
+    g->d_row_ptr = rp;
+    g->d_col = cl;
+    g->d_col_ptr = cp;
+    g->d_rowidx = ri;
+  }
+  *out = g;
+  return FS_OK;
+}
+
+fs_status fs_graph_info(const fs_graph *g, uint32_t *k, uint32_t *n, uint64_t *nnz, uint32_t *max_degree,
+                        uint32_t *max_column_degree) {
+  clear_error();
+  if (!g) return fail(FS_ERR_INVALID, "graph is null");
+  if (k) *k = g->k;
+  if (n) *n = g->n;
+  if (nnz) *nnz = g->nnz;
+  if (max_degree) *max_degree = g->max_deg;
+  if (max_column_degree) *max_column_degree = g->max_cdeg;
+  return FS_OK;
+}
+
+fs_status fs_graph_export(const fs_graph *g, int32_t *row_ptr, int32_t *col, int32_t *col_ptr, int32_t *rowidx) {
+  clear_error();
+  if (!g) return fail(FS_ERR_INVALID, "graph is null");
+  if (row_ptr) std::memcpy(row_ptr, g->row_ptr.data(), g->row_ptr.size() * 4);
+  if (col) std::memcpy(col, g->col.data(), g->col.size() * 4);
+  if (col_ptr) std::memcpy(col_ptr, g->col_ptr.data(), g->col_ptr.size() * 4);
+  if (rowidx) std::memcpy(rowidx, g->rowidx.data(), g->rowidx.size() * 4);
+  return FS_OK;
+}
+
+void fs_graph_free(fs_graph *g) {
+  if (!g) return;
+  if (g->d_base) hipFree(g->d_base);
+  delete g;
+}
+
+fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
+  clear_error();
+  if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
+  if (op < FS_OP_ENCODE || op > FS_OP_UPDATE) return fail(FS_ERR_INVALID, "unknown operation");
+  if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_UPDATE) && (t == 0 || (t & 15)))
+    return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
+  *bytes = workspace_bytes(g, op, t, n_items);
+  return FS_OK;
+}
+
+fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(x, t, "x"));
+  FS_TRY(check_payload(c, t, "c"));
+  GatherJob j{};
+  j.src = static_cast<const uint8_t *>(x);
+  j.src_stride = t;
+  j.dst = static_cast<uint8_t *>(c);
+  j.dst_stride = t;
+  j.ptr = g->d_row_ptr;
+  j.idx = g->d_col;
+  j.nrows = g->n;
+  j.csr_rows = g->n;
+  j.t = t;
+  return launch_gather(j, current_tune(), stream);
+}
+
+fs_status fs_peel(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered, int32_t *status,
+                  int32_t *level_ptr, int32_t *dp_f, int32_t *dp_g, void *ws, size_t ws_bytes,
+                  hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  if (!erased || !recovered || !status || !level_ptr || !dp_f || !dp_g)
+    return fail(FS_ERR_INVALID, "peel arrays must be non-null");
+  FS_TRY(check_ws(g, FS_OP_PEEL, 0, 0, ws, ws_bytes));
+  PeelJob j = peel_job(g, erased, maxit, recovered, status, level_ptr, dp_f, dp_g);
+  Carver cv(ws);
+  peel_carve(cv, j);
+  return launch_peel(j, stream);
+}
+
+fs_status fs_replay(const fs_graph *g, const void *c, const int32_t *status, const int32_t *level_ptr,
+                    const int32_t *dp_f, const int32_t *dp_g, void *x, uint64_t t, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(c, t, "c"));
+  FS_TRY(check_payload(x, t, "x"));
+  if (!status || !level_ptr || !dp_f || !dp_g) return fail(FS_ERR_INVALID, "schedule arrays must be non-null");
+  return launch_replay(replay_job(g, c, x, t, status, level_ptr, dp_f, dp_g), stream);
+}
+
+fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uint32_t maxit, void *x,
+                    uint8_t *recovered, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(c, t, "c"));
+  FS_TRY(check_payload(x, t, "x"));
+  if (!erased || !recovered || !status) return fail(FS_ERR_INVALID, "erased, recovered and status must be non-null");
+  FS_TRY(check_ws(g, FS_OP_DECODE, t, 0, ws, ws_bytes));
+  Carver cv(ws);
+  SchedBufs s;
+  carve_sched(cv, g->k, s, false);
+  PeelJob j = peel_job(g, erased, maxit, recovered, status, s.level_ptr, s.dp_f, s.dp_g);
+  peel_carve(cv, j);
+  FS_TRY(launch_peel(j, stream));
+  return launch_replay(replay_job(g, c, x, t, status, s.level_ptr, s.dp_f, s.dp_g), stream);
+}
+
+fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *erased, const uint32_t *lost,
+                    uint32_t n_lost, uint8_t *repaired, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(c, t, "c"));
+  if (x) FS_TRY(check_payload(x, t, "x"));
+  if ((n_lost && (!lost || !repaired)) || !status)
+    return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
+  const bool conventional = (x == nullptr);
+  const int op = conventional ? FS_OP_REPAIR_CONVENTIONAL : FS_OP_REPAIR;
+  FS_TRY(check_ws(g, op, t, n_lost, ws, ws_bytes));
+  Carver cv(ws);
+  RepairBufs b;
+  carve_repair(cv, g, t, conventional, b);
+
+  RepairPrepJob pj{};
+  pj.n = g->n;
+  pj.k = g->k;
+  pj.lost = lost;
+  pj.n_lost = n_lost;
+  pj.erased = erased;
+  pj.erased2 = b.erased2;
+  pj.seen = b.seen;
+  pj.flag = b.flag;
+  pj.repaired = repaired;
+  pj.status = status;
+  FS_TRY(launch_repair_prep(pj, stream));
+  if (n_lost == 0) return FS_OK;
+
+  GatherJob gj{};
+  gj.src_stride = t;
+  gj.dst = static_cast<uint8_t *>(c);
+  gj.dst_stride = t;
+  gj.ptr = g->d_row_ptr;
+  gj.idx = g->d_col;
+  gj.csr_map = lost;
+  gj.out_map = reinterpret_cast<const int32_t *>(lost);
+  gj.skip_flag = b.flag;
+  gj.nrows = n_lost;
+  gj.csr_rows = g->n;
+  gj.t = t;
+  if (!conventional) {
+    gj.src = static_cast<const uint8_t *>(x);
+    return launch_gather(gj, current_tune(), stream);
+  }
+  PeelJob j = peel_job(g, b.erased2, 0, b.sched.recovered, b.sched.status, b.sched.level_ptr, b.sched.dp_f,
+                       b.sched.dp_g);
+  j.acc = b.peel.acc;
+  j.best = b.peel.best;
+  j.front_a = b.peel.front_a;
+  j.front_b = b.peel.front_b;
+  j.dlist = b.peel.dlist;
+  j.mask = b.peel.mask;
+  j.decmask = b.peel.decmask;
+  j.skip_flag = b.flag;
+  FS_TRY(launch_peel(j, stream));
+  ReplayJob r = replay_job(g, c, b.x, t, b.sched.status, b.sched.level_ptr, b.sched.dp_f, b.sched.dp_g);
+  r.skip_flag = b.flag;
+  FS_TRY(launch_replay(r, stream));
+  RepairCheckJob cj{};
+  cj.row_ptr = g->d_row_ptr;
+  cj.col = g->d_col;
+  cj.n = g->n;
+  cj.lost = lost;
+  cj.n_lost = n_lost;
+  cj.recovered = b.sched.recovered;
+  cj.flag = b.flag;
+  cj.repaired = repaired;
+  cj.status = status;
+  FS_TRY(launch_repair_check(cj, stream));
+  gj.src = b.x;
+  gj.row_ok = repaired;
+  return launch_gather(gj, current_tune(), stream);
+}
+
+fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *ids, uint32_t n_ids,
+                    const void *new_blocks, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(x, t, "x"));
+  FS_TRY(check_payload(c, t, "c"));
+  if (n_ids) {
+    FS_TRY(check_payload(new_blocks, t, "new_blocks"));
+    if (!ids) return fail(FS_ERR_INVALID, "ids is null");
+  }
+  if (!status) return fail(FS_ERR_INVALID, "status is null");
+  FS_TRY(check_ws(g, FS_OP_UPDATE, t, n_ids, ws, ws_bytes));
+  Carver cv(ws);
+  UpdateBufs b;
+  carve_update(cv, g, t, n_ids, b);
+  UpdatePlanJob pj{};
+  pj.k = g->k;
+  pj.n = g->n;
+  pj.col_ptr = g->d_col_ptr;
+  pj.rowidx = g->d_rowidx;
+  pj.ids = ids;
+  pj.n_ids = n_ids;
+  pj.seen = b.seen;
+  pj.cnt = b.cnt;
+  pj.arow = b.arow;
+  pj.aptr = b.aptr;
+  pj.asrc = b.asrc;
+  pj.n_aff = b.n_aff;
+  pj.flag = b.flag;
+  pj.status = status;
+  FS_TRY(launch_update_plan(pj, stream));
+  if (n_ids == 0) return FS_OK;
+  UpdateDeltaJob dj{};
+  dj.x = static_cast<uint8_t *>(x);
+  dj.new_blocks = static_cast<const uint8_t *>(new_blocks);
+  dj.delta = b.delta;
+  dj.ids = ids;
+  dj.n_ids = n_ids;
+  dj.t = t;
+  dj.flag = b.flag;
+  FS_TRY(launch_update_delta(dj, stream));
+  GatherJob gj{};
+  gj.src = b.delta;
+  gj.src_stride = t;
+  gj.dst = static_cast<uint8_t *>(c);
+  gj.dst_stride = t;
+  gj.ptr = b.aptr;
+  gj.idx = b.asrc;
+  gj.out_map = b.arow;
+  gj.nrows_dev = b.n_aff;
+  gj.skip_flag = b.flag;
+  gj.nrows = b.max_rows;
+  gj.csr_rows = b.max_rows;
+  gj.t = t;
+  gj.accumulate = 1;
+  return launch_gather(gj, current_tune(), stream);
+}
+
+}  // extern "C"

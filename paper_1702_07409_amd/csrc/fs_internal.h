@@ -1,0 +1,166 @@
+// Internal declarations shared by the host runtime and the HIP kernels of libfs.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fs_api.h"
+
+// The opaque graph: host CSR/CSC plus one device allocation holding the same
+// four arrays (int32).  Immutable after build.
+struct fs_graph {
+  uint32_t k = 0, n = 0;
+  uint64_t nnz = 0;
+  uint32_t max_deg = 0, max_cdeg = 0;
+  fs_graph_params params{};
+  std::vector<double> finite_w;  // owned copy of the finite table
+  std::vector<int32_t> row_ptr, col, col_ptr, rowidx;
+  int device = -1;
+  void *d_base = nullptr;
+  const int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_col_ptr = nullptr,
+                *d_rowidx = nullptr;
+};
+
+namespace fs {
+
+// thread-local error text; returns s for chaining
+fs_status fail(fs_status s, const std::string &msg);
+void clear_error();
+
+// host graph construction (graph_host.cpp)
+fs_status degree_weights(const fs_graph_params &p, std::vector<double> &w);
+fs_status degree_thresholds(const std::vector<double> &w, std::vector<uint64_t> &T);
+fs_status build_host_graph(const fs_graph_params &p, fs_graph &g);
+
+// device facts cached per device
+struct DeviceInfo {
+  int cu_count = 256;
+  int max_lds_per_block = 65536;
+};
+const DeviceInfo &device_info(int dev);
+
+// workspace carving: aligned sub-buffers of one caller workspace
+struct Carver {
+  uint8_t *base;
+  size_t off = 0;
+  explicit Carver(void *b) : base(static_cast<uint8_t *>(b)) {}
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+  size_t size() const { return (off + 255) & ~size_t(255); }
+};
+
+// ---- kernel launchers (kernels.hip) ----
+
+struct GatherJob {
+  const uint8_t *src;      // source block b at src + b * src_stride
+  uint64_t src_stride;
+  uint8_t *dst;            // output block o at dst + o * dst_stride
+  uint64_t dst_stride;
+  const int32_t *ptr;      // sources of CSR row j: idx[ptr[j] .. ptr[j+1])
+  const int32_t *idx;
+  const uint32_t *csr_map; // CSR row of output item r (null: r)
+  const int32_t *out_map;  // output block of item r (null: csr row)
+  const uint8_t *row_ok;   // item r is zero-filled when row_ok[r] == 0 (null: all ok)
+  const int32_t *nrows_dev;  // device item count (null: nrows)
+  const int32_t *skip_flag;  // non-zero: the launch writes nothing
+  uint32_t nrows;          // item count, or its upper bound with nrows_dev
+  uint32_t csr_rows;       // CSR rows; items mapping beyond are skipped
+  uint64_t t;              // bytes per block (multiple of 16)
+  int accumulate;          // XOR into the existing output
+};
+
+fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s);
+
+struct PeelJob {
+  uint32_t k, n;
+  const int32_t *row_ptr, *col, *col_ptr, *rowidx;
+  const uint8_t *erased;     // device uint8[n]
+  uint32_t maxit;
+  uint8_t *recovered;        // uint8[k]
+  int32_t *status;           // int32[3]
+  int32_t *level_ptr;        // int32[k+1]
+  int32_t *dp_f, *dp_g;      // int32[k]
+  // global-state workspace (used when the state does not fit in LDS)
+  unsigned long long *acc, *best;
+  int32_t *front_a, *front_b, *dlist;
+  uint32_t *mask, *decmask;
+  const int32_t *skip_flag;  // non-zero: write status only
+};
+
+size_t peel_ws_bytes(uint32_t k, uint32_t n);
+void peel_carve(Carver &cv, PeelJob &j);
+size_t peel_lds_bytes(uint32_t k, uint32_t n);
+fs_status launch_peel(const PeelJob &job, hipStream_t s);
+
+struct ReplayJob {
+  uint32_t k, n;
+  const int32_t *row_ptr, *col;
+  const uint8_t *c;
+  uint8_t *x;
+  uint64_t t;
+  const int32_t *status, *level_ptr, *dp_f, *dp_g;
+  const int32_t *skip_flag;  // non-zero: the launch writes nothing
+};
+fs_status launch_replay(const ReplayJob &job, hipStream_t s);
+
+// lost-row validation / masks for repair
+struct RepairPrepJob {
+  uint32_t n, k;
+  const uint32_t *lost;
+  uint32_t n_lost;
+  const uint8_t *erased;   // may be null
+  uint8_t *erased2;        // may be null (mode A): erased | lost
+  uint32_t *seen;          // uint32[ceil(n/32)] scratch
+  int32_t *flag;           // out: 0 ok, FS_ERR_INVALID bad ids
+  uint8_t *repaired;       // out: default value
+  int32_t *status;         // out
+};
+fs_status launch_repair_prep(const RepairPrepJob &job, hipStream_t s);
+
+struct RepairCheckJob {
+  const int32_t *row_ptr, *col;
+  uint32_t n;
+  const uint32_t *lost;
+  uint32_t n_lost;
+  const uint8_t *recovered;   // from the conventional decode
+  const int32_t *flag;
+  uint8_t *repaired;
+  int32_t *status;
+};
+fs_status launch_repair_check(const RepairCheckJob &job, hipStream_t s);
+
+struct UpdatePlanJob {
+  uint32_t k, n;
+  const int32_t *col_ptr, *rowidx;
+  const uint32_t *ids;
+  uint32_t n_ids;
+  uint32_t *seen;      // uint32[ceil(k/32)]
+  int32_t *cnt;        // int32[n]
+  int32_t *arow;       // int32[n]
+  int32_t *aptr;       // int32[n+1]
+  int32_t *asrc;       // int32[max pairs]
+  int32_t *n_aff;      // int32[1]
+  int32_t *flag;       // int32[1]
+  int32_t *status;     // int32[3]
+};
+fs_status launch_update_plan(const UpdatePlanJob &job, hipStream_t s);
+
+struct UpdateDeltaJob {
+  uint8_t *x;
+  const uint8_t *new_blocks;
+  uint8_t *delta;
+  const uint32_t *ids;
+  uint32_t n_ids;
+  uint64_t t;
+  const int32_t *flag;
+};
+fs_status launch_update_delta(const UpdateDeltaJob &job, hipStream_t s);
+
+}  // namespace fs

@@ -1,0 +1,175 @@
+// Host construction of the seeded LDGM graph (degree tables, Floyd sampling,
+// CSR by coded row, CSC by input).  Pure host code: no HIP call here.
+//
+// Floating point: the degree weights and thresholds must be reproducible bit
+// for bit, so this file is compiled with -ffp-contract=off and uses libm log
+// and sqrt only; every sum runs in a fixed order.
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "fs_internal.h"
+
+namespace fs {
+namespace {
+
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kTwo53 = 1ull << 53;
+constexpr uint64_t kPurposeGraph = 1;
+
+// SplitMix64 output function (Steele, Lea & Flood 2014; Stafford Mix13 constants).
+inline uint64_t mix(uint64_t z) {
+  z ^= z >> 30;
+  z *= 0xBF58476D1CE4E5B9ull;
+  z ^= z >> 27;
+  z *= 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  return z;
+}
+
+inline uint64_t row_key(uint64_t seed, uint64_t stripe_key, uint64_t row) {
+  uint64_t h = mix(seed + kGolden);
+  h = mix(h ^ kPurposeGraph);
+  h = mix(h ^ stripe_key);
+  return mix(h ^ row);
+}
+
+inline uint64_t draw(uint64_t key, uint64_t i) { return mix(key + (i + 1) * kGolden); }
+
+// Raptor degree distribution of the paper (§2.2): (degree, Omega_degree).
+const std::pair<uint32_t, double> kRaptor[] = {
+    {1, 0.007969}, {2, 0.49357},   {3, 0.16622},  {4, 0.072646},  {5, 0.082558},
+    {8, 0.056058}, {9, 0.037229},  {19, 0.05559}, {64, 0.025023}, {65, 0.003135},
+};
+
+}  // namespace
+
+fs_status degree_weights(const fs_graph_params &p, std::vector<double> &w) {
+  const uint32_t k = p.k;
+  if (k < 1) return fail(FS_ERR_INVALID, "k must be >= 1");
+  w.clear();
+  if (p.dist == FS_DIST_RSD) {
+    const double c = p.rsd_c, delta = p.rsd_delta;
+    if (!(c > 0.0) || !(delta > 0.0 && delta < 1.0))
+      return fail(FS_ERR_INVALID, "RSD needs c > 0 and 0 < delta < 1");
+    const double R = c * std::log((double)k / delta) * std::sqrt((double)k);
+    if (!(R / delta > 1.0)) return fail(FS_ERR_INVALID, "RSD needs R/delta > 1");
+    double mf = std::floor((double)k / R);
+    uint64_t M = mf < 1.0 ? 1 : (mf > (double)k ? k : (uint64_t)mf);
+    w.assign((size_t)k + 1, 0.0);
+    for (uint64_t i = 1; i <= k; ++i) {
+      const double rho = (i == 1) ? 1.0 / (double)k : 1.0 / (double)(i * (i - 1));
+      double tau = 0.0;
+      if (i < M)
+        tau = R / (double)(i * (uint64_t)k);
+      else if (i == M)
+        tau = R * std::log(R / delta) / (double)k;
+      w[i] = rho + tau;
+    }
+    return FS_OK;
+  }
+  std::vector<double> tab;
+  if (p.dist == FS_DIST_FINITE) {
+    if (p.finite_dmax < 1 || p.finite_w == nullptr)
+      return fail(FS_ERR_INVALID, "finite table needs finite_dmax >= 1 and weights");
+    tab.assign(p.finite_w, p.finite_w + p.finite_dmax);
+  } else if (p.dist == FS_DIST_RAPTOR) {
+    tab.assign(65, 0.0);
+    for (const auto &e : kRaptor) tab[e.first - 1] = e.second;
+  } else {
+    return fail(FS_ERR_INVALID, "unknown degree distribution");
+  }
+  for (double v : tab)
+    if (!(v >= 0.0) || std::isinf(v)) return fail(FS_ERR_INVALID, "finite weights must be finite and >= 0");
+  const size_t D = std::min<size_t>(tab.size(), k);
+  w.assign(D + 1, 0.0);
+  double tot = 0.0;
+  for (size_t d = 1; d <= D; ++d) {
+    w[d] = tab[d - 1];
+    tot += w[d];
+  }
+  if (!(tot > 0.0)) return fail(FS_ERR_INVALID, "finite table has no mass at degrees <= k");
+  return FS_OK;
+}
+
+fs_status degree_thresholds(const std::vector<double> &w, std::vector<uint64_t> &T) {
+  const size_t D = w.size() - 1;
+  double W = 0.0;
+  for (size_t d = 1; d <= D; ++d) W += w[d];
+  T.assign(D, 0);
+  double C = 0.0;
+  for (size_t d = 1; d <= D; ++d) {
+    C += w[d] / W;
+    if (d < D) {
+      const double v = std::floor(C * (double)kTwo53);
+      T[d - 1] = v >= (double)kTwo53 ? kTwo53 : (uint64_t)v;
+    } else {
+      T[d - 1] = kTwo53;
+    }
+  }
+  return FS_OK;
+}
+
+fs_status build_host_graph(const fs_graph_params &p, fs_graph &g) {
+  if (p.k < 1 || p.n < 1) return fail(FS_ERR_INVALID, "k and n must be >= 1");
+  if (p.k > (1u << 20)) return fail(FS_ERR_INVALID, "k above 2^20 is not supported");
+  if (p.reserved != 0) return fail(FS_ERR_INVALID, "reserved field must be 0");
+  std::vector<double> w;
+  fs_status st = degree_weights(p, w);
+  if (st != FS_OK) return st;
+  std::vector<uint64_t> T;
+  degree_thresholds(w, T);
+
+  const uint32_t k = p.k, n = p.n;
+  g.k = k;
+  g.n = n;
+  g.params = p;
+  if (p.dist == FS_DIST_FINITE) {
+    g.finite_w.assign(p.finite_w, p.finite_w + p.finite_dmax);
+    g.params.finite_w = g.finite_w.data();
+  } else {
+    g.params.finite_w = nullptr;
+  }
+  g.row_ptr.assign((size_t)n + 1, 0);
+  g.col.clear();
+  std::vector<uint32_t> stamp(k, 0xFFFFFFFFu);   // stamp[v] == j: v taken in row j
+  std::vector<int32_t> row;
+  uint32_t max_deg = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    const uint64_t key = row_key(p.seed, p.stripe_key, j);
+    const uint64_t v0 = draw(key, 0) >> 11;
+    const uint32_t d = (uint32_t)(std::upper_bound(T.begin(), T.end(), v0) - T.begin()) + 1;
+    row.clear();
+    for (uint32_t s = 0; s < d; ++s) {
+      const uint64_t r = (uint64_t)(k - d) + s;
+      const uint64_t v = ((draw(key, s + 1) >> 32) * (r + 1)) >> 32;
+      const uint32_t pick = (stamp[v] == j) ? (uint32_t)r : (uint32_t)v;
+      stamp[pick] = j;
+      row.push_back((int32_t)pick);
+    }
+    std::sort(row.begin(), row.end());
+    if (g.col.size() + row.size() >= (size_t)INT32_MAX)
+      return fail(FS_ERR_INVALID, "graph has 2^31 or more edges");
+    g.col.insert(g.col.end(), row.begin(), row.end());
+    g.row_ptr[j + 1] = (int32_t)g.col.size();
+    max_deg = std::max(max_deg, d);
+  }
+  g.nnz = g.col.size();
+  g.max_deg = max_deg;
+  // transpose by counting sort; rows are visited in ascending order
+  g.col_ptr.assign((size_t)k + 1, 0);
+  for (int32_t i : g.col) g.col_ptr[(size_t)i + 1]++;
+  for (uint32_t i = 0; i < k; ++i) g.col_ptr[i + 1] += g.col_ptr[i];
+  std::vector<int32_t> fill(g.col_ptr.begin(), g.col_ptr.end() - 1);
+  g.rowidx.assign(g.nnz, 0);
+  uint32_t max_cdeg = 0;
+  for (uint32_t j = 0; j < n; ++j)
+    for (int32_t e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e) g.rowidx[fill[g.col[e]]++] = (int32_t)j;
+  for (uint32_t i = 0; i < k; ++i)
+    max_cdeg = std::max<uint32_t>(max_cdeg, (uint32_t)(g.col_ptr[i + 1] - g.col_ptr[i]));
+  g.max_cdeg = max_cdeg;
+  return FS_OK;
+}
+
+}  // namespace fs

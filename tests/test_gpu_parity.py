@@ -1,0 +1,299 @@
+"""GPU parity: every library result equals the oracle's, bit for bit.
+
+All calls go through the C ABI (ctypes binding); payloads are seeded uniform
+bytes.  Run on an MI355X: pytest -m gpu.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import (check_schedule, dev, empty_i32, empty_u8, gpu_decode, gpu_peel, graphs, host,
+                      oracle_decode)
+from oracle import codec
+from synth import gen, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_07409_amd as fs
+    fs.fs_reset_tune()
+    yield
+    fs.fs_reset_tune()
+
+
+def spec_graphs(sp):
+    return graphs(**sp.graph_kwargs())
+
+
+def encode_case(sp):
+    import paper_1702_07409_amd as fs
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    xd = dev(x)
+    c = empty_u8(sp.n, sp.t)
+    fs.fs_encode(g, xd, c, sp.t)
+    return g, G, x, xd, c
+
+
+# ---------------------------------------------------------------- encode
+
+def test_encode_tiny():
+    sp = workloads.tiny()
+    g, G, x, xd, c = encode_case(sp)
+    assert np.array_equal(host(c), codec.encode(G, x))
+
+
+RAGGED = workloads.StripeSpec(stripe=3, k=300, n=333, t=512 * 7 + 48, dist="rsd", rsd_c=0.1,
+                              rsd_delta=0.05, stripe_key=5, n_erased=20)
+
+
+def test_encode_ragged_every_tuning():
+    import paper_1702_07409_amd as fs
+    sp = RAGGED
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    want = codec.encode(G, x)
+    xd = dev(x)
+    for lpr in (16, 32, 64):
+        for ch in (1, 2, 4):
+            for nt in (0, 1):
+                for remap in (0, 1):
+                    fs.fs_set_tune(lpr, ch, remap, nt)
+                    c = empty_u8(sp.n, sp.t)
+                    c.fill_(0x5A)
+                    fs.fs_encode(g, xd, c, sp.t)
+                    assert np.array_equal(host(c), want), (lpr, ch, nt, remap)
+    fs.fs_reset_tune()
+
+
+def test_encode_large_stripe_full_size():
+    sp = workloads.large_stripe()
+    g, G, x, xd, c = encode_case(sp)
+    assert np.array_equal(host(c), codec.encode(G, x))
+
+
+def test_encode_degree_k_rows_and_k1():
+    import paper_1702_07409_amd as fs
+    for kw, t in [(dict(k=8, n=20, dist="finite", finite_w=(0,) * 7 + (1.0,), seed=3), 64),
+                  (dict(k=1, n=5, seed=2), 16)]:
+        g, G = graphs(**kw)
+        x = gen.payload(1, 0, kw["k"], t)
+        c = empty_u8(kw["n"], t)
+        fs.fs_encode(g, dev(x), c, t)
+        assert np.array_equal(host(c), codec.encode(G, x))
+
+
+def test_encode_rejects_bad_alignment():
+    import paper_1702_07409_amd as fs
+    g, _ = graphs(k=8, n=10, seed=1)
+    x, c = empty_u8(8 * 64 + 16), empty_u8(10 * 64)
+    with pytest.raises(fs.FsError):
+        fs.fs_encode(g, x, c, 40)
+    with pytest.raises(fs.FsError):
+        fs.fs_encode(g, x[1:], c, 64)
+
+
+# ---------------------------------------------------------------- peel + decode
+
+def decode_case(sp, maxit=0):
+    import paper_1702_07409_amd as fs
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    c = dev(c_host)
+    er = sp.erased_mask()
+    sched = codec.peel_schedule(G, er, maxit)
+    check_schedule(sched, gpu_peel(g, er, maxit))
+    got = gpu_decode(g, c, er, sp.t, maxit)
+    xo, reco, sto, _ = oracle_decode(G, c_host, er, maxit)
+    assert list(got.status) == list(sto)
+    assert np.array_equal(got.recovered, reco)
+    assert np.array_equal(got.x, xo)
+    R = reco.astype(bool)
+    assert np.array_equal(got.x[R], x[R])
+    return g, G, got, sched
+
+
+def test_decode_tiny():
+    decode_case(workloads.tiny())
+
+
+def test_decode_ragged():
+    decode_case(RAGGED)
+
+
+def test_decode_large_stripe_full_size():
+    _, _, got, sched = decode_case(workloads.large_stripe())
+    assert sched.L > 10 and 0 < got.status[1] < 4096
+
+
+@pytest.mark.parametrize("maxit", [1, 2, 5])
+def test_decode_maxit(maxit):
+    decode_case(workloads.tiny(), maxit)
+
+
+def test_decode_success_path_high_overhead():
+    sp = workloads.StripeSpec(stripe=1, k=500, n=1000, t=512, dist="rsd", n_erased=100)
+    _, _, got, _ = decode_case(sp)
+    assert got.status[0] == 1
+
+
+def test_decode_no_erasures_and_all_erased():
+    for ne in (0, 96):
+        sp = workloads.tiny()
+        sp.n_erased = ne
+        _, _, got, _ = decode_case(sp)
+        if ne == 96:
+            assert list(got.status) == [0, 64, 0] and not got.x.any()
+
+
+def test_decode_forced_failure_of_one_input():
+    sp = workloads.StripeSpec(stripe=0, k=64, n=200, t=256, dist="rsd", graph_seed=3)
+    g, G = spec_graphs(sp)
+    er = np.zeros(sp.n, np.uint8)
+    er[G.NT(7)] = 1
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    got = gpu_decode(g, dev(c_host), er, sp.t)
+    assert got.recovered[7] == 0 and not got.x[7].any()
+    xo, reco, sto, _ = oracle_decode(G, c_host, er)
+    assert np.array_equal(got.x, xo) and list(got.status) == list(sto)
+
+
+def test_decode_k1_t16():
+    sp = workloads.StripeSpec(stripe=0, k=1, n=4, t=16, dist="rsd", n_erased=2)
+    decode_case(sp)
+
+
+def test_peel_state_beyond_lds_uses_workspace():
+    # k = 16384 does not fit the peel state in LDS: the global-state kernel runs
+    sp = workloads.StripeSpec(stripe=0, k=16384, n=18022, t=16, dist="rsd", stripe_key=1, n_erased=901)
+    decode_case(sp)
+
+
+def test_peel_replay_equals_decode_and_is_deterministic():
+    import paper_1702_07409_amd as fs
+    sp = workloads.large_stripe()
+    sp = workloads.scaled(sp, 1024)
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    c = dev(codec.encode(G, x))
+    er = sp.erased_mask()
+    a = gpu_decode(g, c, er, sp.t)
+    b = gpu_decode(g, c, er, sp.t)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.status, b.status)
+    p = gpu_peel(g, er)
+    x2 = empty_u8(sp.k, sp.t)
+    st = dev(p.status)
+    lp = empty_i32(sp.k + 1)
+    lp[:len(p.level_ptr)] = dev(p.level_ptr)
+    fs.fs_replay(g, c, st, lp, dev(p.dp_f), dev(p.dp_g), x2, sp.t)
+    assert np.array_equal(host(x2), a.x)
+
+
+# ---------------------------------------------------------------- repair
+
+def test_repair_from_inputs():
+    import paper_1702_07409_amd as fs
+    sp = workloads.resident256(2)[1]
+    sp = workloads.scaled(sp, 4096)
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    lost = sp.extra["lost"]
+    c = dev(c_host)
+    c[lost] = 0
+    rep, st = empty_u8(len(lost)), empty_i32(3)
+    ws = fs.workspace(g, fs.FS_OP_REPAIR, sp.t, len(lost))
+    fs.fs_repair(g, dev(x), c, None, dev(np.array(lost, np.uint32)), len(lost), rep, st, sp.t, ws)
+    assert np.array_equal(host(c), c_host)
+    assert host(rep).tolist() == [1] * len(lost) and host(st).tolist() == [1, 0, 0]
+
+
+def test_repair_conventional():
+    import paper_1702_07409_amd as fs
+    sp = workloads.StripeSpec(stripe=2, k=64, n=96, t=512, dist="rsd", graph_seed=2, n_erased=4)
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    er = sp.erased_mask()
+    # rows that the conventional repair can and cannot rebuild
+    lost = [j for j in range(sp.n) if not er[j]][:12]
+    want, ok = codec.repair_conventional(G, c_host, er, lost)
+    assert 0 < ok.sum() < len(lost)
+    c = dev(c_host)
+    c[lost] = 0x77
+    rep, st = empty_u8(len(lost)), empty_i32(3)
+    ws = fs.workspace(g, fs.FS_OP_REPAIR_CONVENTIONAL, sp.t, len(lost))
+    fs.fs_repair(g, None, c, dev(er), dev(np.array(lost, np.uint32)), len(lost), rep, st, sp.t, ws)
+    got = host(c)
+    assert np.array_equal(host(rep), ok)
+    assert np.array_equal(got[lost], want)
+    others = [j for j in range(sp.n) if j not in lost]
+    assert np.array_equal(got[others], c_host[others])
+    assert host(st).tolist() == [0, int(len(lost) - ok.sum()), 0]
+
+
+def test_repair_rejects_bad_lost_ids_without_writing():
+    import paper_1702_07409_amd as fs
+    sp = workloads.tiny()
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    for lost in ([3, 96], [5, 9, 5]):
+        for mode_a in (True, False):
+            c = dev(c_host)
+            rep, st = empty_u8(len(lost)), empty_i32(3)
+            op = fs.FS_OP_REPAIR if mode_a else fs.FS_OP_REPAIR_CONVENTIONAL
+            ws = fs.workspace(g, op, sp.t, len(lost))
+            fs.fs_repair(g, dev(x) if mode_a else None, c, None, dev(np.array(lost, np.uint32)),
+                         len(lost), rep, st, sp.t, ws)
+            assert np.array_equal(host(c), c_host)
+            assert host(st).tolist() == [0, len(lost), fs._lib.FS_ERR_INVALID]
+            assert not host(rep).any()
+
+
+# ---------------------------------------------------------------- update
+
+def update_case(sp, ids, t=None):
+    import paper_1702_07409_amd as fs
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    new = gen.update_blocks(workloads.UPDATE_DATA_SEED, sp.stripe, ids, sp.t)
+    xd, cd = dev(x), dev(c_host)
+    st = empty_i32(3)
+    ws = fs.workspace(g, fs.FS_OP_UPDATE, sp.t, len(ids))
+    fs.fs_update(g, xd, cd, dev(np.array(ids, np.uint32)), len(ids), dev(new), st, sp.t, ws)
+    return G, x, c_host, new, host(xd), host(cd), host(st)
+
+
+def test_update_equals_reencode():
+    sp = workloads.scaled(workloads.resident256(1)[0], 8192)
+    ids = sp.extra["update_ids"]
+    G, x, c_host, new, xg, cg, st = update_case(sp, ids)
+    x2, c2 = codec.update(G, x, ids, new)
+    assert np.array_equal(xg, x2) and np.array_equal(cg, c2)
+    aff = codec.affected_rows(G, ids)
+    assert st.tolist() == [len(aff), sum(len(G.NT(i)) for i in ids), 0]
+
+
+def test_update_rejects_bad_ids_without_writing():
+    sp = workloads.tiny()
+    for ids in ([1, 64], [3, 4, 3]):
+        G, x, c_host, new, xg, cg, st = update_case(sp, ids)
+        assert np.array_equal(xg, x) and np.array_equal(cg, c_host)
+        assert st.tolist()[2] != 0
+
+
+def test_update_all_inputs():
+    sp = workloads.tiny()
+    ids = list(range(sp.k))[::-1]
+    G, x, c_host, new, xg, cg, st = update_case(sp, ids)
+    x2, c2 = codec.update(G, x, ids, new)
+    assert np.array_equal(xg, x2) and np.array_equal(cg, c2)
