@@ -43,7 +43,29 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--mode", choices=["step", "counters"], default="step",
+                    help="counters: only K encode launches plus one plain copy of the same "
+                         "output size, for rocprofv3 --pmc runs")
     return ap.parse_args()
+
+
+def counters_run(args, fs, torch, g, x, c, t, decode):
+    """Encode and decode launches, then a plain device copy of known size
+    (the scale of the traffic counters)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(max(1, args.steps)):
+        fs.fs_encode(g, x, c, t, stream)
+    for _ in range(max(1, args.steps)):
+        decode()
+    src = torch.empty(c.numel(), dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"mode": "counters", "encode_launches": max(1, args.steps),
+                      "decode_launches": max(1, args.steps),
+                      "copy_bytes_each_way": int(src.numel())}), flush=True)
 
 
 def cpu_baseline(spec, seconds):
@@ -93,6 +115,10 @@ def main():
     st = torch.empty(3, dtype=torch.int32, device="cuda")
     ws = fs.workspace(g, fs.FS_OP_DECODE, t)
     stream = torch.cuda.current_stream()
+    if args.mode == "counters":
+        counters_run(args, fs, torch, g, x, c, t,
+                     lambda: fs.fs_decode(g, c, er, 0, xd, rec, st, t, ws, stream))
+        return
 
     def step(ev=None):
         if ev is not None:
@@ -129,13 +155,14 @@ def main():
     df = torch.empty(k, dtype=torch.int32, device="cuda")
     dg = torch.empty(k, dtype=torch.int32, device="cuda")
     pws = fs.workspace(g, fs.FS_OP_PEEL)
+    rws = fs.workspace(g, fs.FS_OP_REPLAY, t)
     e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
     peel_ms, rep_ms = [], []
     for _ in range(5):
         e[0].record(stream)
         fs.fs_peel(g, er, 0, rec, st, lp, df, dg, pws, stream)
         e[1].record(stream)
-        fs.fs_replay(g, c, st, lp, df, dg, xd, t, stream)
+        fs.fs_replay(g, c, st, lp, df, dg, xd, t, rws, stream)
         e[2].record(stream)
         torch.cuda.synchronize()
         peel_ms.append(e[0].elapsed_time(e[1]))

@@ -136,7 +136,7 @@ FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t
 
 /* Operations for fs_workspace_size. */
 enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
-       FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5 };
+       FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6 };
 
 /*
  * Workspace bytes the operation needs for this graph and block size
@@ -173,11 +173,14 @@ FS_API fs_status fs_peel(const fs_graph *g, const uint8_t *erased, uint32_t maxi
  *   x_f = c_g XOR (XOR of x_i for i in N(g), i != f),
  * then x_f = 0 for every f left in F.  Reads c (device uint8[n][t]), writes
  * every block of x (device uint8[k][t]).  status/level_ptr/dp_f/dp_g are the
- * device outputs of fs_peel for the same graph.
+ * device outputs of fs_peel for the same graph.  ws: FS_OP_REPLAY bytes (the
+ * schedule is flattened there into a replay program).  A schedule that does
+ * not come from fs_peel never makes the call touch memory outside x, c and ws,
+ * but the bytes it leaves in x are then unspecified.
  */
 FS_API fs_status fs_replay(const fs_graph *g, const void *c, const int32_t *status,
                     const int32_t *level_ptr, const int32_t *dp_f, const int32_t *dp_g, void *x,
-                    uint64_t t, hipStream_t stream);
+                    uint64_t t, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Decode (Algorithms 1/5, "founsureDec"): fs_peel into the
@@ -224,6 +227,8 @@ typedef struct fs_tune {
   uint32_t chunks;         /* 16-byte chunks per lane per slice: 1, 2 or 4   */
   uint32_t xcd_remap;      /* 1: keep each XCD on a contiguous slice range   */
   uint32_t nt_store;       /* 1: non-temporal stores for outputs             */
+  uint32_t replay_prog_global; /* 1: keep decode replay programs in global
+                                  memory instead of LDS (slower; for checks)  */
 } fs_tune;
 
 /* Override (or with NULL restore) the gather tuning used by this process. */

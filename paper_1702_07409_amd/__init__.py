@@ -7,7 +7,7 @@ supplies device memory and streams.
 
 from ._lib import (  # noqa: F401
     EXPORTED, FS_DEFAULT_SEED, FS_OP_DECODE, FS_OP_ENCODE, FS_OP_PEEL, FS_OP_REPAIR,
-    FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE, FsError, Graph, fs_decode, fs_degree_table,
+    FS_OP_REPAIR_CONVENTIONAL, FS_OP_REPLAY, FS_OP_UPDATE, FsError, Graph, fs_decode, fs_degree_table,
     fs_encode, fs_get_tune, fs_graph_build, fs_peel, fs_repair, fs_replay, fs_reset_tune,
     fs_set_tune, fs_update, fs_workspace_size, version, workspace,
 )

@@ -21,7 +21,7 @@ FS_OK, FS_ERR_INVALID, FS_ERR_ALIGN, FS_ERR_NOMEM, FS_ERR_HIP, FS_ERR_UNSUPPORTE
 FS_DIST_RSD, FS_DIST_FINITE, FS_DIST_RAPTOR = 0, 1, 2
 FS_DEFAULT_SEED = 1389488782
 FS_GRAPH_HOST_ONLY = 1
-FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE = range(6)
+FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE, FS_OP_REPLAY = range(7)
 
 DIST_CODES = {"rsd": FS_DIST_RSD, "finite": FS_DIST_FINITE, "raptor": FS_DIST_RAPTOR}
 
@@ -36,7 +36,8 @@ class fs_graph_params(ctypes.Structure):
 
 class fs_tune(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
-                ("xcd_remap", ctypes.c_uint32), ("nt_store", ctypes.c_uint32)]
+                ("xcd_remap", ctypes.c_uint32), ("nt_store", ctypes.c_uint32),
+                ("replay_prog_global", ctypes.c_uint32)]
 
 
 P = ctypes.c_void_p
@@ -53,7 +54,7 @@ _SIGS = {
     "fs_workspace_size": ([P, I32, U64, U32, ctypes.POINTER(SZ)], ST),
     "fs_encode": ([P, P, P, U64, P], ST),
     "fs_peel": ([P, P, U32, P, P, P, P, P, P, SZ, P], ST),
-    "fs_replay": ([P, P, P, P, P, P, P, U64, P], ST),
+    "fs_replay": ([P, P, P, P, P, P, P, U64, P, SZ, P], ST),
     "fs_decode": ([P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
     "fs_repair": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
@@ -206,9 +207,10 @@ def fs_peel(g, erased, maxit, recovered, status, level_ptr, dp_f, dp_g, ws, stre
                         _ptr(dp_f), _ptr(dp_g), w, wb, _stream(stream)), "fs_peel")
 
 
-def fs_replay(g, c, status, level_ptr, dp_f, dp_g, x, t, stream=None):
+def fs_replay(g, c, status, level_ptr, dp_f, dp_g, x, t, ws, stream=None):
+    w, wb = _ws(ws)
     _check(_lib.fs_replay(g.handle, _ptr(c), _ptr(status), _ptr(level_ptr), _ptr(dp_f), _ptr(dp_g),
-                          _ptr(x), t, _stream(stream)), "fs_replay")
+                          _ptr(x), t, w, wb, _stream(stream)), "fs_replay")
 
 
 def fs_decode(g, c, erased, maxit, x, recovered, status, t, ws, stream=None):
@@ -229,8 +231,8 @@ def fs_update(g, x, c, ids, n_ids, new_blocks, status, t, ws, stream=None):
                           t, w, wb, _stream(stream)), "fs_update")
 
 
-def fs_set_tune(lanes_per_row=16, chunks=2, xcd_remap=1, nt_store=1):
-    tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store)
+def fs_set_tune(lanes_per_row=16, chunks=2, xcd_remap=1, nt_store=1, replay_prog_global=0):
+    tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store, replay_prog_global)
     _check(_lib.fs_set_tune(ctypes.byref(tu)), "fs_set_tune")
 
 
@@ -242,4 +244,4 @@ def fs_get_tune():
     tu = fs_tune()
     _check(_lib.fs_get_tune(ctypes.byref(tu)), "fs_get_tune")
     return dict(lanes_per_row=tu.lanes_per_row, chunks=tu.chunks, xcd_remap=tu.xcd_remap,
-                nt_store=tu.nt_store)
+                nt_store=tu.nt_store, replay_prog_global=tu.replay_prog_global)

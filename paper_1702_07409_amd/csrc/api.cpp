@@ -38,7 +38,7 @@ const DeviceInfo &device_info(int dev) {
 namespace {
 
 std::mutex g_tune_mu;
-fs_tune g_tune = {16, 2, 1, 1};
+fs_tune g_tune = {16, 2, 1, 1, 0};
 
 fs_tune current_tune() {
   std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -48,7 +48,7 @@ fs_tune current_tune() {
 bool tune_ok(const fs_tune &t) {
   const bool lpr = t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64;
   const bool ch = t.chunks == 1 || t.chunks == 2 || t.chunks == 4;
-  return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1;
+  return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1;
 }
 
 fs_status check_graph(const fs_graph *g) {
@@ -93,6 +93,7 @@ struct RepairBufs {
   uint8_t *erased2;
   SchedBufs sched;
   PeelJob peel;
+  ProgJob prog;
   uint8_t *x;
 };
 
@@ -103,12 +104,16 @@ void carve_repair(Carver &cv, const fs_graph *g, uint64_t t, bool conventional, 
   b.x = nullptr;
   b.sched = SchedBufs{};
   b.peel = PeelJob{};
+  b.prog = ProgJob{};
   if (conventional) {
     b.erased2 = cv.take<uint8_t>(g->n);
     carve_sched(cv, g->k, b.sched, true);
     b.peel.k = g->k;
     b.peel.n = g->n;
     peel_carve(cv, b.peel);
+    b.prog.k = g->k;
+    b.prog.n = g->n;
+    prog_carve(cv, b.prog, g->nnz);
     b.x = cv.take<uint8_t>((size_t)g->k * t);
   }
 }
@@ -151,6 +156,17 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
       j.k = g->k;
       j.n = g->n;
       peel_carve(cv, j);
+      ProgJob pj{};
+      pj.k = g->k;
+      pj.n = g->n;
+      prog_carve(cv, pj, g->nnz);
+      return cv.size();
+    }
+    case FS_OP_REPLAY: {
+      ProgJob pj{};
+      pj.k = g->k;
+      pj.n = g->n;
+      prog_carve(cv, pj, g->nnz);
       return cv.size();
     }
     case FS_OP_REPAIR:
@@ -197,6 +213,21 @@ PeelJob peel_job(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8
   return j;
 }
 
+ProgJob prog_job(const fs_graph *g, Carver &cv, const int32_t *status, const int32_t *level_ptr,
+                 const int32_t *dp_f, const int32_t *dp_g) {
+  ProgJob p{};
+  p.k = g->k;
+  p.n = g->n;
+  p.row_ptr = g->d_row_ptr;
+  p.col = g->d_col;
+  p.status = status;
+  p.level_ptr = level_ptr;
+  p.dp_f = dp_f;
+  p.dp_g = dp_g;
+  prog_carve(cv, p, g->nnz);
+  return p;
+}
+
 ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, const int32_t *status,
                      const int32_t *level_ptr, const int32_t *dp_f, const int32_t *dp_g) {
   ReplayJob r{};
@@ -215,6 +246,9 @@ ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, cons
 }
 
 }  // namespace
+
+fs_tune tune_snapshot() { return current_tune(); }
+
 }  // namespace fs
 
 using namespace fs;
@@ -242,7 +276,7 @@ fs_status fs_set_tune(const fs_tune *tune) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_tune_mu);
   if (!tune) {
-    g_tune = fs_tune{16, 2, 1, 1};
+    g_tune = fs_tune{16, 2, 1, 1, 0};
     return FS_OK;
   }
   if (!tune_ok(*tune)) return fail(FS_ERR_INVALID, "tuning out of range");
@@ -348,7 +382,7 @@ void fs_graph_free(fs_graph *g) {
 fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
-  if (op < FS_OP_ENCODE || op > FS_OP_UPDATE) return fail(FS_ERR_INVALID, "unknown operation");
+  if (op < FS_OP_ENCODE || op > FS_OP_REPLAY) return fail(FS_ERR_INVALID, "unknown operation");
   if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_UPDATE) && (t == 0 || (t & 15)))
     return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
   *bytes = workspace_bytes(g, op, t, n_items);
@@ -384,17 +418,21 @@ fs_status fs_peel(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint
   PeelJob j = peel_job(g, erased, maxit, recovered, status, level_ptr, dp_f, dp_g);
   Carver cv(ws);
   peel_carve(cv, j);
-  return launch_peel(j, stream);
+  return launch_peel(j, stream, g->max_deg);
 }
 
 fs_status fs_replay(const fs_graph *g, const void *c, const int32_t *status, const int32_t *level_ptr,
-                    const int32_t *dp_f, const int32_t *dp_g, void *x, uint64_t t, hipStream_t stream) {
+                    const int32_t *dp_f, const int32_t *dp_g, void *x, uint64_t t, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
   clear_error();
   FS_TRY(check_graph(g));
   FS_TRY(check_payload(c, t, "c"));
   FS_TRY(check_payload(x, t, "x"));
   if (!status || !level_ptr || !dp_f || !dp_g) return fail(FS_ERR_INVALID, "schedule arrays must be non-null");
-  return launch_replay(replay_job(g, c, x, t, status, level_ptr, dp_f, dp_g), stream);
+  FS_TRY(check_ws(g, FS_OP_REPLAY, t, 0, ws, ws_bytes));
+  Carver cv(ws);
+  ProgJob p = prog_job(g, cv, status, level_ptr, dp_f, dp_g);
+  return launch_replay(replay_job(g, c, x, t, status, level_ptr, dp_f, dp_g), &p, stream);
 }
 
 fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uint32_t maxit, void *x,
@@ -411,8 +449,9 @@ fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uin
   carve_sched(cv, g->k, s, false);
   PeelJob j = peel_job(g, erased, maxit, recovered, status, s.level_ptr, s.dp_f, s.dp_g);
   peel_carve(cv, j);
-  FS_TRY(launch_peel(j, stream));
-  return launch_replay(replay_job(g, c, x, t, status, s.level_ptr, s.dp_f, s.dp_g), stream);
+  ProgJob p = prog_job(g, cv, status, s.level_ptr, s.dp_f, s.dp_g);
+  FS_TRY(launch_peel(j, stream, g->max_deg));
+  return launch_replay(replay_job(g, c, x, t, status, s.level_ptr, s.dp_f, s.dp_g), &p, stream);
 }
 
 fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *erased, const uint32_t *lost,
@@ -471,10 +510,19 @@ fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *er
   j.mask = b.peel.mask;
   j.decmask = b.peel.decmask;
   j.skip_flag = b.flag;
-  FS_TRY(launch_peel(j, stream));
+  FS_TRY(launch_peel(j, stream, g->max_deg));
   ReplayJob r = replay_job(g, c, b.x, t, b.sched.status, b.sched.level_ptr, b.sched.dp_f, b.sched.dp_g);
   r.skip_flag = b.flag;
-  FS_TRY(launch_replay(r, stream));
+  ProgJob p = b.prog;
+  p.n = g->n;
+  p.row_ptr = g->d_row_ptr;
+  p.col = g->d_col;
+  p.status = b.sched.status;
+  p.level_ptr = b.sched.level_ptr;
+  p.dp_f = b.sched.dp_f;
+  p.dp_g = b.sched.dp_g;
+  p.skip_flag = b.flag;
+  FS_TRY(launch_replay(r, &p, stream));
   RepairCheckJob cj{};
   cj.row_ptr = g->d_row_ptr;
   cj.col = g->d_col;

@@ -41,6 +41,9 @@ struct DeviceInfo {
 };
 const DeviceInfo &device_info(int dev);
 
+// the process-wide tuning (fs_set_tune)
+fs_tune tune_snapshot();
+
 // workspace carving: aligned sub-buffers of one caller workspace
 struct Carver {
   uint8_t *base;
@@ -97,7 +100,8 @@ struct PeelJob {
 size_t peel_ws_bytes(uint32_t k, uint32_t n);
 void peel_carve(Carver &cv, PeelJob &j);
 size_t peel_lds_bytes(uint32_t k, uint32_t n);
-fs_status launch_peel(const PeelJob &job, hipStream_t s);
+// max_deg selects the LDS variant (row degrees kept as 16-bit in LDS)
+fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg);
 
 struct ReplayJob {
   uint32_t k, n;
@@ -108,7 +112,24 @@ struct ReplayJob {
   const int32_t *status, *level_ptr, *dp_f, *dp_g;
   const int32_t *skip_flag;  // non-zero: the launch writes nothing
 };
-fs_status launch_replay(const ReplayJob &job, hipStream_t s);
+// Replay program built from a schedule (workspace arrays).
+struct ProgJob {
+  uint32_t k, n;
+  const int32_t *row_ptr, *col;
+  const int32_t *status, *level_ptr, *dp_f, *dp_g;
+  int32_t *gsrc;       // int32[k]
+  int32_t *finv;       // int32[n]: input decoded by row g, or -1
+  int32_t *gl, *fl;    // int32[k]: decoding rows ascending, and their inputs
+  int32_t *poff;       // int32[k+1]
+  int32_t *pidx;       // int32[pidx_cap]
+  int32_t *meta;       // int32[4]
+  uint32_t pidx_cap;
+  const int32_t *skip_flag;
+};
+void prog_carve(Carver &cv, ProgJob &p, uint64_t nnz);
+
+// prog: workspace for the LDS replay (null: global-memory replay only)
+fs_status launch_replay(const ReplayJob &job, const ProgJob *prog, hipStream_t s);
 
 // lost-row validation / masks for repair
 struct RepairPrepJob {

@@ -16,6 +16,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "fs_internal.h"
 
 namespace fs {
@@ -23,6 +25,8 @@ namespace fs {
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 namespace {
+
+constexpr int kPlanThreads = 1024;
 
 __device__ __forceinline__ v4u ld16(const uint8_t *p) { return *reinterpret_cast<const v4u *>(p); }
 
@@ -78,6 +82,37 @@ __device__ uint32_t block_exclusive_scan(uint32_t v, uint32_t *sh, uint32_t &tot
 // gather-XOR
 // ---------------------------------------------------------------------------
 constexpr int kGatherThreads = 256;
+constexpr int kStageCap = 2048;   // edges of one row tile staged in LDS
+
+// XOR of the sources of one row into acc.  Neighbour ids come from idx (LDS
+// when the tile's edge list was staged, else global); loads are issued in
+// batches of four neighbours x CH chunks before any is consumed.
+template <int CH, uint32_t STEP, class IdxPtr>
+__device__ __forceinline__ void gather_row(v4u (&acc)[CH], const bool (&valid)[CH], IdxPtr idx, int e,
+                                           const int e1, const uint8_t *src, const uint64_t stride) {
+  const v4u zero = {0u, 0u, 0u, 0u};
+  for (; e < e1; e += 4) {
+    const int cnt = e1 - e;
+    const int32_t i0 = idx[e];
+    const int32_t i1 = cnt > 1 ? idx[e + 1] : 0;
+    const int32_t i2 = cnt > 2 ? idx[e + 2] : 0;
+    const int32_t i3 = cnt > 3 ? idx[e + 3] : 0;
+    const uint8_t *p0 = src + (uint64_t)i0 * stride;
+    const uint8_t *p1 = src + (uint64_t)i1 * stride;
+    const uint8_t *p2 = src + (uint64_t)i2 * stride;
+    const uint8_t *p3 = src + (uint64_t)i3 * stride;
+    v4u v0[CH], v1[CH], v2[CH], v3[CH];
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      v0[c] = valid[c] ? ld16(p0 + c * STEP) : zero;
+      v1[c] = (valid[c] && cnt > 1) ? ld16(p1 + c * STEP) : zero;
+      v2[c] = (valid[c] && cnt > 2) ? ld16(p2 + c * STEP) : zero;
+      v3[c] = (valid[c] && cnt > 3) ? ld16(p3 + c * STEP) : zero;
+    }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) acc[c] ^= (v0[c] ^ v1[c]) ^ (v2[c] ^ v3[c]);
+  }
+}
 
 template <int LPR, int CH, bool NT>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uint32_t nslices,
@@ -85,20 +120,41 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uin
   constexpr uint32_t RPB = kGatherThreads / LPR;   // rows per tile
   constexpr uint32_t STEP = LPR * 16;              // bytes between a lane's chunks
   constexpr uint32_t W = STEP * CH;                // slice bytes
+  __shared__ int32_t s_ptr[RPB + 1];
+  __shared__ int32_t s_idx[kStageCap];
   if (j.skip_flag && *j.skip_flag) return;
   uint32_t nrows = j.nrows;
   if (j.nrows_dev) nrows = min(nrows, (uint32_t)max(*j.nrows_dev, 0));
   const uint32_t ntiles = (nrows + RPB - 1) / RPB;
   const uint64_t nitems = (uint64_t)ntiles * nslices;
   const uint32_t vb = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
-  const uint32_t lane = threadIdx.x % LPR;
-  const uint32_t sub = threadIdx.x / LPR;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid % LPR;
+  const uint32_t sub = tid / LPR;
+  const bool contiguous = j.csr_map == nullptr;
   for (uint64_t item = vb; item < nitems; item += gridDim.x) {
+    // tiles of one slice are consecutive items, so a workgroup keeps its slice
     const uint32_t slice = (uint32_t)(item / ntiles);
     const uint32_t tile = (uint32_t)(item % ntiles);
-    const uint32_t r = tile * RPB + sub;
+    const uint32_t r0 = tile * RPB;
+    const uint32_t r = r0 + sub;
+    // stage the tile's edge list (rows r0 .. r0+RPB-1 are contiguous in CSR)
+    bool staged = false;
+    int ebase = 0;
+    if (contiguous) {
+      const uint32_t rend = min(r0 + RPB, nrows);
+      ebase = j.ptr[r0];
+      const int ecount = j.ptr[rend] - ebase;
+      staged = ecount <= kStageCap;
+      __syncthreads();   // the previous item's readers are done with the LDS copy
+      if (staged) {
+        for (int i = (int)tid; i < ecount; i += kGatherThreads) s_idx[i] = j.idx[ebase + i];
+        for (uint32_t i = tid; i <= rend - r0; i += kGatherThreads) s_ptr[i] = j.ptr[r0 + i] - ebase;
+      }
+      __syncthreads();
+    }
     if (r >= nrows) continue;
-    const uint32_t jr = j.csr_map ? j.csr_map[r] : r;
+    const uint32_t jr = contiguous ? r : j.csr_map[r];
     if (jr >= j.csr_rows) continue;
     const uint32_t ob = j.out_map ? (uint32_t)j.out_map[r] : jr;
     const uint64_t off0 = (uint64_t)slice * W + lane * 16u;
@@ -121,33 +177,10 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uin
         if (valid[c]) acc[c] = ld16(out + c * STEP);
     }
     const uint8_t *src = j.src + off0;
-    int e = j.ptr[jr];
-    const int e1 = j.ptr[jr + 1];
-    for (; e + 4 <= e1; e += 4) {
-      const uint8_t *p0 = src + (uint64_t)j.idx[e] * j.src_stride;
-      const uint8_t *p1 = src + (uint64_t)j.idx[e + 1] * j.src_stride;
-      const uint8_t *p2 = src + (uint64_t)j.idx[e + 2] * j.src_stride;
-      const uint8_t *p3 = src + (uint64_t)j.idx[e + 3] * j.src_stride;
-      v4u v0[CH], v1[CH], v2[CH], v3[CH];
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        if (valid[c]) {
-          v0[c] = ld16(p0 + c * STEP);
-          v1[c] = ld16(p1 + c * STEP);
-          v2[c] = ld16(p2 + c * STEP);
-          v3[c] = ld16(p3 + c * STEP);
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (valid[c]) acc[c] ^= (v0[c] ^ v1[c]) ^ (v2[c] ^ v3[c]);
-    }
-    for (; e < e1; ++e) {
-      const uint8_t *p0 = src + (uint64_t)j.idx[e] * j.src_stride;
-#pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (valid[c]) acc[c] ^= ld16(p0 + c * STEP);
-    }
+    if (staged)
+      gather_row<CH, STEP>(acc, valid, s_idx, s_ptr[sub], s_ptr[sub + 1], src, j.src_stride);
+    else
+      gather_row<CH, STEP>(acc, valid, j.idx, j.ptr[jr], j.ptr[jr + 1], src, j.src_stride);
 #pragma unroll
     for (int c = 0; c < CH; ++c)
       if (valid[c]) st16<NT>(out + c * STEP, acc[c]);
@@ -182,23 +215,81 @@ hipError_t run_gather_nt(const GatherJob &j, const fs_tune &t, hipStream_t s, in
 constexpr int kPeelThreads = 1024;
 constexpr unsigned long long kCountOne = 1ull << 40;   // acc = count << 40 | sum of ids
 constexpr unsigned long long kSumMask = kCountOne - 1;
+// Erased rows start with a count far above any degree (2^23): removing all
+// their inputs never brings it near 2, so they never enter a frontier and the
+// propagation step needs no erasure test.
+constexpr unsigned long long kErasedAcc = 1ull << 63;
+
+__device__ __forceinline__ uint32_t words_of(uint32_t k) { return (k + 31) / 32; }
 
 struct PeelState {
   unsigned long long *acc, *best;
   int32_t *fa, *fb, *dl;
   uint32_t *mask, *decm;
+  int32_t *cptr;      // column pointers (LDS copy, or the graph's)
+  uint16_t *deg;      // row degrees (LDS variant only)
 };
 
-__device__ __forceinline__ uint32_t words_of(uint32_t k) { return (k + 31) / 32; }
+// Wave 0 lists the set bits of mask (one k-bit set) in ascending order: each
+// lane owns a contiguous run of words; a wave prefix sum places its ids.
+// clear: also clear the words and OR them into decm; flist: list the
+// complement of decm instead (the unrecovered inputs).
+template <bool FLIST>
+__device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob &J, uint32_t kw,
+                                               uint32_t base) {
+  const uint32_t lane = threadIdx.x;   // caller guarantees wave 0
+  const uint32_t wpl = (kw + 63) / 64;
+  const uint32_t w0 = min(kw, lane * wpl), w1 = min(kw, w0 + wpl);
+  const uint32_t k = J.k;
+  uint32_t cnt = 0;
+  for (uint32_t w = w0; w < w1; ++w) {
+    uint32_t m = FLIST ? ~S.decm[w] : S.mask[w];
+    if (FLIST && w == kw - 1 && (k & 31)) m &= (1u << (k & 31)) - 1u;
+    cnt += __popc(m);
+  }
+  uint32_t incl = cnt;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if ((int)lane >= o) incl += y;
+  }
+  const uint32_t total = __shfl(incl, 63, 64);
+  uint32_t pos = base + incl - cnt;
+  for (uint32_t w = w0; w < w1; ++w) {
+    uint32_t m;
+    if (FLIST) {
+      m = ~S.decm[w];
+      if (w == kw - 1 && (k & 31)) m &= (1u << (k & 31)) - 1u;
+    } else {
+      m = S.mask[w];
+      if (!m) continue;
+      S.mask[w] = 0;
+      S.decm[w] |= m;
+    }
+    while (m) {
+      const uint32_t f = w * 32 + __builtin_ctz(m);
+      J.dp_f[pos] = (int32_t)f;
+      if (FLIST) {
+        J.dp_g[pos] = -1;
+      } else {
+        J.dp_g[pos] = (int32_t)(uint32_t)(S.best[f] & 0xffffffffull);
+        J.recovered[f] = 1;
+      }
+      ++pos;
+      m &= m - 1;
+    }
+  }
+  return total;
+}
 
 template <bool LDS>
 __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  __shared__ uint32_t scan_sh[kPeelThreads / 64 + 1];
   __shared__ int s_nA, s_nB, s_nD;
   if (J.skip_flag && *J.skip_flag) return;
   const uint32_t k = J.k, n = J.n, kw = words_of(k);
   const int tid = threadIdx.x;
+  const int wid = tid >> 6;
   PeelState S;
   if constexpr (LDS) {
     unsigned char *p = smem;
@@ -208,10 +299,14 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
     S.fb = reinterpret_cast<int32_t *>(p); p += 4ull * n;
     S.dl = reinterpret_cast<int32_t *>(p); p += 4ull * k;
     S.mask = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
-    S.decm = reinterpret_cast<uint32_t *>(p);
+    S.decm = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
+    S.cptr = reinterpret_cast<int32_t *>(p); p += 4ull * (k + 1);
+    S.deg = reinterpret_cast<uint16_t *>(p);
   } else {
     S.acc = J.acc; S.best = J.best; S.fa = J.front_a; S.fb = J.front_b; S.dl = J.dlist;
     S.mask = J.mask; S.decm = J.decmask;
+    S.cptr = const_cast<int32_t *>(J.col_ptr);
+    S.deg = nullptr;
   }
   for (uint32_t f = tid; f < k; f += kPeelThreads) {
     S.best[f] = ~0ull;
@@ -221,6 +316,9 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
     S.mask[w] = 0;
     S.decm[w] = 0;
   }
+  if constexpr (LDS) {
+    for (uint32_t i = tid; i <= k; i += kPeelThreads) S.cptr[i] = J.col_ptr[i];
+  }
   if (tid == 0) {
     s_nA = 0;
     s_nB = 0;
@@ -229,11 +327,12 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
   }
   __syncthreads();
   for (uint32_t g = tid; g < n; g += kPeelThreads) {
+    const int e0 = J.row_ptr[g], e1 = J.row_ptr[g + 1];
+    if constexpr (LDS) S.deg[g] = (uint16_t)(e1 - e0);
     if (J.erased[g]) {
-      S.acc[g] = 0;
+      S.acc[g] = kErasedAcc;
       continue;
     }
-    const int e0 = J.row_ptr[g], e1 = J.row_ptr[g + 1];
     unsigned long long sum = 0;
     for (int e = e0; e < e1; ++e) sum += (unsigned)J.col[e];
     S.acc[g] = ((unsigned long long)(e1 - e0) << 40) | sum;
@@ -241,9 +340,6 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
   }
   __syncthreads();
 
-  // words of the k-bit masks handled by this thread (contiguous, ascending)
-  const uint32_t wpt = (kw + kPeelThreads - 1) / kPeelThreads;
-  const uint32_t w0 = min(kw, (uint32_t)tid * wpt), w1 = min(kw, w0 + wpt);
   int32_t *cur = S.fa, *nxt = S.fb;
   uint32_t level = 0, npairs = 0;
   while (true) {
@@ -256,7 +352,11 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
       const unsigned long long a = S.acc[g];
       if ((a >> 40) != 1ull) continue;
       const uint32_t f = (uint32_t)(a & kSumMask);
-      const uint32_t d = (uint32_t)(J.row_ptr[g + 1] - J.row_ptr[g]);
+      uint32_t d;
+      if constexpr (LDS)
+        d = S.deg[g];
+      else
+        d = (uint32_t)(J.row_ptr[g + 1] - J.row_ptr[g]);
       atomicMin(&S.best[f], ((unsigned long long)d << 32) | (uint32_t)g);
       const uint32_t bit = 1u << (f & 31);
       const uint32_t old = atomicOr(&S.mask[f >> 5], bit);
@@ -265,35 +365,21 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
     __syncthreads();
     const int nD = s_nD;
     if (nD == 0) break;
-    // list the level's inputs in ascending order
-    uint32_t cnt = 0;
-    for (uint32_t w = w0; w < w1; ++w) cnt += __popc(S.mask[w]);
-    uint32_t total;
-    uint32_t pos = npairs + block_exclusive_scan<kPeelThreads>(cnt, scan_sh, total);
-    for (uint32_t w = w0; w < w1; ++w) {
-      uint32_t m = S.mask[w];
-      if (!m) continue;
-      S.mask[w] = 0;
-      S.decm[w] |= m;
-      while (m) {
-        const uint32_t f = w * 32 + __builtin_ctz(m);
-        J.dp_f[pos] = (int32_t)f;
-        J.dp_g[pos] = (int32_t)(uint32_t)(S.best[f] & 0xffffffffull);
-        J.recovered[f] = 1;
-        ++pos;
-        m &= m - 1;
-      }
-    }
-    // remove the decoded inputs from every surviving row they touch; a row
-    // whose residual weight drops to 1 joins the next frontier
-    for (int q = tid; q < nD; q += kPeelThreads) {
-      const uint32_t f = (uint32_t)S.dl[q];
-      const unsigned long long dec = 0ull - (kCountOne | f);
-      for (int e = J.col_ptr[f]; e < J.col_ptr[f + 1]; ++e) {
-        const int32_t h = J.rowidx[e];
-        if (J.erased[h]) continue;
-        const unsigned long long old = atomicAdd(&S.acc[h], dec);
-        if ((old >> 40) == 2ull) nxt[atomicAdd(&s_nB, 1)] = h;
+    if (wid == 0) {
+      // list the level's inputs in ascending order with their decoding rows
+      wave0_list<false>(S, J, kw, npairs);
+    } else {
+      // remove the decoded inputs from every row they touch; a row whose
+      // residual weight drops to 1 joins the next frontier
+      for (int q = tid - 64; q < nD; q += kPeelThreads - 64) {
+        const uint32_t f = (uint32_t)S.dl[q];
+        const unsigned long long dec = 0ull - (kCountOne | f);
+        const int c1 = S.cptr[f + 1];
+        for (int e = S.cptr[f]; e < c1; ++e) {
+          const int32_t h = J.rowidx[e];
+          const unsigned long long old = atomicAdd(&S.acc[h], dec);
+          if ((old >> 40) == 2ull) nxt[atomicAdd(&s_nB, 1)] = h;
+        }
       }
     }
     npairs += (uint32_t)nD;
@@ -311,25 +397,7 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
     __syncthreads();
   }
   // the unrecovered inputs follow the schedule, ascending, with row -1
-  uint32_t cnt = 0;
-  for (uint32_t w = w0; w < w1; ++w) {
-    uint32_t um = ~S.decm[w];
-    if (w == kw - 1 && (k & 31)) um &= (1u << (k & 31)) - 1u;
-    cnt += __popc(um);
-  }
-  uint32_t total;
-  uint32_t pos = npairs + block_exclusive_scan<kPeelThreads>(cnt, scan_sh, total);
-  for (uint32_t w = w0; w < w1; ++w) {
-    uint32_t um = ~S.decm[w];
-    if (w == kw - 1 && (k & 31)) um &= (1u << (k & 31)) - 1u;
-    while (um) {
-      const uint32_t f = w * 32 + __builtin_ctz(um);
-      J.dp_f[pos] = (int32_t)f;
-      J.dp_g[pos] = -1;
-      ++pos;
-      um &= um - 1;
-    }
-  }
+  if (wid == 0) wave0_list<true>(S, J, kw, npairs);
   if (tid == 0) {
     J.status[0] = npairs == k ? 1 : 0;
     J.status[1] = (int32_t)(k - npairs);
@@ -338,10 +406,294 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
 }
 
 // ---------------------------------------------------------------------------
-// schedule replay
+// replay program and schedule replay
 // ---------------------------------------------------------------------------
 constexpr int kReplayThreads = 1024;
 
+// Flatten the schedule into a replay program: for pair p (schedule order) the
+// inputs of its decoding row other than f, at pidx[poff[p] .. poff[p+1]);
+// gsrc[f] is the decoding row of f (-1 for unrecovered inputs).  Pairs that
+// do not fit the graph are dropped; meta = {nR, L, entries, usable}.
+// Loads are hoisted in groups of eight pairs so each thread keeps several
+// dependent chains (row -> row pointer -> neighbour ids) in flight.
+__global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) {
+  __shared__ uint32_t scan_sh[kPlanThreads / 64 + 1];
+  constexpr int G = 8;
+  const int tid = threadIdx.x;
+  const int k = (int)P.k;
+  if (P.skip_flag && *P.skip_flag) {
+    if (tid == 0) P.meta[3] = 0;
+    return;
+  }
+  const int L = min(max(P.status[2], 0), k);
+  const int nR = min(max(k - P.status[1], 0), k);
+  // inputs without a decoding row stay at -1, rows decoding nothing too (the
+  // scan below orders these writes before the ones of the pairs)
+  for (int f = tid; f < k; f += kPlanThreads) P.gsrc[f] = -1;
+  for (uint32_t g = tid; g < P.n; g += kPlanThreads) P.finv[g] = -1;
+  const int cpt = (nR + kPlanThreads - 1) / kPlanThreads;
+  const int p0 = min(nR, tid * cpt), p1 = min(nR, p0 + cpt);
+  uint32_t cnt = 0;
+  for (int b = p0; b < p1; b += G) {
+    int32_t f[G], g[G], r0[G], r1[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      f[u] = b + u < p1 ? P.dp_f[b + u] : -1;
+      g[u] = b + u < p1 ? P.dp_g[b + u] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const bool ok = (uint32_t)f[u] < P.k && (uint32_t)g[u] < P.n;
+      r0[u] = ok ? P.row_ptr[g[u]] : 0;
+      r1[u] = ok ? P.row_ptr[g[u] + 1] : 1;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) cnt += (uint32_t)(r1[u] - r0[u] - 1);
+  }
+  uint32_t total;
+  uint32_t o = block_exclusive_scan<kPlanThreads>(cnt, scan_sh, total);   // has barriers
+  const bool fits = total <= P.pidx_cap;
+  for (int b = p0; b < p1; b += G) {
+    int32_t f[G], g[G], r0[G], r1[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      f[u] = b + u < p1 ? P.dp_f[b + u] : -1;
+      g[u] = b + u < p1 ? P.dp_g[b + u] : -1;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      const bool ok = (uint32_t)f[u] < P.k && (uint32_t)g[u] < P.n;
+      r0[u] = ok ? P.row_ptr[g[u]] : 0;
+      r1[u] = ok ? P.row_ptr[g[u] + 1] : 1;
+    }
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+      if (b + u >= p1) break;
+      P.poff[b + u] = (int32_t)o;
+      const uint32_t end = o + (uint32_t)(r1[u] - r0[u] - 1);
+      if ((uint32_t)f[u] < P.k && (uint32_t)g[u] < P.n) {
+        P.gsrc[f[u]] = g[u];
+        P.finv[g[u]] = f[u];
+      }
+      for (int e = r0[u]; e < r1[u] && o < end; ++e) {
+        const int32_t i = P.col[e];
+        if (i != f[u]) {
+          if (fits) P.pidx[o] = i;
+          ++o;
+        }
+      }
+      o = end;
+    }
+  }
+  __syncthreads();
+  // decoding rows in ascending order with their inputs: the slab loads then
+  // walk the coded blocks in address order
+  const uint32_t rpt = (P.n + kPlanThreads - 1) / kPlanThreads;
+  const uint32_t g0 = min(P.n, (uint32_t)tid * rpt), g1 = min(P.n, g0 + rpt);
+  uint32_t used = 0;
+  for (uint32_t g = g0; g < g1; ++g) used += P.finv[g] >= 0;
+  uint32_t nused;
+  uint32_t pos = block_exclusive_scan<kPlanThreads>(used, scan_sh, nused);
+  for (uint32_t g = g0; g < g1; ++g) {
+    const int32_t f = P.finv[g];
+    if (f >= 0 && pos < P.k) {
+      P.gl[pos] = (int32_t)g;
+      P.fl[pos] = f;
+      ++pos;
+    }
+  }
+  if (tid == 0) {
+    P.poff[nR] = (int32_t)total;
+    P.meta[0] = nR;
+    P.meta[1] = L;
+    P.meta[2] = (int32_t)total;
+    P.meta[3] = fits && nused == (uint32_t)nR ? 1 : 0;
+  }
+}
+
+// One workgroup per CU walks byte slices of T = 16 LPS bytes.  For each slice
+// the k x T slab of x lives in LDS: x_f starts as c_{g(f)} (zero for the
+// unrecovered inputs), each level XORs in the other inputs of f's decoding
+// row from the slab, and the finished slab is written out.  The loads of the
+// next slice's c_{g(f)} are issued before the level phase of the current one
+// and held in registers (barriers only wait for LDS traffic), so HBM stays
+// busy while the levels run.  The replay program is copied to LDS as 16-bit
+// indices when it fits, else read from global memory.
+template <int LPS, int M, class IT>
+__device__ __forceinline__ void replay_slices(const ReplayJob &J, v4u *slab, const int32_t *gl, const int32_t *fl,
+                                              const IT *lp, const IT *pf, const IT *poff, const IT *pidx,
+                                              int L, int nR, uint32_t nslices, uint32_t vb) {
+  constexpr int NS = kReplayThreads / LPS;
+  const uint32_t lane = threadIdx.x % LPS, sym = threadIdx.x / LPS;
+  const uint32_t k = J.k;
+  const v4u zero = {0u, 0u, 0u, 0u};
+  // unrecovered inputs stay zero in every slice: clear the slab once, the
+  // slices only rewrite the recovered entries
+  for (uint32_t f = sym; f < k; f += NS) slab[f * LPS + lane] = zero;
+  __syncthreads();
+  // (coded row, input) pairs of this thread, rows ascending across lanes
+  int32_t gm[M], fm[M];
+#pragma unroll
+  for (int m = 0; m < M; ++m) {
+    const int q = (int)sym + m * NS;
+    gm[m] = q < nR ? gl[q] : -1;
+    fm[m] = q < nR ? fl[q] : -1;
+    if ((uint32_t)fm[m] >= k || (uint32_t)gm[m] >= J.n) gm[m] = fm[m] = -1;
+  }
+  v4u pre[M];
+  auto issue = [&](uint32_t slice) {
+    const uint64_t off = (uint64_t)slice * (LPS * 16) + lane * 16u;
+    const bool live = off < J.t;
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+      pre[m] = (live && gm[m] >= 0) ? ld16(J.c + (uint64_t)gm[m] * J.t + off) : zero;
+  };
+  uint32_t slice = vb;
+  if (slice < nslices) issue(slice);
+  while (slice < nslices) {
+    const uint64_t off = (uint64_t)slice * (LPS * 16) + lane * 16u;
+    const bool live = off < J.t;
+#pragma unroll
+    for (int m = 0; m < M; ++m)
+      if (fm[m] >= 0) slab[(uint32_t)fm[m] * LPS + lane] = pre[m];
+    __syncthreads();
+    const uint32_t next = slice + gridDim.x;
+    if (next < nslices) issue(next);
+    for (int l = 0; l < L; ++l) {
+      const int q1 = min((int)lp[l + 1], nR);
+      for (int q = max((int)lp[l], 0) + (int)sym; q < q1; q += NS) {
+        const uint32_t f = (uint32_t)pf[q];
+        if (f >= k) continue;
+        const int o0 = (int)poff[q], o1 = (int)poff[q + 1];
+        v4u acc = slab[f * LPS + lane];
+        int o = o0;
+        for (; o + 2 <= o1; o += 2) {
+          const uint32_t i0 = (uint32_t)pidx[o], i1 = (uint32_t)pidx[o + 1];
+          acc ^= slab[i0 * LPS + lane] ^ slab[i1 * LPS + lane];
+        }
+        if (o < o1) acc ^= slab[(uint32_t)pidx[o] * LPS + lane];
+        slab[f * LPS + lane] = acc;
+      }
+      __syncthreads();
+    }
+    // plain stores: the slices of one 128-byte line are written by
+    // neighbouring workgroups of one XCD and merge in its L2
+    if (live)
+      for (uint32_t f = sym; f < k; f += NS) st16<false>(J.x + (uint64_t)f * J.t + off, slab[f * LPS + lane]);
+    __syncthreads();
+    slice = next;
+  }
+}
+
+template <int LPS, int M>
+__global__ __launch_bounds__(kReplayThreads) void replay_lds_kernel(ReplayJob J, ProgJob P, uint32_t nslices,
+                                                                   uint32_t lds_bytes, uint32_t prog_lds) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  if (J.skip_flag && *J.skip_flag) return;
+  if (!P.meta[3]) return;
+  const uint32_t k = J.k;
+  const int nR = P.meta[0], L = P.meta[1], total = P.meta[2];
+  v4u *slab = reinterpret_cast<v4u *>(smem);
+  const size_t slab_bytes = (size_t)k * LPS * 16;
+  const size_t prog16 = 2ull * ((size_t)(L + 1) + (size_t)nR + (size_t)(nR + 1) + (size_t)total);
+  const uint32_t vb = xcd_remap(blockIdx.x, gridDim.x);
+  // level pointers are clamped to [0, nR] so a foreign schedule stays in bounds
+  if (prog_lds && k <= 65535 && total <= 65535 && slab_bytes + prog16 <= lds_bytes) {
+    uint16_t *q = reinterpret_cast<uint16_t *>(smem + slab_bytes);
+    uint16_t *lp = q; q += L + 1;
+    uint16_t *pf = q; q += nR;
+    uint16_t *poff = q; q += nR + 1;
+    uint16_t *pidx = q;
+    for (int i = threadIdx.x; i <= L; i += kReplayThreads) lp[i] = (uint16_t)min(max(J.level_ptr[i], 0), nR);
+    for (int i = threadIdx.x; i < nR; i += kReplayThreads) pf[i] = (uint16_t)min((uint32_t)J.dp_f[i], 65535u);
+    for (int i = threadIdx.x; i <= nR; i += kReplayThreads) poff[i] = (uint16_t)P.poff[i];
+    for (int i = threadIdx.x; i < total; i += kReplayThreads) pidx[i] = (uint16_t)P.pidx[i];
+    __syncthreads();
+    replay_slices<LPS, M, uint16_t>(J, slab, P.gl, P.fl, lp, pf, poff, pidx, L, nR, nslices, vb);
+  } else {
+    replay_slices<LPS, M, int32_t>(J, slab, P.gl, P.fl, J.level_ptr, J.dp_f, P.poff, P.pidx, L, nR, nslices, vb);
+  }
+}
+
+// Wide-slice replay for large k: one workgroup per W = 16 LPS byte slice
+// keeps x in global memory (full-line accesses; re-reads of x hit L2 or the
+// infinity cache) and walks the levels with a barrier between them.  The
+// program (pairs, decoding rows, other inputs) sits in LDS as 16-bit indices
+// when it fits, so a level costs one round trip to memory: every load of a
+// pair (its coded block and the other inputs) is issued before any is used.
+template <int LPS, class IT>
+__device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT *lp, const IT *pf, const IT *pg,
+                                                   const IT *poff, const IT *pidx, int L, int nR,
+                                                   uint32_t nslices, uint32_t vb) {
+  constexpr int NS = kReplayThreads / LPS;
+  constexpr uint32_t W = LPS * 16;
+  const uint32_t lane = threadIdx.x % LPS, sym = threadIdx.x / LPS;
+  const uint32_t k = J.k;
+  for (uint32_t slice = vb; slice < nslices; slice += gridDim.x) {
+    const uint64_t off = (uint64_t)slice * W + lane * 16u;
+    const bool live = off < J.t;
+    for (int l = 0; l < L; ++l) {
+      const int q1 = min((int)lp[l + 1], nR);
+      for (int q = max((int)lp[l], 0) + (int)sym; q < q1; q += NS) {
+        const uint32_t f = (uint32_t)pf[q], g = (uint32_t)pg[q];
+        if (!live || f >= k || g >= J.n) continue;
+        const int o0 = (int)poff[q], o1 = (int)poff[q + 1];
+        v4u acc = ld16(J.c + (uint64_t)g * J.t + off);
+        int o = o0;
+        for (; o + 4 <= o1; o += 4) {
+          const v4u a = ld16(J.x + (uint64_t)pidx[o] * J.t + off);
+          const v4u b = ld16(J.x + (uint64_t)pidx[o + 1] * J.t + off);
+          const v4u c = ld16(J.x + (uint64_t)pidx[o + 2] * J.t + off);
+          const v4u d = ld16(J.x + (uint64_t)pidx[o + 3] * J.t + off);
+          acc ^= (a ^ b) ^ (c ^ d);
+        }
+        for (; o < o1; ++o) acc ^= ld16(J.x + (uint64_t)pidx[o] * J.t + off);
+        *reinterpret_cast<v4u *>(J.x + (uint64_t)f * J.t + off) = acc;
+      }
+      __syncthreads();
+    }
+    if (live) {
+      for (int q = nR + (int)sym; q < (int)k; q += NS) {
+        const int32_t f = J.dp_f[q];
+        if ((uint32_t)f < k) st16<false>(J.x + (uint64_t)f * J.t + off, v4u{0u, 0u, 0u, 0u});
+      }
+    }
+  }
+}
+
+template <int LPS>
+__global__ __launch_bounds__(kReplayThreads) void replay_wide_kernel(ReplayJob J, ProgJob P, uint32_t nslices,
+                                                                    uint32_t lds_bytes, uint32_t prog_lds) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  if (J.skip_flag && *J.skip_flag) return;
+  if (!P.meta[3]) return;
+  const uint32_t k = J.k;
+  const int nR = P.meta[0], L = P.meta[1], total = P.meta[2];
+  const uint32_t vb = xcd_remap(blockIdx.x, gridDim.x);
+  const size_t prog16 = 2ull * ((size_t)(L + 1) + 2ull * nR + (size_t)(nR + 1) + (size_t)total);
+  if (prog_lds && k <= 65535 && J.n <= 65535 && total <= 65535 && prog16 <= lds_bytes) {
+    uint16_t *q = reinterpret_cast<uint16_t *>(smem);
+    uint16_t *lp = q; q += L + 1;
+    uint16_t *pf = q; q += nR;
+    uint16_t *pg = q; q += nR;
+    uint16_t *poff = q; q += nR + 1;
+    uint16_t *pidx = q;
+    for (int i = threadIdx.x; i <= L; i += kReplayThreads) lp[i] = (uint16_t)min(max(J.level_ptr[i], 0), nR);
+    for (int i = threadIdx.x; i < nR; i += kReplayThreads) {
+      pf[i] = (uint16_t)min((uint32_t)J.dp_f[i], 65535u);
+      pg[i] = (uint16_t)min((uint32_t)J.dp_g[i], 65535u);
+    }
+    for (int i = threadIdx.x; i <= nR; i += kReplayThreads) poff[i] = (uint16_t)P.poff[i];
+    for (int i = threadIdx.x; i < total; i += kReplayThreads) pidx[i] = (uint16_t)P.pidx[i];
+    __syncthreads();
+    replay_wide_slices<LPS, uint16_t>(J, lp, pf, pg, poff, pidx, L, nR, nslices, vb);
+  } else {
+    replay_wide_slices<LPS, int32_t>(J, J.level_ptr, J.dp_f, J.dp_g, P.poff, P.pidx, L, nR, nslices, vb);
+  }
+}
+
+// Fallback for slabs too large for LDS: one workgroup per byte slice reads
+// and writes x in global memory, a barrier between levels.
 template <int LPS>
 __global__ __launch_bounds__(kReplayThreads) void replay_kernel(ReplayJob J) {
   constexpr uint32_t W = LPS * 16;
@@ -381,7 +733,6 @@ __global__ __launch_bounds__(kReplayThreads) void replay_kernel(ReplayJob J) {
 // ---------------------------------------------------------------------------
 // repair and update planning
 // ---------------------------------------------------------------------------
-constexpr int kPlanThreads = 1024;
 
 __global__ __launch_bounds__(kPlanThreads) void repair_prep_kernel(RepairPrepJob J, int default_ok) {
   __shared__ int s_bad;
@@ -534,9 +885,22 @@ static fs_status hip_check(hipError_t e, const char *what) {
   return fail(FS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+#define FS_TRY_LAUNCH(name, job, s)                                                     \
+  do {                                                                                  \
+    hipLaunchKernelGGL(name##_kernel, dim3(1), dim3(kPlanThreads), 0, s, job);          \
+    fs_status _st = hip_check(hipGetLastError(), #name " launch");                      \
+    if (_st != FS_OK) return _st;                                                       \
+  } while (0)
+
+#define FS_HIP_TRY(e, what)                     \
+  do {                                          \
+    fs_status _st = hip_check((e), (what));     \
+    if (_st != FS_OK) return _st;               \
+  } while (0)
+
 fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s) {
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   const int cu = device_info(dev).cu_count;
   hipError_t e;
   switch (tune.lanes_per_row * 10 + tune.chunks) {
@@ -556,7 +920,7 @@ fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s
 
 size_t peel_lds_bytes(uint32_t k, uint32_t n) {
   const size_t kw = (k + 31) / 32;
-  return 8ull * n + 8ull * k + 4ull * n + 4ull * n + 4ull * k + 8ull * kw;
+  return 8ull * n + 8ull * k + 4ull * n + 4ull * n + 4ull * k + 8ull * kw + 4ull * (k + 1) + 2ull * n;
 }
 
 void peel_carve(Carver &cv, PeelJob &j) {
@@ -579,19 +943,22 @@ size_t peel_ws_bytes(uint32_t k, uint32_t n) {
   return cv.size();
 }
 
-fs_status launch_peel(const PeelJob &job, hipStream_t s) {
+static void set_max_lds(const void *fn, int dev, int bytes, bool *done) {
+  if (dev >= 0 && dev < 64 && !done[dev]) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    done[dev] = true;
+  }
+}
+
+fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg) {
   int dev = 0;
-  hipGetDevice(&dev);
+  (void)hipGetDevice(&dev);
   const size_t lds = peel_lds_bytes(job.k, job.n);
-  const size_t static_lds = 4 * (kPeelThreads / 64 + 1) + 16;
-  if (lds + static_lds <= (size_t)device_info(dev).max_lds_per_block) {
-    static bool attr_set[64] = {false};
-    if (dev < 64 && !attr_set[dev]) {
-      hipFuncSetAttribute(reinterpret_cast<const void *>(&peel_kernel<true>),
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          device_info(dev).max_lds_per_block - (int)static_lds);
-      attr_set[dev] = true;
-    }
+  const size_t static_lds = 64;
+  const int budget = device_info(dev).max_lds_per_block;
+  if (max_deg < 65536 && lds + static_lds <= (size_t)budget) {
+    static bool done[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&peel_kernel<true>), dev, budget - (int)static_lds, done);
     hipLaunchKernelGGL(peel_kernel<true>, dim3(1), dim3(kPeelThreads), lds, s, job);
   } else {
     if (!job.acc) return fail(FS_ERR_WORKSPACE, "peel state needs the workspace");
@@ -600,17 +967,102 @@ fs_status launch_peel(const PeelJob &job, hipStream_t s) {
   return hip_check(hipGetLastError(), "peel launch");
 }
 
-fs_status launch_replay(const ReplayJob &job, hipStream_t s) {
-  // 16 lanes (256 B) per symbol on wide blocks; 4 lanes (64 B) when that
-  // would leave fewer than ~2 workgroups per CU
-  if (job.t >= 256ull * 512) {
-    const uint32_t ns = (uint32_t)((job.t + 255) / 256);
-    hipLaunchKernelGGL(replay_kernel<16>, dim3(ns), dim3(kReplayThreads), 0, s, job);
-  } else {
-    const uint32_t ns = (uint32_t)((job.t + 63) / 64);
-    hipLaunchKernelGGL(replay_kernel<4>, dim3(ns), dim3(kReplayThreads), 0, s, job);
+void prog_carve(Carver &cv, ProgJob &p, uint64_t nnz) {
+  p.gsrc = cv.take<int32_t>(p.k);
+  p.finv = cv.take<int32_t>(p.n ? p.n : 1);
+  p.gl = cv.take<int32_t>(p.k);
+  p.fl = cv.take<int32_t>(p.k);
+  p.poff = cv.take<int32_t>((size_t)p.k + 1);
+  p.pidx = cv.take<int32_t>(nnz ? nnz : 1);
+  p.meta = cv.take<int32_t>(4);
+  p.pidx_cap = (uint32_t)(nnz ? nnz : 1);
+}
+
+// LDS layout of the slab replay: the widest row slice (16 LPS bytes, LPS in
+// 64..8) whose k x 16 LPS slab leaves room for a typical 16-bit program;
+// 0 = k too large for a slab of 128-byte rows.
+int replay_lanes(uint32_t k) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t budget = (size_t)device_info(dev).max_lds_per_block;
+  for (int lps = 64; lps >= 8; lps /= 2)
+    if ((size_t)k * 16 * lps + 24576 <= budget) return lps;
+  return 0;
+}
+
+template <int LPS, int M>
+static hipError_t run_replay_lds(const ReplayJob &job, const ProgJob &prog, uint32_t nslices, uint32_t grid,
+                                 int budget, int dev, hipStream_t s) {
+  static bool done[64] = {false};
+  set_max_lds(reinterpret_cast<const void *>(&replay_lds_kernel<LPS, M>), dev, budget, done);
+  hipLaunchKernelGGL((replay_lds_kernel<LPS, M>), dim3(grid), dim3(kReplayThreads), budget, s, job, prog,
+                     nslices, (uint32_t)budget, tune_snapshot().replay_prog_global ? 0u : 1u);
+  return hipGetLastError();
+}
+
+template <int LPS>
+static hipError_t run_replay_wide(const ReplayJob &job, const ProgJob &prog, int budget, int dev, int cu,
+                                  hipStream_t s) {
+  static bool done[64] = {false};
+  set_max_lds(reinterpret_cast<const void *>(&replay_wide_kernel<LPS>), dev, budget, done);
+  const uint32_t w = 16u * LPS;
+  const uint32_t nslices = (uint32_t)((job.t + w - 1) / w);
+  const uint32_t grid = std::min<uint32_t>(nslices, (uint32_t)cu * 2);
+  hipLaunchKernelGGL(replay_wide_kernel<LPS>, dim3(grid), dim3(kReplayThreads), budget, s, job, prog, nslices,
+                     (uint32_t)budget, tune_snapshot().replay_prog_global ? 0u : 1u);
+  return hipGetLastError();
+}
+
+template <int LPS>
+static hipError_t run_replay_lds_m(const ReplayJob &job, const ProgJob &prog, uint32_t mneed, uint32_t nslices,
+                                   uint32_t grid, int budget, int dev, hipStream_t s) {
+  if (mneed <= 4) return run_replay_lds<LPS, 4>(job, prog, nslices, grid, budget, dev, s);
+  if (mneed <= 8) return run_replay_lds<LPS, 8>(job, prog, nslices, grid, budget, dev, s);
+  return run_replay_lds<LPS, 16>(job, prog, nslices, grid, budget, dev, s);
+}
+
+fs_status launch_replay(const ReplayJob &job, const ProgJob *prog, hipStream_t s) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cu = device_info(dev).cu_count;
+  const int budget = device_info(dev).max_lds_per_block;
+  if (!prog) {
+    // no workspace for a program: the plain global-memory replay
+    if (job.t >= 256ull * 512) {
+      const uint32_t ns = (uint32_t)((job.t + 255) / 256);
+      hipLaunchKernelGGL(replay_kernel<16>, dim3(ns), dim3(kReplayThreads), 0, s, job);
+    } else {
+      const uint32_t ns = (uint32_t)((job.t + 63) / 64);
+      hipLaunchKernelGGL(replay_kernel<4>, dim3(ns), dim3(kReplayThreads), 0, s, job);
+    }
+    return hip_check(hipGetLastError(), "replay launch");
   }
-  return hip_check(hipGetLastError(), "replay launch");
+  FS_TRY_LAUNCH(prog_build, *prog, s);
+  const int lps = replay_lanes(job.k);
+  hipError_t e;
+  if (lps) {
+    // small k: the k x 16 LPS slab of a slice lives in LDS
+    const uint32_t mneed = (job.k + (kReplayThreads / lps) - 1) / (kReplayThreads / lps);
+    const uint32_t w = 16u * (uint32_t)lps;
+    const uint32_t nslices = (uint32_t)((job.t + w - 1) / w);
+    const uint32_t grid = std::min<uint32_t>(nslices, (uint32_t)cu);
+    switch (lps) {
+      case 64: e = run_replay_lds_m<64>(job, *prog, mneed, nslices, grid, budget, dev, s); break;
+      case 32: e = run_replay_lds_m<32>(job, *prog, mneed, nslices, grid, budget, dev, s); break;
+      case 16: e = run_replay_lds_m<16>(job, *prog, mneed, nslices, grid, budget, dev, s); break;
+      default: e = run_replay_lds_m<8>(job, *prog, mneed, nslices, grid, budget, dev, s); break;
+    }
+  } else {
+    // large k: wide slices in global memory, about one workgroup per CU
+    const uint64_t per = (job.t + cu - 1) / cu;
+    if (per >= 1024)
+      e = run_replay_wide<64>(job, *prog, budget, dev, cu, s);
+    else if (per >= 512)
+      e = run_replay_wide<32>(job, *prog, budget, dev, cu, s);
+    else
+      e = run_replay_wide<16>(job, *prog, budget, dev, cu, s);
+  }
+  return hip_check(e, "replay launch");
 }
 
 fs_status launch_repair_prep(const RepairPrepJob &job, hipStream_t s) {

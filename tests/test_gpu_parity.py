@@ -88,6 +88,20 @@ def test_encode_degree_k_rows_and_k1():
         assert np.array_equal(host(c), codec.encode(G, x))
 
 
+def test_encode_tiles_beyond_the_lds_edge_stage():
+    # 16-row tiles of degree-200 rows hold 3200 edges: read from global memory
+    import paper_1702_07409_amd as fs
+    kw = dict(k=1000, n=100, dist="finite", finite_w=(0.0,) * 199 + (1.0,), seed=4)
+    g, G = graphs(**kw)
+    x = gen.payload(2, 0, 1000, 1024)
+    for lpr in (16, 64):
+        fs.fs_set_tune(lpr, 2, 1, 1)
+        c = empty_u8(100, 1024)
+        fs.fs_encode(g, dev(x), c, 1024)
+        assert np.array_equal(host(c), codec.encode(G, x))
+    fs.fs_reset_tune()
+
+
 def test_encode_rejects_bad_alignment():
     import paper_1702_07409_amd as fs
     g, _ = graphs(k=8, n=10, seed=1)
@@ -176,6 +190,43 @@ def test_peel_state_beyond_lds_uses_workspace():
     decode_case(sp)
 
 
+@pytest.mark.parametrize("prog_global", [0, 1])
+def test_decode_slab_replay_program_placement(prog_global):
+    # k = 1000 uses the slab replay (k x 128-byte rows in LDS); the program is
+    # read from LDS or, forced by the tuning, from global memory
+    import paper_1702_07409_amd as fs
+    fw = tuple([0.45] + [0.0] * 22 + [0.55])
+    sp = workloads.StripeSpec(stripe=4, k=1000, n=4000, t=1024 + 128, dist="finite", finite_w=fw,
+                              stripe_key=2, n_erased=0)
+    fs.fs_set_tune(replay_prog_global=prog_global)
+    try:
+        _, G, got, sched = decode_case(sp)
+    finally:
+        fs.fs_reset_tune()
+    assert got.status[0] == 1
+
+
+@pytest.mark.parametrize("prog_global", [0, 1])
+def test_decode_wide_replay_program_placement(prog_global):
+    import paper_1702_07409_amd as fs
+    fw = tuple([0.45] + [0.0] * 22 + [0.55])
+    sp = workloads.StripeSpec(stripe=4, k=4000, n=16000, t=256 * 3 + 32, dist="finite", finite_w=fw,
+                              stripe_key=2, n_erased=0)
+    fs.fs_set_tune(replay_prog_global=prog_global)
+    try:
+        _, G, got, sched = decode_case(sp)
+    finally:
+        fs.fs_reset_tune()
+    assert got.status[0] == 1
+
+
+def test_decode_wide_replay_with_more_than_65535_rows():
+    # n > 65535: no 16-bit program, the replay reads its program from global memory
+    sp = workloads.StripeSpec(stripe=5, k=2000, n=70000, t=32, dist="rsd", stripe_key=3, n_erased=7000)
+    _, G, got, sched = decode_case(sp)
+    assert got.status[0] == 1
+
+
 def test_peel_replay_equals_decode_and_is_deterministic():
     import paper_1702_07409_amd as fs
     sp = workloads.large_stripe()
@@ -192,7 +243,7 @@ def test_peel_replay_equals_decode_and_is_deterministic():
     st = dev(p.status)
     lp = empty_i32(sp.k + 1)
     lp[:len(p.level_ptr)] = dev(p.level_ptr)
-    fs.fs_replay(g, c, st, lp, dev(p.dp_f), dev(p.dp_g), x2, sp.t)
+    fs.fs_replay(g, c, st, lp, dev(p.dp_f), dev(p.dp_g), x2, sp.t, fs.workspace(g, fs.FS_OP_REPLAY, sp.t))
     assert np.array_equal(host(x2), a.x)
 
 
