@@ -221,6 +221,22 @@ FS_API fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *
                     const void *new_blocks, int32_t *status, uint64_t t, void *ws,
                     size_t ws_bytes, hipStream_t stream);
 
+/*
+ * Decode in two halves.  fs_decode_plan runs the peeling schedule of fs_peel
+ * for the erasure pattern and flattens it into a replay program, all inside
+ * the workspace (FS_OP_DECODE bytes); it reads no payload.  recovered
+ * (device uint8[k]) and status (device int32[3], may be NULL) are as in
+ * fs_peel.  fs_decode_apply replays that plan on c into x (as fs_replay).  A
+ * plan may be computed on one stream while the coded blocks are still being
+ * written on another, and applied once both are done; a plan can be applied
+ * to any number of stripes that share the graph and the erasure pattern.
+ */
+FS_API fs_status fs_decode_plan(const fs_graph *g, const uint8_t *erased, uint32_t maxit,
+                                uint8_t *recovered, int32_t *status, void *ws, size_t ws_bytes,
+                                hipStream_t stream);
+FS_API fs_status fs_decode_apply(const fs_graph *g, const void *c, void *x, uint64_t t,
+                                 const void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Tuning of the gather-XOR kernel family (encode, repair, update). */
 typedef struct fs_tune {
   uint32_t lanes_per_row;  /* 16, 32 or 64 lanes share one coded row         */

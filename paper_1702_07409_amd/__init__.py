@@ -3,11 +3,27 @@ Founsure 1.0: seeded graph build, encode, level-synchronous peeling decode,
 repair and delta update, as HIP kernels behind the C ABI of libfs.so
 (include/fs_api.h).  This package is the thin ctypes binding; PyTorch only
 supplies device memory and streams.
+
+The binding (and libfs.so) is loaded on first use of one of its names, so
+that the build module can run before the library exists; a missing library
+then raises ImportError.
 """
 
-from ._lib import (  # noqa: F401
-    EXPORTED, FS_DEFAULT_SEED, FS_OP_DECODE, FS_OP_ENCODE, FS_OP_PEEL, FS_OP_REPAIR,
-    FS_OP_REPAIR_CONVENTIONAL, FS_OP_REPLAY, FS_OP_UPDATE, FsError, Graph, fs_decode, fs_degree_table,
-    fs_encode, fs_get_tune, fs_graph_build, fs_peel, fs_repair, fs_replay, fs_reset_tune,
-    fs_set_tune, fs_update, fs_workspace_size, version, workspace,
+_BINDING = (
+    "EXPORTED", "FS_DEFAULT_SEED", "FS_OP_DECODE", "FS_OP_ENCODE", "FS_OP_PEEL", "FS_OP_REPAIR",
+    "FS_OP_REPAIR_CONVENTIONAL", "FS_OP_REPLAY", "FS_OP_UPDATE", "FsError", "Graph", "fs_decode",
+    "fs_decode_apply", "fs_decode_plan", "fs_degree_table", "fs_encode", "fs_get_tune",
+    "fs_graph_build", "fs_peel", "fs_repair", "fs_replay", "fs_reset_tune", "fs_set_tune",
+    "fs_update", "fs_workspace_size", "version", "workspace",
 )
+
+
+def __getattr__(name):
+    if name in _BINDING:
+        from . import _lib
+        return getattr(_lib, name)
+    raise AttributeError("module %r has no attribute %r" % (__name__, name))
+
+
+def __dir__():
+    return sorted(list(globals()) + list(_BINDING))

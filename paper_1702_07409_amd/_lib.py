@@ -56,6 +56,8 @@ _SIGS = {
     "fs_peel": ([P, P, U32, P, P, P, P, P, P, SZ, P], ST),
     "fs_replay": ([P, P, P, P, P, P, P, U64, P, SZ, P], ST),
     "fs_decode": ([P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
+    "fs_decode_plan": ([P, P, U32, P, P, P, SZ, P], ST),
+    "fs_decode_apply": ([P, P, P, U64, P, SZ, P], ST),
     "fs_repair": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_set_tune": ([ctypes.POINTER(fs_tune)], ST),
@@ -217,6 +219,17 @@ def fs_decode(g, c, erased, maxit, x, recovered, status, t, ws, stream=None):
     w, wb = _ws(ws)
     _check(_lib.fs_decode(g.handle, _ptr(c), _ptr(erased), maxit, _ptr(x), _ptr(recovered), _ptr(status),
                           t, w, wb, _stream(stream)), "fs_decode")
+
+
+def fs_decode_plan(g, erased, maxit, recovered, status, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_decode_plan(g.handle, _ptr(erased), maxit, _ptr(recovered), _ptr(status), w, wb,
+                               _stream(stream)), "fs_decode_plan")
+
+
+def fs_decode_apply(g, c, x, t, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_decode_apply(g.handle, _ptr(c), _ptr(x), t, w, wb, _stream(stream)), "fs_decode_apply")
 
 
 def fs_repair(g, x, c, erased, lost, n_lost, repaired, status, t, ws, stream=None):

@@ -435,6 +435,63 @@ fs_status fs_replay(const fs_graph *g, const void *c, const int32_t *status, con
   return launch_replay(replay_job(g, c, x, t, status, level_ptr, dp_f, dp_g), &p, stream);
 }
 
+// Decode workspace: schedule arrays, peel state, replay program.
+struct DecodeBufs {
+  SchedBufs sched;
+  PeelJob peel;
+  ProgJob prog;
+};
+
+static void carve_decode(Carver &cv, const fs_graph *g, DecodeBufs &b) {
+  carve_sched(cv, g->k, b.sched, false);
+  b.peel = PeelJob{};
+  b.peel.k = g->k;
+  b.peel.n = g->n;
+  peel_carve(cv, b.peel);
+  b.prog = prog_job(g, cv, b.sched.status, b.sched.level_ptr, b.sched.dp_f, b.sched.dp_g);
+}
+
+fs_status fs_decode_plan(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered,
+                         int32_t *status, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  if (!erased || !recovered) return fail(FS_ERR_INVALID, "erased and recovered must be non-null");
+  FS_TRY(check_ws(g, FS_OP_DECODE, 16, 0, ws, ws_bytes));
+  Carver cv(ws);
+  DecodeBufs b;
+  carve_decode(cv, g, b);
+  PeelJob j = peel_job(g, erased, maxit, recovered, b.sched.status, b.sched.level_ptr, b.sched.dp_f,
+                       b.sched.dp_g);
+  j.acc = b.peel.acc;
+  j.best = b.peel.best;
+  j.front_a = b.peel.front_a;
+  j.front_b = b.peel.front_b;
+  j.dlist = b.peel.dlist;
+  j.mask = b.peel.mask;
+  j.decmask = b.peel.decmask;
+  FS_TRY(launch_peel(j, stream, g->max_deg));
+  FS_TRY(launch_prog(b.prog, stream));
+  if (status) {
+    const hipError_t e = hipMemcpyAsync(status, b.sched.status, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice, stream);
+    if (e != hipSuccess) return fail(FS_ERR_HIP, std::string("status copy: ") + hipGetErrorString(e));
+  }
+  return FS_OK;
+}
+
+fs_status fs_decode_apply(const fs_graph *g, const void *c, void *x, uint64_t t, const void *ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(c, t, "c"));
+  FS_TRY(check_payload(x, t, "x"));
+  FS_TRY(check_ws(g, FS_OP_DECODE, t, 0, const_cast<void *>(ws), ws_bytes));
+  Carver cv(const_cast<void *>(ws));
+  DecodeBufs b;
+  carve_decode(cv, g, b);
+  return launch_replay_prog(replay_job(g, c, x, t, b.sched.status, b.sched.level_ptr, b.sched.dp_f, b.sched.dp_g),
+                            &b.prog, stream);
+}
+
 fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uint32_t maxit, void *x,
                     uint8_t *recovered, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
                     hipStream_t stream) {
@@ -443,15 +500,8 @@ fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uin
   FS_TRY(check_payload(c, t, "c"));
   FS_TRY(check_payload(x, t, "x"));
   if (!erased || !recovered || !status) return fail(FS_ERR_INVALID, "erased, recovered and status must be non-null");
-  FS_TRY(check_ws(g, FS_OP_DECODE, t, 0, ws, ws_bytes));
-  Carver cv(ws);
-  SchedBufs s;
-  carve_sched(cv, g->k, s, false);
-  PeelJob j = peel_job(g, erased, maxit, recovered, status, s.level_ptr, s.dp_f, s.dp_g);
-  peel_carve(cv, j);
-  ProgJob p = prog_job(g, cv, status, s.level_ptr, s.dp_f, s.dp_g);
-  FS_TRY(launch_peel(j, stream, g->max_deg));
-  return launch_replay(replay_job(g, c, x, t, status, s.level_ptr, s.dp_f, s.dp_g), &p, stream);
+  FS_TRY(fs_decode_plan(g, erased, maxit, recovered, status, ws, ws_bytes, stream));
+  return fs_decode_apply(g, c, x, t, ws, ws_bytes, stream);
 }
 
 fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *erased, const uint32_t *lost,

@@ -128,8 +128,12 @@ struct ProgJob {
 };
 void prog_carve(Carver &cv, ProgJob &p, uint64_t nnz);
 
-// prog: workspace for the LDS replay (null: global-memory replay only)
+// prog: workspace for the replay program (null: global-memory replay only).
+// launch_replay builds the program then replays; launch_prog and
+// launch_replay_prog are the two halves.
 fs_status launch_replay(const ReplayJob &job, const ProgJob *prog, hipStream_t s);
+fs_status launch_prog(const ProgJob &prog, hipStream_t s);
+fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStream_t s);
 
 // lost-row validation / masks for repair
 struct RepairPrepJob {

@@ -626,20 +626,42 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
                                                    const IT *poff, const IT *pidx, int L, int nR,
                                                    uint32_t nslices, uint32_t vb) {
   constexpr int NS = kReplayThreads / LPS;
+  constexpr int MP = 4;                 // pairs per thread whose coded block is prefetched
   constexpr uint32_t W = LPS * 16;
   const uint32_t lane = threadIdx.x % LPS, sym = threadIdx.x / LPS;
   const uint32_t k = J.k;
+  const v4u zero = {0u, 0u, 0u, 0u};
   for (uint32_t slice = vb; slice < nslices; slice += gridDim.x) {
     const uint64_t off = (uint64_t)slice * W + lane * 16u;
     const bool live = off < J.t;
+    // coded blocks of the first MP pairs of a level are loaded while the
+    // previous level runs (c is never written here)
+    v4u cb[MP];
+    auto prefetch = [&](int l) {
+      const int q0 = max((int)lp[l], 0), q1 = min((int)lp[l + 1], nR);
+#pragma unroll
+      for (int m = 0; m < MP; ++m) {
+        const int q = q0 + (int)sym + m * NS;
+        const uint32_t g = q < q1 ? (uint32_t)pg[q] : 0xffffffffu;
+        cb[m] = (live && g < J.n) ? ld16(J.c + (uint64_t)g * J.t + off) : zero;
+      }
+    };
+    if (L > 0) prefetch(0);
     for (int l = 0; l < L; ++l) {
-      const int q1 = min((int)lp[l + 1], nR);
-      for (int q = max((int)lp[l], 0) + (int)sym; q < q1; q += NS) {
+      const int q0 = max((int)lp[l], 0), q1 = min((int)lp[l + 1], nR);
+      v4u cur[MP];
+#pragma unroll
+      for (int m = 0; m < MP; ++m) cur[m] = cb[m];
+      if (l + 1 < L) prefetch(l + 1);
+#pragma unroll
+      for (int m = 0; m < MP; ++m) {
+        const int q = q0 + (int)sym + m * NS;
+        if (q >= q1 || !live) continue;
         const uint32_t f = (uint32_t)pf[q], g = (uint32_t)pg[q];
-        if (!live || f >= k || g >= J.n) continue;
-        const int o0 = (int)poff[q], o1 = (int)poff[q + 1];
-        v4u acc = ld16(J.c + (uint64_t)g * J.t + off);
-        int o = o0;
+        if (f >= k || g >= J.n) continue;
+        const int o1 = (int)poff[q + 1];
+        v4u acc = cur[m];
+        int o = (int)poff[q];
         for (; o + 4 <= o1; o += 4) {
           const v4u a = ld16(J.x + (uint64_t)pidx[o] * J.t + off);
           const v4u b = ld16(J.x + (uint64_t)pidx[o + 1] * J.t + off);
@@ -650,12 +672,21 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
         for (; o < o1; ++o) acc ^= ld16(J.x + (uint64_t)pidx[o] * J.t + off);
         *reinterpret_cast<v4u *>(J.x + (uint64_t)f * J.t + off) = acc;
       }
+      // pairs beyond MP per thread (very large levels) load their block here
+      for (int q = q0 + (int)sym + MP * NS; q < q1; q += NS) {
+        const uint32_t f = (uint32_t)pf[q], g = (uint32_t)pg[q];
+        if (!live || f >= k || g >= J.n) continue;
+        v4u acc = ld16(J.c + (uint64_t)g * J.t + off);
+        const int o1 = (int)poff[q + 1];
+        for (int o = (int)poff[q]; o < o1; ++o) acc ^= ld16(J.x + (uint64_t)pidx[o] * J.t + off);
+        *reinterpret_cast<v4u *>(J.x + (uint64_t)f * J.t + off) = acc;
+      }
       __syncthreads();
     }
     if (live) {
       for (int q = nR + (int)sym; q < (int)k; q += NS) {
         const int32_t f = J.dp_f[q];
-        if ((uint32_t)f < k) st16<false>(J.x + (uint64_t)f * J.t + off, v4u{0u, 0u, 0u, 0u});
+        if ((uint32_t)f < k) st16<false>(J.x + (uint64_t)f * J.t + off, zero);
       }
     }
   }
@@ -1021,7 +1052,20 @@ static hipError_t run_replay_lds_m(const ReplayJob &job, const ProgJob &prog, ui
   return run_replay_lds<LPS, 16>(job, prog, nslices, grid, budget, dev, s);
 }
 
+fs_status launch_prog(const ProgJob &prog, hipStream_t s) {
+  FS_TRY_LAUNCH(prog_build, prog, s);
+  return FS_OK;
+}
+
 fs_status launch_replay(const ReplayJob &job, const ProgJob *prog, hipStream_t s) {
+  if (prog) {
+    const fs_status st = launch_prog(*prog, s);
+    if (st != FS_OK) return st;
+  }
+  return launch_replay_prog(job, prog, s);
+}
+
+fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStream_t s) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int cu = device_info(dev).cu_count;
@@ -1037,7 +1081,6 @@ fs_status launch_replay(const ReplayJob &job, const ProgJob *prog, hipStream_t s
     }
     return hip_check(hipGetLastError(), "replay launch");
   }
-  FS_TRY_LAUNCH(prog_build, *prog, s);
   const int lps = replay_lanes(job.k);
   hipError_t e;
   if (lps) {

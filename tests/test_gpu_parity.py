@@ -247,6 +247,27 @@ def test_peel_replay_equals_decode_and_is_deterministic():
     assert np.array_equal(host(x2), a.x)
 
 
+def test_decode_plan_applied_to_several_stripes():
+    # one plan (schedule + replay program) serves every stripe that shares the
+    # graph and the erasure pattern
+    import paper_1702_07409_amd as fs
+    for sp in (workloads.tiny(), workloads.scaled(workloads.large_stripe(), 2048)):
+        g, G = spec_graphs(sp)
+        er = sp.erased_mask()
+        rec, st = empty_u8(sp.k), empty_i32(3)
+        ws = fs.workspace(g, fs.FS_OP_DECODE, sp.t)
+        fs.fs_decode_plan(g, dev(er), 0, rec, st, ws)
+        for stripe in (0, 7):
+            x = gen.payload(0, stripe, sp.k, sp.t)
+            c_host = codec.encode(G, x)
+            xd = empty_u8(sp.k, sp.t)
+            xd.fill_(0x3C)
+            fs.fs_decode_apply(g, dev(c_host), xd, sp.t, ws)
+            xo, reco, sto, _ = oracle_decode(G, c_host, er)
+            assert np.array_equal(host(xd), xo)
+            assert np.array_equal(host(rec), reco) and host(st).tolist() == list(sto)
+
+
 # ---------------------------------------------------------------- repair
 
 def test_repair_from_inputs():
