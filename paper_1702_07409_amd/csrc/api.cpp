@@ -318,34 +318,49 @@ fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_g
       delete g;
       return fail(FS_ERR_HIP, "hipGetDevice failed");
     }
-    const size_t a = ((size_t)g->n + 1) * 4, b = g->nnz * 4, c = ((size_t)g->k + 1) * 4;
-    auto up = [](size_t v) { return (v + 255) & ~size_t(255); };
-    const size_t total = up(a) + up(b) + up(c) + up(b) + 256;
+    // every device array of the graph in one allocation
+    struct Part {
+      const void *src;
+      size_t bytes;
+      size_t off;
+    };
+    Part parts[8] = {{g->row_ptr.data(), g->row_ptr.size() * 4, 0},
+                     {g->col.data(), g->col.size() * 4, 0},
+                     {g->col_ptr.data(), g->col_ptr.size() * 4, 0},
+                     {g->rowidx.data(), g->rowidx.size() * 4, 0},
+                     {g->seg_ptr.data(), g->seg_ptr.size() * 4, 0},
+                     {g->seg_row.data(), g->seg_row.size() * 4, 0},
+                     {g->heavy.data(), g->heavy.size() * 4, 0},
+                     {g->seg_atomic.data(), g->seg_atomic.size(), 0}};
+    size_t total = 0;
+    for (Part &pt : parts) {
+      pt.off = total;
+      total += (pt.bytes + 255) & ~size_t(255);
+    }
     void *base = nullptr;
-    if (hipMalloc(&base, total) != hipSuccess) {
+    if (hipMalloc(&base, total + 256) != hipSuccess) {
       delete g;
       return fail(FS_ERR_NOMEM, "device allocation for the graph failed");
     }
     g->d_base = base;
     uint8_t *p = static_cast<uint8_t *>(base);
-    int32_t *rp = reinterpret_cast<int32_t *>(p);
-    int32_t *cl = reinterpret_cast<int32_t *>(p + up(a));
-    int32_t *cp = reinterpret_cast<int32_t *>(p + up(a) + up(b));
-    int32_t *ri = reinterpret_cast<int32_t *>(p + up(a) + up(b) + up(c));
-    hipError_t e = hipMemcpyAsync(rp, g->row_ptr.data(), a, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && b) e = hipMemcpyAsync(cl, g->col.data(), b, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(cp, g->col_ptr.data(), c, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess && b) e = hipMemcpyAsync(ri, g->rowidx.data(), b, hipMemcpyHostToDevice, stream);
+    hipError_t e = hipSuccess;
+    for (const Part &pt : parts)
+      if (e == hipSuccess && pt.bytes) e = hipMemcpyAsync(p + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
-      hipFree(base);
+      (void)hipFree(base);
       delete g;
       return fail(FS_ERR_HIP, std::string("graph upload: ") + hipGetErrorString(e));
     }
-    g->d_row_ptr = rp;
-    g->d_col = cl;
-    g->d_col_ptr = cp;
-    g->d_rowidx = ri;
+    g->d_row_ptr = reinterpret_cast<const int32_t *>(p + parts[0].off);
+    g->d_col = reinterpret_cast<const int32_t *>(p + parts[1].off);
+    g->d_col_ptr = reinterpret_cast<const int32_t *>(p + parts[2].off);
+    g->d_rowidx = reinterpret_cast<const int32_t *>(p + parts[3].off);
+    g->d_seg_ptr = reinterpret_cast<const int32_t *>(p + parts[4].off);
+    g->d_seg_row = reinterpret_cast<const int32_t *>(p + parts[5].off);
+    g->d_heavy = reinterpret_cast<const int32_t *>(p + parts[6].off);
+    g->d_seg_atomic = reinterpret_cast<const uint8_t *>(p + parts[7].off);
   }
   *out = g;
   return FS_OK;
@@ -394,15 +409,20 @@ fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t, hipSt
   FS_TRY(check_graph(g));
   FS_TRY(check_payload(x, t, "x"));
   FS_TRY(check_payload(c, t, "c"));
+  // rows split into several segments are zeroed, then combined atomically
+  if (!g->heavy.empty())
+    FS_TRY(launch_zero_rows(static_cast<uint8_t *>(c), g->d_heavy, (uint32_t)g->heavy.size(), t, stream));
   GatherJob j{};
   j.src = static_cast<const uint8_t *>(x);
   j.src_stride = t;
   j.dst = static_cast<uint8_t *>(c);
   j.dst_stride = t;
-  j.ptr = g->d_row_ptr;
+  j.ptr = g->d_seg_ptr;
   j.idx = g->d_col;
-  j.nrows = g->n;
-  j.csr_rows = g->n;
+  j.out_map = g->d_seg_row;
+  j.seg_atomic = g->heavy.empty() ? nullptr : g->d_seg_atomic;
+  j.nrows = (uint32_t)g->seg_row.size();
+  j.csr_rows = j.nrows;
   j.t = t;
   return launch_gather(j, current_tune(), stream);
 }

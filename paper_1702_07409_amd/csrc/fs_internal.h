@@ -17,13 +17,24 @@ struct fs_graph {
   fs_graph_params params{};
   std::vector<double> finite_w;  // owned copy of the finite table
   std::vector<int32_t> row_ptr, col, col_ptr, rowidx;
+  // Encode segments: rows cut into runs of at most kSegMax edges, so that a
+  // row of huge degree (the Robust Soliton tail) is spread over many
+  // workgroups.  seg_ptr[s]..seg_ptr[s+1] are edges of row seg_row[s];
+  // seg_atomic[s] = 1 when the row has several segments (combined by atomic
+  // XOR into a zeroed row); heavy lists those rows once.
+  std::vector<int32_t> seg_ptr, seg_row, heavy;
+  std::vector<uint8_t> seg_atomic;
   int device = -1;
   void *d_base = nullptr;
   const int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_col_ptr = nullptr,
                 *d_rowidx = nullptr;
+  const int32_t *d_seg_ptr = nullptr, *d_seg_row = nullptr, *d_heavy = nullptr;
+  const uint8_t *d_seg_atomic = nullptr;
 };
 
 namespace fs {
+
+constexpr uint32_t kSegMax = 64;
 
 // thread-local error text; returns s for chaining
 fs_status fail(fs_status s, const std::string &msg);
@@ -73,6 +84,7 @@ struct GatherJob {
   const uint8_t *row_ok;   // item r is zero-filled when row_ok[r] == 0 (null: all ok)
   const int32_t *nrows_dev;  // device item count (null: nrows)
   const int32_t *skip_flag;  // non-zero: the launch writes nothing
+  const uint8_t *seg_atomic; // item r XORs atomically into its (zeroed) output when set
   uint32_t nrows;          // item count, or its upper bound with nrows_dev
   uint32_t csr_rows;       // CSR rows; items mapping beyond are skipped
   uint64_t t;              // bytes per block (multiple of 16)
@@ -80,6 +92,8 @@ struct GatherJob {
 };
 
 fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s);
+// zero the listed blocks (dst + rows[i] * t)
+fs_status launch_zero_rows(uint8_t *dst, const int32_t *rows, uint32_t nrows, uint64_t t, hipStream_t s);
 
 struct PeelJob {
   uint32_t k, n;

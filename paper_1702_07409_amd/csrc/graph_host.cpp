@@ -169,6 +169,21 @@ fs_status build_host_graph(const fs_graph_params &p, fs_graph &g) {
   for (uint32_t i = 0; i < k; ++i)
     max_cdeg = std::max<uint32_t>(max_cdeg, (uint32_t)(g.col_ptr[i + 1] - g.col_ptr[i]));
   g.max_cdeg = max_cdeg;
+  // encode segments
+  g.seg_ptr.assign(1, 0);
+  g.seg_row.clear();
+  g.seg_atomic.clear();
+  g.heavy.clear();
+  for (uint32_t j = 0; j < n; ++j) {
+    const int32_t e0 = g.row_ptr[j], e1 = g.row_ptr[j + 1];
+    const bool split = (uint32_t)(e1 - e0) > kSegMax;
+    if (split) g.heavy.push_back((int32_t)j);
+    for (int32_t e = e0; e < e1; e += (int32_t)kSegMax) {
+      g.seg_ptr.push_back(std::min<int32_t>(e1, e + (int32_t)kSegMax));
+      g.seg_row.push_back((int32_t)j);
+      g.seg_atomic.push_back(split ? 1 : 0);
+    }
+  }
   return FS_OK;
 }
 

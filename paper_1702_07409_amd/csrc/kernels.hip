@@ -181,10 +181,29 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uin
       gather_row<CH, STEP>(acc, valid, s_idx, s_ptr[sub], s_ptr[sub + 1], src, j.src_stride);
     else
       gather_row<CH, STEP>(acc, valid, j.idx, j.ptr[jr], j.ptr[jr + 1], src, j.src_stride);
+    if (j.seg_atomic && j.seg_atomic[r]) {
+      // one of several segments of a long row: XOR into the zeroed row
+#pragma unroll
+      for (int c = 0; c < CH; ++c) {
+        if (!valid[c]) continue;
+        unsigned long long *q = reinterpret_cast<unsigned long long *>(out + c * STEP);
+        atomicXor(q, ((unsigned long long)acc[c].y << 32) | acc[c].x);
+        atomicXor(q + 1, ((unsigned long long)acc[c].w << 32) | acc[c].z);
+      }
+      continue;
+    }
 #pragma unroll
     for (int c = 0; c < CH; ++c)
       if (valid[c]) st16<NT>(out + c * STEP, acc[c]);
   }
+}
+
+__global__ __launch_bounds__(256) void zero_rows_kernel(uint8_t *dst, const int32_t *rows, uint32_t nrows,
+                                                        uint64_t t, uint32_t chunks) {
+  const uint32_t r = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+  if (r >= nrows) return;
+  const uint64_t off = (uint64_t)ch * 4096 + threadIdx.x * 16u;
+  if (off < t) *reinterpret_cast<v4u *>(dst + (uint64_t)rows[r] * t + off) = v4u{0u, 0u, 0u, 0u};
 }
 
 template <int LPR, int CH, bool NT>
@@ -327,16 +346,22 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
   }
   __syncthreads();
   for (uint32_t g = tid; g < n; g += kPeelThreads) {
-    const int e0 = J.row_ptr[g], e1 = J.row_ptr[g + 1];
-    if constexpr (LDS) S.deg[g] = (uint16_t)(e1 - e0);
+    const int d = J.row_ptr[g + 1] - J.row_ptr[g];
+    if constexpr (LDS) S.deg[g] = (uint16_t)d;
     if (J.erased[g]) {
       S.acc[g] = kErasedAcc;
       continue;
     }
-    unsigned long long sum = 0;
-    for (int e = e0; e < e1; ++e) sum += (unsigned)J.col[e];
-    S.acc[g] = ((unsigned long long)(e1 - e0) << 40) | sum;
-    if (e1 - e0 == 1) S.fa[atomicAdd(&s_nA, 1)] = (int32_t)g;
+    S.acc[g] = (unsigned long long)d << 40;
+    if (d == 1) S.fa[atomicAdd(&s_nA, 1)] = (int32_t)g;
+  }
+  __syncthreads();
+  // sums of neighbour ids, accumulated by input over the CSC: the work per
+  // thread follows the column degrees, which stay small even when a few rows
+  // have huge degree
+  for (uint32_t i = tid; i < k; i += kPeelThreads) {
+    const int c1 = S.cptr[i + 1];
+    for (int e = S.cptr[i]; e < c1; ++e) atomicAdd(&S.acc[J.rowidx[e]], (unsigned long long)i);
   }
   __syncthreads();
 
@@ -947,6 +972,14 @@ fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s
     default: return fail(FS_ERR_INVALID, "unsupported gather tuning");
   }
   return hip_check(e, "gather launch");
+}
+
+fs_status launch_zero_rows(uint8_t *dst, const int32_t *rows, uint32_t nrows, uint64_t t, hipStream_t s) {
+  const uint32_t chunks = (uint32_t)((t + 4095) / 4096);
+  const uint64_t grid = (uint64_t)nrows * chunks;
+  if (grid == 0) return FS_OK;
+  hipLaunchKernelGGL(zero_rows_kernel, dim3((uint32_t)grid), dim3(256), 0, s, dst, rows, nrows, t, chunks);
+  return hip_check(hipGetLastError(), "zero rows launch");
 }
 
 size_t peel_lds_bytes(uint32_t k, uint32_t n) {

@@ -102,6 +102,26 @@ def test_encode_tiles_beyond_the_lds_edge_stage():
     fs.fs_reset_tune()
 
 
+def test_encode_and_decode_rsd_heavy_tail():
+    # Robust Soliton at k = 8192 has rows of degree in the thousands: they are
+    # encoded as several segments combined by atomic XOR
+    import paper_1702_07409_amd as fs
+    sp = workloads.StripeSpec(stripe=9, k=8192, n=8847, t=512 + 64, dist="rsd", rsd_c=0.05,
+                              rsd_delta=0.01, stripe_key=11, n_erased=354)
+    g, G = spec_graphs(sp)
+    assert int(G.degrees().max()) > 1000
+    x = sp.x()
+    want = codec.encode(G, x)
+    for lpr, ch in ((16, 2), (64, 1), (32, 4)):
+        fs.fs_set_tune(lpr, ch, 1, 1)
+        c = empty_u8(sp.n, sp.t)
+        c.fill_(0x77)
+        fs.fs_encode(g, dev(x), c, sp.t)
+        assert np.array_equal(host(c), want), (lpr, ch)
+    fs.fs_reset_tune()
+    decode_case(sp)
+
+
 def test_encode_rejects_bad_alignment():
     import paper_1702_07409_amd as fs
     g, _ = graphs(k=8, n=10, seed=1)
