@@ -251,6 +251,84 @@ typedef struct fs_tune {
 FS_API fs_status fs_set_tune(const fs_tune *tune);
 FS_API fs_status fs_get_tune(fs_tune *tune);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many stripes of uneven k and block size in one captured launch.
+ *
+ * A plan binds a list of work items (encode, decode, repair from resident
+ * inputs, update) to their buffers.  At creation it lays out one device
+ * workspace for all items, writes the job descriptors to device memory and
+ * captures the launch sequence in a hipGraph:
+ *   branch A: peeling schedules of every decode (one workgroup per stripe),
+ *             their replay programs, then the replays;
+ *   branch B: zeroing of split rows, repair id checks, update plans and
+ *             deltas, then ONE persistent gather-XOR kernel over the tiles
+ *             of every encode, repair and update job.
+ * fs_plan_launch replays the graph.  Items of one plan must be independent:
+ * no item may write a buffer another item of the plan reads or writes.
+ * Results are those of the single-stripe calls (bit for bit).
+ * ------------------------------------------------------------------------- */
+enum { FS_WORK_ENCODE = 0, FS_WORK_DECODE = 1, FS_WORK_REPAIR = 2, FS_WORK_UPDATE = 3 };
+
+typedef struct fs_work {
+  uint32_t op;              /* FS_WORK_*                                              */
+  uint32_t n_ids;           /* repair: lost rows; update: updated inputs              */
+  const fs_graph *graph;    /* built on the current device                            */
+  uint64_t t;               /* block bytes, multiple of 16                            */
+  void *x;                  /* encode: in; decode: out; repair: in; update: in/out    */
+  void *c;                  /* encode: out; decode: in; repair, update: in/out        */
+  const uint8_t *erased;    /* decode: device uint8[n]                                */
+  uint32_t maxit;           /* decode (0 = no limit)                                  */
+  uint32_t reserved;        /* must be 0                                              */
+  uint8_t *recovered;       /* decode: device uint8[k] (out)                          */
+  int32_t *status;          /* device int32[3] (out) as the single call; decode: may
+                               be NULL                                                 */
+  const uint32_t *ids;      /* repair: device lost rows; update: device input ids     */
+  const void *new_blocks;   /* update: device uint8[n_ids][t]                         */
+  uint8_t *repaired;        /* repair: device uint8[n_ids] (out)                      */
+} fs_work;
+
+typedef struct fs_plan fs_plan;
+
+/* fs_plan_create flags */
+enum {
+  FS_PLAN_AUTOTUNE = 1,  /* time candidate gather tilings on the bound buffers and
+                            keep the fastest (encode and repair outputs are
+                            written during the timing; updates are not run)     */
+  FS_PLAN_NO_GRAPH = 2   /* launch the kernels one by one instead of a hipGraph */
+};
+
+typedef struct fs_plan_info {
+  uint32_t items, gather_jobs, decode_items, update_items, repair_items, encode_items;
+  uint64_t gather_tiles;     /* items of the persistent gather                   */
+  uint32_t replay_workgroups;
+  uint32_t tune_source;      /* 0 default, 1 timed now, 2 read from the cache    */
+  fs_tune tune;              /* gather tiling used by the plan                   */
+  uint64_t workspace_bytes;  /* device memory owned by the plan                  */
+  double tuned_ms;           /* timed gather of the chosen tiling (0 if none)    */
+} fs_plan_info;
+
+/*
+ * Create a plan for count items.  tune_cache: optional path of a text file
+ * of tilings keyed by the plan's shape (read, and appended after timing).
+ * The stream is used for uploads and timing; the call synchronises it.
+ * Errors: FS_ERR_INVALID / FS_ERR_ALIGN for a bad item (fs_last_error names
+ * it), FS_ERR_UNSUPPORTED for a repair without resident inputs (x == NULL),
+ * FS_ERR_NOMEM, FS_ERR_HIP.
+ */
+FS_API fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_cache, uint32_t flags,
+                                hipStream_t stream, fs_plan **out);
+/* Run the plan on a stream (asynchronous). */
+FS_API fs_status fs_plan_launch(fs_plan *plan, hipStream_t stream);
+/*
+ * Point the plan at new buffers: same count and, item by item, the same op,
+ * graph, t and n_ids (else FS_ERR_INVALID).  The descriptors are rewritten
+ * in device memory on the stream; the captured graph is reused.  A launch
+ * already enqueued on another stream must have completed.
+ */
+FS_API fs_status fs_plan_rebind(fs_plan *plan, const fs_work *items, uint32_t count, hipStream_t stream);
+FS_API fs_status fs_plan_get_info(const fs_plan *plan, fs_plan_info *info);
+FS_API void fs_plan_free(fs_plan *plan);
+
 FS_API const char *fs_status_string(fs_status s);
 /* Message of the last error on the calling thread ("" if none). */
 FS_API const char *fs_last_error(void);

@@ -40,6 +40,23 @@ class fs_tune(ctypes.Structure):
                 ("replay_prog_global", ctypes.c_uint32)]
 
 
+class fs_work(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("n_ids", ctypes.c_uint32), ("graph", ctypes.c_void_p),
+                ("t", ctypes.c_uint64), ("x", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("erased", ctypes.c_void_p), ("maxit", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("recovered", ctypes.c_void_p), ("status", ctypes.c_void_p), ("ids", ctypes.c_void_p),
+                ("new_blocks", ctypes.c_void_p), ("repaired", ctypes.c_void_p)]
+
+
+class fs_plan_info(ctypes.Structure):
+    _fields_ = [("items", ctypes.c_uint32), ("gather_jobs", ctypes.c_uint32),
+                ("decode_items", ctypes.c_uint32), ("update_items", ctypes.c_uint32),
+                ("repair_items", ctypes.c_uint32), ("encode_items", ctypes.c_uint32),
+                ("gather_tiles", ctypes.c_uint64), ("replay_workgroups", ctypes.c_uint32),
+                ("tune_source", ctypes.c_uint32), ("tune", fs_tune),
+                ("workspace_bytes", ctypes.c_uint64), ("tuned_ms", ctypes.c_double)]
+
+
 P = ctypes.c_void_p
 U32, U64, SZ, I32 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t, ctypes.c_int
 ST = ctypes.c_int
@@ -60,6 +77,11 @@ _SIGS = {
     "fs_decode_apply": ([P, P, P, U64, P, SZ, P], ST),
     "fs_repair": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
+    "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
+    "fs_plan_launch": ([P, P], ST),
+    "fs_plan_rebind": ([P, ctypes.POINTER(fs_work), U32, P], ST),
+    "fs_plan_get_info": ([P, ctypes.POINTER(fs_plan_info)], ST),
+    "fs_plan_free": ([P], None),
     "fs_set_tune": ([ctypes.POINTER(fs_tune)], ST),
     "fs_get_tune": ([ctypes.POINTER(fs_tune)], ST),
     "fs_status_string": ([I32], ctypes.c_char_p),
@@ -258,3 +280,66 @@ def fs_get_tune():
     _check(_lib.fs_get_tune(ctypes.byref(tu)), "fs_get_tune")
     return dict(lanes_per_row=tu.lanes_per_row, chunks=tu.chunks, xcd_remap=tu.xcd_remap,
                 nt_store=tu.nt_store, replay_prog_global=tu.replay_prog_global)
+
+
+FS_WORK_ENCODE, FS_WORK_DECODE, FS_WORK_REPAIR, FS_WORK_UPDATE = range(4)
+FS_PLAN_AUTOTUNE, FS_PLAN_NO_GRAPH = 1, 2
+WORK_OPS = {"encode": FS_WORK_ENCODE, "decode": FS_WORK_DECODE, "repair": FS_WORK_REPAIR,
+            "update": FS_WORK_UPDATE}
+
+
+def work(op, graph, t, x=None, c=None, erased=None, maxit=0, recovered=None, status=None, ids=None,
+         n_ids=0, new_blocks=None, repaired=None):
+    """One fs_work item (tensors are kept alive by the returned object)."""
+    w = fs_work()
+    w.op = WORK_OPS[op] if isinstance(op, str) else op
+    w.n_ids = n_ids
+    w.graph = graph.handle
+    w.t = t
+    w.x, w.c, w.erased = _ptr(x), _ptr(c), _ptr(erased)
+    w.maxit = maxit
+    w.recovered, w.status, w.ids = _ptr(recovered), _ptr(status), _ptr(ids)
+    w.new_blocks, w.repaired = _ptr(new_blocks), _ptr(repaired)
+    w._keep = (graph, x, c, erased, recovered, status, ids, new_blocks, repaired)
+    return w
+
+
+class Plan:
+    """Owner of an fs_plan handle."""
+
+    def __init__(self, items, tune_cache=None, autotune=False, graph=True, stream=None):
+        arr = (fs_work * len(items))(*items)
+        h = P()
+        flags = (FS_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else FS_PLAN_NO_GRAPH)
+        path = tune_cache.encode() if tune_cache else None
+        _check(_lib.fs_plan_create(arr, len(items), path, flags, _stream(stream), ctypes.byref(h)),
+               "fs_plan_create")
+        self.handle = h
+        self._items = list(items)
+
+    def launch(self, stream=None):
+        _check(_lib.fs_plan_launch(self.handle, _stream(stream)), "fs_plan_launch")
+
+    def rebind(self, items, stream=None):
+        arr = (fs_work * len(items))(*items)
+        _check(_lib.fs_plan_rebind(self.handle, arr, len(items), _stream(stream)), "fs_plan_rebind")
+        self._items = list(items)
+
+    def info(self):
+        i = fs_plan_info()
+        _check(_lib.fs_plan_get_info(self.handle, ctypes.byref(i)), "fs_plan_get_info")
+        out = {f: getattr(i, f) for f, _ in fs_plan_info._fields_ if f != "tune"}
+        out["tune"] = dict(lanes_per_row=i.tune.lanes_per_row, chunks=i.tune.chunks,
+                           xcd_remap=i.tune.xcd_remap, nt_store=i.tune.nt_store)
+        return out
+
+    def free(self):
+        if self.handle:
+            _lib.fs_plan_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

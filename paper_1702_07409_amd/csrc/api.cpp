@@ -36,16 +36,17 @@ const DeviceInfo &device_info(int dev) {
 }
 
 namespace {
-
 std::mutex g_tune_mu;
 fs_tune g_tune = {16, 2, 1, 1, 0};
+
+}  // namespace
 
 fs_tune current_tune() {
   std::lock_guard<std::mutex> lock(g_tune_mu);
   return g_tune;
 }
 
-bool tune_ok(const fs_tune &t) {
+static bool tune_ok(const fs_tune &t) {
   const bool lpr = t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64;
   const bool ch = t.chunks == 1 || t.chunks == 2 || t.chunks == 4;
   return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1;
@@ -73,11 +74,6 @@ fs_status check_payload(const void *p, uint64_t t, const char *name) {
     if (_s != FS_OK) return _s;       \
   } while (0)
 
-// Schedule arrays kept in a decode workspace.
-struct SchedBufs {
-  int32_t *status, *level_ptr, *dp_f, *dp_g;
-  uint8_t *recovered;
-};
 
 void carve_sched(Carver &cv, uint32_t k, SchedBufs &s, bool with_recovered) {
   s.status = cv.take<int32_t>(4);
@@ -87,15 +83,6 @@ void carve_sched(Carver &cv, uint32_t k, SchedBufs &s, bool with_recovered) {
   s.recovered = with_recovered ? cv.take<uint8_t>(k) : nullptr;
 }
 
-struct RepairBufs {
-  uint32_t *seen;
-  int32_t *flag;
-  uint8_t *erased2;
-  SchedBufs sched;
-  PeelJob peel;
-  ProgJob prog;
-  uint8_t *x;
-};
 
 void carve_repair(Carver &cv, const fs_graph *g, uint64_t t, bool conventional, RepairBufs &b) {
   b.seen = cv.take<uint32_t>((g->n + 31) / 32);
@@ -118,12 +105,6 @@ void carve_repair(Carver &cv, const fs_graph *g, uint64_t t, bool conventional, 
   }
 }
 
-struct UpdateBufs {
-  uint32_t *seen;
-  int32_t *cnt, *arow, *aptr, *asrc, *n_aff, *flag;
-  uint8_t *delta;
-  uint32_t max_rows;
-};
 
 void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, UpdateBufs &b) {
   const uint64_t max_pairs = (uint64_t)n_ids * g->max_cdeg;
@@ -244,8 +225,6 @@ ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, cons
   r.dp_g = dp_g;
   return r;
 }
-
-}  // namespace
 
 fs_tune tune_snapshot() { return current_tune(); }
 
@@ -412,19 +391,7 @@ fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t, hipSt
   // rows split into several segments are zeroed, then combined atomically
   if (!g->heavy.empty())
     FS_TRY(launch_zero_rows(static_cast<uint8_t *>(c), g->d_heavy, (uint32_t)g->heavy.size(), t, stream));
-  GatherJob j{};
-  j.src = static_cast<const uint8_t *>(x);
-  j.src_stride = t;
-  j.dst = static_cast<uint8_t *>(c);
-  j.dst_stride = t;
-  j.ptr = g->d_seg_ptr;
-  j.idx = g->d_col;
-  j.out_map = g->d_seg_row;
-  j.seg_atomic = g->heavy.empty() ? nullptr : g->d_seg_atomic;
-  j.nrows = (uint32_t)g->seg_row.size();
-  j.csr_rows = j.nrows;
-  j.t = t;
-  return launch_gather(j, current_tune(), stream);
+  return launch_gather(encode_job(g, x, c, t), current_tune(), stream);
 }
 
 fs_status fs_peel(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered, int32_t *status,
@@ -455,14 +422,26 @@ fs_status fs_replay(const fs_graph *g, const void *c, const int32_t *status, con
   return launch_replay(replay_job(g, c, x, t, status, level_ptr, dp_f, dp_g), &p, stream);
 }
 
-// Decode workspace: schedule arrays, peel state, replay program.
-struct DecodeBufs {
-  SchedBufs sched;
-  PeelJob peel;
-  ProgJob prog;
-};
+}  // extern "C"
 
-static void carve_decode(Carver &cv, const fs_graph *g, DecodeBufs &b) {
+namespace fs {
+GatherJob encode_job(const fs_graph *g, const void *x, void *c, uint64_t t) {
+  GatherJob j{};
+  j.src = static_cast<const uint8_t *>(x);
+  j.src_stride = t;
+  j.dst = static_cast<uint8_t *>(c);
+  j.dst_stride = t;
+  j.ptr = g->d_seg_ptr;
+  j.idx = g->d_col;
+  j.out_map = g->d_seg_row;
+  j.seg_atomic = g->heavy.empty() ? nullptr : g->d_seg_atomic;
+  j.nrows = (uint32_t)g->seg_row.size();
+  j.csr_rows = j.nrows;
+  j.t = t;
+  return j;
+}
+
+void carve_decode(Carver &cv, const fs_graph *g, DecodeBufs &b) {
   carve_sched(cv, g->k, b.sched, false);
   b.peel = PeelJob{};
   b.peel.k = g->k;
@@ -470,6 +449,11 @@ static void carve_decode(Carver &cv, const fs_graph *g, DecodeBufs &b) {
   peel_carve(cv, b.peel);
   b.prog = prog_job(g, cv, b.sched.status, b.sched.level_ptr, b.sched.dp_f, b.sched.dp_g);
 }
+}  // namespace fs
+
+using namespace fs;
+
+extern "C" {
 
 fs_status fs_decode_plan(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered,
                          int32_t *status, void *ws, size_t ws_bytes, hipStream_t stream) {

@@ -202,4 +202,74 @@ struct UpdateDeltaJob {
 };
 fs_status launch_update_delta(const UpdateDeltaJob &job, hipStream_t s);
 
+// ---- batched launches (one launch for many stripes) ----
+struct ZeroEntry {
+  uint8_t *base;
+  uint64_t t;
+  int64_t row;
+};
+// device arrays of job descriptors; see kernels.hip for the item spaces
+fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long *d_prefix, uint32_t njobs,
+                              const fs_tune &tune, uint32_t grid, hipStream_t s);
+fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, bool lds, size_t lds_bytes, hipStream_t s);
+fs_status launch_prog_batch(const ProgJob *d_jobs, uint32_t njobs, hipStream_t s);
+fs_status launch_replay_batch(const ReplayJob *d_rj, const ProgJob *d_pj, const uint32_t *d_wg_prefix,
+                              uint32_t nitems, uint32_t total_wg, hipStream_t s);
+fs_status launch_repair_prep_batch(const RepairPrepJob *d_jobs, uint32_t njobs, hipStream_t s);
+fs_status launch_update_plan_batch(const UpdatePlanJob *d_jobs, uint32_t njobs, hipStream_t s);
+fs_status launch_update_delta_batch(const UpdateDeltaJob *d_jobs, const uint32_t *d_prefix, uint32_t njobs,
+                                    uint32_t total_wg, hipStream_t s);
+fs_status launch_zero_batch(const ZeroEntry *d_rows, uint32_t nrows, uint64_t max_t, hipStream_t s);
+// set the LDS limits of the batched kernels (before a graph capture)
+void prepare_batch_kernels();
+// batch replay geometry: 16-byte lanes per symbol (W = 16 LPS) and slices per workgroup
+constexpr uint32_t kBatchReplayLanes = 16;
+constexpr uint32_t kBatchReplaySlicesPerWg = 8;
+constexpr uint32_t kDeltaBytesPerWg = 4096;
+
+// ---- workspace layouts and argument checks shared by the entry points ----
+
+// Schedule arrays kept in a decode workspace.
+struct SchedBufs {
+  int32_t *status, *level_ptr, *dp_f, *dp_g;
+  uint8_t *recovered;
+};
+// Decode workspace: schedule arrays, peel state, replay program.
+struct DecodeBufs {
+  SchedBufs sched;
+  PeelJob peel;
+  ProgJob prog;
+};
+struct RepairBufs {
+  uint32_t *seen;
+  int32_t *flag;
+  uint8_t *erased2;
+  SchedBufs sched;
+  PeelJob peel;
+  ProgJob prog;
+  uint8_t *x;
+};
+struct UpdateBufs {
+  uint32_t *seen;
+  int32_t *cnt, *arow, *aptr, *asrc, *n_aff, *flag;
+  uint8_t *delta;
+  uint32_t max_rows;
+};
+
+fs_tune current_tune();
+fs_status check_graph(const fs_graph *g);
+fs_status check_payload(const void *p, uint64_t t, const char *name);
+void carve_sched(Carver &cv, uint32_t k, SchedBufs &s, bool with_recovered);
+void carve_repair(Carver &cv, const fs_graph *g, uint64_t t, bool conventional, RepairBufs &b);
+void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, UpdateBufs &b);
+void carve_decode(Carver &cv, const fs_graph *g, DecodeBufs &b);
+PeelJob peel_job(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered, int32_t *status,
+                 int32_t *level_ptr, int32_t *dp_f, int32_t *dp_g);
+ProgJob prog_job(const fs_graph *g, Carver &cv, const int32_t *status, const int32_t *level_ptr,
+                 const int32_t *dp_f, const int32_t *dp_g);
+ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, const int32_t *status,
+                     const int32_t *level_ptr, const int32_t *dp_f, const int32_t *dp_g);
+// the graph's encode as one gather job (segments of long rows combine atomically)
+GatherJob encode_job(const fs_graph *g, const void *x, void *c, uint64_t t);
+
 }  // namespace fs

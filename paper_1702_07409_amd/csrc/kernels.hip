@@ -114,87 +114,136 @@ __device__ __forceinline__ void gather_row(v4u (&acc)[CH], const bool (&valid)[C
   }
 }
 
+// One (slice, tile) item of a gather job.  All threads of the workgroup call
+// it with the same arguments (it contains barriers).  ntiles is the tile
+// count the item index was decomposed with, nrows the live row count.
 template <int LPR, int CH, bool NT>
-__global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uint32_t nslices,
-                                                                 uint32_t remap) {
+__device__ __forceinline__ void gather_item(const GatherJob &j, uint32_t nrows, uint32_t ntiles, uint64_t item,
+                                            int32_t *s_ptr, int32_t *s_idx) {
   constexpr uint32_t RPB = kGatherThreads / LPR;   // rows per tile
   constexpr uint32_t STEP = LPR * 16;              // bytes between a lane's chunks
   constexpr uint32_t W = STEP * CH;                // slice bytes
-  __shared__ int32_t s_ptr[RPB + 1];
-  __shared__ int32_t s_idx[kStageCap];
-  if (j.skip_flag && *j.skip_flag) return;
-  uint32_t nrows = j.nrows;
-  if (j.nrows_dev) nrows = min(nrows, (uint32_t)max(*j.nrows_dev, 0));
-  const uint32_t ntiles = (nrows + RPB - 1) / RPB;
-  const uint64_t nitems = (uint64_t)ntiles * nslices;
-  const uint32_t vb = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
   const uint32_t tid = threadIdx.x;
   const uint32_t lane = tid % LPR;
   const uint32_t sub = tid / LPR;
   const bool contiguous = j.csr_map == nullptr;
-  for (uint64_t item = vb; item < nitems; item += gridDim.x) {
-    // tiles of one slice are consecutive items, so a workgroup keeps its slice
-    const uint32_t slice = (uint32_t)(item / ntiles);
-    const uint32_t tile = (uint32_t)(item % ntiles);
-    const uint32_t r0 = tile * RPB;
-    const uint32_t r = r0 + sub;
-    // stage the tile's edge list (rows r0 .. r0+RPB-1 are contiguous in CSR)
-    bool staged = false;
-    int ebase = 0;
-    if (contiguous) {
-      const uint32_t rend = min(r0 + RPB, nrows);
-      ebase = j.ptr[r0];
-      const int ecount = j.ptr[rend] - ebase;
-      staged = ecount <= kStageCap;
-      __syncthreads();   // the previous item's readers are done with the LDS copy
-      if (staged) {
-        for (int i = (int)tid; i < ecount; i += kGatherThreads) s_idx[i] = j.idx[ebase + i];
-        for (uint32_t i = tid; i <= rend - r0; i += kGatherThreads) s_ptr[i] = j.ptr[r0 + i] - ebase;
-      }
-      __syncthreads();
+  // tiles of one slice are consecutive items, so neighbouring workgroups share a slice
+  const uint32_t slice = (uint32_t)(item / ntiles);
+  const uint32_t tile = (uint32_t)(item % ntiles);
+  const uint32_t r0 = tile * RPB;
+  if (r0 >= nrows) return;
+  const uint32_t r = r0 + sub;
+  // stage the tile's edge list (rows r0 .. r0+RPB-1 are contiguous in CSR)
+  bool staged = false;
+  if (contiguous) {
+    const uint32_t rend = min(r0 + RPB, nrows);
+    const int ebase = j.ptr[r0];
+    const int ecount = j.ptr[rend] - ebase;
+    staged = ecount <= kStageCap;
+    __syncthreads();   // the previous item's readers are done with the LDS copy
+    if (staged) {
+      for (int i = (int)tid; i < ecount; i += kGatherThreads) s_idx[i] = j.idx[ebase + i];
+      for (uint32_t i = tid; i <= rend - r0; i += kGatherThreads) s_ptr[i] = j.ptr[r0 + i] - ebase;
     }
-    if (r >= nrows) continue;
-    const uint32_t jr = contiguous ? r : j.csr_map[r];
-    if (jr >= j.csr_rows) continue;
-    const uint32_t ob = j.out_map ? (uint32_t)j.out_map[r] : jr;
-    const uint64_t off0 = (uint64_t)slice * W + lane * 16u;
-    uint8_t *out = j.dst + (uint64_t)ob * j.dst_stride + off0;
-    bool valid[CH];
+    __syncthreads();
+  }
+  if (r >= nrows) return;
+  const uint32_t jr = contiguous ? r : j.csr_map[r];
+  if (jr >= j.csr_rows) return;
+  const uint32_t ob = j.out_map ? (uint32_t)j.out_map[r] : jr;
+  const uint64_t off0 = (uint64_t)slice * W + lane * 16u;
+  uint8_t *out = j.dst + (uint64_t)ob * j.dst_stride + off0;
+  bool valid[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) valid[c] = off0 + (uint64_t)c * STEP < j.t;
-    v4u acc[CH];
+  for (int c = 0; c < CH; ++c) valid[c] = off0 + (uint64_t)c * STEP < j.t;
+  v4u acc[CH];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] = v4u{0u, 0u, 0u, 0u};
-    if (j.row_ok && j.row_ok[r] == 0) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (valid[c]) st16<NT>(out + c * STEP, acc[c]);
-      continue;
-    }
-    if (j.accumulate) {
-#pragma unroll
-      for (int c = 0; c < CH; ++c)
-        if (valid[c]) acc[c] = ld16(out + c * STEP);
-    }
-    const uint8_t *src = j.src + off0;
-    if (staged)
-      gather_row<CH, STEP>(acc, valid, s_idx, s_ptr[sub], s_ptr[sub + 1], src, j.src_stride);
-    else
-      gather_row<CH, STEP>(acc, valid, j.idx, j.ptr[jr], j.ptr[jr + 1], src, j.src_stride);
-    if (j.seg_atomic && j.seg_atomic[r]) {
-      // one of several segments of a long row: XOR into the zeroed row
-#pragma unroll
-      for (int c = 0; c < CH; ++c) {
-        if (!valid[c]) continue;
-        unsigned long long *q = reinterpret_cast<unsigned long long *>(out + c * STEP);
-        atomicXor(q, ((unsigned long long)acc[c].y << 32) | acc[c].x);
-        atomicXor(q + 1, ((unsigned long long)acc[c].w << 32) | acc[c].z);
-      }
-      continue;
-    }
+  for (int c = 0; c < CH; ++c) acc[c] = v4u{0u, 0u, 0u, 0u};
+  if (j.row_ok && j.row_ok[r] == 0) {
 #pragma unroll
     for (int c = 0; c < CH; ++c)
       if (valid[c]) st16<NT>(out + c * STEP, acc[c]);
+    return;
+  }
+  if (j.accumulate) {
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      if (valid[c]) acc[c] = ld16(out + c * STEP);
+  }
+  const uint8_t *src = j.src + off0;
+  if (staged)
+    gather_row<CH, STEP>(acc, valid, s_idx, s_ptr[sub], s_ptr[sub + 1], src, j.src_stride);
+  else
+    gather_row<CH, STEP>(acc, valid, j.idx, j.ptr[jr], j.ptr[jr + 1], src, j.src_stride);
+  if (j.seg_atomic && j.seg_atomic[r]) {
+    // one of several segments of a long row: XOR into the zeroed row
+#pragma unroll
+    for (int c = 0; c < CH; ++c) {
+      if (!valid[c]) continue;
+      unsigned long long *q = reinterpret_cast<unsigned long long *>(out + c * STEP);
+      atomicXor(q, ((unsigned long long)acc[c].y << 32) | acc[c].x);
+      atomicXor(q + 1, ((unsigned long long)acc[c].w << 32) | acc[c].z);
+    }
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < CH; ++c)
+    if (valid[c]) st16<NT>(out + c * STEP, acc[c]);
+}
+
+__device__ __forceinline__ uint32_t live_rows(const GatherJob &j) {
+  uint32_t nrows = j.nrows;
+  if (j.nrows_dev) nrows = min(nrows, (uint32_t)max(*j.nrows_dev, 0));
+  return nrows;
+}
+
+template <int LPR, int CH, bool NT>
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uint32_t nslices,
+                                                                 uint32_t remap) {
+  constexpr uint32_t RPB = kGatherThreads / LPR;
+  __shared__ int32_t s_ptr[RPB + 1];
+  __shared__ int32_t s_idx[kStageCap];
+  if (j.skip_flag && *j.skip_flag) return;
+  const uint32_t nrows = live_rows(j);
+  const uint32_t ntiles = (nrows + RPB - 1) / RPB;
+  const uint64_t nitems = (uint64_t)ntiles * nslices;
+  const uint32_t vb = remap ? xcd_remap(blockIdx.x, gridDim.x) : blockIdx.x;
+  for (uint64_t item = vb; item < nitems; item += gridDim.x)
+    gather_item<LPR, CH, NT>(j, nrows, ntiles, item, s_ptr, s_idx);
+}
+
+// Persistent gather over the items of many jobs (a batch): the item space is
+// the concatenation of every job's (slice, tile) items (prefix[] holds the
+// running counts, computed with each job's row-count bound).  Workgroups
+// stride over it; XCD-aware numbering keeps each XCD on a contiguous window,
+// so concurrent items share a job and a slice.
+template <int LPR, int CH, bool NT>
+__global__ __launch_bounds__(kGatherThreads) void gather_batch_kernel(const GatherJob *jobs,
+                                                                       const unsigned long long *prefix,
+                                                                       uint32_t njobs) {
+  constexpr uint32_t RPB = kGatherThreads / LPR;
+  constexpr uint32_t W = LPR * 16 * CH;
+  __shared__ int32_t s_ptr[RPB + 1];
+  __shared__ int32_t s_idx[kStageCap];
+  const unsigned long long total = prefix[njobs];
+  const uint32_t vb = xcd_remap(blockIdx.x, gridDim.x);
+  uint32_t jb = 0;
+  // first job: binary search; later items only move forward
+  {
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (prefix[mid] <= vb) lo = mid; else hi = mid;
+    }
+    jb = lo;
+  }
+  for (unsigned long long item = vb; item < total; item += gridDim.x) {
+    while (jb + 1 < njobs && prefix[jb + 1] <= item) ++jb;
+    const GatherJob &j = jobs[jb];
+    if (j.skip_flag && *j.skip_flag) continue;
+    const uint32_t ntiles = (j.nrows + RPB - 1) / RPB;   // decomposition uses the bound
+    (void)W;
+    gather_item<LPR, CH, NT>(j, live_rows(j), ntiles, item - prefix[jb], s_ptr, s_idx);
   }
 }
 
@@ -302,7 +351,7 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
 }
 
 template <bool LDS>
-__global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
+__device__ __forceinline__ void peel_body(const PeelJob &J) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_nA, s_nB, s_nD;
   if (J.skip_flag && *J.skip_flag) return;
@@ -430,6 +479,17 @@ __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
   }
 }
 
+template <bool LDS>
+__global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
+  peel_body<LDS>(J);
+}
+
+// one workgroup per stripe of a batch
+template <bool LDS>
+__global__ __launch_bounds__(kPeelThreads) void peel_batch_kernel(const PeelJob *jobs) {
+  peel_body<LDS>(jobs[blockIdx.x]);
+}
+
 // ---------------------------------------------------------------------------
 // replay program and schedule replay
 // ---------------------------------------------------------------------------
@@ -441,7 +501,7 @@ constexpr int kReplayThreads = 1024;
 // do not fit the graph are dropped; meta = {nR, L, entries, usable}.
 // Loads are hoisted in groups of eight pairs so each thread keeps several
 // dependent chains (row -> row pointer -> neighbour ids) in flight.
-__global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) {
+__device__ __forceinline__ void prog_body(const ProgJob &P) {
   __shared__ uint32_t scan_sh[kPlanThreads / 64 + 1];
   constexpr int G = 8;
   const int tid = threadIdx.x;
@@ -535,6 +595,10 @@ __global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) {
     P.meta[3] = fits && nused == (uint32_t)nR ? 1 : 0;
   }
 }
+
+__global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) { prog_body(P); }
+
+__global__ __launch_bounds__(kPlanThreads) void prog_batch_kernel(const ProgJob *jobs) { prog_body(jobs[blockIdx.x]); }
 
 // One workgroup per CU walks byte slices of T = 16 LPS bytes.  For each slice
 // the k x T slab of x lives in LDS: x_f starts as c_{g(f)} (zero for the
@@ -649,14 +713,14 @@ __global__ __launch_bounds__(kReplayThreads) void replay_lds_kernel(ReplayJob J,
 template <int LPS, class IT>
 __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT *lp, const IT *pf, const IT *pg,
                                                    const IT *poff, const IT *pidx, int L, int nR,
-                                                   uint32_t nslices, uint32_t vb) {
+                                                   uint32_t nslices, uint32_t vb, uint32_t stride) {
   constexpr int NS = kReplayThreads / LPS;
   constexpr int MP = 4;                 // pairs per thread whose coded block is prefetched
   constexpr uint32_t W = LPS * 16;
   const uint32_t lane = threadIdx.x % LPS, sym = threadIdx.x / LPS;
   const uint32_t k = J.k;
   const v4u zero = {0u, 0u, 0u, 0u};
-  for (uint32_t slice = vb; slice < nslices; slice += gridDim.x) {
+  for (uint32_t slice = vb; slice < nslices; slice += stride) {
     const uint64_t off = (uint64_t)slice * W + lane * 16u;
     const bool live = off < J.t;
     // coded blocks of the first MP pairs of a level are loaded while the
@@ -718,14 +782,14 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
 }
 
 template <int LPS>
-__global__ __launch_bounds__(kReplayThreads) void replay_wide_kernel(ReplayJob J, ProgJob P, uint32_t nslices,
-                                                                    uint32_t lds_bytes, uint32_t prog_lds) {
+__device__ __forceinline__ void replay_wide_body(const ReplayJob &J, const ProgJob &P, uint32_t nslices,
+                                                 uint32_t lds_bytes, uint32_t prog_lds, uint32_t vb,
+                                                 uint32_t stride) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   if (J.skip_flag && *J.skip_flag) return;
   if (!P.meta[3]) return;
   const uint32_t k = J.k;
   const int nR = P.meta[0], L = P.meta[1], total = P.meta[2];
-  const uint32_t vb = xcd_remap(blockIdx.x, gridDim.x);
   const size_t prog16 = 2ull * ((size_t)(L + 1) + 2ull * nR + (size_t)(nR + 1) + (size_t)total);
   if (prog_lds && k <= 65535 && J.n <= 65535 && total <= 65535 && prog16 <= lds_bytes) {
     uint16_t *q = reinterpret_cast<uint16_t *>(smem);
@@ -742,10 +806,34 @@ __global__ __launch_bounds__(kReplayThreads) void replay_wide_kernel(ReplayJob J
     for (int i = threadIdx.x; i <= nR; i += kReplayThreads) poff[i] = (uint16_t)P.poff[i];
     for (int i = threadIdx.x; i < total; i += kReplayThreads) pidx[i] = (uint16_t)P.pidx[i];
     __syncthreads();
-    replay_wide_slices<LPS, uint16_t>(J, lp, pf, pg, poff, pidx, L, nR, nslices, vb);
+    replay_wide_slices<LPS, uint16_t>(J, lp, pf, pg, poff, pidx, L, nR, nslices, vb, stride);
   } else {
-    replay_wide_slices<LPS, int32_t>(J, J.level_ptr, J.dp_f, J.dp_g, P.poff, P.pidx, L, nR, nslices, vb);
+    replay_wide_slices<LPS, int32_t>(J, J.level_ptr, J.dp_f, J.dp_g, P.poff, P.pidx, L, nR, nslices, vb, stride);
   }
+}
+
+template <int LPS>
+__global__ __launch_bounds__(kReplayThreads) void replay_wide_kernel(ReplayJob J, ProgJob P, uint32_t nslices,
+                                                                    uint32_t lds_bytes, uint32_t prog_lds) {
+  replay_wide_body<LPS>(J, P, nslices, lds_bytes, prog_lds, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Replays of a batch: stripe i owns workgroups [wg_prefix[i], wg_prefix[i+1])
+// which stride over its slices.
+template <int LPS>
+__global__ __launch_bounds__(kReplayThreads) void replay_batch_kernel(const ReplayJob *rj, const ProgJob *pj,
+                                                                     const uint32_t *wg_prefix, uint32_t nitems,
+                                                                     uint32_t lds_bytes, uint32_t prog_lds) {
+  const uint32_t b = blockIdx.x;
+  uint32_t lo = 0, hi = nitems;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (wg_prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  const ReplayJob &J = rj[lo];
+  const uint32_t w = 16u * LPS;
+  const uint32_t nslices = (uint32_t)((J.t + w - 1) / w);
+  replay_wide_body<LPS>(J, pj[lo], nslices, lds_bytes, prog_lds, b - wg_prefix[lo], wg_prefix[lo + 1] - wg_prefix[lo]);
 }
 
 // Fallback for slabs too large for LDS: one workgroup per byte slice reads
@@ -790,7 +878,7 @@ __global__ __launch_bounds__(kReplayThreads) void replay_kernel(ReplayJob J) {
 // repair and update planning
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(kPlanThreads) void repair_prep_kernel(RepairPrepJob J, int default_ok) {
+__device__ __forceinline__ void repair_prep_body(const RepairPrepJob &J, int default_ok) {
   __shared__ int s_bad;
   const int tid = threadIdx.x;
   const uint32_t nw = (J.n + 31) / 32;
@@ -820,6 +908,14 @@ __global__ __launch_bounds__(kPlanThreads) void repair_prep_kernel(RepairPrepJob
   }
 }
 
+__global__ __launch_bounds__(kPlanThreads) void repair_prep_kernel(RepairPrepJob J, int default_ok) {
+  repair_prep_body(J, default_ok);
+}
+
+__global__ __launch_bounds__(kPlanThreads) void repair_prep_batch_kernel(const RepairPrepJob *jobs) {
+  repair_prep_body(jobs[blockIdx.x], jobs[blockIdx.x].erased2 ? 0 : 1);
+}
+
 __global__ __launch_bounds__(kPlanThreads) void repair_check_kernel(RepairCheckJob J) {
   __shared__ int s_fail;
   const int tid = threadIdx.x;
@@ -841,7 +937,7 @@ __global__ __launch_bounds__(kPlanThreads) void repair_check_kernel(RepairCheckJ
   }
 }
 
-__global__ __launch_bounds__(kPlanThreads) void update_plan_kernel(UpdatePlanJob J) {
+__device__ __forceinline__ void update_plan_body(const UpdatePlanJob &J) {
   __shared__ uint32_t scan_sh[kPlanThreads / 64 + 1];
   __shared__ int s_bad;
   const int tid = threadIdx.x;
@@ -916,6 +1012,12 @@ __global__ __launch_bounds__(kPlanThreads) void update_plan_kernel(UpdatePlanJob
   }
 }
 
+__global__ __launch_bounds__(kPlanThreads) void update_plan_kernel(UpdatePlanJob J) { update_plan_body(J); }
+
+__global__ __launch_bounds__(kPlanThreads) void update_plan_batch_kernel(const UpdatePlanJob *jobs) {
+  update_plan_body(jobs[blockIdx.x]);
+}
+
 constexpr int kDeltaThreads = 256;
 
 __global__ __launch_bounds__(kDeltaThreads) void update_delta_kernel(UpdateDeltaJob J, uint32_t nslices) {
@@ -928,6 +1030,38 @@ __global__ __launch_bounds__(kDeltaThreads) void update_delta_kernel(UpdateDelta
   const v4u ov = ld16(xi);
   *reinterpret_cast<v4u *>(J.delta + (uint64_t)u * J.t + off) = ov ^ nv;
   *reinterpret_cast<v4u *>(xi) = nv;
+}
+
+// delta pass of a batch of updates: job i owns workgroups [prefix[i], prefix[i+1])
+__global__ __launch_bounds__(kDeltaThreads) void update_delta_batch_kernel(const UpdateDeltaJob *jobs,
+                                                                           const uint32_t *prefix, uint32_t njobs) {
+  const uint32_t b = blockIdx.x;
+  uint32_t lo = 0, hi = njobs;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  const UpdateDeltaJob &J = jobs[lo];
+  if (J.flag[0]) return;
+  const uint32_t nslices = (uint32_t)((J.t + kDeltaThreads * 16 - 1) / (kDeltaThreads * 16));
+  const uint32_t local = b - prefix[lo];
+  const uint32_t u = local / nslices, sl = local % nslices;
+  const uint64_t off = (uint64_t)sl * (kDeltaThreads * 16) + threadIdx.x * 16u;
+  if (u >= J.n_ids || off >= J.t) return;
+  uint8_t *xi = J.x + (uint64_t)J.ids[u] * J.t + off;
+  const v4u nv = ld16(J.new_blocks + (uint64_t)u * J.t + off);
+  const v4u ov = ld16(xi);
+  *reinterpret_cast<v4u *>(J.delta + (uint64_t)u * J.t + off) = ov ^ nv;
+  *reinterpret_cast<v4u *>(xi) = nv;
+}
+
+// zero the listed blocks of a batch: entry i is (base, t, row)
+__global__ __launch_bounds__(256) void zero_batch_kernel(const ZeroEntry *rows, uint32_t nrows, uint32_t chunks) {
+  const uint32_t r = blockIdx.x / chunks, ch = blockIdx.x % chunks;
+  if (r >= nrows) return;
+  const ZeroEntry z = rows[r];
+  const uint64_t off = (uint64_t)ch * 4096 + threadIdx.x * 16u;
+  if (off < z.t) *reinterpret_cast<v4u *>(z.base + (uint64_t)z.row * z.t + off) = v4u{0u, 0u, 0u, 0u};
 }
 
 }  // namespace
@@ -1163,6 +1297,115 @@ fs_status launch_update_delta(const UpdateDeltaJob &job, hipStream_t s) {
   if (grid == 0) return FS_OK;
   hipLaunchKernelGGL(update_delta_kernel, dim3((uint32_t)grid), dim3(kDeltaThreads), 0, s, job, nslices);
   return hip_check(hipGetLastError(), "update delta launch");
+}
+
+}  // namespace fs
+
+// ---------------------------------------------------------------------------
+// batched launchers
+// ---------------------------------------------------------------------------
+namespace fs {
+
+template <int LPR, int CH>
+static hipError_t run_gather_batch(const GatherJob *jobs, const unsigned long long *prefix, uint32_t njobs,
+                                   bool nt, uint32_t grid, hipStream_t s) {
+  if (nt)
+    hipLaunchKernelGGL((gather_batch_kernel<LPR, CH, true>), dim3(grid), dim3(kGatherThreads), 0, s, jobs, prefix,
+                       njobs);
+  else
+    hipLaunchKernelGGL((gather_batch_kernel<LPR, CH, false>), dim3(grid), dim3(kGatherThreads), 0, s, jobs, prefix,
+                       njobs);
+  return hipGetLastError();
+}
+
+fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long *d_prefix, uint32_t njobs,
+                              const fs_tune &tune, uint32_t grid, hipStream_t s) {
+  if (njobs == 0 || grid == 0) return FS_OK;
+  const bool nt = tune.nt_store != 0;
+  hipError_t e;
+  switch (tune.lanes_per_row * 10 + tune.chunks) {
+    case 161: e = run_gather_batch<16, 1>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 162: e = run_gather_batch<16, 2>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 164: e = run_gather_batch<16, 4>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 321: e = run_gather_batch<32, 1>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 322: e = run_gather_batch<32, 2>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 324: e = run_gather_batch<32, 4>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 641: e = run_gather_batch<64, 1>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 642: e = run_gather_batch<64, 2>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 644: e = run_gather_batch<64, 4>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    default: return fail(FS_ERR_INVALID, "unsupported gather tuning");
+  }
+  return hip_check(e, "batched gather launch");
+}
+
+fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, bool lds, size_t lds_bytes, hipStream_t s) {
+  if (njobs == 0) return FS_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  if (lds) {
+    static bool done[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<true>), dev,
+                device_info(dev).max_lds_per_block - 64, done);
+    hipLaunchKernelGGL(peel_batch_kernel<true>, dim3(njobs), dim3(kPeelThreads), lds_bytes, s, d_jobs);
+  } else {
+    hipLaunchKernelGGL(peel_batch_kernel<false>, dim3(njobs), dim3(kPeelThreads), 0, s, d_jobs);
+  }
+  return hip_check(hipGetLastError(), "batched peel launch");
+}
+
+fs_status launch_prog_batch(const ProgJob *d_jobs, uint32_t njobs, hipStream_t s) {
+  if (njobs == 0) return FS_OK;
+  hipLaunchKernelGGL(prog_batch_kernel, dim3(njobs), dim3(kPlanThreads), 0, s, d_jobs);
+  return hip_check(hipGetLastError(), "batched program launch");
+}
+
+fs_status launch_replay_batch(const ReplayJob *d_rj, const ProgJob *d_pj, const uint32_t *d_wg_prefix,
+                              uint32_t nitems, uint32_t total_wg, hipStream_t s) {
+  if (nitems == 0 || total_wg == 0) return FS_OK;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int budget = device_info(dev).max_lds_per_block;
+  static bool done[64] = {false};
+  set_max_lds(reinterpret_cast<const void *>(&replay_batch_kernel<kBatchReplayLanes>), dev, budget, done);
+  hipLaunchKernelGGL(replay_batch_kernel<kBatchReplayLanes>, dim3(total_wg), dim3(kReplayThreads), budget, s, d_rj,
+                     d_pj, d_wg_prefix, nitems, (uint32_t)budget, tune_snapshot().replay_prog_global ? 0u : 1u);
+  return hip_check(hipGetLastError(), "batched replay launch");
+}
+
+fs_status launch_repair_prep_batch(const RepairPrepJob *d_jobs, uint32_t njobs, hipStream_t s) {
+  if (njobs == 0) return FS_OK;
+  hipLaunchKernelGGL(repair_prep_batch_kernel, dim3(njobs), dim3(kPlanThreads), 0, s, d_jobs);
+  return hip_check(hipGetLastError(), "batched repair prep launch");
+}
+
+fs_status launch_update_plan_batch(const UpdatePlanJob *d_jobs, uint32_t njobs, hipStream_t s) {
+  if (njobs == 0) return FS_OK;
+  hipLaunchKernelGGL(update_plan_batch_kernel, dim3(njobs), dim3(kPlanThreads), 0, s, d_jobs);
+  return hip_check(hipGetLastError(), "batched update plan launch");
+}
+
+fs_status launch_update_delta_batch(const UpdateDeltaJob *d_jobs, const uint32_t *d_prefix, uint32_t njobs,
+                                    uint32_t total_wg, hipStream_t s) {
+  if (njobs == 0 || total_wg == 0) return FS_OK;
+  hipLaunchKernelGGL(update_delta_batch_kernel, dim3(total_wg), dim3(kDeltaThreads), 0, s, d_jobs, d_prefix, njobs);
+  return hip_check(hipGetLastError(), "batched update delta launch");
+}
+
+void prepare_batch_kernels() {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int budget = device_info(dev).max_lds_per_block;
+  static bool d1[64] = {false}, d2[64] = {false};
+  set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<true>), dev, budget - 64, d1);
+  set_max_lds(reinterpret_cast<const void *>(&replay_batch_kernel<kBatchReplayLanes>), dev, budget, d2);
+}
+
+fs_status launch_zero_batch(const ZeroEntry *d_rows, uint32_t nrows, uint64_t max_t, hipStream_t s) {
+  const uint32_t chunks = (uint32_t)((max_t + 4095) / 4096);
+  const uint64_t grid = (uint64_t)nrows * chunks;
+  if (grid == 0) return FS_OK;
+  hipLaunchKernelGGL(zero_batch_kernel, dim3((uint32_t)grid), dim3(256), 0, s, d_rows, nrows, chunks);
+  return hip_check(hipGetLastError(), "batched zero launch");
 }
 
 }  // namespace fs

@@ -1,0 +1,620 @@
+// Batches of stripes: descriptors in device memory, one workspace, a captured
+// hipGraph, and an autotuner for the gather tiling.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "fs_internal.h"
+
+using namespace fs;
+
+struct fs_plan {
+  int device = -1;
+  uint32_t flags = 0;
+  std::vector<fs_work> items;
+  fs_tune tune{};
+  uint32_t tune_source = 0;
+  double tuned_ms = 0.0;
+
+  // host copies of the descriptor arrays
+  std::vector<GatherJob> gjobs;          // encode, repair and update-accumulate jobs
+  std::vector<uint8_t> gjob_accumulate;  // 1 for update jobs (not run while tuning)
+  std::vector<unsigned long long> gprefix;
+  std::vector<PeelJob> peels;
+  std::vector<ProgJob> progs;
+  std::vector<ReplayJob> replays;
+  std::vector<uint32_t> rprefix;
+  std::vector<RepairPrepJob> rpreps;
+  std::vector<UpdatePlanJob> uplans;
+  std::vector<UpdateDeltaJob> udeltas;
+  std::vector<uint32_t> uprefix;
+  std::vector<ZeroEntry> zeros;
+  uint64_t zero_max_t = 0;
+  bool peel_lds = true;
+  size_t peel_lds_bytes = 0;
+  uint32_t gather_grid = 0;
+
+  // device memory
+  void *d_ws = nullptr;
+  size_t ws_bytes = 0;
+  void *d_desc = nullptr;
+  size_t desc_bytes = 0;
+  GatherJob *d_gjobs = nullptr;
+  unsigned long long *d_gprefix = nullptr;
+  PeelJob *d_peels = nullptr;
+  ProgJob *d_progs = nullptr;
+  ReplayJob *d_replays = nullptr;
+  uint32_t *d_rprefix = nullptr;
+  RepairPrepJob *d_rpreps = nullptr;
+  UpdatePlanJob *d_uplans = nullptr;
+  UpdateDeltaJob *d_udeltas = nullptr;
+  uint32_t *d_uprefix = nullptr;
+  ZeroEntry *d_zeros = nullptr;
+  // tuning runs: the gather jobs without the accumulating ones
+  GatherJob *d_tjobs = nullptr;
+  unsigned long long *d_tprefix = nullptr;
+  uint32_t n_tjobs = 0;
+
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+namespace {
+
+#define PL_TRY(expr)              \
+  do {                            \
+    fs_status _s = (expr);        \
+    if (_s != FS_OK) return _s;   \
+  } while (0)
+
+fs_status hip_ok(hipError_t e, const char *what) {
+  if (e == hipSuccess) return FS_OK;
+  return fail(FS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+fs_status check_item(const fs_work &w, uint32_t i) {
+  const std::string at = "item " + std::to_string(i) + ": ";
+  fs_status st = check_graph(w.graph);
+  if (st != FS_OK) return fail(st, at + fs_last_error());
+  if (w.reserved != 0) return fail(FS_ERR_INVALID, at + "reserved field must be 0");
+  if (w.t == 0 || (w.t & 15)) return fail(FS_ERR_ALIGN, at + "t must be a positive multiple of 16");
+  auto al = [&](const void *p, const char *name, bool need) -> fs_status {
+    if (!p) return need ? fail(FS_ERR_INVALID, at + name + " is null") : FS_OK;
+    if (reinterpret_cast<uintptr_t>(p) & 15) return fail(FS_ERR_ALIGN, at + name + " is not 16-byte aligned");
+    return FS_OK;
+  };
+  switch (w.op) {
+    case FS_WORK_ENCODE:
+      PL_TRY(al(w.x, "x", true));
+      PL_TRY(al(w.c, "c", true));
+      return FS_OK;
+    case FS_WORK_DECODE:
+      PL_TRY(al(w.x, "x", true));
+      PL_TRY(al(w.c, "c", true));
+      if (!w.erased || !w.recovered) return fail(FS_ERR_INVALID, at + "erased and recovered must be non-null");
+      return FS_OK;
+    case FS_WORK_REPAIR:
+      if (!w.x) return fail(FS_ERR_UNSUPPORTED, at + "batched repair needs the resident inputs (x)");
+      PL_TRY(al(w.x, "x", true));
+      PL_TRY(al(w.c, "c", true));
+      if (!w.status || (w.n_ids && (!w.ids || !w.repaired)))
+        return fail(FS_ERR_INVALID, at + "ids, repaired and status must be non-null");
+      return FS_OK;
+    case FS_WORK_UPDATE:
+      PL_TRY(al(w.x, "x", true));
+      PL_TRY(al(w.c, "c", true));
+      if (w.n_ids) PL_TRY(al(w.new_blocks, "new_blocks", true));
+      if (!w.status || (w.n_ids && !w.ids)) return fail(FS_ERR_INVALID, at + "ids and status must be non-null");
+      return FS_OK;
+  }
+  return fail(FS_ERR_INVALID, at + "unknown op");
+}
+
+// Per item workspace carving (also used for sizing with base == nullptr).
+struct ItemWs {
+  DecodeBufs dec;
+  RepairBufs rep;
+  UpdateBufs upd;
+};
+
+void carve_item(Carver &cv, const fs_work &w, ItemWs &b) {
+  switch (w.op) {
+    case FS_WORK_DECODE: carve_decode(cv, w.graph, b.dec); break;
+    case FS_WORK_REPAIR: carve_repair(cv, w.graph, w.t, false, b.rep); break;
+    case FS_WORK_UPDATE: carve_update(cv, w.graph, w.t, w.n_ids, b.upd); break;
+    default: break;
+  }
+}
+
+uint64_t gather_items_of(const GatherJob &j, const fs_tune &tune) {
+  const uint32_t rpb = 256 / tune.lanes_per_row;
+  const uint64_t w = 16ull * tune.lanes_per_row * tune.chunks;
+  const uint64_t nslices = (j.t + w - 1) / w;
+  const uint64_t ntiles = (j.nrows + rpb - 1) / rpb;
+  return nslices * ntiles;
+}
+
+// Build every descriptor of the plan from its items (device pointers into the
+// items' buffers and into the plan workspace).
+void build_descriptors(fs_plan &P) {
+  P.gjobs.clear();
+  P.gjob_accumulate.clear();
+  P.peels.clear();
+  P.progs.clear();
+  P.replays.clear();
+  P.rprefix.assign(1, 0);
+  P.rpreps.clear();
+  P.uplans.clear();
+  P.udeltas.clear();
+  P.uprefix.assign(1, 0);
+  P.zeros.clear();
+  P.zero_max_t = 0;
+  P.peel_lds = true;
+  P.peel_lds_bytes = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t lds_budget = (size_t)device_info(dev).max_lds_per_block - 64;
+  Carver cv(P.d_ws);
+  for (const fs_work &w : P.items) {
+    const fs_graph *g = w.graph;
+    ItemWs b{};
+    carve_item(cv, w, b);
+    switch (w.op) {
+      case FS_WORK_ENCODE: {
+        for (int32_t row : g->heavy) P.zeros.push_back(ZeroEntry{static_cast<uint8_t *>(w.c), w.t, row});
+        if (!g->heavy.empty()) P.zero_max_t = std::max(P.zero_max_t, w.t);
+        P.gjobs.push_back(encode_job(g, w.x, w.c, w.t));
+        P.gjob_accumulate.push_back(0);
+        break;
+      }
+      case FS_WORK_DECODE: {
+        int32_t *status = w.status ? w.status : b.dec.sched.status;
+        PeelJob pj = peel_job(g, w.erased, w.maxit, w.recovered, status, b.dec.sched.level_ptr, b.dec.sched.dp_f,
+                              b.dec.sched.dp_g);
+        pj.acc = b.dec.peel.acc;
+        pj.best = b.dec.peel.best;
+        pj.front_a = b.dec.peel.front_a;
+        pj.front_b = b.dec.peel.front_b;
+        pj.dlist = b.dec.peel.dlist;
+        pj.mask = b.dec.peel.mask;
+        pj.decmask = b.dec.peel.decmask;
+        const size_t need = peel_lds_bytes(g->k, g->n);
+        if (g->max_deg >= 65536 || need > lds_budget) P.peel_lds = false;
+        P.peel_lds_bytes = std::max(P.peel_lds_bytes, need);
+        P.peels.push_back(pj);
+        ProgJob prog = b.dec.prog;
+        prog.status = status;
+        P.progs.push_back(prog);
+        P.replays.push_back(replay_job(g, w.c, w.x, w.t, status, b.dec.sched.level_ptr, b.dec.sched.dp_f,
+                                       b.dec.sched.dp_g));
+        const uint64_t wsl = 16ull * kBatchReplayLanes;
+        const uint64_t nslices = (w.t + wsl - 1) / wsl;
+        const uint32_t nwg = (uint32_t)((nslices + kBatchReplaySlicesPerWg - 1) / kBatchReplaySlicesPerWg);
+        P.rprefix.push_back(P.rprefix.back() + nwg);
+        break;
+      }
+      case FS_WORK_REPAIR: {
+        RepairPrepJob rp{};
+        rp.n = g->n;
+        rp.k = g->k;
+        rp.lost = w.ids;
+        rp.n_lost = w.n_ids;
+        rp.seen = b.rep.seen;
+        rp.flag = b.rep.flag;
+        rp.repaired = w.repaired;
+        rp.status = w.status;
+        P.rpreps.push_back(rp);
+        if (w.n_ids) {
+          GatherJob gj{};
+          gj.src = static_cast<const uint8_t *>(w.x);
+          gj.src_stride = w.t;
+          gj.dst = static_cast<uint8_t *>(w.c);
+          gj.dst_stride = w.t;
+          gj.ptr = g->d_row_ptr;
+          gj.idx = g->d_col;
+          gj.csr_map = w.ids;
+          gj.out_map = reinterpret_cast<const int32_t *>(w.ids);
+          gj.skip_flag = b.rep.flag;
+          gj.nrows = w.n_ids;
+          gj.csr_rows = g->n;
+          gj.t = w.t;
+          P.gjobs.push_back(gj);
+          P.gjob_accumulate.push_back(0);
+        }
+        break;
+      }
+      case FS_WORK_UPDATE: {
+        UpdatePlanJob up{};
+        up.k = g->k;
+        up.n = g->n;
+        up.col_ptr = g->d_col_ptr;
+        up.rowidx = g->d_rowidx;
+        up.ids = w.ids;
+        up.n_ids = w.n_ids;
+        up.seen = b.upd.seen;
+        up.cnt = b.upd.cnt;
+        up.arow = b.upd.arow;
+        up.aptr = b.upd.aptr;
+        up.asrc = b.upd.asrc;
+        up.n_aff = b.upd.n_aff;
+        up.flag = b.upd.flag;
+        up.status = w.status;
+        P.uplans.push_back(up);
+        UpdateDeltaJob dj{};
+        dj.x = static_cast<uint8_t *>(w.x);
+        dj.new_blocks = static_cast<const uint8_t *>(w.new_blocks);
+        dj.delta = b.upd.delta;
+        dj.ids = w.ids;
+        dj.n_ids = w.n_ids;
+        dj.t = w.t;
+        dj.flag = b.upd.flag;
+        P.udeltas.push_back(dj);
+        const uint32_t per = (uint32_t)((w.t + kDeltaBytesPerWg - 1) / kDeltaBytesPerWg);
+        P.uprefix.push_back(P.uprefix.back() + per * w.n_ids);
+        if (w.n_ids && b.upd.max_rows) {
+          GatherJob gj{};
+          gj.src = b.upd.delta;
+          gj.src_stride = w.t;
+          gj.dst = static_cast<uint8_t *>(w.c);
+          gj.dst_stride = w.t;
+          gj.ptr = b.upd.aptr;
+          gj.idx = b.upd.asrc;
+          gj.out_map = b.upd.arow;
+          gj.nrows_dev = b.upd.n_aff;
+          gj.skip_flag = b.upd.flag;
+          gj.nrows = b.upd.max_rows;
+          gj.csr_rows = b.upd.max_rows;
+          gj.t = w.t;
+          gj.accumulate = 1;
+          P.gjobs.push_back(gj);
+          P.gjob_accumulate.push_back(1);
+        }
+        break;
+      }
+      default: break;
+    }
+  }
+  if (!P.peel_lds) P.peel_lds_bytes = 0;
+}
+
+void gather_prefix(const std::vector<GatherJob> &jobs, const fs_tune &tune, std::vector<unsigned long long> &pre) {
+  pre.assign(1, 0);
+  for (const GatherJob &j : jobs) pre.push_back(pre.back() + gather_items_of(j, tune));
+}
+
+template <class T>
+T *place(uint8_t *base, size_t &off, size_t count) {
+  off = (off + 255) & ~size_t(255);
+  T *p = reinterpret_cast<T *>(base + off);
+  off += std::max<size_t>(count, 1) * sizeof(T);
+  return p;
+}
+
+// Lay out every descriptor array in one device buffer (sizes are fixed for
+// the life of the plan) and copy the host arrays into it.
+fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate) {
+  std::vector<GatherJob> tjobs;
+  for (size_t i = 0; i < P.gjobs.size(); ++i)
+    if (!P.gjob_accumulate[i]) tjobs.push_back(P.gjobs[i]);
+  std::vector<unsigned long long> tprefix;
+  gather_prefix(tjobs, P.tune, tprefix);
+  gather_prefix(P.gjobs, P.tune, P.gprefix);
+  size_t off = 0;
+  uint8_t *base = static_cast<uint8_t *>(P.d_desc);
+  P.d_gjobs = place<GatherJob>(base, off, P.gjobs.size());
+  P.d_gprefix = place<unsigned long long>(base, off, P.gprefix.size());
+  P.d_peels = place<PeelJob>(base, off, P.peels.size());
+  P.d_progs = place<ProgJob>(base, off, P.progs.size());
+  P.d_replays = place<ReplayJob>(base, off, P.replays.size());
+  P.d_rprefix = place<uint32_t>(base, off, P.rprefix.size());
+  P.d_rpreps = place<RepairPrepJob>(base, off, P.rpreps.size());
+  P.d_uplans = place<UpdatePlanJob>(base, off, P.uplans.size());
+  P.d_udeltas = place<UpdateDeltaJob>(base, off, P.udeltas.size());
+  P.d_uprefix = place<uint32_t>(base, off, P.uprefix.size());
+  P.d_zeros = place<ZeroEntry>(base, off, P.zeros.size());
+  P.d_tjobs = place<GatherJob>(base, off, tjobs.size());
+  P.d_tprefix = place<unsigned long long>(base, off, tprefix.size());
+  P.n_tjobs = (uint32_t)tjobs.size();
+  off = (off + 255) & ~size_t(255);
+  if (allocate) {
+    P.desc_bytes = off;
+    return FS_OK;   // caller allocates desc_bytes and calls again
+  }
+  if (off > P.desc_bytes) return fail(FS_ERR_INVALID, "descriptor layout changed");
+  auto put = [&](void *dst, const void *src, size_t bytes) -> fs_status {
+    if (!bytes) return FS_OK;
+    return hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "descriptor upload");
+  };
+  PL_TRY(put(P.d_gjobs, P.gjobs.data(), P.gjobs.size() * sizeof(GatherJob)));
+  PL_TRY(put(P.d_gprefix, P.gprefix.data(), P.gprefix.size() * sizeof(unsigned long long)));
+  PL_TRY(put(P.d_peels, P.peels.data(), P.peels.size() * sizeof(PeelJob)));
+  PL_TRY(put(P.d_progs, P.progs.data(), P.progs.size() * sizeof(ProgJob)));
+  PL_TRY(put(P.d_replays, P.replays.data(), P.replays.size() * sizeof(ReplayJob)));
+  PL_TRY(put(P.d_rprefix, P.rprefix.data(), P.rprefix.size() * sizeof(uint32_t)));
+  PL_TRY(put(P.d_rpreps, P.rpreps.data(), P.rpreps.size() * sizeof(RepairPrepJob)));
+  PL_TRY(put(P.d_uplans, P.uplans.data(), P.uplans.size() * sizeof(UpdatePlanJob)));
+  PL_TRY(put(P.d_udeltas, P.udeltas.data(), P.udeltas.size() * sizeof(UpdateDeltaJob)));
+  PL_TRY(put(P.d_uprefix, P.uprefix.data(), P.uprefix.size() * sizeof(uint32_t)));
+  PL_TRY(put(P.d_zeros, P.zeros.data(), P.zeros.size() * sizeof(ZeroEntry)));
+  PL_TRY(put(P.d_tjobs, tjobs.data(), tjobs.size() * sizeof(GatherJob)));
+  PL_TRY(put(P.d_tprefix, tprefix.data(), tprefix.size() * sizeof(unsigned long long)));
+  return FS_OK;
+}
+
+uint32_t gather_grid_for(uint64_t items) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const uint64_t cap = (uint64_t)device_info(dev).cu_count * 8;   // persistent: ~8 workgroups per CU
+  return (uint32_t)std::min<uint64_t>(items, cap);
+}
+
+// The whole plan as launches on s (branch A on P.side when it exists).
+fs_status enqueue(fs_plan &P, hipStream_t s) {
+  const bool fork = P.side != nullptr && !P.peels.empty();
+  hipStream_t a = fork ? P.side : s;
+  if (fork) {
+    PL_TRY(hip_ok(hipEventRecord(P.fork, s), "fork"));
+    PL_TRY(hip_ok(hipStreamWaitEvent(P.side, P.fork, 0), "fork wait"));
+  }
+  // branch A: decodes (schedule, program, replay)
+  PL_TRY(launch_peel_batch(P.d_peels, (uint32_t)P.peels.size(), P.peel_lds, P.peel_lds_bytes, a));
+  PL_TRY(launch_prog_batch(P.d_progs, (uint32_t)P.progs.size(), a));
+  PL_TRY(launch_replay_batch(P.d_replays, P.d_progs, P.d_rprefix, (uint32_t)P.replays.size(), P.rprefix.back(), a));
+  // branch B: zeroing, checks, update planning, then the persistent gather
+  PL_TRY(launch_zero_batch(P.d_zeros, (uint32_t)P.zeros.size(), P.zero_max_t, s));
+  PL_TRY(launch_repair_prep_batch(P.d_rpreps, (uint32_t)P.rpreps.size(), s));
+  PL_TRY(launch_update_plan_batch(P.d_uplans, (uint32_t)P.uplans.size(), s));
+  PL_TRY(launch_update_delta_batch(P.d_udeltas, P.d_uprefix, (uint32_t)P.udeltas.size(), P.uprefix.back(), s));
+  PL_TRY(launch_gather_batch(P.d_gjobs, P.d_gprefix, (uint32_t)P.gjobs.size(), P.tune, P.gather_grid, s));
+  if (fork) {
+    PL_TRY(hip_ok(hipEventRecord(P.join, P.side), "join"));
+    PL_TRY(hip_ok(hipStreamWaitEvent(s, P.join, 0), "join wait"));
+  }
+  return FS_OK;
+}
+
+std::string shape_key(const fs_plan &P) {
+  // the plan's shape: per item op, k, n, nnz, t (arch first)
+  std::ostringstream os;
+  os << "gfx950";
+  uint64_t h = 1469598103934665603ull;
+  for (const fs_work &w : P.items) {
+    const uint64_t v[5] = {w.op, w.graph->k, w.graph->n, w.graph->nnz, w.t};
+    for (uint64_t x : v) {
+      h ^= x;
+      h *= 1099511628211ull;
+    }
+  }
+  os << ":" << P.items.size() << ":" << std::hex << h;
+  return os.str();
+}
+
+bool cache_lookup(const char *path, const std::string &key, fs_tune &t) {
+  if (!path) return false;
+  std::ifstream f(path);
+  std::string k;
+  uint32_t lpr, ch, rm, nt;
+  bool found = false;
+  while (f >> k >> lpr >> ch >> rm >> nt) {
+    if (k == key) {
+      t.lanes_per_row = lpr;
+      t.chunks = ch;
+      t.xcd_remap = rm;
+      t.nt_store = nt;
+      found = true;   // the last entry wins
+    }
+  }
+  return found;
+}
+
+void cache_store(const char *path, const std::string &key, const fs_tune &t) {
+  if (!path) return;
+  std::ofstream f(path, std::ios::app);
+  f << key << " " << t.lanes_per_row << " " << t.chunks << " " << t.xcd_remap << " " << t.nt_store << "\n";
+}
+
+// Time the persistent gather (without the accumulating jobs) for a few
+// tilings and keep the fastest.
+fs_status autotune(fs_plan &P, hipStream_t s) {
+  if (P.n_tjobs == 0) return FS_OK;
+  static const uint32_t cand[][2] = {{16, 2}, {32, 2}, {32, 4}, {64, 1}, {64, 2}, {64, 4}};
+  hipEvent_t e0, e1;
+  PL_TRY(hip_ok(hipEventCreate(&e0), "event"));
+  PL_TRY(hip_ok(hipEventCreate(&e1), "event"));
+  float best = 1e30f;
+  fs_tune best_t = P.tune;
+  std::vector<GatherJob> tjobs;
+  for (size_t i = 0; i < P.gjobs.size(); ++i)
+    if (!P.gjob_accumulate[i]) tjobs.push_back(P.gjobs[i]);
+  fs_status st = FS_OK;
+  for (const auto &c : cand) {
+    fs_tune t = P.tune;
+    t.lanes_per_row = c[0];
+    t.chunks = c[1];
+    std::vector<unsigned long long> pre;
+    gather_prefix(tjobs, t, pre);
+    st = hip_ok(hipMemcpyAsync(P.d_tprefix, pre.data(), pre.size() * sizeof(unsigned long long),
+                               hipMemcpyHostToDevice, s), "tune prefix");
+    if (st != FS_OK) break;
+    const uint32_t grid = gather_grid_for(pre.back());
+    // one warm run, then the timed one
+    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, t, grid, s);
+    if (st != FS_OK) break;
+    (void)hipEventRecord(e0, s);
+    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, t, grid, s);
+    if (st != FS_OK) break;
+    (void)hipEventRecord(e1, s);
+    st = hip_ok(hipEventSynchronize(e1), "tune sync");
+    if (st != FS_OK) break;
+    float ms = 0.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    if (ms < best) {
+      best = ms;
+      best_t = t;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (st != FS_OK) return st;
+  P.tune = best_t;
+  P.tuned_ms = best;
+  P.tune_source = 1;
+  return FS_OK;
+}
+
+void release(fs_plan *P) {
+  if (!P) return;
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  if (P->fork) (void)hipEventDestroy(P->fork);
+  if (P->join) (void)hipEventDestroy(P->join);
+  if (P->side) (void)hipStreamDestroy(P->side);
+  if (P->d_desc) (void)hipFree(P->d_desc);
+  if (P->d_ws) (void)hipFree(P->d_ws);
+  delete P;
+}
+
+}  // namespace
+
+extern "C" {
+
+fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_cache, uint32_t flags,
+                         hipStream_t stream, fs_plan **out) {
+  clear_error();
+  if (!out || (count && !items)) return fail(FS_ERR_INVALID, "items and out must be non-null");
+  if (flags & ~3u) return fail(FS_ERR_INVALID, "unknown plan flags");
+  for (uint32_t i = 0; i < count; ++i) PL_TRY(check_item(items[i], i));
+  fs_plan *P = new (std::nothrow) fs_plan();
+  if (!P) return fail(FS_ERR_NOMEM, "host allocation failed");
+  P->flags = flags;
+  P->items.assign(items, items + count);
+  P->tune = current_tune();
+  (void)hipGetDevice(&P->device);
+  auto bail = [&](fs_status s) {
+    const std::string msg = fs_last_error();
+    release(P);
+    return fail(s, msg);
+  };
+  // workspace
+  {
+    Carver cv(nullptr);
+    for (const fs_work &w : P->items) {
+      ItemWs b{};
+      carve_item(cv, w, b);
+    }
+    P->ws_bytes = cv.size();
+    if (P->ws_bytes && hipMalloc(&P->d_ws, P->ws_bytes) != hipSuccess)
+      return bail(fail(FS_ERR_NOMEM, "plan workspace allocation failed"));
+    // flags start cleared (tuning runs read them before any check kernel ran)
+    if (P->ws_bytes && hipMemsetAsync(P->d_ws, 0, P->ws_bytes, stream) != hipSuccess)
+      return bail(fail(FS_ERR_HIP, "plan workspace clear failed"));
+  }
+  build_descriptors(*P);
+  fs_status st = upload_descriptors(*P, stream, true);   // sizes only
+  if (st != FS_OK) return bail(st);
+  if (hipMalloc(&P->d_desc, P->desc_bytes) != hipSuccess)
+    return bail(fail(FS_ERR_NOMEM, "plan descriptor allocation failed"));
+  const std::string key = shape_key(*P);
+  if (cache_lookup(tune_cache, key, P->tune)) P->tune_source = 2;
+  st = upload_descriptors(*P, stream, false);
+  if (st != FS_OK) return bail(st);
+  if ((flags & FS_PLAN_AUTOTUNE) && P->tune_source != 2) {
+    st = autotune(*P, stream);
+    if (st != FS_OK) return bail(st);
+    cache_store(tune_cache, key, P->tune);
+    st = upload_descriptors(*P, stream, false);   // prefix of the chosen tiling
+    if (st != FS_OK) return bail(st);
+  }
+  P->gather_grid = gather_grid_for(P->gprefix.back());
+  if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(FS_ERR_HIP, "plan upload failed"));
+  if (!P->peels.empty()) {
+    if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(FS_ERR_HIP, "plan stream/event creation failed"));
+  }
+  prepare_batch_kernels();
+  if (!(flags & FS_PLAN_NO_GRAPH)) {
+    hipStream_t cap = nullptr;
+    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+      return bail(fail(FS_ERR_HIP, "capture stream creation failed"));
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+    if (e == hipSuccess) {
+      st = enqueue(*P, cap);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(cap, &g);
+      if (st == FS_OK && e2 != hipSuccess) st = fail(FS_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+      P->graph = g;
+    } else {
+      st = fail(FS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
+    }
+    (void)hipStreamDestroy(cap);
+    if (st != FS_OK) return bail(st);
+    if (hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess)
+      return bail(fail(FS_ERR_HIP, "graph instantiation failed"));
+  }
+  *out = P;
+  return FS_OK;
+}
+
+fs_status fs_plan_launch(fs_plan *plan, hipStream_t stream) {
+  clear_error();
+  if (!plan) return fail(FS_ERR_INVALID, "plan is null");
+  int dev = -1;
+  (void)hipGetDevice(&dev);
+  if (dev != plan->device) return fail(FS_ERR_INVALID, "plan lives on another device");
+  if (plan->exec) return hip_ok(hipGraphLaunch(plan->exec, stream), "graph launch");
+  return enqueue(*plan, stream);
+}
+
+fs_status fs_plan_rebind(fs_plan *plan, const fs_work *items, uint32_t count, hipStream_t stream) {
+  clear_error();
+  if (!plan || (count && !items)) return fail(FS_ERR_INVALID, "plan and items must be non-null");
+  if (count != plan->items.size()) return fail(FS_ERR_INVALID, "rebind needs the same number of items");
+  for (uint32_t i = 0; i < count; ++i) {
+    const fs_work &a = plan->items[i], &b = items[i];
+    if (a.op != b.op || a.graph != b.graph || a.t != b.t || a.n_ids != b.n_ids)
+      return fail(FS_ERR_INVALID, "item " + std::to_string(i) + ": rebind must keep op, graph, t and n_ids");
+    PL_TRY(check_item(b, i));
+    // the decode status slot moves between caller memory and the workspace
+    if (a.op == FS_WORK_DECODE && ((a.status == nullptr) != (b.status == nullptr)))
+      return fail(FS_ERR_INVALID, "item " + std::to_string(i) + ": rebind must keep status null or not");
+  }
+  plan->items.assign(items, items + count);
+  build_descriptors(*plan);
+  return upload_descriptors(*plan, stream, false);
+}
+
+fs_status fs_plan_get_info(const fs_plan *plan, fs_plan_info *info) {
+  clear_error();
+  if (!plan || !info) return fail(FS_ERR_INVALID, "plan and info must be non-null");
+  std::memset(info, 0, sizeof(*info));
+  info->items = (uint32_t)plan->items.size();
+  for (const fs_work &w : plan->items) {
+    info->decode_items += w.op == FS_WORK_DECODE;
+    info->update_items += w.op == FS_WORK_UPDATE;
+    info->repair_items += w.op == FS_WORK_REPAIR;
+    info->encode_items += w.op == FS_WORK_ENCODE;
+  }
+  info->gather_jobs = (uint32_t)plan->gjobs.size();
+  info->gather_tiles = plan->gprefix.empty() ? 0 : plan->gprefix.back();
+  info->replay_workgroups = plan->rprefix.back();
+  info->tune_source = plan->tune_source;
+  info->tune = plan->tune;
+  info->workspace_bytes = plan->ws_bytes + plan->desc_bytes;
+  info->tuned_ms = plan->tuned_ms;
+  return FS_OK;
+}
+
+void fs_plan_free(fs_plan *plan) { release(plan); }
+
+}  // extern "C"

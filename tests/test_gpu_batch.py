@@ -1,0 +1,171 @@
+"""Batched plans (one captured launch for many stripes) give the oracle's
+results bit for bit; graph replays, rebinds and the autotuner keep them."""
+
+import os
+import tempfile
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, empty_i32, empty_u8, graphs, host
+from oracle import codec
+from synth import gen, workloads
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1702_07409_amd as fs
+    fs.fs_reset_tune()
+    yield
+
+
+def S(**kw):
+    return workloads.StripeSpec(**kw)
+
+
+# stripes of uneven k, block size and distribution (one graph each)
+ENC = [S(stripe=20, k=64, n=96, t=4096, dist="rsd", stripe_key=20),
+       S(stripe=21, k=2000, n=2160, t=1024 + 16, dist="rsd", rsd_c=0.05, rsd_delta=0.01, stripe_key=21),
+       S(stripe=22, k=512, n=563, t=8192, dist="finite", finite_w=workloads.finite16_weights(), stripe_key=22)]
+DEC = [S(stripe=30, k=64, n=96, t=4096, dist="rsd", stripe_key=30, n_erased=16),
+       S(stripe=31, k=500, n=1000, t=512 + 32, dist="rsd", stripe_key=31, n_erased=100),
+       S(stripe=32, k=3000, n=3300, t=2048, dist="finite", finite_w=workloads.finite16_weights(),
+         stripe_key=32, n_erased=165)]
+REP = [S(stripe=40, k=1024, n=1126, t=4096, dist="rsd", stripe_key=40)]
+UPD = [S(stripe=50, k=1024, n=1126, t=2048, dist="rsd", stripe_key=50)]
+
+
+class Batch:
+    """Buffers of one batch and the oracle's expected outputs."""
+
+    def __init__(self, data_seed=0):
+        import paper_1702_07409_amd as fs
+        self.items, self.checks = [], []
+        for sp in ENC:
+            g, G = graphs(**sp.graph_kwargs())
+            x = gen.payload(data_seed, sp.stripe, sp.k, sp.t)
+            c = empty_u8(sp.n, sp.t)
+            c.fill_(0xEE)
+            self.items.append(fs.work("encode", g, sp.t, x=dev(x), c=c))
+            want = codec.encode(G, x)
+            self.checks.append(lambda c=c, want=want: np.array_equal(host(c), want))
+        for sp in DEC:
+            g, G = graphs(**sp.graph_kwargs())
+            x = gen.payload(data_seed, sp.stripe, sp.k, sp.t)
+            c_host = codec.encode(G, x)
+            er = sp.erased_mask()
+            xo = empty_u8(sp.k, sp.t)
+            xo.fill_(0x11)
+            rec, st = empty_u8(sp.k), empty_i32(3)
+            self.items.append(fs.work("decode", g, sp.t, x=xo, c=dev(c_host), erased=dev(er), recovered=rec,
+                                      status=st))
+            xw, recw, stw, _ = codec.decode(G, c_host, er)
+            self.checks.append(lambda xo=xo, rec=rec, st=st, xw=xw, recw=recw, stw=stw:
+                               np.array_equal(host(xo), xw) and np.array_equal(host(rec), recw)
+                               and host(st).tolist() == list(stw))
+        for sp in REP:
+            g, G = graphs(**sp.graph_kwargs())
+            x = gen.payload(data_seed, sp.stripe, sp.k, sp.t)
+            c_host = codec.encode(G, x)
+            lost = [5, 77, 1100]
+            c = dev(c_host)
+            c[lost] = 0
+            rep, st = empty_u8(len(lost)), empty_i32(3)
+            self.items.append(fs.work("repair", g, sp.t, x=dev(x), c=c, ids=dev(np.array(lost, np.uint32)),
+                                      n_ids=len(lost), repaired=rep, status=st))
+            self.checks.append(lambda c=c, want=c_host, rep=rep, st=st, m=len(lost):
+                               np.array_equal(host(c), want) and host(rep).tolist() == [1] * m
+                               and host(st).tolist() == [1, 0, 0])
+        for sp in UPD:
+            g, G = graphs(**sp.graph_kwargs())
+            x = gen.payload(data_seed, sp.stripe, sp.k, sp.t)
+            c_host = codec.encode(G, x)
+            ids = gen.update_ids(workloads.UPDATE_IDS_SEED, sp.stripe, sp.k, 10)
+            new = gen.update_blocks(workloads.UPDATE_DATA_SEED + data_seed, sp.stripe, ids, sp.t)
+            xd, cd, st = dev(x), dev(c_host), empty_i32(3)
+            self.items.append(fs.work("update", g, sp.t, x=xd, c=cd, ids=dev(np.array(ids, np.uint32)),
+                                      n_ids=len(ids), new_blocks=dev(new), status=st))
+            x2, c2 = codec.update(G, x, ids, new)
+            self.checks.append(lambda xd=xd, cd=cd, x2=x2, c2=c2: np.array_equal(host(xd), x2)
+                               and np.array_equal(host(cd), c2))
+
+    def verify(self):
+        bad = [i for i, ok in enumerate(self.checks) if not ok()]
+        assert not bad, "items differing from the oracle: %s" % bad
+
+
+def test_plan_mixed_batch_and_graph_replays():
+    import paper_1702_07409_amd as fs
+    import torch
+    b = Batch()
+    plan = fs.Plan(b.items)
+    info = plan.info()
+    assert info["items"] == len(b.items) and info["decode_items"] == len(DEC)
+    for _ in range(3):
+        plan.launch()
+        torch.cuda.synchronize()
+        b.verify()
+
+
+def test_plan_without_graph_matches():
+    import paper_1702_07409_amd as fs
+    b = Batch(data_seed=3)
+    plan = fs.Plan(b.items, graph=False)
+    plan.launch()
+    b.verify()
+
+
+def test_plan_rebind_to_new_buffers():
+    import paper_1702_07409_amd as fs
+    a = Batch(data_seed=1)
+    plan = fs.Plan(a.items)
+    plan.launch()
+    a.verify()
+    b = Batch(data_seed=2)
+    # same graphs are required: rebuild b's items on a's graphs
+    items = []
+    for wa, wb in zip(a.items, b.items):
+        wb.graph = wa.graph
+        wb._keep = wb._keep + (wa._keep[0],)
+        items.append(wb)
+    plan.rebind(items)
+    plan.launch()
+    b.verify()
+
+
+def test_plan_autotune_and_cache():
+    import paper_1702_07409_amd as fs
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "tune.txt")
+        b = Batch(data_seed=4)
+        p1 = fs.Plan(b.items, tune_cache=path, autotune=True)
+        i1 = p1.info()
+        assert i1["tune_source"] == 1 and i1["tuned_ms"] > 0
+        p1.launch()
+        b.verify()
+        b2 = Batch(data_seed=4)
+        p2 = fs.Plan(b2.items, tune_cache=path, autotune=True)
+        i2 = p2.info()
+        assert i2["tune_source"] == 2 and i2["tune"] == i1["tune"]
+        p2.launch()
+        b2.verify()
+
+
+def test_plan_rejects_bad_items():
+    import paper_1702_07409_amd as fs
+    sp = workloads.tiny()
+    g, _ = graphs(**sp.graph_kwargs())
+    c = empty_u8(sp.n, sp.t)
+    st, rep = empty_i32(3), empty_u8(1)
+    with pytest.raises(fs.FsError) as e:
+        fs.Plan([fs.work("repair", g, sp.t, x=None, c=c, ids=dev(np.array([1], np.uint32)), n_ids=1,
+                         repaired=rep, status=st)])
+    assert e.value.status == fs._lib.FS_ERR_UNSUPPORTED
+    with pytest.raises(fs.FsError) as e:
+        fs.Plan([fs.work("encode", g, 4100, x=empty_u8(sp.k * 4112), c=empty_u8(sp.n * 4112))])
+    assert e.value.status == fs._lib.FS_ERR_ALIGN
