@@ -45,6 +45,13 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--workload", default="large_stripe",
+                    choices=["large_stripe", "batch512", "resident256", "all"],
+                    help="large_stripe: plain one-stripe path (the headline line); batch512 / "
+                         "resident256: batched plans vs the plain loop; all: the headline line "
+                         "with the batched results attached")
+    ap.add_argument("--batch-stripes", type=int, default=512)
+    ap.add_argument("--resident-stripes", type=int, default=256)
     ap.add_argument("--mode", choices=["step", "counters"], default="step",
                     help="counters: only K encode launches plus one plain copy of the same "
                          "output size, for rocprofv3 --pmc runs")
@@ -106,6 +113,12 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
+    if args.workload in ("batch512", "resident256"):
+        import bench_batch
+        res = (bench_batch.run_batch512(args.batch_stripes) if args.workload == "batch512"
+               else bench_batch.run_resident256(args.resident_stripes))
+        print(json.dumps(res), flush=True)
+        return
     spec = workloads.large_stripe()
     k, n, t = spec.k, spec.n, spec.t
     g = fs.fs_graph_build(**spec.graph_kwargs())
@@ -242,6 +255,13 @@ def main():
         "paper_cpu_context": "Table 2: encode 2722 MB/s, decode 3291/2852/2340 MB/s (2-4 disks lost), "
                              "k=1036 n=2180 t=1024, 2x Xeon E5-2620 with 12 threads",
     }
+    if args.workload == "all":
+        import bench_batch
+        del x, c, xd, ws, wss, rws, pws
+        torch.cuda.empty_cache()
+        out["batched"] = bench_batch.run_batch512(args.batch_stripes)
+        torch.cuda.empty_cache()
+        out["resident"] = bench_batch.run_resident256(args.resident_stripes)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(out), flush=True)

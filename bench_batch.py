@@ -1,0 +1,216 @@
+"""Batched workloads for bench.py: many stripes per captured launch (fs_plan)
+against the plain path (one fs_encode / fs_decode / fs_repair / fs_update
+call per stripe) on the same stripes.
+
+batch512     512 stripes, k log-uniform in [64, 8192), blocks 4 KiB..1 MiB,
+             RSD (c=0.05, delta=0.01), 8 % overhead, 4 % erasures.  Processed
+             in waves that fit HBM; a wave is an encode plan then a decode plan.
+resident256  256 stripes k=1024 x 256 KiB, n=1126, RSD (c=0.1, delta=0.05),
+             resident in HBM: repair of 1-4 lost coded blocks per stripe from
+             the inputs, and an update of 10 inputs per stripe.
+"""
+
+import sys
+import time
+
+import numpy as np
+
+
+def _progress(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+HBM_PEAK_GBPS = 8000.0
+
+
+def _ev():
+    import torch
+    return torch.cuda.Event(enable_timing=True)
+
+
+def _time(fn, reps):
+    import torch
+    e0, e1 = _ev(), _ev()
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _compulsory_encode(g, t):
+    _, col, _, _ = g.export()
+    return (len(np.unique(col)) + g.n) * t
+
+
+def run_batch512(count=512, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
+    import torch
+    import paper_1702_07409_amd as fs
+    import synth.gpu as sg
+    from synth import workloads
+
+    specs = workloads.batch512(count)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free * 0.55)
+    waves, cur, used = [], [], 0
+    for sp in specs:
+        need = (2 * sp.k + sp.n) * sp.t
+        if cur and used + need > budget:
+            waves.append(cur)
+            cur, used = [], 0
+        cur.append(sp)
+        used += need
+    if cur:
+        waves.append(cur)
+    tot = dict(enc_user=0, dec_user=0, comp=0, t_batch=0.0, t_plain=0.0, t_enc=0.0, t_dec=0.0, recovered=0, k=0)
+    tune = None
+    t_setup = time.perf_counter()
+    for wave in waves:
+        bufs = []
+        for sp in wave:
+            g = fs.fs_graph_build(**sp.graph_kwargs())
+            x = torch.empty((sp.k, sp.t), dtype=torch.uint8, device="cuda")
+            sg.fill(x, sp.data_seed, sp.stripe, sp.t)
+            c = torch.empty((sp.n, sp.t), dtype=torch.uint8, device="cuda")
+            xd = torch.empty((sp.k, sp.t), dtype=torch.uint8, device="cuda")
+            er = torch.from_numpy(sp.erased_mask()).cuda()
+            rec = torch.empty(sp.k, dtype=torch.uint8, device="cuda")
+            st = torch.empty(3, dtype=torch.int32, device="cuda")
+            bufs.append((sp, g, x, c, xd, er, rec, st))
+        enc = fs.Plan([fs.work("encode", g, sp.t, x=x, c=c) for sp, g, x, c, xd, er, rec, st in bufs],
+                      tune_cache=tune_cache, autotune=True)
+        dec = fs.Plan([fs.work("decode", g, sp.t, x=xd, c=c, erased=er, recovered=rec, status=st)
+                       for sp, g, x, c, xd, er, rec, st in bufs])
+        tune = enc.info()["tune"]
+        t_enc = _time(enc.launch, reps)
+        t_dec = _time(dec.launch, reps)
+        # check: every recovered block equals its input (sampled rows)
+        nrec = 0
+        for sp, g, x, c, xd, er, rec, st in bufs:
+            r = rec.cpu().numpy().astype(bool)
+            nrec += int(r.sum())
+            rows = np.flatnonzero(r)[:: max(1, int(r.sum()) // 8)]
+            if len(rows):
+                ix = torch.from_numpy(rows).cuda()
+                assert torch.equal(xd[ix], x[ix]), "decoded blocks differ from the inputs"
+        wss = {id(b[1]): fs.workspace(b[1], fs.FS_OP_DECODE, b[0].t) for b in bufs}
+
+        def plain():
+            for sp, g, x, c, xd, er, rec, st in bufs:
+                fs.fs_encode(g, x, c, sp.t)
+                fs.fs_decode(g, c, er, 0, xd, rec, st, sp.t, wss[id(g)])
+
+        t_plain = _time(plain, max(1, reps - 1))
+        tot["enc_user"] += sum(sp.k * sp.t for sp, *_ in bufs)
+        tot["dec_user"] += sum(int(b[6].sum().item()) * b[0].t for b in bufs)
+        tot["comp"] += sum(_compulsory_encode(g, sp.t) + (int(rec.sum().item()) + sp.k) * sp.t
+                           for sp, g, x, c, xd, er, rec, st in bufs)
+        tot["t_enc"] += t_enc
+        tot["t_dec"] += t_dec
+        tot["t_batch"] += t_enc + t_dec
+        tot["t_plain"] += t_plain
+        tot["recovered"] += nrec
+        tot["k"] += sum(sp.k for sp in wave)
+        del enc, dec, bufs, wss
+        torch.cuda.empty_cache()
+        _progress("batch512: wave of %d stripes done (enc %.2f ms, dec %.2f ms, plain %.2f ms)"
+                  % (len(wave), t_enc, t_dec, t_plain))
+    user = tot["enc_user"] + tot["dec_user"]
+    return {
+        "workload": "batch512", "stripes": count, "waves": len(waves),
+        "input_GB": round(tot["enc_user"] / 1e9, 2),
+        "batched_GBps_user": round(user / (tot["t_batch"] * 1e-3) / 1e9, 1),
+        "plain_loop_GBps_user": round(user / (tot["t_plain"] * 1e-3) / 1e9, 1),
+        "batched_encode_GBps_user": round(tot["enc_user"] / (tot["t_enc"] * 1e-3) / 1e9, 1),
+        "batched_decode_GBps_user": round(tot["dec_user"] / (tot["t_dec"] * 1e-3) / 1e9, 1),
+        "batched_hbm_frac_effective": round(tot["comp"] / (tot["t_batch"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "recovered_fraction": round(tot["recovered"] / tot["k"], 4),
+        "batched_ms": round(tot["t_batch"], 3), "plain_ms": round(tot["t_plain"], 3),
+        "tune": tune, "setup_s": round(time.perf_counter() - t_setup, 1),
+    }
+
+
+def run_resident256(count=256, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
+    import torch
+    import paper_1702_07409_amd as fs
+    import synth.gpu as sg
+    from synth import gen, workloads
+
+    specs = workloads.resident256(count)
+    t0 = time.perf_counter()
+    st_ = []
+    for sp in specs:
+        g = fs.fs_graph_build(**sp.graph_kwargs())
+        x = torch.empty((sp.k, sp.t), dtype=torch.uint8, device="cuda")
+        sg.fill(x, sp.data_seed, sp.stripe, sp.t)
+        c = torch.empty((sp.n, sp.t), dtype=torch.uint8, device="cuda")
+        lost = sp.extra["lost"]
+        ids = sp.extra["update_ids"]
+        new = torch.empty((len(ids), sp.t), dtype=torch.uint8, device="cuda")
+        for u, i in enumerate(ids):
+            sg.fill(new[u:u + 1], workloads.UPDATE_DATA_SEED, sp.stripe, sp.t, first_block=i,
+                    purpose=sg.UPDATE_DATA)
+        st_.append(dict(sp=sp, g=g, x=x, c=c, lost=torch.from_numpy(np.array(lost, np.uint32)).cuda(),
+                        nl=len(lost), ids=torch.from_numpy(np.array(ids, np.uint32)).cuda(), nu=len(ids),
+                        new=new, rep=torch.empty(len(lost), dtype=torch.uint8, device="cuda"),
+                        rst=torch.empty(3, dtype=torch.int32, device="cuda"),
+                        ust=torch.empty(3, dtype=torch.int32, device="cuda")))
+    _progress("resident256: %d stripes resident" % len(st_))
+    enc = fs.Plan([fs.work("encode", d["g"], d["sp"].t, x=d["x"], c=d["c"]) for d in st_])
+    enc.launch()
+    torch.cuda.synchronize()
+    rep = fs.Plan([fs.work("repair", d["g"], d["sp"].t, x=d["x"], c=d["c"], ids=d["lost"], n_ids=d["nl"],
+                           repaired=d["rep"], status=d["rst"]) for d in st_],
+                  tune_cache=tune_cache, autotune=True)
+    upd = fs.Plan([fs.work("update", d["g"], d["sp"].t, x=d["x"], c=d["c"], ids=d["ids"], n_ids=d["nu"],
+                           new_blocks=d["new"], status=d["ust"]) for d in st_])
+    t_rep = _time(rep.launch, reps)
+    # the first update applies the new blocks; repeats carry zero deltas but the same traffic
+    t_upd = _time(upd.launch, reps)
+    assert all(d["rst"].cpu().tolist() == [1, 0, 0] for d in st_)
+    ws = {}
+    for d in st_:
+        ws[id(d)] = (fs.workspace(d["g"], fs.FS_OP_REPAIR, d["sp"].t, d["nl"]),
+                     fs.workspace(d["g"], fs.FS_OP_UPDATE, d["sp"].t, d["nu"]))
+
+    def plain_rep():
+        for d in st_:
+            fs.fs_repair(d["g"], d["x"], d["c"], None, d["lost"], d["nl"], d["rep"], d["rst"], d["sp"].t,
+                         ws[id(d)][0])
+
+    def plain_upd():
+        for d in st_:
+            fs.fs_update(d["g"], d["x"], d["c"], d["ids"], d["nu"], d["new"], d["ust"], d["sp"].t, ws[id(d)][1])
+
+    tp_rep = _time(plain_rep, reps)
+    tp_upd = _time(plain_upd, reps)
+    # bytes: repair rebuilds |lost| blocks; update rewrites |U| inputs
+    t = specs[0].t
+    rep_user = sum(d["nl"] for d in st_) * t
+    upd_user = sum(d["nu"] for d in st_) * t
+    rep_comp = 0
+    upd_comp = 0
+    for d in st_:
+        rp, col, cp, ri = d["g"].export()
+        lost = d["sp"].extra["lost"]
+        nb = set()
+        for j in lost:
+            nb.update(col[rp[j]:rp[j + 1]].tolist())
+        rep_comp += (len(nb) + len(lost)) * t
+        aff = set()
+        for i in d["sp"].extra["update_ids"]:
+            aff.update(ri[cp[i]:cp[i + 1]].tolist())
+        upd_comp += (3 * d["nu"] + 2 * len(aff)) * t
+    return {
+        "workload": "resident256", "stripes": count,
+        "resident_GB": round(sum((d["sp"].k + d["sp"].n) * d["sp"].t for d in st_) / 1e9, 1),
+        "repair_batched_ms": round(t_rep, 3), "repair_plain_ms": round(tp_rep, 3),
+        "repair_batched_GBps_user": round(rep_user / (t_rep * 1e-3) / 1e9, 1),
+        "repair_hbm_frac_effective": round(rep_comp / (t_rep * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "update_batched_ms": round(t_upd, 3), "update_plain_ms": round(tp_upd, 3),
+        "update_batched_GBps_user": round(upd_user / (t_upd * 1e-3) / 1e9, 1),
+        "update_hbm_frac_effective": round(upd_comp / (t_upd * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "repair_tune": rep.info()["tune"], "setup_s": round(time.perf_counter() - t0, 1),
+    }

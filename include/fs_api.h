@@ -317,6 +317,21 @@ typedef struct fs_plan_info {
  */
 FS_API fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_cache, uint32_t flags,
                                 hipStream_t stream, fs_plan **out);
+/*
+ * Device bytes a plan of these items needs (workspace and descriptors), for
+ * fs_plan_create_in.
+ */
+FS_API fs_status fs_plan_memory_size(const fs_work *items, uint32_t count, size_t *bytes);
+/*
+ * As fs_plan_create, but the plan lives in caller device memory mem (256-byte
+ * aligned, at least fs_plan_memory_size bytes, owned by the caller and kept
+ * until fs_plan_free) and is launched without a graph, all on the launch
+ * stream: no device allocation, stream or graph is created.  For request
+ * loops that build a plan per tick (FS_PLAN_AUTOTUNE is ignored; the process
+ * tuning of fs_set_tune applies).
+ */
+FS_API fs_status fs_plan_create_in(const fs_work *items, uint32_t count, void *mem, size_t mem_bytes,
+                                   hipStream_t stream, fs_plan **out);
 /* Run the plan on a stream (asynchronous). */
 FS_API fs_status fs_plan_launch(fs_plan *plan, hipStream_t stream);
 /*

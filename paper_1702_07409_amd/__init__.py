@@ -14,7 +14,7 @@ _BINDING = (
     "FS_OP_REPAIR_CONVENTIONAL", "FS_OP_REPLAY", "FS_OP_UPDATE", "FsError", "Graph", "fs_decode",
     "fs_decode_apply", "fs_decode_plan", "fs_degree_table", "fs_encode", "fs_get_tune",
     "fs_graph_build", "fs_peel", "fs_repair", "fs_replay", "fs_reset_tune", "fs_set_tune",
-    "fs_update", "fs_workspace_size", "version", "workspace", "Plan", "work",
+    "fs_update", "fs_workspace_size", "version", "workspace", "Plan", "work", "plan_memory_size",
     "FS_WORK_ENCODE", "FS_WORK_DECODE", "FS_WORK_REPAIR", "FS_WORK_UPDATE",
 )
 

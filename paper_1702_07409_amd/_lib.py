@@ -79,6 +79,8 @@ _SIGS = {
     "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
+    "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ)], ST),
+    "fs_plan_create_in": ([ctypes.POINTER(fs_work), U32, P, SZ, P, ctypes.POINTER(P)], ST),
     "fs_plan_rebind": ([P, ctypes.POINTER(fs_work), U32, P], ST),
     "fs_plan_get_info": ([P, ctypes.POINTER(fs_plan_info)], ST),
     "fs_plan_free": ([P], None),
@@ -304,18 +306,34 @@ def work(op, graph, t, x=None, c=None, erased=None, maxit=0, recovered=None, sta
     return w
 
 
-class Plan:
-    """Owner of an fs_plan handle."""
+def plan_memory_size(items):
+    arr = (fs_work * len(items))(*items)
+    b = SZ()
+    _check(_lib.fs_plan_memory_size(arr, len(items), ctypes.byref(b)), "fs_plan_memory_size")
+    return b.value
 
-    def __init__(self, items, tune_cache=None, autotune=False, graph=True, stream=None):
+
+class Plan:
+    """Owner of an fs_plan handle.
+
+    memory: optional device tensor (uint8) that holds the plan
+    (fs_plan_create_in: no allocation, no graph, one stream)."""
+
+    def __init__(self, items, tune_cache=None, autotune=False, graph=True, stream=None, memory=None):
         arr = (fs_work * len(items))(*items)
         h = P()
-        flags = (FS_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else FS_PLAN_NO_GRAPH)
-        path = tune_cache.encode() if tune_cache else None
-        _check(_lib.fs_plan_create(arr, len(items), path, flags, _stream(stream), ctypes.byref(h)),
-               "fs_plan_create")
+        if memory is not None:
+            w, wb = _ws(memory)
+            _check(_lib.fs_plan_create_in(arr, len(items), w, wb, _stream(stream), ctypes.byref(h)),
+                   "fs_plan_create_in")
+        else:
+            flags = (FS_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else FS_PLAN_NO_GRAPH)
+            path = tune_cache.encode() if tune_cache else None
+            _check(_lib.fs_plan_create(arr, len(items), path, flags, _stream(stream), ctypes.byref(h)),
+                   "fs_plan_create")
         self.handle = h
         self._items = list(items)
+        self._memory = memory
 
     def launch(self, stream=None):
         _check(_lib.fs_plan_launch(self.handle, _stream(stream)), "fs_plan_launch")

@@ -49,6 +49,24 @@ def _compile(src, flags, cc):
     return out
 
 
+SYNTH_SRC = os.path.join(ROOT, "synth", "csrc", "datagen.hip")
+SYNTH_LIB = os.path.join(ROOT, "synth", "libsynth.so")
+
+
+def build_synth(verbose=False):
+    """The seeded payload generator used by tests and the benchmark."""
+    cc = hipcc()
+    tmp = SYNTH_LIB + ".tmp"
+    cmd = [cc, *DEVICE, "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden", SYNTH_SRC, "-o", tmp]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))
+    os.replace(tmp, SYNTH_LIB)
+    if verbose:
+        print("built", SYNTH_LIB)
+    return SYNTH_LIB
+
+
 def build_library(verbose=False):
     """Compile every source and link libfs.so; returns the library path."""
     os.makedirs(OBJ, exist_ok=True)
@@ -68,4 +86,5 @@ def build_library(verbose=False):
 
 if __name__ == "__main__":
     build_library(verbose=True)
+    build_synth(verbose=True)
     sys.exit(0)

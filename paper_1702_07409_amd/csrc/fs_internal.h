@@ -209,8 +209,10 @@ struct ZeroEntry {
   int64_t row;
 };
 // device arrays of job descriptors; see kernels.hip for the item spaces
+// d_counter: a device word the launch resets and then uses to hand out items
 fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long *d_prefix, uint32_t njobs,
-                              const fs_tune &tune, uint32_t grid, hipStream_t s);
+                              unsigned long long *d_counter, const fs_tune &tune, uint32_t grid,
+                              uint64_t total_items, hipStream_t s);
 fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, bool lds, size_t lds_bytes, hipStream_t s);
 fs_status launch_prog_batch(const ProgJob *d_jobs, uint32_t njobs, hipStream_t s);
 fs_status launch_replay_batch(const ReplayJob *d_rj, const ProgJob *d_pj, const uint32_t *d_wg_prefix,

@@ -214,37 +214,68 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uin
 
 // Persistent gather over the items of many jobs (a batch): the item space is
 // the concatenation of every job's (slice, tile) items (prefix[] holds the
-// running counts, computed with each job's row-count bound).  Workgroups
-// stride over it; XCD-aware numbering keeps each XCD on a contiguous window,
-// so concurrent items share a job and a slice.
+// running counts, computed with each job's row-count bound).  It is cut into
+// 8 contiguous partitions, one per XCD, each with its own counter: the
+// workgroups of an XCD (hardware places workgroup b on XCD b % 8) claim small
+// chunks of consecutive items from their partition, so the items in flight on
+// an XCD stay close together (same job, same slice: the slice's input slab
+// stays in that XCD's L2) while uneven stripes still balance dynamically.  A
+// workgroup whose partition is used up moves on to the next partitions.
+// counters[x] must start at the first item of partition x (reset kernel).
+constexpr uint32_t kXcds = 8;
+
 template <int LPR, int CH, bool NT>
 __global__ __launch_bounds__(kGatherThreads) void gather_batch_kernel(const GatherJob *jobs,
                                                                        const unsigned long long *prefix,
-                                                                       uint32_t njobs) {
+                                                                       uint32_t njobs,
+                                                                       unsigned long long *counters,
+                                                                       uint32_t chunk) {
   constexpr uint32_t RPB = kGatherThreads / LPR;
-  constexpr uint32_t W = LPR * 16 * CH;
   __shared__ int32_t s_ptr[RPB + 1];
   __shared__ int32_t s_idx[kStageCap];
+  __shared__ unsigned long long s_next;
   const unsigned long long total = prefix[njobs];
-  const uint32_t vb = xcd_remap(blockIdx.x, gridDim.x);
-  uint32_t jb = 0;
-  // first job: binary search; later items only move forward
-  {
-    uint32_t lo = 0, hi = njobs;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) / 2;
-      if (prefix[mid] <= vb) lo = mid; else hi = mid;
+  uint32_t jb = 0, jcur = 0xffffffffu;
+  GatherJob j{};
+  uint32_t nrows = 0, ntiles = 1;
+  bool skip = false;
+  for (uint32_t pass = 0; pass < kXcds; ++pass) {
+    const uint32_t part = (blockIdx.x + pass) % kXcds;
+    const unsigned long long hi = total * (part + 1) / kXcds;
+    for (;;) {
+      __syncthreads();   // everyone has read s_next
+      if (threadIdx.x == 0) s_next = atomicAdd(&counters[part], (unsigned long long)chunk);
+      __syncthreads();
+      const unsigned long long base = s_next;
+      if (base >= hi) break;
+      const unsigned long long end = min(base + chunk, hi);
+      for (unsigned long long item = base; item < end; ++item) {
+        if (jcur == 0xffffffffu || item < prefix[jb]) {
+          uint32_t lo = 0, hj = njobs;
+          while (hj - lo > 1) {
+            const uint32_t mid = (lo + hj) / 2;
+            if (prefix[mid] <= item) lo = mid; else hj = mid;
+          }
+          jb = lo;
+        }
+        while (jb + 1 < njobs && prefix[jb + 1] <= item) ++jb;
+        if (jb != jcur) {
+          j = jobs[jb];
+          jcur = jb;
+          skip = j.skip_flag && *j.skip_flag;
+          nrows = live_rows(j);
+          ntiles = (j.nrows + RPB - 1) / RPB;   // the decomposition uses the bound
+        }
+        if (!skip) gather_item<LPR, CH, NT>(j, nrows, ntiles, item - prefix[jb], s_ptr, s_idx);
+      }
     }
-    jb = lo;
   }
-  for (unsigned long long item = vb; item < total; item += gridDim.x) {
-    while (jb + 1 < njobs && prefix[jb + 1] <= item) ++jb;
-    const GatherJob &j = jobs[jb];
-    if (j.skip_flag && *j.skip_flag) continue;
-    const uint32_t ntiles = (j.nrows + RPB - 1) / RPB;   // decomposition uses the bound
-    (void)W;
-    gather_item<LPR, CH, NT>(j, live_rows(j), ntiles, item - prefix[jb], s_ptr, s_idx);
-  }
+}
+
+// counter reset for the batched gather (a kernel, so it can sit in a graph):
+// partition x starts at total * x / 8
+__global__ void reset_counter_kernel(unsigned long long *counters, const unsigned long long *prefix, uint32_t njobs) {
+  if (threadIdx.x < kXcds) counters[threadIdx.x] = prefix[njobs] * threadIdx.x / kXcds;
 }
 
 __global__ __launch_bounds__(256) void zero_rows_kernel(uint8_t *dst, const int32_t *rows, uint32_t nrows,
@@ -1308,31 +1339,36 @@ namespace fs {
 
 template <int LPR, int CH>
 static hipError_t run_gather_batch(const GatherJob *jobs, const unsigned long long *prefix, uint32_t njobs,
-                                   bool nt, uint32_t grid, hipStream_t s) {
+                                   unsigned long long *counter, bool nt, uint32_t grid, uint32_t chunk,
+                                   hipStream_t s) {
+  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter, prefix, njobs);
   if (nt)
     hipLaunchKernelGGL((gather_batch_kernel<LPR, CH, true>), dim3(grid), dim3(kGatherThreads), 0, s, jobs, prefix,
-                       njobs);
+                       njobs, counter, chunk);
   else
     hipLaunchKernelGGL((gather_batch_kernel<LPR, CH, false>), dim3(grid), dim3(kGatherThreads), 0, s, jobs, prefix,
-                       njobs);
+                       njobs, counter, chunk);
   return hipGetLastError();
 }
 
 fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long *d_prefix, uint32_t njobs,
-                              const fs_tune &tune, uint32_t grid, hipStream_t s) {
+                              unsigned long long *d_counter, const fs_tune &tune, uint32_t grid,
+                              uint64_t total_items, hipStream_t s) {
   if (njobs == 0 || grid == 0) return FS_OK;
+  // small chunks keep the items in flight on an XCD close together
+  const uint32_t chunk = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(2, total_items / ((uint64_t)grid * 64)));
   const bool nt = tune.nt_store != 0;
   hipError_t e;
   switch (tune.lanes_per_row * 10 + tune.chunks) {
-    case 161: e = run_gather_batch<16, 1>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 162: e = run_gather_batch<16, 2>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 164: e = run_gather_batch<16, 4>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 321: e = run_gather_batch<32, 1>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 322: e = run_gather_batch<32, 2>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 324: e = run_gather_batch<32, 4>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 641: e = run_gather_batch<64, 1>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 642: e = run_gather_batch<64, 2>(d_jobs, d_prefix, njobs, nt, grid, s); break;
-    case 644: e = run_gather_batch<64, 4>(d_jobs, d_prefix, njobs, nt, grid, s); break;
+    case 161: e = run_gather_batch<16, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 162: e = run_gather_batch<16, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 164: e = run_gather_batch<16, 4>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 321: e = run_gather_batch<32, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 322: e = run_gather_batch<32, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 324: e = run_gather_batch<32, 4>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 641: e = run_gather_batch<64, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 642: e = run_gather_batch<64, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 644: e = run_gather_batch<64, 4>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
     default: return fail(FS_ERR_INVALID, "unsupported gather tuning");
   }
   return hip_check(e, "batched gather launch");

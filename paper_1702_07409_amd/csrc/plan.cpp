@@ -61,7 +61,9 @@ struct fs_plan {
   GatherJob *d_tjobs = nullptr;
   unsigned long long *d_tprefix = nullptr;
   uint32_t n_tjobs = 0;
+  unsigned long long *d_counter = nullptr;   // 8 work counters (one per XCD) of the persistent gather
 
+  bool external = false;   // workspace and descriptors in caller memory
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   hipStream_t side = nullptr;
@@ -323,6 +325,7 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate) {
   P.d_zeros = place<ZeroEntry>(base, off, P.zeros.size());
   P.d_tjobs = place<GatherJob>(base, off, tjobs.size());
   P.d_tprefix = place<unsigned long long>(base, off, tprefix.size());
+  P.d_counter = place<unsigned long long>(base, off, 8);
   P.n_tjobs = (uint32_t)tjobs.size();
   off = (off + 255) & ~size_t(255);
   if (allocate) {
@@ -374,7 +377,8 @@ fs_status enqueue(fs_plan &P, hipStream_t s) {
   PL_TRY(launch_repair_prep_batch(P.d_rpreps, (uint32_t)P.rpreps.size(), s));
   PL_TRY(launch_update_plan_batch(P.d_uplans, (uint32_t)P.uplans.size(), s));
   PL_TRY(launch_update_delta_batch(P.d_udeltas, P.d_uprefix, (uint32_t)P.udeltas.size(), P.uprefix.back(), s));
-  PL_TRY(launch_gather_batch(P.d_gjobs, P.d_gprefix, (uint32_t)P.gjobs.size(), P.tune, P.gather_grid, s));
+  PL_TRY(launch_gather_batch(P.d_gjobs, P.d_gprefix, (uint32_t)P.gjobs.size(), P.d_counter, P.tune, P.gather_grid,
+                             P.gprefix.back(), s));
   if (fork) {
     PL_TRY(hip_ok(hipEventRecord(P.join, P.side), "join"));
     PL_TRY(hip_ok(hipStreamWaitEvent(s, P.join, 0), "join wait"));
@@ -447,10 +451,10 @@ fs_status autotune(fs_plan &P, hipStream_t s) {
     if (st != FS_OK) break;
     const uint32_t grid = gather_grid_for(pre.back());
     // one warm run, then the timed one
-    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, t, grid, s);
+    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, P.d_counter, t, grid, pre.back(), s);
     if (st != FS_OK) break;
     (void)hipEventRecord(e0, s);
-    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, t, grid, s);
+    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, P.d_counter, t, grid, pre.back(), s);
     if (st != FS_OK) break;
     (void)hipEventRecord(e1, s);
     st = hip_ok(hipEventSynchronize(e1), "tune sync");
@@ -478,8 +482,10 @@ void release(fs_plan *P) {
   if (P->fork) (void)hipEventDestroy(P->fork);
   if (P->join) (void)hipEventDestroy(P->join);
   if (P->side) (void)hipStreamDestroy(P->side);
-  if (P->d_desc) (void)hipFree(P->d_desc);
-  if (P->d_ws) (void)hipFree(P->d_ws);
+  if (!P->external) {
+    if (P->d_desc) (void)hipFree(P->d_desc);
+    if (P->d_ws) (void)hipFree(P->d_ws);
+  }
   delete P;
 }
 
@@ -616,5 +622,65 @@ fs_status fs_plan_get_info(const fs_plan *plan, fs_plan_info *info) {
 }
 
 void fs_plan_free(fs_plan *plan) { release(plan); }
+
+fs_status fs_plan_memory_size(const fs_work *items, uint32_t count, size_t *bytes) {
+  clear_error();
+  if (!bytes || (count && !items)) return fail(FS_ERR_INVALID, "items and bytes must be non-null");
+  for (uint32_t i = 0; i < count; ++i) PL_TRY(check_item(items[i], i));
+  fs_plan P;
+  P.items.assign(items, items + count);
+  P.tune = current_tune();
+  Carver cv(nullptr);
+  for (const fs_work &w : P.items) {
+    ItemWs b{};
+    carve_item(cv, w, b);
+  }
+  P.ws_bytes = cv.size();
+  build_descriptors(P);
+  PL_TRY(upload_descriptors(P, nullptr, true));
+  *bytes = P.ws_bytes + P.desc_bytes + 512;
+  return FS_OK;
+}
+
+fs_status fs_plan_create_in(const fs_work *items, uint32_t count, void *mem, size_t mem_bytes, hipStream_t stream,
+                            fs_plan **out) {
+  clear_error();
+  if (!out || (count && !items)) return fail(FS_ERR_INVALID, "items and out must be non-null");
+  if (!mem || (reinterpret_cast<uintptr_t>(mem) & 255)) return fail(FS_ERR_ALIGN, "mem must be 256-byte aligned");
+  for (uint32_t i = 0; i < count; ++i) PL_TRY(check_item(items[i], i));
+  fs_plan *P = new (std::nothrow) fs_plan();
+  if (!P) return fail(FS_ERR_NOMEM, "host allocation failed");
+  P->external = true;
+  P->flags = FS_PLAN_NO_GRAPH;
+  P->items.assign(items, items + count);
+  P->tune = current_tune();
+  (void)hipGetDevice(&P->device);
+  Carver cv(nullptr);
+  for (const fs_work &w : P->items) {
+    ItemWs b{};
+    carve_item(cv, w, b);
+  }
+  P->ws_bytes = cv.size();
+  P->d_ws = mem;
+  build_descriptors(*P);   // carves the workspace at d_ws
+  fs_status st = upload_descriptors(*P, stream, true);
+  if (st == FS_OK && P->ws_bytes + P->desc_bytes > mem_bytes)
+    st = fail(FS_ERR_WORKSPACE, "plan memory too small: need " + std::to_string(P->ws_bytes + P->desc_bytes));
+  if (st == FS_OK) {
+    P->d_desc = static_cast<uint8_t *>(mem) + P->ws_bytes;
+    // flags of the workspace start cleared; descriptors follow
+    st = hip_ok(hipMemsetAsync(P->d_ws, 0, P->ws_bytes, stream), "plan workspace clear");
+  }
+  if (st == FS_OK) st = upload_descriptors(*P, stream, false);
+  if (st != FS_OK) {
+    const std::string msg = fs_last_error();
+    release(P);
+    return fail(st, msg);
+  }
+  P->gather_grid = gather_grid_for(P->gprefix.back());
+  prepare_batch_kernels();
+  *out = P;
+  return FS_OK;
+}
 
 }  // extern "C"
