@@ -46,10 +46,12 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="large_stripe",
-                    choices=["large_stripe", "batch512", "resident256", "all"],
+                    choices=["large_stripe", "batch512", "resident256", "serve", "all"],
                     help="large_stripe: plain one-stripe path (the headline line); batch512 / "
-                         "resident256: batched plans vs the plain loop; all: the headline line "
-                         "with the batched results attached")
+                         "resident256: batched plans vs the plain loop; serve: the request loop "
+                         "on a Poisson mix; all: the headline line with the others attached")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--batch-stripes", type=int, default=512)
     ap.add_argument("--resident-stripes", type=int, default=256)
     ap.add_argument("--mode", choices=["step", "counters"], default="step",
@@ -113,10 +115,14 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.workload in ("batch512", "resident256"):
+    if args.workload in ("batch512", "resident256", "serve"):
         import bench_batch
-        res = (bench_batch.run_batch512(args.batch_stripes) if args.workload == "batch512"
-               else bench_batch.run_resident256(args.resident_stripes))
+        if args.workload == "batch512":
+            res = bench_batch.run_batch512(args.batch_stripes)
+        elif args.workload == "resident256":
+            res = bench_batch.run_resident256(args.resident_stripes)
+        else:
+            res = bench_batch.run_serve(args.serve_rate, args.serve_seconds)
         print(json.dumps(res), flush=True)
         return
     spec = workloads.large_stripe()
@@ -262,6 +268,8 @@ def main():
         out["batched"] = bench_batch.run_batch512(args.batch_stripes)
         torch.cuda.empty_cache()
         out["resident"] = bench_batch.run_resident256(args.resident_stripes)
+        torch.cuda.empty_cache()
+        out["serve"] = bench_batch.run_serve(args.serve_rate, args.serve_seconds)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
     print(json.dumps(out), flush=True)

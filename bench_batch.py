@@ -214,3 +214,75 @@ def run_resident256(count=256, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
         "update_hbm_frac_effective": round(upd_comp / (t_upd * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "repair_tune": rep.info()["tune"], "setup_s": round(time.perf_counter() - t0, 1),
     }
+
+
+def _fresh(reqs, Request):
+    """New request objects with the same inputs (results cleared)."""
+    out = []
+    for r in reqs:
+        out.append(Request(r.kind, arrival=r.arrival, params=r.params, t=r.t, x=r.x, stripe=r.stripe,
+                           erased=r.erased, maxit=r.maxit, ids=r.ids, new_blocks=r.new_blocks, rid=r.rid))
+    return out
+
+
+def run_serve(rate=2000.0, duration=1.0, pool_size=256, sweep=(8000.0, 32000.0, 0.0), budget_gib=48):
+    """Poisson mix of requests served by the continuous-batching loop.
+
+    The pool of resident stripes and every request's device inputs are made
+    before the clock starts (inputs resident in HBM).  The headline run
+    replays the trace at `rate`; the sweep replays the same requests with
+    arrival times scaled to higher rates (0: all at once), with the graph
+    cache already warm.  Busy time is the union of the ticks' device
+    intervals (HIP events); user bytes: k t per encode, |recovered| t per
+    decode, m t per repair and update.
+    """
+    import torch
+    from paper_1702_07409_amd.serve import Request, Server
+    from synth import serving, workloads
+
+    srv = Server(budget=budget_gib << 30, streams=3, max_inflight=4, max_items=64, workers=12)
+    t0 = time.perf_counter()
+    pool = serving.build_pool(srv, pool_size)
+    torch.cuda.synchronize()
+    _progress("serve: pool of %d stripes ready (%.1f s)" % (pool_size, time.perf_counter() - t0))
+    # warm the allocator and the launch path on a trace of another seed
+    warm = serving.build_requests(workloads.serving_trace(rate=20000.0, duration=0.002, seed=99,
+                                                          pool_size=pool_size, hi=8 << 20),
+                                  pool, Request)
+    srv.run(warm)
+    trace = workloads.serving_trace(rate=rate, duration=duration, pool_size=pool_size)
+    reqs = serving.build_requests(trace, pool, Request)
+    torch.cuda.synchronize()
+    _progress("serve: %d requests staged (%.1f s)" % (len(reqs), time.perf_counter() - t0))
+    b0, h0 = srv.cache.builds, srv.cache.hits
+    head = srv.run(reqs)
+    head["graph_builds"] -= b0
+    head["graph_hits"] -= h0
+    head["rate_offered"] = rate
+    head["hbm_frac_busy"] = (round(head["user_GBps_busy"] / HBM_PEAK_GBPS, 4)
+                             if head["user_GBps_busy"] else None)
+    _progress("serve: rate %.0f p50 %.3f ms p99 %.3f ms" % (rate, head["p50_ms"], head["p99_ms"]))
+    runs = []
+    for r2 in sweep:
+        scale = rate / r2 if r2 > 0 else 0.0
+        b0, h0 = srv.cache.builds, srv.cache.hits
+        st = srv.run(_fresh(reqs, Request), time_scale=scale)
+        st["graph_builds"] -= b0
+        st["graph_hits"] -= h0
+        st["rate_offered"] = r2 if r2 > 0 else "all_at_once"
+        st.pop("by_kind", None)
+        runs.append(st)
+        _progress("serve: rate %s p50 %.3f ms p99 %.3f ms busy %.1f GB/s"
+                  % (st["rate_offered"], st["p50_ms"], st["p99_ms"], st["user_GBps_busy"] or 0))
+    srv.close()
+    mix = {}
+    for r in reqs:
+        mix[r.kind] = mix.get(r.kind, 0) + 1
+    return {
+        "workload": "serving",
+        "trace": {"rate_per_s": rate, "duration_s": duration, "requests": len(reqs), "mix": mix,
+                  "pool_stripes": pool_size,
+                  "encode_input_GB": round(sum(r.x.numel() for r in reqs if r.kind == "encode") / 1e9, 2)},
+        "headline": head,
+        "saturation_sweep": runs,
+    }

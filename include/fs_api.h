@@ -128,6 +128,24 @@ FS_API fs_status fs_graph_export(const fs_graph *g, int32_t *row_ptr, int32_t *c
 FS_API void fs_graph_free(fs_graph *g);
 
 /*
+ * Device copy of a graph in caller memory, for request loops that keep
+ * graphs in memory they manage.  fs_graph_image_size gives the bytes of the
+ * copy (CSR, CSC and the encode segments, each 256-byte aligned).
+ * fs_graph_upload copies a graph built with FS_GRAPH_HOST_ONLY into dev_mem
+ * (device memory, 256-byte aligned, at least the image size, owned by the
+ * caller and kept while the graph is used) on `stream`, and makes the graph
+ * usable on the current device.  host_stage is null (the call returns after
+ * the copy has completed) or pinned host memory of at least the image size
+ * that the caller leaves untouched until the stream has passed the copy (the
+ * call then returns at once; work on other streams that uses the graph must
+ * be ordered after the copy).  fs_graph_free never frees dev_mem.
+ * Errors: FS_ERR_INVALID (null, or the graph already has a device copy),
+ * FS_ERR_ALIGN, FS_ERR_WORKSPACE (dev_mem too small), FS_ERR_HIP.
+ */
+FS_API fs_status fs_graph_image_size(const fs_graph *g, size_t *bytes);
+FS_API fs_status fs_graph_upload(fs_graph *g, void *dev_mem, size_t bytes, void *host_stage, hipStream_t stream);
+
+/*
  * Encode (§2.2 encoding step 2): c_g = XOR_{i in N(g)} x_i for every
  * g in [0, n).  x: device uint8[k][t]; c: device uint8[n][t] (written, not
  * read).  x and c must not overlap.
@@ -318,20 +336,27 @@ typedef struct fs_plan_info {
 FS_API fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_cache, uint32_t flags,
                                 hipStream_t stream, fs_plan **out);
 /*
- * Device bytes a plan of these items needs (workspace and descriptors), for
- * fs_plan_create_in.
+ * Memory a plan of these items needs for fs_plan_create_in: device_bytes of
+ * device memory (workspace and descriptors) and stage_bytes (may be null) of
+ * host staging for the descriptors.
  */
-FS_API fs_status fs_plan_memory_size(const fs_work *items, uint32_t count, size_t *bytes);
+FS_API fs_status fs_plan_memory_size(const fs_work *items, uint32_t count, size_t *device_bytes,
+                                     size_t *stage_bytes);
 /*
  * As fs_plan_create, but the plan lives in caller device memory mem (256-byte
- * aligned, at least fs_plan_memory_size bytes, owned by the caller and kept
- * until fs_plan_free) and is launched without a graph, all on the launch
- * stream: no device allocation, stream or graph is created.  For request
- * loops that build a plan per tick (FS_PLAN_AUTOTUNE is ignored; the process
- * tuning of fs_set_tune applies).
+ * aligned, at least device_bytes, owned by the caller and kept until
+ * fs_plan_free) and is launched without a graph, all on the launch stream: no
+ * device allocation, stream or graph is created.  For request loops that
+ * build a plan per tick (FS_PLAN_AUTOTUNE is ignored; the process tuning of
+ * fs_set_tune applies).  The workspace is cleared and the descriptors copied
+ * on `stream`: from host_stage (pinned host memory of at least stage_bytes,
+ * left untouched by the caller until the stream has passed the copy) the
+ * call returns at once; with host_stage null it returns after the copy.
+ * Errors: as fs_plan_create, and FS_ERR_ALIGN (mem), FS_ERR_WORKSPACE (mem or
+ * host_stage too small).
  */
 FS_API fs_status fs_plan_create_in(const fs_work *items, uint32_t count, void *mem, size_t mem_bytes,
-                                   hipStream_t stream, fs_plan **out);
+                                   void *host_stage, size_t stage_bytes, hipStream_t stream, fs_plan **out);
 /* Run the plan on a stream (asynchronous). */
 FS_API fs_status fs_plan_launch(fs_plan *plan, hipStream_t stream);
 /*

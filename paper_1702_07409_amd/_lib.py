@@ -15,6 +15,20 @@ LIB_PATH = os.path.join(PKG, "libfs.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError("libfs.so is not built (run python -m paper_1702_07409_amd.build)")
 
+
+def _torch_runtime_first():
+    """Initialise torch's HIP runtime before loading a library linked against
+    the system one: in a process that also uses torch, a library loaded
+    before torch's runtime is up has been seen to find no device."""
+    try:
+        import torch
+    except ImportError:
+        return
+    if torch.cuda.is_available():
+        torch.cuda.init()
+
+
+_torch_runtime_first()
 _lib = ctypes.CDLL(LIB_PATH)
 
 FS_OK, FS_ERR_INVALID, FS_ERR_ALIGN, FS_ERR_NOMEM, FS_ERR_HIP, FS_ERR_UNSUPPORTED, FS_ERR_WORKSPACE = range(7)
@@ -68,6 +82,8 @@ _SIGS = {
                        ctypes.POINTER(U32), ctypes.POINTER(U32)], ST),
     "fs_graph_export": ([P, P, P, P, P], ST),
     "fs_graph_free": ([P], None),
+    "fs_graph_image_size": ([P, ctypes.POINTER(SZ)], ST),
+    "fs_graph_upload": ([P, P, SZ, P, P], ST),
     "fs_workspace_size": ([P, I32, U64, U32, ctypes.POINTER(SZ)], ST),
     "fs_encode": ([P, P, P, U64, P], ST),
     "fs_peel": ([P, P, U32, P, P, P, P, P, P, SZ, P], ST),
@@ -79,8 +95,8 @@ _SIGS = {
     "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
-    "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ)], ST),
-    "fs_plan_create_in": ([ctypes.POINTER(fs_work), U32, P, SZ, P, ctypes.POINTER(P)], ST),
+    "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ST),
+    "fs_plan_create_in": ([ctypes.POINTER(fs_work), U32, P, SZ, P, SZ, P, ctypes.POINTER(P)], ST),
     "fs_plan_rebind": ([P, ctypes.POINTER(fs_work), U32, P], ST),
     "fs_plan_get_info": ([P, ctypes.POINTER(fs_plan_info)], ST),
     "fs_plan_free": ([P], None),
@@ -180,6 +196,19 @@ class Graph:
 
     def workspace_size(self, op, t=16, n_items=0):
         return fs_workspace_size(self, op, t, n_items)
+
+    def image_size(self):
+        b = SZ()
+        _check(_lib.fs_graph_image_size(self.handle, ctypes.byref(b)), "fs_graph_image_size")
+        return b.value
+
+    def upload(self, memory, stage=None, stream=None):
+        """Device copy into `memory` (a device uint8 tensor kept by the caller);
+        `stage`: optional pinned host uint8 tensor for an asynchronous copy."""
+        w, wb = _ws(memory)
+        sp = stage.data_ptr() if stage is not None else None
+        _check(_lib.fs_graph_upload(self.handle, w, wb, sp, _stream(stream)), "fs_graph_upload")
+        self._memory = memory
 
     def free(self):
         if self.handle:
@@ -307,24 +336,28 @@ def work(op, graph, t, x=None, c=None, erased=None, maxit=0, recovered=None, sta
 
 
 def plan_memory_size(items):
+    """(device bytes, host staging bytes) of fs_plan_create_in for these items."""
     arr = (fs_work * len(items))(*items)
-    b = SZ()
-    _check(_lib.fs_plan_memory_size(arr, len(items), ctypes.byref(b)), "fs_plan_memory_size")
-    return b.value
+    b, h = SZ(), SZ()
+    _check(_lib.fs_plan_memory_size(arr, len(items), ctypes.byref(b), ctypes.byref(h)), "fs_plan_memory_size")
+    return b.value, h.value
 
 
 class Plan:
     """Owner of an fs_plan handle.
 
     memory: optional device tensor (uint8) that holds the plan
-    (fs_plan_create_in: no allocation, no graph, one stream)."""
+    (fs_plan_create_in: no allocation, no graph, one stream); stage: optional
+    pinned host uint8 tensor for an asynchronous descriptor copy."""
 
-    def __init__(self, items, tune_cache=None, autotune=False, graph=True, stream=None, memory=None):
+    def __init__(self, items, tune_cache=None, autotune=False, graph=True, stream=None, memory=None,
+                 stage=None):
         arr = (fs_work * len(items))(*items)
         h = P()
         if memory is not None:
             w, wb = _ws(memory)
-            _check(_lib.fs_plan_create_in(arr, len(items), w, wb, _stream(stream), ctypes.byref(h)),
+            sp, sb = (stage.data_ptr(), stage.numel()) if stage is not None else (None, 0)
+            _check(_lib.fs_plan_create_in(arr, len(items), w, wb, sp, sb, _stream(stream), ctypes.byref(h)),
                    "fs_plan_create_in")
         else:
             flags = (FS_PLAN_AUTOTUNE if autotune else 0) | (0 if graph else FS_PLAN_NO_GRAPH)
@@ -334,6 +367,7 @@ class Plan:
         self.handle = h
         self._items = list(items)
         self._memory = memory
+        self._stage = stage
 
     def launch(self, stream=None):
         _check(_lib.fs_plan_launch(self.handle, _stream(stream)), "fs_plan_launch")

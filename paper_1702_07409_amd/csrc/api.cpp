@@ -52,11 +52,42 @@ static bool tune_ok(const fs_tune &t) {
   return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1;
 }
 
+// The device copy of a graph: eight arrays, each 256-byte aligned, in one buffer.
+void graph_image(const fs_graph &g, GraphImage &img) {
+  img.parts[0] = {g.row_ptr.data(), g.row_ptr.size() * 4, 0};
+  img.parts[1] = {g.col.data(), g.col.size() * 4, 0};
+  img.parts[2] = {g.col_ptr.data(), g.col_ptr.size() * 4, 0};
+  img.parts[3] = {g.rowidx.data(), g.rowidx.size() * 4, 0};
+  img.parts[4] = {g.seg_ptr.data(), g.seg_ptr.size() * 4, 0};
+  img.parts[5] = {g.seg_row.data(), g.seg_row.size() * 4, 0};
+  img.parts[6] = {g.heavy.data(), g.heavy.size() * 4, 0};
+  img.parts[7] = {g.seg_atomic.data(), g.seg_atomic.size(), 0};
+  size_t total = 0;
+  for (GraphImage::Part &pt : img.parts) {
+    pt.off = total;
+    total += (pt.bytes + 255) & ~size_t(255);
+  }
+  img.total = total + 256;
+}
+
+void bind_image(fs_graph &g, const GraphImage &img, void *base) {
+  uint8_t *p = static_cast<uint8_t *>(base);
+  g.d_row_ptr = reinterpret_cast<const int32_t *>(p + img.parts[0].off);
+  g.d_col = reinterpret_cast<const int32_t *>(p + img.parts[1].off);
+  g.d_col_ptr = reinterpret_cast<const int32_t *>(p + img.parts[2].off);
+  g.d_rowidx = reinterpret_cast<const int32_t *>(p + img.parts[3].off);
+  g.d_seg_ptr = reinterpret_cast<const int32_t *>(p + img.parts[4].off);
+  g.d_seg_row = reinterpret_cast<const int32_t *>(p + img.parts[5].off);
+  g.d_heavy = reinterpret_cast<const int32_t *>(p + img.parts[6].off);
+  g.d_seg_atomic = reinterpret_cast<const uint8_t *>(p + img.parts[7].off);
+}
+
 fs_status check_graph(const fs_graph *g) {
   if (!g) return fail(FS_ERR_INVALID, "graph is null");
-  if (!g->d_base) return fail(FS_ERR_INVALID, "graph was built host-only");
+  if (!g->d_row_ptr) return fail(FS_ERR_INVALID, "graph has no device copy (host-only and not uploaded)");
   int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(FS_ERR_HIP, "hipGetDevice failed");
+  if (const hipError_t e = hipGetDevice(&dev); e != hipSuccess)
+    return fail(FS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
   if (dev != g->device) return fail(FS_ERR_INVALID, "graph lives on another device");
   return FS_OK;
 }
@@ -293,55 +324,69 @@ fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_g
     return st;
   }
   if (!(params->flags & FS_GRAPH_HOST_ONLY)) {
-    if (hipGetDevice(&g->device) != hipSuccess) {
+    if (const hipError_t e = hipGetDevice(&g->device); e != hipSuccess) {
       delete g;
-      return fail(FS_ERR_HIP, "hipGetDevice failed");
+      return fail(FS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
     }
-    // every device array of the graph in one allocation
-    struct Part {
-      const void *src;
-      size_t bytes;
-      size_t off;
-    };
-    Part parts[8] = {{g->row_ptr.data(), g->row_ptr.size() * 4, 0},
-                     {g->col.data(), g->col.size() * 4, 0},
-                     {g->col_ptr.data(), g->col_ptr.size() * 4, 0},
-                     {g->rowidx.data(), g->rowidx.size() * 4, 0},
-                     {g->seg_ptr.data(), g->seg_ptr.size() * 4, 0},
-                     {g->seg_row.data(), g->seg_row.size() * 4, 0},
-                     {g->heavy.data(), g->heavy.size() * 4, 0},
-                     {g->seg_atomic.data(), g->seg_atomic.size(), 0}};
-    size_t total = 0;
-    for (Part &pt : parts) {
-      pt.off = total;
-      total += (pt.bytes + 255) & ~size_t(255);
-    }
+    GraphImage img;
+    graph_image(*g, img);
     void *base = nullptr;
-    if (hipMalloc(&base, total + 256) != hipSuccess) {
+    if (hipMalloc(&base, img.total) != hipSuccess) {
       delete g;
       return fail(FS_ERR_NOMEM, "device allocation for the graph failed");
     }
-    g->d_base = base;
-    uint8_t *p = static_cast<uint8_t *>(base);
     hipError_t e = hipSuccess;
-    for (const Part &pt : parts)
-      if (e == hipSuccess && pt.bytes) e = hipMemcpyAsync(p + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice, stream);
+    for (const GraphImage::Part &pt : img.parts)
+      if (e == hipSuccess && pt.bytes)
+        e = hipMemcpyAsync(static_cast<uint8_t *>(base) + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) {
       (void)hipFree(base);
       delete g;
       return fail(FS_ERR_HIP, std::string("graph upload: ") + hipGetErrorString(e));
     }
-    g->d_row_ptr = reinterpret_cast<const int32_t *>(p + parts[0].off);
-    g->d_col = reinterpret_cast<const int32_t *>(p + parts[1].off);
-    g->d_col_ptr = reinterpret_cast<const int32_t *>(p + parts[2].off);
-    g->d_rowidx = reinterpret_cast<const int32_t *>(p + parts[3].off);
-    g->d_seg_ptr = reinterpret_cast<const int32_t *>(p + parts[4].off);
-    g->d_seg_row = reinterpret_cast<const int32_t *>(p + parts[5].off);
-    g->d_heavy = reinterpret_cast<const int32_t *>(p + parts[6].off);
-    g->d_seg_atomic = reinterpret_cast<const uint8_t *>(p + parts[7].off);
+    g->d_base = base;
+    bind_image(*g, img, base);
   }
   *out = g;
+  return FS_OK;
+}
+
+fs_status fs_graph_image_size(const fs_graph *g, size_t *bytes) {
+  clear_error();
+  if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
+  GraphImage img;
+  graph_image(*g, img);
+  *bytes = img.total;
+  return FS_OK;
+}
+
+fs_status fs_graph_upload(fs_graph *g, void *dev_mem, size_t bytes, void *host_stage, hipStream_t stream) {
+  clear_error();
+  if (!g || !dev_mem) return fail(FS_ERR_INVALID, "graph and dev_mem must be non-null");
+  if (g->d_row_ptr) return fail(FS_ERR_INVALID, "graph is already on a device");
+  if (reinterpret_cast<uintptr_t>(dev_mem) & 255) return fail(FS_ERR_ALIGN, "dev_mem must be 256-byte aligned");
+  GraphImage img;
+  graph_image(*g, img);
+  if (bytes < img.total) return fail(FS_ERR_WORKSPACE, "graph image needs " + std::to_string(img.total) + " bytes");
+  int dev = 0;
+  if (const hipError_t e = hipGetDevice(&dev); e != hipSuccess)
+    return fail(FS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  uint8_t *dst = static_cast<uint8_t *>(dev_mem);
+  hipError_t e = hipSuccess;
+  if (host_stage) {
+    uint8_t *st = static_cast<uint8_t *>(host_stage);
+    for (const GraphImage::Part &pt : img.parts)
+      if (pt.bytes) std::memcpy(st + pt.off, pt.src, pt.bytes);
+    e = hipMemcpyAsync(dst, st, img.total, hipMemcpyHostToDevice, stream);
+  } else {
+    for (const GraphImage::Part &pt : img.parts)
+      if (e == hipSuccess && pt.bytes) e = hipMemcpyAsync(dst + pt.off, pt.src, pt.bytes, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  }
+  if (e != hipSuccess) return fail(FS_ERR_HIP, std::string("graph upload: ") + hipGetErrorString(e));
+  g->device = dev;
+  bind_image(*g, img, dev_mem);
   return FS_OK;
 }
 

@@ -258,6 +258,18 @@ struct UpdateBufs {
   uint32_t max_rows;
 };
 
+// Device copy of a graph: the eight arrays, 256-byte aligned, in one buffer.
+struct GraphImage {
+  struct Part {
+    const void *src;
+    size_t bytes;
+    size_t off;
+  } parts[8];
+  size_t total;
+};
+void graph_image(const fs_graph &g, GraphImage &img);
+void bind_image(fs_graph &g, const GraphImage &img, void *base);
+
 fs_tune current_tune();
 fs_status check_graph(const fs_graph *g);
 fs_status check_payload(const void *p, uint64_t t, const char *name);

@@ -46,6 +46,7 @@ struct fs_plan {
   size_t ws_bytes = 0;
   void *d_desc = nullptr;
   size_t desc_bytes = 0;
+  std::vector<uint8_t> himage;   // host image of the descriptor buffer
   GatherJob *d_gjobs = nullptr;
   unsigned long long *d_gprefix = nullptr;
   PeelJob *d_peels = nullptr;
@@ -302,8 +303,12 @@ T *place(uint8_t *base, size_t &off, size_t count) {
 }
 
 // Lay out every descriptor array in one device buffer (sizes are fixed for
-// the life of the plan) and copy the host arrays into it.
-fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate) {
+// the life of the plan), pack the same layout into a host image and copy it
+// with one transfer.  With `stage` (pinned host memory of >= desc_bytes that
+// the caller keeps until the stream passes the copy) the copy is
+// asynchronous; otherwise it is made from the plan's own host image and the
+// call waits for it.
+fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *stage = nullptr) {
   std::vector<GatherJob> tjobs;
   for (size_t i = 0; i < P.gjobs.size(); ++i)
     if (!P.gjob_accumulate[i]) tjobs.push_back(P.gjobs[i]);
@@ -333,23 +338,31 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate) {
     return FS_OK;   // caller allocates desc_bytes and calls again
   }
   if (off > P.desc_bytes) return fail(FS_ERR_INVALID, "descriptor layout changed");
-  auto put = [&](void *dst, const void *src, size_t bytes) -> fs_status {
-    if (!bytes) return FS_OK;
-    return hip_ok(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s), "descriptor upload");
+  uint8_t *img = static_cast<uint8_t *>(stage);
+  if (!img) {
+    P.himage.assign(P.desc_bytes, 0);
+    img = P.himage.data();
+  } else {
+    std::memset(img, 0, P.desc_bytes);
+  }
+  auto put = [&](const void *dst, const void *src, size_t bytes) {
+    if (bytes) std::memcpy(img + (static_cast<const uint8_t *>(dst) - base), src, bytes);
   };
-  PL_TRY(put(P.d_gjobs, P.gjobs.data(), P.gjobs.size() * sizeof(GatherJob)));
-  PL_TRY(put(P.d_gprefix, P.gprefix.data(), P.gprefix.size() * sizeof(unsigned long long)));
-  PL_TRY(put(P.d_peels, P.peels.data(), P.peels.size() * sizeof(PeelJob)));
-  PL_TRY(put(P.d_progs, P.progs.data(), P.progs.size() * sizeof(ProgJob)));
-  PL_TRY(put(P.d_replays, P.replays.data(), P.replays.size() * sizeof(ReplayJob)));
-  PL_TRY(put(P.d_rprefix, P.rprefix.data(), P.rprefix.size() * sizeof(uint32_t)));
-  PL_TRY(put(P.d_rpreps, P.rpreps.data(), P.rpreps.size() * sizeof(RepairPrepJob)));
-  PL_TRY(put(P.d_uplans, P.uplans.data(), P.uplans.size() * sizeof(UpdatePlanJob)));
-  PL_TRY(put(P.d_udeltas, P.udeltas.data(), P.udeltas.size() * sizeof(UpdateDeltaJob)));
-  PL_TRY(put(P.d_uprefix, P.uprefix.data(), P.uprefix.size() * sizeof(uint32_t)));
-  PL_TRY(put(P.d_zeros, P.zeros.data(), P.zeros.size() * sizeof(ZeroEntry)));
-  PL_TRY(put(P.d_tjobs, tjobs.data(), tjobs.size() * sizeof(GatherJob)));
-  PL_TRY(put(P.d_tprefix, tprefix.data(), tprefix.size() * sizeof(unsigned long long)));
+  put(P.d_gjobs, P.gjobs.data(), P.gjobs.size() * sizeof(GatherJob));
+  put(P.d_gprefix, P.gprefix.data(), P.gprefix.size() * sizeof(unsigned long long));
+  put(P.d_peels, P.peels.data(), P.peels.size() * sizeof(PeelJob));
+  put(P.d_progs, P.progs.data(), P.progs.size() * sizeof(ProgJob));
+  put(P.d_replays, P.replays.data(), P.replays.size() * sizeof(ReplayJob));
+  put(P.d_rprefix, P.rprefix.data(), P.rprefix.size() * sizeof(uint32_t));
+  put(P.d_rpreps, P.rpreps.data(), P.rpreps.size() * sizeof(RepairPrepJob));
+  put(P.d_uplans, P.uplans.data(), P.uplans.size() * sizeof(UpdatePlanJob));
+  put(P.d_udeltas, P.udeltas.data(), P.udeltas.size() * sizeof(UpdateDeltaJob));
+  put(P.d_uprefix, P.uprefix.data(), P.uprefix.size() * sizeof(uint32_t));
+  put(P.d_zeros, P.zeros.data(), P.zeros.size() * sizeof(ZeroEntry));
+  put(P.d_tjobs, tjobs.data(), tjobs.size() * sizeof(GatherJob));
+  put(P.d_tprefix, tprefix.data(), tprefix.size() * sizeof(unsigned long long));
+  PL_TRY(hip_ok(hipMemcpyAsync(P.d_desc, img, P.desc_bytes, hipMemcpyHostToDevice, s), "descriptor upload"));
+  if (!stage) PL_TRY(hip_ok(hipStreamSynchronize(s), "descriptor upload"));
   return FS_OK;
 }
 
@@ -623,9 +636,9 @@ fs_status fs_plan_get_info(const fs_plan *plan, fs_plan_info *info) {
 
 void fs_plan_free(fs_plan *plan) { release(plan); }
 
-fs_status fs_plan_memory_size(const fs_work *items, uint32_t count, size_t *bytes) {
+fs_status fs_plan_memory_size(const fs_work *items, uint32_t count, size_t *device_bytes, size_t *stage_bytes) {
   clear_error();
-  if (!bytes || (count && !items)) return fail(FS_ERR_INVALID, "items and bytes must be non-null");
+  if (!device_bytes || (count && !items)) return fail(FS_ERR_INVALID, "items and device_bytes must be non-null");
   for (uint32_t i = 0; i < count; ++i) PL_TRY(check_item(items[i], i));
   fs_plan P;
   P.items.assign(items, items + count);
@@ -638,12 +651,13 @@ fs_status fs_plan_memory_size(const fs_work *items, uint32_t count, size_t *byte
   P.ws_bytes = cv.size();
   build_descriptors(P);
   PL_TRY(upload_descriptors(P, nullptr, true));
-  *bytes = P.ws_bytes + P.desc_bytes + 512;
+  *device_bytes = P.ws_bytes + P.desc_bytes + 512;
+  if (stage_bytes) *stage_bytes = P.desc_bytes;
   return FS_OK;
 }
 
-fs_status fs_plan_create_in(const fs_work *items, uint32_t count, void *mem, size_t mem_bytes, hipStream_t stream,
-                            fs_plan **out) {
+fs_status fs_plan_create_in(const fs_work *items, uint32_t count, void *mem, size_t mem_bytes, void *host_stage,
+                            size_t stage_bytes, hipStream_t stream, fs_plan **out) {
   clear_error();
   if (!out || (count && !items)) return fail(FS_ERR_INVALID, "items and out must be non-null");
   if (!mem || (reinterpret_cast<uintptr_t>(mem) & 255)) return fail(FS_ERR_ALIGN, "mem must be 256-byte aligned");
@@ -666,12 +680,14 @@ fs_status fs_plan_create_in(const fs_work *items, uint32_t count, void *mem, siz
   fs_status st = upload_descriptors(*P, stream, true);
   if (st == FS_OK && P->ws_bytes + P->desc_bytes > mem_bytes)
     st = fail(FS_ERR_WORKSPACE, "plan memory too small: need " + std::to_string(P->ws_bytes + P->desc_bytes));
+  if (st == FS_OK && host_stage && stage_bytes < P->desc_bytes)
+    st = fail(FS_ERR_WORKSPACE, "host stage too small: need " + std::to_string(P->desc_bytes));
   if (st == FS_OK) {
     P->d_desc = static_cast<uint8_t *>(mem) + P->ws_bytes;
     // flags of the workspace start cleared; descriptors follow
-    st = hip_ok(hipMemsetAsync(P->d_ws, 0, P->ws_bytes, stream), "plan workspace clear");
+    if (P->ws_bytes) st = hip_ok(hipMemsetAsync(P->d_ws, 0, P->ws_bytes, stream), "plan workspace clear");
   }
-  if (st == FS_OK) st = upload_descriptors(*P, stream, false);
+  if (st == FS_OK) st = upload_descriptors(*P, stream, false, host_stage);
   if (st != FS_OK) {
     const std::string msg = fs_last_error();
     release(P);

@@ -8,6 +8,12 @@ import os
 LIB = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynth.so")
 if not os.path.exists(LIB):
     raise ImportError("synth/libsynth.so is not built")
+try:   # torch's HIP runtime first (the library links the system one)
+    import torch as _torch
+    if _torch.cuda.is_available():
+        _torch.cuda.init()
+except ImportError:
+    pass
 _lib = ctypes.CDLL(LIB)
 _lib.synth_fill.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                             ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]

@@ -14,6 +14,11 @@ content, so seeded uniform bytes stand in for the paper's unspecified files.
                 4 % erasures
   resident256   256 stripes, k=1024 x 256 KiB, n=1126, RSD (c=0.1, delta=0.05);
                 1-4 lost coded rows per stripe, 10 updated inputs per stripe
+  serving       Poisson arrivals of encode / decode / repair / update requests
+                (50/30/15/5 %), payloads log-uniform in [64 KiB, 256 MiB),
+                blocks of 16, 64 or 256 KiB, k = ceil(P / B), n = max(k+1,
+                round(1.1 k)), RSD (c=0.1, delta=0.05); decode, repair and
+                update target a resident pool of 256 such stripes
 """
 
 from dataclasses import dataclass, field, replace
@@ -130,3 +135,70 @@ def resident256(count=256):
                                                 max(1, gen.round_half_up(0.01 * sp.k)))
         out.append(sp)
     return out
+
+
+# ---------------------------------------------------------------- serving
+
+SERVE_MIX = (("encode", 0.50), ("decode", 0.30), ("repair", 0.15), ("update", 0.05))
+SERVE_BLOCKS = (16 << 10, 64 << 10, 256 << 10)
+
+
+def serve_stripe(stripe, payload, block):
+    """A stripe holding `payload` bytes in blocks of `block` bytes (the last
+    block zero-padded): k = ceil(P / B), n = max(k + 1, round(1.1 k)),
+    Robust Soliton (c = 0.1, delta = 0.05); stripes of equal (k, n) share
+    one graph (stripe key 0)."""
+    k = max(1, -(-payload // block))
+    n = max(k + 1, gen.overhead_n(k, 0.10))
+    return StripeSpec(stripe=stripe, k=k, n=n, t=block, dist="rsd", rsd_c=0.1, rsd_delta=0.05,
+                      stripe_key=0, n_erased=gen.round_half_up(0.05 * n),
+                      extra={"payload": payload})
+
+
+def serve_payload(u, lo=64 << 10, hi=256 << 20):
+    """Log-uniform payload size in [lo, hi)."""
+    return int(math.floor(lo * (hi / lo) ** u))
+
+
+def serving_pool(count=256, seed=SERVE_SEED, hi=256 << 20):
+    """Resident stripes targeted by decode, repair and update requests."""
+    out = []
+    for s in range(count):
+        key = gen.stream_key(seed, gen.WORKLOAD, 5, s)
+        P = serve_payload(gen.uniform01(gen.draw(key, 0)), hi=hi)
+        B = SERVE_BLOCKS[int(gen.uniform01(gen.draw(key, 1)) * len(SERVE_BLOCKS))]
+        out.append(serve_stripe(1_000_000 + s, P, B))
+    return out
+
+
+def serving_trace(rate=2000.0, duration=1.0, seed=SERVE_SEED, pool_size=256, hi=256 << 20):
+    """Requests with Poisson arrivals at `rate` per second over `duration` s.
+
+    Request r draws from key(seed, ARRIVAL, 0, r): u0 the exponential gap,
+    u1 the type (50/30/15/5 % encode/decode/repair/update), u2 the payload
+    (encode) or the target stripe of the pool (others), u3 the block size.
+    Decode erases 5 % of the target's coded blocks; repair loses 1-4 coded
+    blocks; update rewrites 1 % (at least one) of the target's inputs.
+    """
+    reqs, t, r = [], 0.0, 0
+    while True:
+        key = gen.stream_key(seed, gen.ARRIVAL, 0, r)
+        u = [gen.uniform01(gen.draw(key, i)) for i in range(4)]
+        t += -math.log(1.0 - u[0]) / rate
+        if t >= duration:
+            break
+        acc, kind = 0.0, SERVE_MIX[-1][0]
+        for name, p in SERVE_MIX:
+            acc += p
+            if u[1] < acc:
+                kind = name
+                break
+        req = {"id": r, "t": t, "type": kind}
+        if kind == "encode":
+            req["payload"] = serve_payload(u[2], hi=hi)
+            req["block"] = SERVE_BLOCKS[int(u[3] * len(SERVE_BLOCKS))]
+        else:
+            req["target"] = int(u[2] * pool_size)
+        reqs.append(req)
+        r += 1
+    return reqs

@@ -106,3 +106,16 @@ def test_workspace_sizes_and_host_only_graph_rejects_payload_calls():
     assert fs.fs_workspace_size(g, fs.FS_OP_UPDATE, 4096, 10) >= 10 * 4096
     with pytest.raises(fs.FsError):
         fs.fs_workspace_size(g, fs.FS_OP_UPDATE, 4100, 10)
+
+
+def test_graph_image_size_covers_every_array():
+    import paper_1702_07409_amd as fs
+    g = fs.fs_graph_build(k=300, n=330, dist="rsd", rsd_c=0.05, rsd_delta=0.01, seed=1, host_only=True)
+    rp, col, cp, ri = g.export()
+    al = lambda b: (b + 255) // 256 * 256
+    # CSR, CSC, and the encode segments (at most one per 64 edges plus one per row)
+    base = al(rp.nbytes) + al(col.nbytes) + al(cp.nbytes) + al(ri.nbytes)
+    size = g.image_size()
+    assert size % 256 == 0 and size >= base + 256
+    segs = sum(-(-int(rp[j + 1] - rp[j]) // 64) for j in range(g.n))
+    assert size <= base + al(4 * (segs + 1)) + al(4 * segs) + al(4 * g.n) + al(segs) + 256

@@ -169,3 +169,57 @@ def test_plan_rejects_bad_items():
     with pytest.raises(fs.FsError) as e:
         fs.Plan([fs.work("encode", g, 4100, x=empty_u8(sp.k * 4112), c=empty_u8(sp.n * 4112))])
     assert e.value.status == fs._lib.FS_ERR_ALIGN
+
+
+@pytest.mark.parametrize("staged", [False, True])
+def test_plan_in_caller_memory(staged):
+    import paper_1702_07409_amd as fs
+    import torch
+    b = Batch(data_seed=5)
+    dev_bytes, stage_bytes = fs.plan_memory_size(b.items)
+    assert 0 < stage_bytes < dev_bytes
+    mem = torch.empty(dev_bytes, dtype=torch.uint8, device="cuda")
+    stage = torch.empty(stage_bytes, dtype=torch.uint8, pin_memory=True) if staged else None
+    s = torch.cuda.Stream()
+    plan = fs.Plan(b.items, memory=mem, stage=stage, stream=s)
+    plan.launch(stream=s)
+    s.synchronize()
+    b.verify()
+    plan.free()
+    with pytest.raises(fs.FsError) as e:
+        fs.Plan(b.items, memory=mem[:1024], stream=s)
+    assert e.value.status == fs._lib.FS_ERR_WORKSPACE
+    if staged:
+        with pytest.raises(fs.FsError) as e:
+            fs.Plan(b.items, memory=mem, stage=stage[:16], stream=s)
+        assert e.value.status == fs._lib.FS_ERR_WORKSPACE
+
+
+def test_graph_in_caller_memory():
+    import paper_1702_07409_amd as fs
+    import torch
+    sp = S(stripe=60, k=700, n=780, t=1024, dist="rsd", stripe_key=60)
+    owned, G = graphs(**sp.graph_kwargs())
+    x = dev(gen.payload(0, sp.stripe, sp.k, sp.t))
+    want = codec.encode(G, host(x))
+    for staged in (False, True):
+        g = fs.fs_graph_build(host_only=True, **sp.graph_kwargs())
+        nbytes = g.image_size()
+        mem = torch.empty(nbytes + 512, dtype=torch.uint8, device="cuda")
+        stage = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True) if staged else None
+        s = torch.cuda.Stream()
+        with pytest.raises(fs.FsError) as e:
+            g.upload(mem[:64], stream=s)
+        assert e.value.status == fs._lib.FS_ERR_WORKSPACE
+        g.upload(mem, stage=stage, stream=s)
+        c = empty_u8(sp.n, sp.t)
+        fs.fs_encode(g, x, c, sp.t, stream=s)
+        s.synchronize()
+        assert np.array_equal(host(c), want)
+        with pytest.raises(fs.FsError) as e:
+            g.upload(mem, stream=s)
+        assert e.value.status == fs._lib.FS_ERR_INVALID
+        g.free()
+    with pytest.raises(fs.FsError) as e:
+        owned.upload(torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
+    assert e.value.status == fs._lib.FS_ERR_INVALID
