@@ -30,12 +30,17 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
 PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "encode_large_stripe_traffic.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_1702_07409_amd", "csrc", "kernels.hip")
+CSRC = os.path.join(ROOT, "paper_1702_07409_amd", "csrc")
 
 
 def kernel_source_hash():
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of every library source (kernels, launch choices, graph layout):
+    counters taken on other sources are not reported."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():

@@ -52,7 +52,7 @@ static bool tune_ok(const fs_tune &t) {
   return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1;
 }
 
-// The device copy of a graph: eight arrays, each 256-byte aligned, in one buffer.
+// The device copy of a graph: nine arrays, each 256-byte aligned, in one buffer.
 void graph_image(const fs_graph &g, GraphImage &img) {
   img.parts[0] = {g.row_ptr.data(), g.row_ptr.size() * 4, 0};
   img.parts[1] = {g.col.data(), g.col.size() * 4, 0};
@@ -62,6 +62,7 @@ void graph_image(const fs_graph &g, GraphImage &img) {
   img.parts[5] = {g.seg_row.data(), g.seg_row.size() * 4, 0};
   img.parts[6] = {g.heavy.data(), g.heavy.size() * 4, 0};
   img.parts[7] = {g.seg_atomic.data(), g.seg_atomic.size(), 0};
+  img.parts[8] = {g.seg_col.data(), g.seg_col.size() * 4, 0};
   size_t total = 0;
   for (GraphImage::Part &pt : img.parts) {
     pt.off = total;
@@ -80,6 +81,7 @@ void bind_image(fs_graph &g, const GraphImage &img, void *base) {
   g.d_seg_row = reinterpret_cast<const int32_t *>(p + img.parts[5].off);
   g.d_heavy = reinterpret_cast<const int32_t *>(p + img.parts[6].off);
   g.d_seg_atomic = reinterpret_cast<const uint8_t *>(p + img.parts[7].off);
+  g.d_seg_col = reinterpret_cast<const int32_t *>(p + img.parts[8].off);
 }
 
 fs_status check_graph(const fs_graph *g) {
@@ -477,7 +479,7 @@ GatherJob encode_job(const fs_graph *g, const void *x, void *c, uint64_t t) {
   j.dst = static_cast<uint8_t *>(c);
   j.dst_stride = t;
   j.ptr = g->d_seg_ptr;
-  j.idx = g->d_col;
+  j.idx = g->d_seg_col;
   j.out_map = g->d_seg_row;
   j.seg_atomic = g->heavy.empty() ? nullptr : g->d_seg_atomic;
   j.nrows = (uint32_t)g->seg_row.size();

@@ -19,16 +19,17 @@ struct fs_graph {
   std::vector<int32_t> row_ptr, col, col_ptr, rowidx;
   // Encode segments: rows cut into runs of at most kSegMax edges, so that a
   // row of huge degree (the Robust Soliton tail) is spread over many
-  // workgroups.  seg_ptr[s]..seg_ptr[s+1] are edges of row seg_row[s];
-  // seg_atomic[s] = 1 when the row has several segments (combined by atomic
-  // XOR into a zeroed row); heavy lists those rows once.
-  std::vector<int32_t> seg_ptr, seg_row, heavy;
+  // workgroups, ordered longest first.  seg_col[seg_ptr[s]..seg_ptr[s+1]) are
+  // the edges of segment s, part of row seg_row[s]; seg_atomic[s] = 1 when
+  // the row has several segments (combined by atomic XOR into a zeroed row);
+  // heavy lists those rows once.
+  std::vector<int32_t> seg_ptr, seg_row, seg_col, heavy;
   std::vector<uint8_t> seg_atomic;
   int device = -1;
   void *d_base = nullptr;
   const int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_col_ptr = nullptr,
                 *d_rowidx = nullptr;
-  const int32_t *d_seg_ptr = nullptr, *d_seg_row = nullptr, *d_heavy = nullptr;
+  const int32_t *d_seg_ptr = nullptr, *d_seg_row = nullptr, *d_seg_col = nullptr, *d_heavy = nullptr;
   const uint8_t *d_seg_atomic = nullptr;
 };
 
@@ -215,8 +216,14 @@ fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long 
                               uint64_t total_items, hipStream_t s);
 fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, bool lds, size_t lds_bytes, hipStream_t s);
 fs_status launch_prog_batch(const ProgJob *d_jobs, uint32_t njobs, hipStream_t s);
+// prog_lds: dynamic LDS of each workgroup, enough for the 16-bit program of
+// the largest item (replay_prog_lds_bound); items whose program does not fit
+// read it from global memory
 fs_status launch_replay_batch(const ReplayJob *d_rj, const ProgJob *d_pj, const uint32_t *d_wg_prefix,
-                              uint32_t nitems, uint32_t total_wg, hipStream_t s);
+                              uint32_t nitems, uint32_t total_wg, size_t prog_lds, hipStream_t s);
+// largest LDS size of the 16-bit replay program of a graph with k inputs and
+// pidx_cap program entries
+size_t replay_prog_lds_bound(uint32_t k, uint32_t pidx_cap);
 fs_status launch_repair_prep_batch(const RepairPrepJob *d_jobs, uint32_t njobs, hipStream_t s);
 fs_status launch_update_plan_batch(const UpdatePlanJob *d_jobs, uint32_t njobs, hipStream_t s);
 fs_status launch_update_delta_batch(const UpdateDeltaJob *d_jobs, const uint32_t *d_prefix, uint32_t njobs,
@@ -258,13 +265,13 @@ struct UpdateBufs {
   uint32_t max_rows;
 };
 
-// Device copy of a graph: the eight arrays, 256-byte aligned, in one buffer.
+// Device copy of a graph: its nine arrays, 256-byte aligned, in one buffer.
 struct GraphImage {
   struct Part {
     const void *src;
     size_t bytes;
     size_t off;
-  } parts[8];
+  } parts[9];
   size_t total;
 };
 void graph_image(const fs_graph &g, GraphImage &img);

@@ -169,20 +169,41 @@ fs_status build_host_graph(const fs_graph_params &p, fs_graph &g) {
   for (uint32_t i = 0; i < k; ++i)
     max_cdeg = std::max<uint32_t>(max_cdeg, (uint32_t)(g.col_ptr[i + 1] - g.col_ptr[i]));
   g.max_cdeg = max_cdeg;
-  // encode segments
-  g.seg_ptr.assign(1, 0);
-  g.seg_row.clear();
-  g.seg_atomic.clear();
+  // encode segments: rows longer than kSegMax are cut into kSegMax-edge
+  // pieces; the pieces are then ordered by length (longest first, stable) and
+  // their edges copied into seg_col in that order, so that a tile of
+  // consecutive segments holds segments of equal or similar length (the
+  // lanes of a wave then finish together) and its edges stay contiguous.
+  std::vector<int32_t> sb, se, srow;
+  std::vector<uint8_t> sat;
   g.heavy.clear();
   for (uint32_t j = 0; j < n; ++j) {
     const int32_t e0 = g.row_ptr[j], e1 = g.row_ptr[j + 1];
     const bool split = (uint32_t)(e1 - e0) > kSegMax;
     if (split) g.heavy.push_back((int32_t)j);
     for (int32_t e = e0; e < e1; e += (int32_t)kSegMax) {
-      g.seg_ptr.push_back(std::min<int32_t>(e1, e + (int32_t)kSegMax));
-      g.seg_row.push_back((int32_t)j);
-      g.seg_atomic.push_back(split ? 1 : 0);
+      sb.push_back(e);
+      se.push_back(std::min<int32_t>(e1, e + (int32_t)kSegMax));
+      srow.push_back((int32_t)j);
+      sat.push_back(split ? 1 : 0);
     }
+  }
+  const size_t ns = sb.size();
+  std::vector<uint32_t> order(ns);
+  for (size_t i = 0; i < ns; ++i) order[i] = (uint32_t)i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](uint32_t a, uint32_t b) { return se[a] - sb[a] > se[b] - sb[b]; });
+  g.seg_ptr.assign(1, 0);
+  g.seg_row.resize(ns);
+  g.seg_atomic.resize(ns);
+  g.seg_col.resize(g.nnz);
+  size_t pos = 0;
+  for (size_t i = 0; i < ns; ++i) {
+    const uint32_t s = order[i];
+    for (int32_t e = sb[s]; e < se[s]; ++e) g.seg_col[pos++] = g.col[e];
+    g.seg_ptr.push_back((int32_t)pos);
+    g.seg_row[i] = srow[s];
+    g.seg_atomic[i] = sat[s];
   }
   return FS_OK;
 }

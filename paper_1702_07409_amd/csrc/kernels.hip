@@ -312,6 +312,7 @@ hipError_t run_gather_nt(const GatherJob &j, const fs_tune &t, hipStream_t s, in
 // level-synchronous peeling schedule
 // ---------------------------------------------------------------------------
 constexpr int kPeelThreads = 1024;
+constexpr int kPeelBatch = 8;   // column entries loaded before any is applied
 constexpr unsigned long long kCountOne = 1ull << 40;   // acc = count << 40 | sum of ids
 constexpr unsigned long long kSumMask = kCountOne - 1;
 // Erased rows start with a count far above any degree (2^23): removing all
@@ -441,7 +442,14 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   // have huge degree
   for (uint32_t i = tid; i < k; i += kPeelThreads) {
     const int c1 = S.cptr[i + 1];
-    for (int e = S.cptr[i]; e < c1; ++e) atomicAdd(&S.acc[J.rowidx[e]], (unsigned long long)i);
+    for (int e = S.cptr[i]; e < c1; e += kPeelBatch) {
+      int32_t h[kPeelBatch];
+#pragma unroll
+      for (int u = 0; u < kPeelBatch; ++u) h[u] = e + u < c1 ? J.rowidx[e + u] : -1;
+#pragma unroll
+      for (int u = 0; u < kPeelBatch; ++u)
+        if (h[u] >= 0) atomicAdd(&S.acc[h[u]], (unsigned long long)i);
+    }
   }
   __syncthreads();
 
@@ -480,10 +488,17 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
         const uint32_t f = (uint32_t)S.dl[q];
         const unsigned long long dec = 0ull - (kCountOne | f);
         const int c1 = S.cptr[f + 1];
-        for (int e = S.cptr[f]; e < c1; ++e) {
-          const int32_t h = J.rowidx[e];
-          const unsigned long long old = atomicAdd(&S.acc[h], dec);
-          if ((old >> 40) == 2ull) nxt[atomicAdd(&s_nB, 1)] = h;
+        for (int e = S.cptr[f]; e < c1; e += kPeelBatch) {
+          // the column's row ids are loaded together, then applied
+          int32_t h[kPeelBatch];
+#pragma unroll
+          for (int u = 0; u < kPeelBatch; ++u) h[u] = e + u < c1 ? J.rowidx[e + u] : -1;
+#pragma unroll
+          for (int u = 0; u < kPeelBatch; ++u) {
+            if (h[u] < 0) continue;
+            const unsigned long long old = atomicAdd(&S.acc[h[u]], dec);
+            if ((old >> 40) == 2ull) nxt[atomicAdd(&s_nB, 1)] = h[u];
+          }
         }
       }
     }
@@ -591,11 +606,16 @@ __device__ __forceinline__ void prog_body(const ProgJob &P) {
         P.gsrc[f[u]] = g[u];
         P.finv[g[u]] = f[u];
       }
-      for (int e = r0[u]; e < r1[u] && o < end; ++e) {
-        const int32_t i = P.col[e];
-        if (i != f[u]) {
-          if (fits) P.pidx[o] = i;
-          ++o;
+      for (int e = r0[u]; e < r1[u] && o < end; e += G) {
+        int32_t cv[G];
+#pragma unroll
+        for (int v = 0; v < G; ++v) cv[v] = e + v < r1[u] ? P.col[e + v] : f[u];
+#pragma unroll
+        for (int v = 0; v < G; ++v) {
+          if (cv[v] != f[u] && o < end) {
+            if (fits) P.pidx[o] = cv[v];
+            ++o;
+          }
         }
       }
       o = end;
@@ -746,7 +766,7 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
                                                    const IT *poff, const IT *pidx, int L, int nR,
                                                    uint32_t nslices, uint32_t vb, uint32_t stride) {
   constexpr int NS = kReplayThreads / LPS;
-  constexpr int MP = 4;                 // pairs per thread whose coded block is prefetched
+  constexpr int MP = LPS >= 32 ? 4 : 2;   // pairs per thread whose coded block is prefetched
   constexpr uint32_t W = LPS * 16;
   const uint32_t lane = threadIdx.x % LPS, sym = threadIdx.x / LPS;
   const uint32_t k = J.k;
@@ -843,9 +863,11 @@ __device__ __forceinline__ void replay_wide_body(const ReplayJob &J, const ProgJ
   }
 }
 
+// Narrow slices (LPS <= 16) run two workgroups per CU: registers are capped
+// for 8 waves per SIMD, so a level's pairs fit one round of the two groups.
 template <int LPS>
-__global__ __launch_bounds__(kReplayThreads) void replay_wide_kernel(ReplayJob J, ProgJob P, uint32_t nslices,
-                                                                    uint32_t lds_bytes, uint32_t prog_lds) {
+__global__ __launch_bounds__(kReplayThreads) __attribute__((amdgpu_waves_per_eu(LPS <= 16 ? 8 : 1)))
+void replay_wide_kernel(ReplayJob J, ProgJob P, uint32_t nslices, uint32_t lds_bytes, uint32_t prog_lds) {
   replay_wide_body<LPS>(J, P, nslices, lds_bytes, prog_lds, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
@@ -1237,8 +1259,11 @@ static hipError_t run_replay_wide(const ReplayJob &job, const ProgJob &prog, int
   const uint32_t w = 16u * LPS;
   const uint32_t nslices = (uint32_t)((job.t + w - 1) / w);
   const uint32_t grid = std::min<uint32_t>(nslices, (uint32_t)cu * 2);
-  hipLaunchKernelGGL(replay_wide_kernel<LPS>, dim3(grid), dim3(kReplayThreads), budget, s, job, prog, nslices,
-                     (uint32_t)budget, tune_snapshot().replay_prog_global ? 0u : 1u);
+  // LDS for the 16-bit program: its largest possible size (the kernel checks
+  // the actual one), so that two workgroups share a CU when it is small
+  const int lds = (int)std::min<size_t>((size_t)budget, replay_prog_lds_bound(job.k, prog.pidx_cap));
+  hipLaunchKernelGGL(replay_wide_kernel<LPS>, dim3(grid), dim3(kReplayThreads), lds, s, job, prog, nslices,
+                     (uint32_t)lds, tune_snapshot().replay_prog_global ? 0u : 1u);
   return hipGetLastError();
 }
 
@@ -1294,14 +1319,16 @@ fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStrea
       default: e = run_replay_lds_m<8>(job, *prog, mneed, nslices, grid, budget, dev, s); break;
     }
   } else {
-    // large k: wide slices in global memory, about one workgroup per CU
-    const uint64_t per = (job.t + cu - 1) / cu;
+    // large k: wide slices in global memory, about two workgroups per CU
+    const uint64_t per = (job.t + 2ull * cu - 1) / (2ull * cu);
     if (per >= 1024)
       e = run_replay_wide<64>(job, *prog, budget, dev, cu, s);
     else if (per >= 512)
       e = run_replay_wide<32>(job, *prog, budget, dev, cu, s);
-    else
+    else if (per >= 256)
       e = run_replay_wide<16>(job, *prog, budget, dev, cu, s);
+    else
+      e = run_replay_wide<8>(job, *prog, budget, dev, cu, s);
   }
   return hip_check(e, "replay launch");
 }
@@ -1395,16 +1422,22 @@ fs_status launch_prog_batch(const ProgJob *d_jobs, uint32_t njobs, hipStream_t s
   return hip_check(hipGetLastError(), "batched program launch");
 }
 
+size_t replay_prog_lds_bound(uint32_t k, uint32_t pidx_cap) {
+  const uint64_t bound = 2ull * (2ull * (k + 1) + 2ull * k + pidx_cap) + 256;
+  return (size_t)((bound + 255) & ~255ull);
+}
+
 fs_status launch_replay_batch(const ReplayJob *d_rj, const ProgJob *d_pj, const uint32_t *d_wg_prefix,
-                              uint32_t nitems, uint32_t total_wg, hipStream_t s) {
+                              uint32_t nitems, uint32_t total_wg, size_t prog_lds, hipStream_t s) {
   if (nitems == 0 || total_wg == 0) return FS_OK;
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int budget = device_info(dev).max_lds_per_block;
   static bool done[64] = {false};
   set_max_lds(reinterpret_cast<const void *>(&replay_batch_kernel<kBatchReplayLanes>), dev, budget, done);
-  hipLaunchKernelGGL(replay_batch_kernel<kBatchReplayLanes>, dim3(total_wg), dim3(kReplayThreads), budget, s, d_rj,
-                     d_pj, d_wg_prefix, nitems, (uint32_t)budget, tune_snapshot().replay_prog_global ? 0u : 1u);
+  const int lds = (int)std::min<size_t>((size_t)budget, prog_lds);
+  hipLaunchKernelGGL(replay_batch_kernel<kBatchReplayLanes>, dim3(total_wg), dim3(kReplayThreads), lds, s, d_rj,
+                     d_pj, d_wg_prefix, nitems, (uint32_t)lds, tune_snapshot().replay_prog_global ? 0u : 1u);
   return hip_check(hipGetLastError(), "batched replay launch");
 }
 

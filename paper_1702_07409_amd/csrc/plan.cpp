@@ -39,6 +39,7 @@ struct fs_plan {
   uint64_t zero_max_t = 0;
   bool peel_lds = true;
   size_t peel_lds_bytes = 0;
+  size_t replay_lds = 256;   // dynamic LDS of the batched replay
   uint32_t gather_grid = 0;
 
   // device memory
@@ -163,6 +164,7 @@ void build_descriptors(fs_plan &P) {
   P.zero_max_t = 0;
   P.peel_lds = true;
   P.peel_lds_bytes = 0;
+  P.replay_lds = 256;
   int dev = 0;
   (void)hipGetDevice(&dev);
   const size_t lds_budget = (size_t)device_info(dev).max_lds_per_block - 64;
@@ -197,6 +199,7 @@ void build_descriptors(fs_plan &P) {
         ProgJob prog = b.dec.prog;
         prog.status = status;
         P.progs.push_back(prog);
+        P.replay_lds = std::max(P.replay_lds, replay_prog_lds_bound(g->k, prog.pidx_cap));
         P.replays.push_back(replay_job(g, w.c, w.x, w.t, status, b.dec.sched.level_ptr, b.dec.sched.dp_f,
                                        b.dec.sched.dp_g));
         const uint64_t wsl = 16ull * kBatchReplayLanes;
@@ -384,7 +387,8 @@ fs_status enqueue(fs_plan &P, hipStream_t s) {
   // branch A: decodes (schedule, program, replay)
   PL_TRY(launch_peel_batch(P.d_peels, (uint32_t)P.peels.size(), P.peel_lds, P.peel_lds_bytes, a));
   PL_TRY(launch_prog_batch(P.d_progs, (uint32_t)P.progs.size(), a));
-  PL_TRY(launch_replay_batch(P.d_replays, P.d_progs, P.d_rprefix, (uint32_t)P.replays.size(), P.rprefix.back(), a));
+  PL_TRY(launch_replay_batch(P.d_replays, P.d_progs, P.d_rprefix, (uint32_t)P.replays.size(), P.rprefix.back(),
+                             P.replay_lds, a));
   // branch B: zeroing, checks, update planning, then the persistent gather
   PL_TRY(launch_zero_batch(P.d_zeros, (uint32_t)P.zeros.size(), P.zero_max_t, s));
   PL_TRY(launch_repair_prep_batch(P.d_rpreps, (uint32_t)P.rpreps.size(), s));

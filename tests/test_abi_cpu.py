@@ -113,8 +113,9 @@ def test_graph_image_size_covers_every_array():
     g = fs.fs_graph_build(k=300, n=330, dist="rsd", rsd_c=0.05, rsd_delta=0.01, seed=1, host_only=True)
     rp, col, cp, ri = g.export()
     al = lambda b: (b + 255) // 256 * 256
-    # CSR, CSC, and the encode segments (at most one per 64 edges plus one per row)
-    base = al(rp.nbytes) + al(col.nbytes) + al(cp.nbytes) + al(ri.nbytes)
+    # CSR, CSC, the encode segments (at most one per 64 edges plus one per
+    # row) and their edge list
+    base = al(rp.nbytes) + al(col.nbytes) + al(cp.nbytes) + al(ri.nbytes) + al(col.nbytes)
     size = g.image_size()
     assert size % 256 == 0 and size >= base + 256
     segs = sum(-(-int(rp[j + 1] - rp[j]) // 64) for j in range(g.n))
