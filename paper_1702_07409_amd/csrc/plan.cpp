@@ -37,6 +37,14 @@ struct fs_plan {
   std::vector<uint32_t> uprefix;
   std::vector<ZeroEntry> zeros;
   uint64_t zero_max_t = 0;
+  // large jobs run as launches of their own: gathers (1 = accumulating) and
+  // the replays of large decodes (program index into progs)
+  std::vector<GatherJob> solo;
+  std::vector<uint8_t> solo_accumulate;
+  std::vector<ReplayJob> solo_replays;
+  std::vector<uint32_t> solo_replay_prog;
+  std::vector<ProgJob> replay_progs;   // programs of the batched replays, in their order
+  std::vector<PeelJob> peels_global;   // schedules too large for LDS
   bool peel_lds = true;
   size_t peel_lds_bytes = 0;
   size_t replay_lds = 256;   // dynamic LDS of the batched replay
@@ -51,8 +59,10 @@ struct fs_plan {
   GatherJob *d_gjobs = nullptr;
   unsigned long long *d_gprefix = nullptr;
   PeelJob *d_peels = nullptr;
+  PeelJob *d_peels_global = nullptr;
   ProgJob *d_progs = nullptr;
   ReplayJob *d_replays = nullptr;
+  ProgJob *d_replay_progs = nullptr;
   uint32_t *d_rprefix = nullptr;
   RepairPrepJob *d_rpreps = nullptr;
   UpdatePlanJob *d_uplans = nullptr;
@@ -147,6 +157,23 @@ uint64_t gather_items_of(const GatherJob &j, const fs_tune &tune) {
   return nslices * ntiles;
 }
 
+// A gather job of at least this many (slice, tile) items at the default
+// tiling fills the device by itself: it runs as its own launch, where the
+// hardware dispatcher balances it with no claim traffic.  Smaller jobs share
+// the persistent kernel.
+constexpr uint64_t kSoloItems = 8192;
+// A decode whose k t reaches this size replays with the one-stripe kernels
+// (which pick the slice width and LDS layout for its shape).
+constexpr uint64_t kSoloReplayBytes = 32ull << 20;
+
+bool solo_gather(const GatherJob &j) {
+  // jobs sized on the device (update deltas) only know a bound: they stay
+  // in the persistent kernel, which skips their dead tiles cheaply
+  if (j.nrows_dev) return false;
+  const fs_tune dflt{16, 2, 1, 1, 0};
+  return gather_items_of(j, dflt) >= kSoloItems;
+}
+
 // Build every descriptor of the plan from its items (device pointers into the
 // items' buffers and into the plan workspace).
 void build_descriptors(fs_plan &P) {
@@ -162,6 +189,12 @@ void build_descriptors(fs_plan &P) {
   P.uprefix.assign(1, 0);
   P.zeros.clear();
   P.zero_max_t = 0;
+  P.solo.clear();
+  P.solo_accumulate.clear();
+  P.solo_replays.clear();
+  P.solo_replay_prog.clear();
+  P.replay_progs.clear();
+  P.peels_global.clear();
   P.peel_lds = true;
   P.peel_lds_bytes = 0;
   P.replay_lds = 256;
@@ -193,15 +226,25 @@ void build_descriptors(fs_plan &P) {
         pj.mask = b.dec.peel.mask;
         pj.decmask = b.dec.peel.decmask;
         const size_t need = peel_lds_bytes(g->k, g->n);
-        if (g->max_deg >= 65536 || need > lds_budget) P.peel_lds = false;
-        P.peel_lds_bytes = std::max(P.peel_lds_bytes, need);
-        P.peels.push_back(pj);
+        if (g->max_deg >= 65536 || need > lds_budget) {
+          P.peels_global.push_back(pj);
+        } else {
+          P.peel_lds_bytes = std::max(P.peel_lds_bytes, need);
+          P.peels.push_back(pj);
+        }
         ProgJob prog = b.dec.prog;
         prog.status = status;
         P.progs.push_back(prog);
+        const ReplayJob rj = replay_job(g, w.c, w.x, w.t, status, b.dec.sched.level_ptr, b.dec.sched.dp_f,
+                                        b.dec.sched.dp_g);
+        if ((uint64_t)g->k * w.t >= kSoloReplayBytes) {
+          P.solo_replays.push_back(rj);
+          P.solo_replay_prog.push_back((uint32_t)(P.progs.size() - 1));
+          break;
+        }
         P.replay_lds = std::max(P.replay_lds, replay_prog_lds_bound(g->k, prog.pidx_cap));
-        P.replays.push_back(replay_job(g, w.c, w.x, w.t, status, b.dec.sched.level_ptr, b.dec.sched.dp_f,
-                                       b.dec.sched.dp_g));
+        P.replays.push_back(rj);
+        P.replay_progs.push_back(prog);
         const uint64_t wsl = 16ull * kBatchReplayLanes;
         const uint64_t nslices = (w.t + wsl - 1) / wsl;
         const uint32_t nwg = (uint32_t)((nslices + kBatchReplaySlicesPerWg - 1) / kBatchReplaySlicesPerWg);
@@ -289,7 +332,20 @@ void build_descriptors(fs_plan &P) {
       default: break;
     }
   }
-  if (!P.peel_lds) P.peel_lds_bytes = 0;
+  // move the large gather jobs out of the persistent kernel
+  std::vector<GatherJob> shared;
+  std::vector<uint8_t> shared_acc;
+  for (size_t i = 0; i < P.gjobs.size(); ++i) {
+    if (solo_gather(P.gjobs[i])) {
+      P.solo.push_back(P.gjobs[i]);
+      P.solo_accumulate.push_back(P.gjob_accumulate[i]);
+    } else {
+      shared.push_back(P.gjobs[i]);
+      shared_acc.push_back(P.gjob_accumulate[i]);
+    }
+  }
+  P.gjobs.swap(shared);
+  P.gjob_accumulate.swap(shared_acc);
 }
 
 void gather_prefix(const std::vector<GatherJob> &jobs, const fs_tune &tune, std::vector<unsigned long long> &pre) {
@@ -323,8 +379,10 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   P.d_gjobs = place<GatherJob>(base, off, P.gjobs.size());
   P.d_gprefix = place<unsigned long long>(base, off, P.gprefix.size());
   P.d_peels = place<PeelJob>(base, off, P.peels.size());
+  P.d_peels_global = place<PeelJob>(base, off, P.peels_global.size());
   P.d_progs = place<ProgJob>(base, off, P.progs.size());
   P.d_replays = place<ReplayJob>(base, off, P.replays.size());
+  P.d_replay_progs = place<ProgJob>(base, off, P.replay_progs.size());
   P.d_rprefix = place<uint32_t>(base, off, P.rprefix.size());
   P.d_rpreps = place<RepairPrepJob>(base, off, P.rpreps.size());
   P.d_uplans = place<UpdatePlanJob>(base, off, P.uplans.size());
@@ -354,8 +412,10 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   put(P.d_gjobs, P.gjobs.data(), P.gjobs.size() * sizeof(GatherJob));
   put(P.d_gprefix, P.gprefix.data(), P.gprefix.size() * sizeof(unsigned long long));
   put(P.d_peels, P.peels.data(), P.peels.size() * sizeof(PeelJob));
+  put(P.d_peels_global, P.peels_global.data(), P.peels_global.size() * sizeof(PeelJob));
   put(P.d_progs, P.progs.data(), P.progs.size() * sizeof(ProgJob));
   put(P.d_replays, P.replays.data(), P.replays.size() * sizeof(ReplayJob));
+  put(P.d_replay_progs, P.replay_progs.data(), P.replay_progs.size() * sizeof(ProgJob));
   put(P.d_rprefix, P.rprefix.data(), P.rprefix.size() * sizeof(uint32_t));
   put(P.d_rpreps, P.rpreps.data(), P.rpreps.size() * sizeof(RepairPrepJob));
   put(P.d_uplans, P.uplans.data(), P.uplans.size() * sizeof(UpdatePlanJob));
@@ -378,17 +438,21 @@ uint32_t gather_grid_for(uint64_t items) {
 
 // The whole plan as launches on s (branch A on P.side when it exists).
 fs_status enqueue(fs_plan &P, hipStream_t s) {
-  const bool fork = P.side != nullptr && !P.peels.empty();
+  const bool fork = P.side != nullptr && !(P.peels.empty() && P.peels_global.empty());
   hipStream_t a = fork ? P.side : s;
   if (fork) {
     PL_TRY(hip_ok(hipEventRecord(P.fork, s), "fork"));
     PL_TRY(hip_ok(hipStreamWaitEvent(P.side, P.fork, 0), "fork wait"));
   }
   // branch A: decodes (schedule, program, replay)
-  PL_TRY(launch_peel_batch(P.d_peels, (uint32_t)P.peels.size(), P.peel_lds, P.peel_lds_bytes, a));
+  PL_TRY(launch_peel_batch(P.d_peels, (uint32_t)P.peels.size(), true, P.peel_lds_bytes, a));
+  PL_TRY(launch_peel_batch(P.d_peels_global, (uint32_t)P.peels_global.size(), false, 0, a));
   PL_TRY(launch_prog_batch(P.d_progs, (uint32_t)P.progs.size(), a));
-  PL_TRY(launch_replay_batch(P.d_replays, P.d_progs, P.d_rprefix, (uint32_t)P.replays.size(), P.rprefix.back(),
-                             P.replay_lds, a));
+  // replays[i] runs the program replay_progs[i] (built above for every decode)
+  PL_TRY(launch_replay_batch(P.d_replays, P.d_replay_progs, P.d_rprefix, (uint32_t)P.replays.size(),
+                             P.rprefix.back(), P.replay_lds, a));
+  for (size_t i = 0; i < P.solo_replays.size(); ++i)
+    PL_TRY(launch_replay_prog(P.solo_replays[i], &P.progs[P.solo_replay_prog[i]], a));
   // branch B: zeroing, checks, update planning, then the persistent gather
   PL_TRY(launch_zero_batch(P.d_zeros, (uint32_t)P.zeros.size(), P.zero_max_t, s));
   PL_TRY(launch_repair_prep_batch(P.d_rpreps, (uint32_t)P.rpreps.size(), s));
@@ -396,10 +460,40 @@ fs_status enqueue(fs_plan &P, hipStream_t s) {
   PL_TRY(launch_update_delta_batch(P.d_udeltas, P.d_uprefix, (uint32_t)P.udeltas.size(), P.uprefix.back(), s));
   PL_TRY(launch_gather_batch(P.d_gjobs, P.d_gprefix, (uint32_t)P.gjobs.size(), P.d_counter, P.tune, P.gather_grid,
                              P.gprefix.back(), s));
+  for (const GatherJob &j : P.solo) PL_TRY(launch_gather(j, P.tune, s));
   if (fork) {
     PL_TRY(hip_ok(hipEventRecord(P.join, P.side), "join"));
     PL_TRY(hip_ok(hipStreamWaitEvent(s, P.join, 0), "join wait"));
   }
+  return FS_OK;
+}
+
+// Capture the plan's launches into a graph and instantiate it (replacing
+// any earlier one: a rebind changes the arguments of the large jobs' own
+// launches, which a graph holds by value).
+fs_status capture(fs_plan &P) {
+  if (P.exec) (void)hipGraphExecDestroy(P.exec);
+  if (P.graph) (void)hipGraphDestroy(P.graph);
+  P.exec = nullptr;
+  P.graph = nullptr;
+  hipStream_t cap = nullptr;
+  if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
+    return fail(FS_ERR_HIP, "capture stream creation failed");
+  fs_status st = FS_OK;
+  hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
+  if (e == hipSuccess) {
+    st = enqueue(P, cap);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(cap, &g);
+    if (st == FS_OK && e2 != hipSuccess) st = fail(FS_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
+    P.graph = g;
+  } else {
+    st = fail(FS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
+  }
+  (void)hipStreamDestroy(cap);
+  if (st != FS_OK) return st;
+  if (hipGraphInstantiate(&P.exec, P.graph, nullptr, nullptr, 0) != hipSuccess)
+    return fail(FS_ERR_HIP, "graph instantiation failed");
   return FS_OK;
 }
 
@@ -446,7 +540,9 @@ void cache_store(const char *path, const std::string &key, const fs_tune &t) {
 // Time the persistent gather (without the accumulating jobs) for a few
 // tilings and keep the fastest.
 fs_status autotune(fs_plan &P, hipStream_t s) {
-  if (P.n_tjobs == 0) return FS_OK;
+  size_t solo_tuned = 0;
+  for (uint8_t a : P.solo_accumulate) solo_tuned += a == 0;
+  if (P.n_tjobs == 0 && solo_tuned == 0) return FS_OK;
   static const uint32_t cand[][2] = {{16, 2}, {32, 2}, {32, 4}, {64, 1}, {64, 2}, {64, 4}};
   hipEvent_t e0, e1;
   PL_TRY(hip_ok(hipEventCreate(&e0), "event"));
@@ -467,11 +563,18 @@ fs_status autotune(fs_plan &P, hipStream_t s) {
                                hipMemcpyHostToDevice, s), "tune prefix");
     if (st != FS_OK) break;
     const uint32_t grid = gather_grid_for(pre.back());
-    // one warm run, then the timed one
-    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, P.d_counter, t, grid, pre.back(), s);
+    // the persistent kernel and the large jobs' own launches (without the
+    // accumulating ones): one warm run, then the timed one
+    auto run = [&]() -> fs_status {
+      PL_TRY(launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, P.d_counter, t, grid, pre.back(), s));
+      for (size_t i = 0; i < P.solo.size(); ++i)
+        if (!P.solo_accumulate[i]) PL_TRY(launch_gather(P.solo[i], t, s));
+      return FS_OK;
+    };
+    st = run();
     if (st != FS_OK) break;
     (void)hipEventRecord(e0, s);
-    st = launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, P.d_counter, t, grid, pre.back(), s);
+    st = run();
     if (st != FS_OK) break;
     (void)hipEventRecord(e1, s);
     st = hip_ok(hipEventSynchronize(e1), "tune sync");
@@ -559,7 +662,7 @@ fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_
   }
   P->gather_grid = gather_grid_for(P->gprefix.back());
   if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(FS_ERR_HIP, "plan upload failed"));
-  if (!P->peels.empty()) {
+  if (!P->peels.empty() || !P->peels_global.empty()) {
     if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess)
@@ -567,23 +670,8 @@ fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_
   }
   prepare_batch_kernels();
   if (!(flags & FS_PLAN_NO_GRAPH)) {
-    hipStream_t cap = nullptr;
-    if (hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess)
-      return bail(fail(FS_ERR_HIP, "capture stream creation failed"));
-    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed);
-    if (e == hipSuccess) {
-      st = enqueue(*P, cap);
-      hipGraph_t g = nullptr;
-      const hipError_t e2 = hipStreamEndCapture(cap, &g);
-      if (st == FS_OK && e2 != hipSuccess) st = fail(FS_ERR_HIP, std::string("end capture: ") + hipGetErrorString(e2));
-      P->graph = g;
-    } else {
-      st = fail(FS_ERR_HIP, std::string("begin capture: ") + hipGetErrorString(e));
-    }
-    (void)hipStreamDestroy(cap);
+    st = capture(*P);
     if (st != FS_OK) return bail(st);
-    if (hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0) != hipSuccess)
-      return bail(fail(FS_ERR_HIP, "graph instantiation failed"));
   }
   *out = P;
   return FS_OK;
@@ -614,7 +702,9 @@ fs_status fs_plan_rebind(fs_plan *plan, const fs_work *items, uint32_t count, hi
   }
   plan->items.assign(items, items + count);
   build_descriptors(*plan);
-  return upload_descriptors(*plan, stream, false);
+  PL_TRY(upload_descriptors(*plan, stream, false));
+  if (plan->exec && !plan->solo.size() && !plan->solo_replays.size()) return FS_OK;
+  return plan->exec ? capture(*plan) : FS_OK;
 }
 
 fs_status fs_plan_get_info(const fs_plan *plan, fs_plan_info *info) {
@@ -628,7 +718,7 @@ fs_status fs_plan_get_info(const fs_plan *plan, fs_plan_info *info) {
     info->repair_items += w.op == FS_WORK_REPAIR;
     info->encode_items += w.op == FS_WORK_ENCODE;
   }
-  info->gather_jobs = (uint32_t)plan->gjobs.size();
+  info->gather_jobs = (uint32_t)(plan->gjobs.size() + plan->solo.size());
   info->gather_tiles = plan->gprefix.empty() ? 0 : plan->gprefix.back();
   info->replay_workgroups = plan->rprefix.back();
   info->tune_source = plan->tune_source;

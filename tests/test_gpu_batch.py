@@ -1,6 +1,7 @@
 """Batched plans (one captured launch for many stripes) give the oracle's
 results bit for bit; graph replays, rebinds and the autotuner keep them."""
 
+import dataclasses
 import os
 import tempfile
 
@@ -223,3 +224,67 @@ def test_graph_in_caller_memory():
     with pytest.raises(fs.FsError) as e:
         owned.upload(torch.empty(1 << 20, dtype=torch.uint8, device="cuda"))
     assert e.value.status == fs._lib.FS_ERR_INVALID
+
+
+def test_plan_with_large_items_and_rebind():
+    """Stripes large enough to run as launches of their own (a 64 MiB encode,
+    a 32 MiB decode, a device-sized update) next to small ones: the oracle's
+    results on graph replays and after a rebind to new buffers."""
+    import paper_1702_07409_amd as fs
+    import torch
+    big_enc = S(stripe=70, k=1024, n=1126, t=65536, dist="rsd", stripe_key=70)
+    big_dec = S(stripe=71, k=1024, n=1126, t=32768, dist="finite", finite_w=workloads.finite16_weights(),
+                stripe_key=71, n_erased=56)
+    small = S(stripe=72, k=64, n=96, t=4096, dist="rsd", stripe_key=72)
+    ge, Ge = graphs(**big_enc.graph_kwargs())
+    gd, Gd = graphs(**big_dec.graph_kwargs())
+    gs, Gs = graphs(**small.graph_kwargs())
+
+    def make(seed):
+        items, checks = [], []
+        x = gen.payload(seed, big_enc.stripe, big_enc.k, big_enc.t)
+        c = empty_u8(big_enc.n, big_enc.t)
+        items.append(fs.work("encode", ge, big_enc.t, x=dev(x), c=c))
+        want = codec.encode(Ge, x)
+        checks.append(lambda c=c, want=want: np.array_equal(host(c), want))
+        xd = gen.payload(seed, big_dec.stripe, big_dec.k, big_dec.t)
+        cd = codec.encode(Gd, xd)
+        er = big_dec.erased_mask()
+        xo, rec, st = empty_u8(big_dec.k, big_dec.t), empty_u8(big_dec.k), empty_i32(3)
+        items.append(fs.work("decode", gd, big_dec.t, x=xo, c=dev(cd), erased=dev(er), recovered=rec, status=st))
+        xw, recw, stw, _ = codec.decode(Gd, cd, er)
+        checks.append(lambda xo=xo, rec=rec, st=st, xw=xw, recw=recw, stw=stw:
+                      np.array_equal(host(xo), xw) and np.array_equal(host(rec), recw)
+                      and host(st).tolist() == list(stw))
+        xs = gen.payload(seed, small.stripe, small.k, small.t)
+        cs = empty_u8(small.n, small.t)
+        items.append(fs.work("encode", gs, small.t, x=dev(xs), c=cs))
+        wants = codec.encode(Gs, xs)
+        checks.append(lambda cs=cs, wants=wants: np.array_equal(host(cs), wants))
+        # a small decode after the large one: it shares the batched replay
+        # while the large one replays on its own
+        cs_host = codec.encode(Gs, xs)
+        ers = dataclasses.replace(small, n_erased=12).erased_mask()
+        xso, recs, sts = empty_u8(small.k, small.t), empty_u8(small.k), empty_i32(3)
+        items.append(fs.work("decode", gs, small.t, x=xso, c=dev(cs_host), erased=dev(ers), recovered=recs,
+                             status=sts))
+        xsw, recsw, stsw, _ = codec.decode(Gs, cs_host, ers)
+        checks.append(lambda xso=xso, recs=recs, sts=sts, xsw=xsw, recsw=recsw, stsw=stsw:
+                      np.array_equal(host(xso), xsw) and np.array_equal(host(recs), recsw)
+                      and host(sts).tolist() == list(stsw))
+        return items, checks
+
+    items, checks = make(10)
+    plan = fs.Plan(items)
+    assert plan.info()["gather_jobs"] == 2
+    for _ in range(2):
+        plan.launch()
+        torch.cuda.synchronize()
+        bad = [i for i, ok in enumerate(checks) if not ok()]
+        assert not bad, bad
+    items2, checks2 = make(11)
+    plan.rebind(items2)
+    plan.launch()
+    torch.cuda.synchronize()
+    bad = [i for i, ok in enumerate(checks2) if not ok()]
+    assert not bad, bad
