@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <thread>
 
 #include "fs_internal.h"
 
@@ -131,80 +132,138 @@ fs_status build_host_graph(const fs_graph_params &p, fs_graph &g) {
   } else {
     g.params.finite_w = nullptr;
   }
+  // Rows depend only on their own stream, so large graphs are built by
+  // several threads over contiguous row ranges, then concatenated in order.
+  const uint32_t nthreads = n >= 8192 ? std::min<uint32_t>(8, std::max(1u, std::thread::hardware_concurrency())) : 1;
+  std::vector<std::vector<int32_t>> part_col(nthreads);
+  std::vector<std::vector<int32_t>> part_deg(nthreads);
+  std::vector<uint32_t> part_max(nthreads, 0);
+  auto build_rows = [&](uint32_t tid) {
+    const uint32_t j0 = (uint32_t)((uint64_t)n * tid / nthreads), j1 = (uint32_t)((uint64_t)n * (tid + 1) / nthreads);
+    std::vector<uint32_t> stamp(k, 0xFFFFFFFFu);   // stamp[v] == j: v taken in row j
+    std::vector<int32_t> row;
+    std::vector<int32_t> &out = part_col[tid];
+    std::vector<int32_t> &deg = part_deg[tid];
+    deg.reserve(j1 - j0);
+    for (uint32_t j = j0; j < j1; ++j) {
+      const uint64_t key = row_key(p.seed, p.stripe_key, j);
+      const uint64_t v0 = draw(key, 0) >> 11;
+      const uint32_t d = (uint32_t)(std::upper_bound(T.begin(), T.end(), v0) - T.begin()) + 1;
+      row.clear();
+      for (uint32_t s = 0; s < d; ++s) {
+        const uint64_t r = (uint64_t)(k - d) + s;
+        const uint64_t v = ((draw(key, s + 1) >> 32) * (r + 1)) >> 32;
+        const uint32_t pick = (stamp[v] == j) ? (uint32_t)r : (uint32_t)v;
+        stamp[pick] = j;
+        row.push_back((int32_t)pick);
+      }
+      std::sort(row.begin(), row.end());
+      out.insert(out.end(), row.begin(), row.end());
+      deg.push_back((int32_t)d);
+      part_max[tid] = std::max(part_max[tid], d);
+    }
+  };
+  if (nthreads == 1) {
+    build_rows(0);
+  } else {
+    std::vector<std::thread> pool;
+    for (uint32_t t = 0; t < nthreads; ++t) pool.emplace_back(build_rows, t);
+    for (std::thread &th : pool) th.join();
+  }
+  size_t total = 0;
+  for (const auto &pc : part_col) total += pc.size();
+  if (total >= (size_t)INT32_MAX) return fail(FS_ERR_INVALID, "graph has 2^31 or more edges");
   g.row_ptr.assign((size_t)n + 1, 0);
   g.col.clear();
-  std::vector<uint32_t> stamp(k, 0xFFFFFFFFu);   // stamp[v] == j: v taken in row j
-  std::vector<int32_t> row;
-  uint32_t max_deg = 0;
-  for (uint32_t j = 0; j < n; ++j) {
-    const uint64_t key = row_key(p.seed, p.stripe_key, j);
-    const uint64_t v0 = draw(key, 0) >> 11;
-    const uint32_t d = (uint32_t)(std::upper_bound(T.begin(), T.end(), v0) - T.begin()) + 1;
-    row.clear();
-    for (uint32_t s = 0; s < d; ++s) {
-      const uint64_t r = (uint64_t)(k - d) + s;
-      const uint64_t v = ((draw(key, s + 1) >> 32) * (r + 1)) >> 32;
-      const uint32_t pick = (stamp[v] == j) ? (uint32_t)r : (uint32_t)v;
-      stamp[pick] = j;
-      row.push_back((int32_t)pick);
+  g.col.reserve(total);
+  uint32_t max_deg = 0, j = 0;
+  for (uint32_t t = 0; t < nthreads; ++t) {
+    g.col.insert(g.col.end(), part_col[t].begin(), part_col[t].end());
+    for (int32_t d : part_deg[t]) {
+      g.row_ptr[j + 1] = g.row_ptr[j] + d;
+      ++j;
     }
-    std::sort(row.begin(), row.end());
-    if (g.col.size() + row.size() >= (size_t)INT32_MAX)
-      return fail(FS_ERR_INVALID, "graph has 2^31 or more edges");
-    g.col.insert(g.col.end(), row.begin(), row.end());
-    g.row_ptr[j + 1] = (int32_t)g.col.size();
-    max_deg = std::max(max_deg, d);
+    max_deg = std::max(max_deg, part_max[t]);
   }
   g.nnz = g.col.size();
   g.max_deg = max_deg;
-  // transpose by counting sort; rows are visited in ascending order
+  auto parallel = [&](auto &&fn) {
+    if (nthreads == 1) {
+      fn(0u);
+      return;
+    }
+    std::vector<std::thread> pool;
+    for (uint32_t t = 0; t < nthreads; ++t) pool.emplace_back(fn, t);
+    for (std::thread &th : pool) th.join();
+  };
+  // transpose by counting sort, rows ascending within a column
   g.col_ptr.assign((size_t)k + 1, 0);
   for (int32_t i : g.col) g.col_ptr[(size_t)i + 1]++;
-  for (uint32_t i = 0; i < k; ++i) g.col_ptr[i + 1] += g.col_ptr[i];
-  std::vector<int32_t> fill(g.col_ptr.begin(), g.col_ptr.end() - 1);
-  g.rowidx.assign(g.nnz, 0);
   uint32_t max_cdeg = 0;
-  for (uint32_t j = 0; j < n; ++j)
-    for (int32_t e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e) g.rowidx[fill[g.col[e]]++] = (int32_t)j;
-  for (uint32_t i = 0; i < k; ++i)
-    max_cdeg = std::max<uint32_t>(max_cdeg, (uint32_t)(g.col_ptr[i + 1] - g.col_ptr[i]));
+  for (uint32_t i = 0; i < k; ++i) {
+    max_cdeg = std::max<uint32_t>(max_cdeg, (uint32_t)g.col_ptr[i + 1]);
+    g.col_ptr[i + 1] += g.col_ptr[i];
+  }
+  g.rowidx.assign(g.nnz, 0);
   g.max_cdeg = max_cdeg;
   // encode segments: rows longer than kSegMax are cut into kSegMax-edge
-  // pieces; the pieces are then ordered by length (longest first, stable) and
-  // their edges copied into seg_col in that order, so that a tile of
-  // consecutive segments holds segments of equal or similar length (the
-  // lanes of a wave then finish together) and its edges stay contiguous.
-  std::vector<int32_t> sb, se, srow;
-  std::vector<uint8_t> sat;
+  // pieces; the pieces are then ordered by length (longest first, ties in
+  // row order: a counting sort over lengths 1..kSegMax) and their edges
+  // copied into seg_col in that order, so that a tile of consecutive
+  // segments holds segments of equal or similar length (the lanes of a wave
+  // then finish together) and its edges stay contiguous.
   g.heavy.clear();
+  std::vector<uint32_t> by_len(kSegMax + 2, 0);   // segments per length, then start positions
+  size_t ns = 0;
+  for (uint32_t j = 0; j < n; ++j) {
+    const int32_t d = g.row_ptr[j + 1] - g.row_ptr[j];
+    if ((uint32_t)d > kSegMax) g.heavy.push_back((int32_t)j);
+    const uint32_t full = (uint32_t)d / kSegMax, rest = (uint32_t)d % kSegMax;
+    by_len[kSegMax] += full;
+    if (rest) by_len[rest]++;
+    ns += full + (rest ? 1 : 0);
+  }
+  // start index of each length, longest first
+  std::vector<uint32_t> first(kSegMax + 1, 0);
+  uint32_t acc = 0;
+  for (uint32_t len = kSegMax; len >= 1; --len) {
+    first[len] = acc;
+    acc += by_len[len];
+  }
+  std::vector<int32_t> sbeg(ns);
+  g.seg_row.resize(ns);
+  g.seg_atomic.resize(ns);
+  std::vector<uint32_t> slen(ns);
   for (uint32_t j = 0; j < n; ++j) {
     const int32_t e0 = g.row_ptr[j], e1 = g.row_ptr[j + 1];
     const bool split = (uint32_t)(e1 - e0) > kSegMax;
-    if (split) g.heavy.push_back((int32_t)j);
     for (int32_t e = e0; e < e1; e += (int32_t)kSegMax) {
-      sb.push_back(e);
-      se.push_back(std::min<int32_t>(e1, e + (int32_t)kSegMax));
-      srow.push_back((int32_t)j);
-      sat.push_back(split ? 1 : 0);
+      const uint32_t len = (uint32_t)(std::min<int32_t>(e1, e + (int32_t)kSegMax) - e);
+      const uint32_t at = first[len]++;
+      sbeg[at] = e;
+      slen[at] = len;
+      g.seg_row[at] = (int32_t)j;
+      g.seg_atomic[at] = split ? 1 : 0;
     }
   }
-  const size_t ns = sb.size();
-  std::vector<uint32_t> order(ns);
-  for (size_t i = 0; i < ns; ++i) order[i] = (uint32_t)i;
-  std::stable_sort(order.begin(), order.end(),
-                   [&](uint32_t a, uint32_t b) { return se[a] - sb[a] > se[b] - sb[b]; });
-  g.seg_ptr.assign(1, 0);
-  g.seg_row.resize(ns);
-  g.seg_atomic.resize(ns);
+  g.seg_ptr.assign(ns + 1, 0);
+  for (size_t i = 0; i < ns; ++i) g.seg_ptr[i + 1] = g.seg_ptr[i] + (int32_t)slen[i];
   g.seg_col.resize(g.nnz);
-  size_t pos = 0;
-  for (size_t i = 0; i < ns; ++i) {
-    const uint32_t s = order[i];
-    for (int32_t e = sb[s]; e < se[s]; ++e) g.seg_col[pos++] = g.col[e];
-    g.seg_ptr.push_back((int32_t)pos);
-    g.seg_row[i] = srow[s];
-    g.seg_atomic[i] = sat[s];
-  }
+  // thread t fills the CSC columns of its range (scanning every row in
+  // order, so rows stay ascending, and writing only its own columns) and
+  // copies its share of the segments
+  parallel([&](uint32_t t) {
+    const uint32_t c0 = (uint32_t)((uint64_t)k * t / nthreads), c1 = (uint32_t)((uint64_t)k * (t + 1) / nthreads);
+    std::vector<int32_t> slot(g.col_ptr.begin() + c0, g.col_ptr.begin() + c1);
+    for (uint32_t j = 0; j < n; ++j)
+      for (int32_t e = g.row_ptr[j]; e < g.row_ptr[j + 1]; ++e) {
+        const uint32_t i = (uint32_t)g.col[e];
+        if (i >= c0 && i < c1) g.rowidx[slot[i - c0]++] = (int32_t)j;
+      }
+    const size_t s0 = ns * t / nthreads, s1 = ns * (t + 1) / nthreads;
+    for (size_t i = s0; i < s1; ++i)
+      std::memcpy(&g.seg_col[g.seg_ptr[i]], &g.col[sbeg[i]], sizeof(int32_t) * slen[i]);
+  });
   return FS_OK;
 }
 

@@ -52,6 +52,8 @@ CASES = [
     dict(k=40, n=70, dist="raptor", seed=9),
     dict(k=8, n=20, dist="finite", finite_w=(0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 1.0), seed=3),
     dict(k=8041, n=8684, dist="rsd", rsd_c=0.05, rsd_delta=0.01, seed=1, stripe_key=300),
+    # n >= 8192: rows and columns are built by several host threads
+    dict(k=12000, n=13300, dist="rsd", rsd_c=0.1, rsd_delta=0.05, seed=1, stripe_key=0),
 ]
 
 
