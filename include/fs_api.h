@@ -265,7 +265,11 @@ typedef struct fs_tune {
                                   memory instead of LDS (slower; for checks)  */
 } fs_tune;
 
-/* Override (or with NULL restore) the gather tuning used by this process. */
+/*
+ * Override (or with NULL restore) the gather tuning used by this process.
+ * The default is {64, 4, 1, 1, 0}: 4 KiB slices, which read each neighbour
+ * block in long runs (best when the inputs are not already cached).
+ */
 FS_API fs_status fs_set_tune(const fs_tune *tune);
 FS_API fs_status fs_get_tune(fs_tune *tune);
 

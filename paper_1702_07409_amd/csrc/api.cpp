@@ -37,7 +37,7 @@ const DeviceInfo &device_info(int dev) {
 
 namespace {
 std::mutex g_tune_mu;
-fs_tune g_tune = {16, 2, 1, 1, 0};
+fs_tune g_tune = {64, 4, 1, 1, 0};
 
 }  // namespace
 
@@ -288,7 +288,7 @@ fs_status fs_set_tune(const fs_tune *tune) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_tune_mu);
   if (!tune) {
-    g_tune = fs_tune{16, 2, 1, 1, 0};
+    g_tune = fs_tune{64, 4, 1, 1, 0};
     return FS_OK;
   }
   if (!tune_ok(*tune)) return fail(FS_ERR_INVALID, "tuning out of range");

@@ -766,7 +766,10 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
                                                    const IT *poff, const IT *pidx, int L, int nR,
                                                    uint32_t nslices, uint32_t vb, uint32_t stride) {
   constexpr int NS = kReplayThreads / LPS;
-  constexpr int MP = LPS >= 32 ? 4 : 2;   // pairs per thread whose coded block is prefetched
+  // pairs per thread whose coded block is prefetched, and how many levels
+  // ahead (two levels ahead measured no faster than one)
+  constexpr int MP = LPS >= 32 ? 4 : 2;
+  constexpr int PD = 1;
   constexpr uint32_t W = LPS * 16;
   const uint32_t lane = threadIdx.x % LPS, sym = threadIdx.x / LPS;
   const uint32_t k = J.k;
@@ -774,25 +777,31 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
   for (uint32_t slice = vb; slice < nslices; slice += stride) {
     const uint64_t off = (uint64_t)slice * W + lane * 16u;
     const bool live = off < J.t;
-    // coded blocks of the first MP pairs of a level are loaded while the
-    // previous level runs (c is never written here)
-    v4u cb[MP];
-    auto prefetch = [&](int l) {
+    // coded blocks of the first MP pairs of a level are loaded PD levels
+    // before it runs (c is never written here); cb[d] holds level l + d
+    v4u cb[PD][MP];
+    auto prefetch = [&](int l, v4u (&dst)[MP]) {
       const int q0 = max((int)lp[l], 0), q1 = min((int)lp[l + 1], nR);
 #pragma unroll
       for (int m = 0; m < MP; ++m) {
         const int q = q0 + (int)sym + m * NS;
         const uint32_t g = q < q1 ? (uint32_t)pg[q] : 0xffffffffu;
-        cb[m] = (live && g < J.n) ? ld16(J.c + (uint64_t)g * J.t + off) : zero;
+        dst[m] = (live && g < J.n) ? ld16(J.c + (uint64_t)g * J.t + off) : zero;
       }
     };
-    if (L > 0) prefetch(0);
+#pragma unroll
+    for (int d = 0; d < PD; ++d)
+      if (d < L) prefetch(d, cb[d]);
     for (int l = 0; l < L; ++l) {
       const int q0 = max((int)lp[l], 0), q1 = min((int)lp[l + 1], nR);
       v4u cur[MP];
 #pragma unroll
-      for (int m = 0; m < MP; ++m) cur[m] = cb[m];
-      if (l + 1 < L) prefetch(l + 1);
+      for (int m = 0; m < MP; ++m) cur[m] = cb[0][m];
+#pragma unroll
+      for (int d = 0; d + 1 < PD; ++d)
+#pragma unroll
+        for (int m = 0; m < MP; ++m) cb[d][m] = cb[d + 1][m];
+      if (l + PD < L) prefetch(l + PD, cb[PD - 1]);
 #pragma unroll
       for (int m = 0; m < MP; ++m) {
         const int q = q0 + (int)sym + m * NS;
