@@ -263,12 +263,16 @@ typedef struct fs_tune {
   uint32_t nt_store;       /* 1: non-temporal stores for outputs             */
   uint32_t replay_prog_global; /* 1: keep decode replay programs in global
                                   memory instead of LDS (slower; for checks)  */
+  uint32_t encode_slab;    /* 1: encode stripes with k <= 8192 whose block is
+                              wide enough to fill the device from an LDS copy
+                              of each byte slice of every input (below)       */
 } fs_tune;
 
 /*
  * Override (or with NULL restore) the gather tuning used by this process.
- * The default is {64, 4, 1, 1, 0}: 4 KiB slices, which read each neighbour
- * block in long runs (best when the inputs are not already cached).
+ * The default is {64, 4, 1, 1, 0, 1}: 4 KiB gather slices, which read each
+ * neighbour block in long runs (best when the inputs are not already
+ * cached), and the LDS-slab encode where it applies.
  */
 FS_API fs_status fs_set_tune(const fs_tune *tune);
 FS_API fs_status fs_get_tune(fs_tune *tune);

@@ -37,7 +37,7 @@ const DeviceInfo &device_info(int dev) {
 
 namespace {
 std::mutex g_tune_mu;
-fs_tune g_tune = {64, 4, 1, 1, 0};
+fs_tune g_tune = {64, 4, 1, 1, 0, 1};
 
 }  // namespace
 
@@ -49,7 +49,7 @@ fs_tune current_tune() {
 static bool tune_ok(const fs_tune &t) {
   const bool lpr = t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64;
   const bool ch = t.chunks == 1 || t.chunks == 2 || t.chunks == 4;
-  return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1;
+  return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1 && t.encode_slab <= 1;
 }
 
 // The device copy of a graph: nine arrays, each 256-byte aligned, in one buffer.
@@ -288,7 +288,7 @@ fs_status fs_set_tune(const fs_tune *tune) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_tune_mu);
   if (!tune) {
-    g_tune = fs_tune{64, 4, 1, 1, 0};
+    g_tune = fs_tune{64, 4, 1, 1, 0, 1};
     return FS_OK;
   }
   if (!tune_ok(*tune)) return fail(FS_ERR_INVALID, "tuning out of range");
@@ -485,6 +485,7 @@ GatherJob encode_job(const fs_graph *g, const void *x, void *c, uint64_t t) {
   j.nrows = (uint32_t)g->seg_row.size();
   j.csr_rows = j.nrows;
   j.t = t;
+  j.slab_k = g->k;
   return j;
 }
 

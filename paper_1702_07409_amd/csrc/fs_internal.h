@@ -90,6 +90,8 @@ struct GatherJob {
   uint32_t csr_rows;       // CSR rows; items mapping beyond are skipped
   uint64_t t;              // bytes per block (multiple of 16)
   int accumulate;          // XOR into the existing output
+  uint32_t slab_k;         // encode jobs: source blocks (k), for the LDS-slab
+                           // kernel; 0 for every other job
 };
 
 fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s);

@@ -286,6 +286,126 @@ __global__ __launch_bounds__(256) void zero_rows_kernel(uint8_t *dst, const int3
   if (off < t) *reinterpret_cast<v4u *>(dst + (uint64_t)rows[r] * t + off) = v4u{0u, 0u, 0u, 0u};
 }
 
+// ---------------------------------------------------------------------------
+// LDS-slab encode
+// ---------------------------------------------------------------------------
+// One workgroup per CU walks byte slices of W = 16 LPS bytes.  For each slice
+// the k x W bytes of every input block are copied into LDS once; every encode
+// segment then XORs its neighbours from LDS and writes its part of the slice.
+// The gather reads a neighbour through the caches once per edge; here each
+// input byte is read from memory once per slice and the edges read LDS.  The
+// next slice's inputs are loaded into registers while the current one is
+// computed.  k LPS <= kSlabEntries, so every thread holds at most M entries.
+constexpr int kSlabThreads = 1024;
+constexpr uint32_t kSlabEntries = 8192;                  // 16-byte entries: 128 KiB
+constexpr int kSlabPerThread = kSlabEntries / kSlabThreads;
+
+template <int LPS>
+__global__ __launch_bounds__(kSlabThreads) void slab_encode_kernel(GatherJob j, uint32_t k, uint32_t nslices) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  v4u *slab = reinterpret_cast<v4u *>(smem);
+  constexpr uint32_t NS = kSlabThreads / LPS;
+  constexpr uint32_t W = 16u * LPS;
+  constexpr int M = kSlabPerThread;
+  const uint32_t lane = threadIdx.x % LPS, grp = threadIdx.x / LPS;
+  const uint32_t nseg = j.nrows;
+  const v4u zero = {0u, 0u, 0u, 0u};
+  v4u pre[M];
+  auto issue = [&](uint32_t slice) {
+    const uint64_t off = (uint64_t)slice * W + lane * 16u;
+    const bool live = off < j.t;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint32_t i = grp + (uint32_t)m * NS;
+      pre[m] = (live && i < k) ? ld16(j.src + (uint64_t)i * j.src_stride + off) : zero;
+    }
+  };
+  uint32_t slice = xcd_remap(blockIdx.x, gridDim.x);
+  if (slice < nslices) issue(slice);
+  while (slice < nslices) {
+    const uint64_t off = (uint64_t)slice * W + lane * 16u;
+    const bool live = off < j.t;
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const uint32_t i = grp + (uint32_t)m * NS;
+      if (i < k) slab[i * LPS + lane] = pre[m];
+    }
+    __syncthreads();
+    const uint32_t next = slice + gridDim.x;
+    if (next < nslices) issue(next);
+    if (live) {
+      for (uint32_t r = grp; r < nseg; r += NS) {
+        const int e1 = j.ptr[r + 1];
+        int e = j.ptr[r];
+        v4u acc = zero;
+        for (; e + 4 <= e1; e += 4) {
+          const uint32_t a = (uint32_t)j.idx[e], b = (uint32_t)j.idx[e + 1];
+          const uint32_t c = (uint32_t)j.idx[e + 2], d = (uint32_t)j.idx[e + 3];
+          acc ^= (slab[a * LPS + lane] ^ slab[b * LPS + lane]) ^ (slab[c * LPS + lane] ^ slab[d * LPS + lane]);
+        }
+        for (; e < e1; ++e) acc ^= slab[(uint32_t)j.idx[e] * LPS + lane];
+        uint8_t *out = j.dst + (uint64_t)j.out_map[r] * j.dst_stride + off;
+        if (j.seg_atomic && j.seg_atomic[r]) {
+          unsigned long long *q = reinterpret_cast<unsigned long long *>(out);
+          atomicXor(q, ((unsigned long long)acc.y << 32) | acc.x);
+          atomicXor(q + 1, ((unsigned long long)acc.w << 32) | acc.z);
+        } else {
+          // plain stores: the slices of one 128-byte line are written by
+          // neighbouring workgroups of one XCD and merge in its L2
+          *reinterpret_cast<v4u *>(out) = acc;
+        }
+      }
+    }
+    __syncthreads();   // the slab is rewritten for the next slice
+    slice = next;
+  }
+}
+
+// Lanes per slab row for k inputs (0: the slab does not apply).  Slices
+// narrower than 256 bytes (k > 512) read memory in pieces too short to
+// keep up with the gather, which wins there.
+int slab_lanes(uint32_t k) {
+  for (int lps = 64; lps >= 16; lps /= 2)
+    if ((uint64_t)k * lps <= kSlabEntries) return lps;
+  return 0;
+}
+
+template <int LPS>
+hipError_t run_slab_encode(const GatherJob &j, uint32_t nslices, int grid, int dev, hipStream_t s) {
+  static bool done[64] = {false};
+  const int bytes = (int)(kSlabEntries * 16);
+  if (dev >= 0 && dev < 64 && !done[dev]) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void *>(&slab_encode_kernel<LPS>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    done[dev] = true;
+  }
+  hipLaunchKernelGGL(slab_encode_kernel<LPS>, dim3(grid), dim3(kSlabThreads), bytes, s, j, j.slab_k, nslices);
+  return hipGetLastError();
+}
+
+// The slab encode for an encode job when it applies: k fits the slab and
+// the slices are enough to give every CU one.
+bool try_slab_encode(const GatherJob &j, const fs_tune &tune, hipStream_t s, hipError_t &e) {
+  if (!tune.encode_slab || j.slab_k == 0 || j.accumulate || j.csr_map || j.nrows_dev || j.row_ok || j.skip_flag)
+    return false;
+  const int lps = slab_lanes(j.slab_k);
+  if (lps == 0) return false;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cu = device_info(dev).cu_count;
+  if ((int)device_info(dev).max_lds_per_block < (int)(kSlabEntries * 16)) return false;
+  const uint32_t w = 16u * (uint32_t)lps;
+  const uint64_t nslices = (j.t + w - 1) / w;
+  if (nslices < (uint64_t)cu || nslices > 0xffffffffull) return false;
+  const int grid = cu;
+  switch (lps) {
+    case 64: e = run_slab_encode<64>(j, (uint32_t)nslices, grid, dev, s); break;
+    case 32: e = run_slab_encode<32>(j, (uint32_t)nslices, grid, dev, s); break;
+    default: e = run_slab_encode<16>(j, (uint32_t)nslices, grid, dev, s); break;
+  }
+  return true;
+}
+
 template <int LPR, int CH, bool NT>
 hipError_t run_gather(const GatherJob &j, uint32_t remap, hipStream_t s, int cu_count) {
   constexpr uint32_t RPB = kGatherThreads / LPR;
@@ -1151,10 +1271,11 @@ static fs_status hip_check(hipError_t e, const char *what) {
   } while (0)
 
 fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s) {
+  hipError_t e;
+  if (try_slab_encode(job, tune, s, e)) return hip_check(e, "slab encode launch");
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int cu = device_info(dev).cu_count;
-  hipError_t e;
   switch (tune.lanes_per_row * 10 + tune.chunks) {
     case 161: e = run_gather_nt<16, 1>(job, tune, s, cu); break;
     case 162: e = run_gather_nt<16, 2>(job, tune, s, cu); break;

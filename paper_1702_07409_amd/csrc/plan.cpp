@@ -170,7 +170,7 @@ bool solo_gather(const GatherJob &j) {
   // jobs sized on the device (update deltas) only know a bound: they stay
   // in the persistent kernel, which skips their dead tiles cheaply
   if (j.nrows_dev) return false;
-  const fs_tune dflt{16, 2, 1, 1, 0};
+  const fs_tune dflt{16, 2, 1, 1, 0, 0};
   return gather_items_of(j, dflt) >= kSoloItems;
 }
 

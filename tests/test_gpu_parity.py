@@ -122,6 +122,39 @@ def test_encode_and_decode_rsd_heavy_tail():
     decode_case(sp)
 
 
+SLAB_CASES = [
+    # (k, n, t, dist): the slab cases have >= 256 slices of the slab width,
+    # so the LDS-slab encode runs; t is ragged against the slice width
+    (500, 550, 65536 + 48, "rsd"),          # 16 lanes, 256-byte slices
+    (512, 553, 65536 + 256, "rsd_heavy"),   # 16 lanes, rows split into atomic segments
+    (200, 220, 131072 + 512, "finite"),     # 32 lanes
+    (64, 96, 262144 + 1024, "rsd"),         # 64 lanes
+    (2000, 2160, 16384 + 16, "rsd_heavy"),  # above the slab's k: the gather runs
+]
+
+
+@pytest.mark.parametrize("case", SLAB_CASES, ids=lambda c: "k%d-t%d-%s" % (c[0], c[2], c[3]))
+@pytest.mark.parametrize("slab", [1, 0])
+def test_encode_lds_slab_and_gather_match_oracle(case, slab):
+    import paper_1702_07409_amd as fs
+    k, n, t, kind = case
+    kw = dict(stripe=80 + k % 7, k=k, n=n, t=t, stripe_key=k)
+    if kind == "finite":
+        sp = workloads.StripeSpec(dist="finite", finite_w=workloads.finite16_weights(), **kw)
+    elif kind == "rsd_heavy":
+        sp = workloads.StripeSpec(dist="rsd", rsd_c=0.05, rsd_delta=0.01, **kw)
+    else:
+        sp = workloads.StripeSpec(dist="rsd", **kw)
+    fs.fs_set_tune(encode_slab=slab)
+    try:
+        g, G, x, xd, c = encode_case(sp)
+        if kind == "rsd_heavy":
+            assert g.max_degree > 64
+        assert np.array_equal(host(c), codec.encode(G, x))
+    finally:
+        fs.fs_reset_tune()
+
+
 def test_encode_rejects_bad_alignment():
     import paper_1702_07409_amd as fs
     g, _ = graphs(k=8, n=10, seed=1)
