@@ -141,8 +141,6 @@ class Stripe:
         self.sid = sid
         self.entry = entry
         self.x, self.c, self.t = x, c, t
-        self.busy = False
-        self.queue = collections.deque()   # pending requests on this stripe, in arrival order
 
 
 class Request:
@@ -179,6 +177,71 @@ class Tick:
     __slots__ = ("requests", "plan", "keep", "stream", "start", "end", "footprint", "t_launch")
 
 
+class Scheduler:
+    """Admission of pending requests (host logic only, no device calls).
+
+    Requests are admitted in arrival order while their footprint fits the
+    budget; the first one that does not fit stops admission (unless nothing
+    is in flight and the tick is empty: a request larger than the whole
+    budget then runs alone), so large requests are not starved.  A request
+    is skipped (it stays pending, later ones may pass it) while its graph is
+    not built yet, or while its stripe is held by an earlier request: each
+    stripe serves its requests one at a time in arrival order.
+
+    footprint(r): device bytes request r holds while in flight.
+    """
+
+    def __init__(self, budget, max_items, footprint):
+        self.budget = budget
+        self.max_items = max_items
+        self.footprint = footprint
+        self.pending = collections.deque()
+        self.used = 0
+        self.busy = set()                  # stripes held by an in-flight request
+        self.queues = {}                   # stripe -> its pending requests, in arrival order
+
+    def submit(self, r):
+        if r.stripe is not None:
+            self.queues.setdefault(r.stripe, collections.deque()).append(r)
+        self.pending.append(r)
+
+    def eligible(self, r):
+        if not r.entry.ready():
+            return False
+        if r.stripe is None:
+            return True
+        return r.stripe not in self.busy and self.queues[r.stripe][0] is r
+
+    def admit(self, inflight):
+        """Requests for the next tick (their footprint is charged)."""
+        batch, rest = [], collections.deque()
+        blocked = False
+        while self.pending:
+            r = self.pending.popleft()
+            if blocked or len(batch) >= self.max_items or not self.eligible(r):
+                rest.append(r)
+                continue
+            fp = self.footprint(r)
+            if self.used + fp > self.budget and (inflight or batch):
+                blocked = True   # keep arrival order for memory
+                rest.append(r)
+                continue
+            r.footprint = fp
+            self.used += fp
+            if r.stripe is not None:
+                self.busy.add(r.stripe)
+            batch.append(r)
+        self.pending = rest
+        return batch
+
+    def release(self, r):
+        """Request r has completed: free its footprint and its stripe."""
+        self.used -= r.footprint
+        if r.stripe is not None:
+            self.busy.discard(r.stripe)
+            self.queues[r.stripe].popleft()
+
+
 class Server:
     """Continuous-batching request loop on one GPU.
 
@@ -199,9 +262,8 @@ class Server:
         self.keep_outputs = keep_outputs
         self.cache = GraphCache(self.device, workers, graph_cache_bytes)
         self.stripes = {}
-        self.pending = collections.deque()
+        self.sched = Scheduler(budget, max_items, self._footprint)
         self.inflight = collections.deque()
-        self.used = 0
         self.done = []
         self.ticks = 0
         self.tick_items = []
@@ -241,53 +303,23 @@ class Server:
         r.t_submit = time.perf_counter()
         if r.kind == ENCODE:
             r.entry = self.cache.prefetch(r.params)
+            r.stripe = None
         else:
-            st = self.stripes[r.stripe]
-            r.entry = st.entry
-            st.queue.append(r)
+            r.entry = self.stripes[r.stripe].entry
         r.entry.refs += 1
-        self.pending.append(r)
+        self.sched.submit(r)
 
     def _footprint(self, r):
         """Device bytes of the request's outputs (its workspace is part of the
         tick's plan memory, counted when the tick is launched)."""
+        if r.entry.graph is None:
+            r.entry.graph = r.entry.future.result()
         g = r.entry.graph
         if r.kind == ENCODE:
             return g.n * r.t + 1024
         if r.kind == DECODE:
             return g.k * r.t + g.k + 1024
         return int(r.ids.numel()) + 1024
-
-    def _eligible(self, r):
-        if not r.entry.ready():
-            return False
-        if r.kind == ENCODE:
-            return True
-        st = self.stripes[r.stripe]
-        return not st.busy and st.queue[0] is r
-
-    def _admit(self):
-        batch, rest = [], collections.deque()
-        blocked = False
-        while self.pending:
-            r = self.pending.popleft()
-            if blocked or len(batch) >= self.max_items or not self._eligible(r):
-                rest.append(r)
-                continue
-            if r.entry.graph is None:
-                r.entry.graph = r.entry.future.result()
-            fp = self._footprint(r)
-            if self.used + fp > self.budget and (self.inflight or batch):
-                blocked = True   # keep arrival order for memory
-                rest.append(r)
-                continue
-            r.footprint = fp
-            self.used += fp
-            if r.kind != ENCODE:
-                self.stripes[r.stripe].busy = True
-            batch.append(r)
-        self.pending = rest
-        return batch
 
     def _items(self, batch, stream, keep):
         items = []
@@ -339,7 +371,7 @@ class Server:
         tk.end.record(stream)
         tk.keep += [mem, stage, items]
         tk.footprint = dev_bytes
-        self.used += dev_bytes
+        self.sched.used += dev_bytes
         tk.t_launch = time.perf_counter()
         for r in batch:
             r.t_launch = tk.t_launch
@@ -352,15 +384,11 @@ class Server:
 
     def _complete(self, tk, now):
         tk.plan.free()
-        self.used -= tk.footprint
+        self.sched.used -= tk.footprint
         for r in tk.requests:
             r.t_done = now
-            self.used -= r.footprint
+            self.sched.release(r)
             r.entry.refs -= 1
-            if r.kind != ENCODE:
-                st = self.stripes[r.stripe]
-                st.busy = False
-                st.queue.popleft()
             if not self.keep_outputs:
                 r.c = r.out = None
             self.done.append(r)
@@ -385,16 +413,16 @@ class Server:
     def step(self):
         """One pass of the loop; returns True when it launched a tick."""
         self.poll()
-        if not self.pending or len(self.inflight) >= self.max_inflight:
+        if not self.sched.pending or len(self.inflight) >= self.max_inflight:
             return False
-        batch = self._admit()
+        batch = self.sched.admit(len(self.inflight))
         if not batch:
             return False
         self._launch(batch)
         return True
 
     def drain(self):
-        while self.pending or self.inflight:
+        while self.sched.pending or self.inflight:
             if not self.step():
                 time.sleep(0)
 
@@ -412,7 +440,7 @@ class Server:
         self.tick_items = []
         t0 = time.perf_counter()
         i, nreq = 0, len(requests)
-        while i < nreq or self.pending or self.inflight:
+        while i < nreq or self.sched.pending or self.inflight:
             now = time.perf_counter() - t0
             while i < nreq and requests[i].arrival * time_scale <= now:
                 self.submit(requests[i])
