@@ -216,7 +216,10 @@ struct ZeroEntry {
 fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long *d_prefix, uint32_t njobs,
                               unsigned long long *d_counter, const fs_tune &tune, uint32_t grid,
                               uint64_t total_items, hipStream_t s);
-fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, bool lds, size_t lds_bytes, hipStream_t s);
+// mode: where the peel keeps its state (peel_mode); lds_bytes: dynamic LDS
+fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, int mode, size_t lds_bytes, hipStream_t s);
+// 2: all of the peel's state fits LDS, 1: its per-row counters do, 0: none
+int peel_mode(uint32_t k, uint32_t n, uint32_t max_deg);
 fs_status launch_prog_batch(const ProgJob *d_jobs, uint32_t njobs, hipStream_t s);
 // prog_lds: dynamic LDS of each workgroup, enough for the 16-bit program of
 // the largest item (replay_prog_lds_bound); items whose program does not fit

@@ -502,7 +502,12 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
   return total;
 }
 
-template <bool LDS>
+// Where the peel keeps its state: kPeelLds all of it in LDS, kPeelLdsRows
+// only the per-row counters (the one array every edge updates atomically;
+// for stripes whose full state does not fit), kPeelGlobal none of it.
+constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2;
+
+template <int MODE>
 __device__ __forceinline__ void peel_body(const PeelJob &J) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   __shared__ int s_nA, s_nB, s_nD;
@@ -511,7 +516,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   const int tid = threadIdx.x;
   const int wid = tid >> 6;
   PeelState S;
-  if constexpr (LDS) {
+  if constexpr (MODE == kPeelLds) {
     unsigned char *p = smem;
     S.acc = reinterpret_cast<unsigned long long *>(p); p += 8ull * n;
     S.best = reinterpret_cast<unsigned long long *>(p); p += 8ull * k;
@@ -523,7 +528,8 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.cptr = reinterpret_cast<int32_t *>(p); p += 4ull * (k + 1);
     S.deg = reinterpret_cast<uint16_t *>(p);
   } else {
-    S.acc = J.acc; S.best = J.best; S.fa = J.front_a; S.fb = J.front_b; S.dl = J.dlist;
+    S.acc = MODE == kPeelLdsRows ? reinterpret_cast<unsigned long long *>(smem) : J.acc;
+    S.best = J.best; S.fa = J.front_a; S.fb = J.front_b; S.dl = J.dlist;
     S.mask = J.mask; S.decm = J.decmask;
     S.cptr = const_cast<int32_t *>(J.col_ptr);
     S.deg = nullptr;
@@ -536,7 +542,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.mask[w] = 0;
     S.decm[w] = 0;
   }
-  if constexpr (LDS) {
+  if constexpr (MODE == kPeelLds) {
     for (uint32_t i = tid; i <= k; i += kPeelThreads) S.cptr[i] = J.col_ptr[i];
   }
   if (tid == 0) {
@@ -548,7 +554,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   __syncthreads();
   for (uint32_t g = tid; g < n; g += kPeelThreads) {
     const int d = J.row_ptr[g + 1] - J.row_ptr[g];
-    if constexpr (LDS) S.deg[g] = (uint16_t)d;
+    if constexpr (MODE == kPeelLds) S.deg[g] = (uint16_t)d;
     if (J.erased[g]) {
       S.acc[g] = kErasedAcc;
       continue;
@@ -586,7 +592,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
       if ((a >> 40) != 1ull) continue;
       const uint32_t f = (uint32_t)(a & kSumMask);
       uint32_t d;
-      if constexpr (LDS)
+      if constexpr (MODE == kPeelLds)
         d = S.deg[g];
       else
         d = (uint32_t)(J.row_ptr[g + 1] - J.row_ptr[g]);
@@ -645,15 +651,15 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   }
 }
 
-template <bool LDS>
+template <int MODE>
 __global__ __launch_bounds__(kPeelThreads) void peel_kernel(PeelJob J) {
-  peel_body<LDS>(J);
+  peel_body<MODE>(J);
 }
 
 // one workgroup per stripe of a batch
-template <bool LDS>
+template <int MODE>
 __global__ __launch_bounds__(kPeelThreads) void peel_batch_kernel(const PeelJob *jobs) {
-  peel_body<LDS>(jobs[blockIdx.x]);
+  peel_body<MODE>(jobs[blockIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1331,19 +1337,35 @@ static void set_max_lds(const void *fn, int dev, int bytes, bool *done) {
   }
 }
 
+int peel_mode(uint32_t k, uint32_t n, uint32_t max_deg) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const size_t budget = (size_t)device_info(dev).max_lds_per_block - 64;
+  if (max_deg < 65536 && peel_lds_bytes(k, n) <= budget) return kPeelLds;
+  if (8ull * n <= budget) return kPeelLdsRows;
+  return kPeelGlobal;
+}
+
 fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg) {
   int dev = 0;
   (void)hipGetDevice(&dev);
   const size_t lds = peel_lds_bytes(job.k, job.n);
   const size_t static_lds = 64;
   const int budget = device_info(dev).max_lds_per_block;
-  if (max_deg < 65536 && lds + static_lds <= (size_t)budget) {
+  const int mode = peel_mode(job.k, job.n, max_deg);
+  if (mode == kPeelLds) {
     static bool done[64] = {false};
-    set_max_lds(reinterpret_cast<const void *>(&peel_kernel<true>), dev, budget - (int)static_lds, done);
-    hipLaunchKernelGGL(peel_kernel<true>, dim3(1), dim3(kPeelThreads), lds, s, job);
+    set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLds>), dev, budget - (int)static_lds, done);
+    hipLaunchKernelGGL(peel_kernel<kPeelLds>, dim3(1), dim3(kPeelThreads), lds, s, job);
   } else {
     if (!job.acc) return fail(FS_ERR_WORKSPACE, "peel state needs the workspace");
-    hipLaunchKernelGGL(peel_kernel<false>, dim3(1), dim3(kPeelThreads), 0, s, job);
+    if (mode == kPeelLdsRows) {
+      static bool done[64] = {false};
+      set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLdsRows>), dev, budget - (int)static_lds, done);
+      hipLaunchKernelGGL(peel_kernel<kPeelLdsRows>, dim3(1), dim3(kPeelThreads), 8ull * job.n, s, job);
+    } else {
+      hipLaunchKernelGGL(peel_kernel<kPeelGlobal>, dim3(1), dim3(kPeelThreads), 0, s, job);
+    }
   }
   return hip_check(hipGetLastError(), "peel launch");
 }
@@ -1531,17 +1553,22 @@ fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long 
   return hip_check(e, "batched gather launch");
 }
 
-fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, bool lds, size_t lds_bytes, hipStream_t s) {
+fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, int mode, size_t lds_bytes, hipStream_t s) {
   if (njobs == 0) return FS_OK;
   int dev = 0;
   (void)hipGetDevice(&dev);
-  if (lds) {
+  if (mode == kPeelLds) {
     static bool done[64] = {false};
-    set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<true>), dev,
+    set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLds>), dev,
                 device_info(dev).max_lds_per_block - 64, done);
-    hipLaunchKernelGGL(peel_batch_kernel<true>, dim3(njobs), dim3(kPeelThreads), lds_bytes, s, d_jobs);
+    hipLaunchKernelGGL(peel_batch_kernel<kPeelLds>, dim3(njobs), dim3(kPeelThreads), lds_bytes, s, d_jobs);
+  } else if (mode == kPeelLdsRows) {
+    static bool done[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLdsRows>), dev,
+                device_info(dev).max_lds_per_block - 64, done);
+    hipLaunchKernelGGL(peel_batch_kernel<kPeelLdsRows>, dim3(njobs), dim3(kPeelThreads), lds_bytes, s, d_jobs);
   } else {
-    hipLaunchKernelGGL(peel_batch_kernel<false>, dim3(njobs), dim3(kPeelThreads), 0, s, d_jobs);
+    hipLaunchKernelGGL(peel_batch_kernel<kPeelGlobal>, dim3(njobs), dim3(kPeelThreads), 0, s, d_jobs);
   }
   return hip_check(hipGetLastError(), "batched peel launch");
 }
@@ -1595,7 +1622,7 @@ void prepare_batch_kernels() {
   (void)hipGetDevice(&dev);
   const int budget = device_info(dev).max_lds_per_block;
   static bool d1[64] = {false}, d2[64] = {false};
-  set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<true>), dev, budget - 64, d1);
+  set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLds>), dev, budget - 64, d1);
   set_max_lds(reinterpret_cast<const void *>(&replay_batch_kernel<kBatchReplayLanes>), dev, budget, d2);
 }
 

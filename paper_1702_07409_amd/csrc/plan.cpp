@@ -44,6 +44,8 @@ struct fs_plan {
   std::vector<ReplayJob> solo_replays;
   std::vector<uint32_t> solo_replay_prog;
   std::vector<ProgJob> replay_progs;   // programs of the batched replays, in their order
+  std::vector<PeelJob> peels_rows;     // schedules whose row counters alone fit LDS
+  size_t peel_rows_bytes = 0;
   std::vector<PeelJob> peels_global;   // schedules too large for LDS
   bool peel_lds = true;
   size_t peel_lds_bytes = 0;
@@ -59,6 +61,7 @@ struct fs_plan {
   GatherJob *d_gjobs = nullptr;
   unsigned long long *d_gprefix = nullptr;
   PeelJob *d_peels = nullptr;
+  PeelJob *d_peels_rows = nullptr;
   PeelJob *d_peels_global = nullptr;
   ProgJob *d_progs = nullptr;
   ReplayJob *d_replays = nullptr;
@@ -195,12 +198,11 @@ void build_descriptors(fs_plan &P) {
   P.solo_replay_prog.clear();
   P.replay_progs.clear();
   P.peels_global.clear();
+  P.peels_rows.clear();
+  P.peel_rows_bytes = 0;
   P.peel_lds = true;
   P.peel_lds_bytes = 0;
   P.replay_lds = 256;
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  const size_t lds_budget = (size_t)device_info(dev).max_lds_per_block - 64;
   Carver cv(P.d_ws);
   for (const fs_work &w : P.items) {
     const fs_graph *g = w.graph;
@@ -225,12 +227,15 @@ void build_descriptors(fs_plan &P) {
         pj.dlist = b.dec.peel.dlist;
         pj.mask = b.dec.peel.mask;
         pj.decmask = b.dec.peel.decmask;
-        const size_t need = peel_lds_bytes(g->k, g->n);
-        if (g->max_deg >= 65536 || need > lds_budget) {
-          P.peels_global.push_back(pj);
-        } else {
-          P.peel_lds_bytes = std::max(P.peel_lds_bytes, need);
+        const int mode = peel_mode(g->k, g->n, g->max_deg);
+        if (mode == 2) {
+          P.peel_lds_bytes = std::max(P.peel_lds_bytes, peel_lds_bytes(g->k, g->n));
           P.peels.push_back(pj);
+        } else if (mode == 1) {
+          P.peel_rows_bytes = std::max<size_t>(P.peel_rows_bytes, 8ull * g->n);
+          P.peels_rows.push_back(pj);
+        } else {
+          P.peels_global.push_back(pj);
         }
         ProgJob prog = b.dec.prog;
         prog.status = status;
@@ -379,6 +384,7 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   P.d_gjobs = place<GatherJob>(base, off, P.gjobs.size());
   P.d_gprefix = place<unsigned long long>(base, off, P.gprefix.size());
   P.d_peels = place<PeelJob>(base, off, P.peels.size());
+  P.d_peels_rows = place<PeelJob>(base, off, P.peels_rows.size());
   P.d_peels_global = place<PeelJob>(base, off, P.peels_global.size());
   P.d_progs = place<ProgJob>(base, off, P.progs.size());
   P.d_replays = place<ReplayJob>(base, off, P.replays.size());
@@ -412,6 +418,7 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   put(P.d_gjobs, P.gjobs.data(), P.gjobs.size() * sizeof(GatherJob));
   put(P.d_gprefix, P.gprefix.data(), P.gprefix.size() * sizeof(unsigned long long));
   put(P.d_peels, P.peels.data(), P.peels.size() * sizeof(PeelJob));
+  put(P.d_peels_rows, P.peels_rows.data(), P.peels_rows.size() * sizeof(PeelJob));
   put(P.d_peels_global, P.peels_global.data(), P.peels_global.size() * sizeof(PeelJob));
   put(P.d_progs, P.progs.data(), P.progs.size() * sizeof(ProgJob));
   put(P.d_replays, P.replays.data(), P.replays.size() * sizeof(ReplayJob));
@@ -438,15 +445,16 @@ uint32_t gather_grid_for(uint64_t items) {
 
 // The whole plan as launches on s (branch A on P.side when it exists).
 fs_status enqueue(fs_plan &P, hipStream_t s) {
-  const bool fork = P.side != nullptr && !(P.peels.empty() && P.peels_global.empty());
+  const bool fork = P.side != nullptr && !(P.peels.empty() && P.peels_rows.empty() && P.peels_global.empty());
   hipStream_t a = fork ? P.side : s;
   if (fork) {
     PL_TRY(hip_ok(hipEventRecord(P.fork, s), "fork"));
     PL_TRY(hip_ok(hipStreamWaitEvent(P.side, P.fork, 0), "fork wait"));
   }
   // branch A: decodes (schedule, program, replay)
-  PL_TRY(launch_peel_batch(P.d_peels, (uint32_t)P.peels.size(), true, P.peel_lds_bytes, a));
-  PL_TRY(launch_peel_batch(P.d_peels_global, (uint32_t)P.peels_global.size(), false, 0, a));
+  PL_TRY(launch_peel_batch(P.d_peels, (uint32_t)P.peels.size(), 2, P.peel_lds_bytes, a));
+  PL_TRY(launch_peel_batch(P.d_peels_rows, (uint32_t)P.peels_rows.size(), 1, P.peel_rows_bytes, a));
+  PL_TRY(launch_peel_batch(P.d_peels_global, (uint32_t)P.peels_global.size(), 0, 0, a));
   PL_TRY(launch_prog_batch(P.d_progs, (uint32_t)P.progs.size(), a));
   // replays[i] runs the program replay_progs[i] (built above for every decode)
   PL_TRY(launch_replay_batch(P.d_replays, P.d_replay_progs, P.d_rprefix, (uint32_t)P.replays.size(),
@@ -662,7 +670,7 @@ fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_
   }
   P->gather_grid = gather_grid_for(P->gprefix.back());
   if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(FS_ERR_HIP, "plan upload failed"));
-  if (!P->peels.empty() || !P->peels_global.empty()) {
+  if (!P->peels.empty() || !P->peels_rows.empty() || !P->peels_global.empty()) {
     if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess)

@@ -237,9 +237,12 @@ def test_decode_k1_t16():
     decode_case(sp)
 
 
-def test_peel_state_beyond_lds_uses_workspace():
-    # k = 16384 does not fit the peel state in LDS: the global-state kernel runs
-    sp = workloads.StripeSpec(stripe=0, k=16384, n=18022, t=16, dist="rsd", stripe_key=1, n_erased=901)
+@pytest.mark.parametrize("k,n", [(16384, 18022), (20000, 22000)])
+def test_peel_state_beyond_lds_uses_workspace(k, n):
+    # k = 16384: the full peel state does not fit LDS, its per-row counters
+    # (8 n bytes) do; n = 22000: not even those, everything stays in the
+    # workspace
+    sp = workloads.StripeSpec(stripe=0, k=k, n=n, t=16, dist="rsd", stripe_key=1, n_erased=round(0.05 * n))
     decode_case(sp)
 
 
