@@ -258,7 +258,8 @@ FS_API fs_status fs_decode_apply(const fs_graph *g, const void *c, void *x, uint
 /* Tuning of the gather-XOR kernel family (encode, repair, update). */
 typedef struct fs_tune {
   uint32_t lanes_per_row;  /* 16, 32 or 64 lanes share one coded row         */
-  uint32_t chunks;         /* 16-byte chunks per lane per slice: 1, 2 or 4   */
+  uint32_t chunks;         /* 16-byte chunks per lane per slice: 1, 2 or 4
+                              (both 0: chosen per graph, see fs_set_tune)    */
   uint32_t xcd_remap;      /* 1: keep each XCD on a contiguous slice range   */
   uint32_t nt_store;       /* 1: non-temporal stores for outputs             */
   uint32_t replay_prog_global; /* 1: keep decode replay programs in global
@@ -270,9 +271,11 @@ typedef struct fs_tune {
 
 /*
  * Override (or with NULL restore) the gather tuning used by this process.
- * The default is {64, 4, 1, 1, 0, 1}: 4 KiB gather slices, which read each
- * neighbour block in long runs (best when the inputs are not already
- * cached), and the LDS-slab encode where it applies.
+ * The default is {0, 0, 1, 1, 0, 1}: the gather slice is chosen per graph
+ * (4 KiB for graphs of mean degree <= 6, which read each neighbour block in
+ * long runs; for denser graphs 2 MiB / k within [512 B, 4 KiB], so that one
+ * slice of every input stays in an XCD's L2), and the LDS-slab encode
+ * where it applies.
  */
 FS_API fs_status fs_set_tune(const fs_tune *tune);
 FS_API fs_status fs_get_tune(fs_tune *tune);

@@ -297,7 +297,7 @@ def fs_update(g, x, c, ids, n_ids, new_blocks, status, t, ws, stream=None):
                           t, w, wb, _stream(stream)), "fs_update")
 
 
-def fs_set_tune(lanes_per_row=64, chunks=4, xcd_remap=1, nt_store=1, replay_prog_global=0, encode_slab=1):
+def fs_set_tune(lanes_per_row=0, chunks=0, xcd_remap=1, nt_store=1, replay_prog_global=0, encode_slab=1):
     tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store, replay_prog_global, encode_slab)
     _check(_lib.fs_set_tune(ctypes.byref(tu)), "fs_set_tune")
 

@@ -283,6 +283,8 @@ void graph_image(const fs_graph &g, GraphImage &img);
 void bind_image(fs_graph &g, const GraphImage &img, void *base);
 
 fs_tune current_tune();
+// the tuning with its gather tiling filled in for graph g when left open
+fs_tune tile_for(const fs_tune &t, const fs_graph *g);
 fs_status check_graph(const fs_graph *g);
 fs_status check_payload(const void *p, uint64_t t, const char *name);
 void carve_sched(Carver &cv, uint32_t k, SchedBufs &s, bool with_recovered);

@@ -41,6 +41,8 @@ struct fs_plan {
   // the replays of large decodes (program index into progs)
   std::vector<GatherJob> solo;
   std::vector<uint8_t> solo_accumulate;
+  std::vector<const fs_graph *> solo_graph;   // graph of each solo job (its tiling)
+  std::vector<const fs_graph *> gjob_graph;   // graph of each gather job while building
   std::vector<ReplayJob> solo_replays;
   std::vector<uint32_t> solo_replay_prog;
   std::vector<ProgJob> replay_progs;   // programs of the batched replays, in their order
@@ -169,6 +171,16 @@ constexpr uint64_t kSoloItems = 8192;
 // (which pick the slice width and LDS layout for its shape).
 constexpr uint64_t kSoloReplayBytes = 32ull << 20;
 
+// The persistent kernel's tiling: the plan's (tuned or set) tiling, or,
+// left open, 16 lanes x 2 chunks: its jobs are the small ones.
+fs_tune batch_tune(const fs_tune &t) {
+  if (t.lanes_per_row != 0) return t;
+  fs_tune r = t;
+  r.lanes_per_row = 16;
+  r.chunks = 2;
+  return r;
+}
+
 bool solo_gather(const GatherJob &j) {
   // jobs sized on the device (update deltas) only know a bound: they stay
   // in the persistent kernel, which skips their dead tiles cheaply
@@ -194,6 +206,8 @@ void build_descriptors(fs_plan &P) {
   P.zero_max_t = 0;
   P.solo.clear();
   P.solo_accumulate.clear();
+  P.solo_graph.clear();
+  P.gjob_graph.clear();
   P.solo_replays.clear();
   P.solo_replay_prog.clear();
   P.replay_progs.clear();
@@ -214,6 +228,7 @@ void build_descriptors(fs_plan &P) {
         if (!g->heavy.empty()) P.zero_max_t = std::max(P.zero_max_t, w.t);
         P.gjobs.push_back(encode_job(g, w.x, w.c, w.t));
         P.gjob_accumulate.push_back(0);
+        P.gjob_graph.push_back(g);
         break;
       }
       case FS_WORK_DECODE: {
@@ -283,6 +298,7 @@ void build_descriptors(fs_plan &P) {
           gj.t = w.t;
           P.gjobs.push_back(gj);
           P.gjob_accumulate.push_back(0);
+          P.gjob_graph.push_back(g);
         }
         break;
       }
@@ -331,6 +347,7 @@ void build_descriptors(fs_plan &P) {
           gj.accumulate = 1;
           P.gjobs.push_back(gj);
           P.gjob_accumulate.push_back(1);
+          P.gjob_graph.push_back(g);
         }
         break;
       }
@@ -344,6 +361,7 @@ void build_descriptors(fs_plan &P) {
     if (solo_gather(P.gjobs[i])) {
       P.solo.push_back(P.gjobs[i]);
       P.solo_accumulate.push_back(P.gjob_accumulate[i]);
+      P.solo_graph.push_back(P.gjob_graph[i]);
     } else {
       shared.push_back(P.gjobs[i]);
       shared_acc.push_back(P.gjob_accumulate[i]);
@@ -377,8 +395,8 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   for (size_t i = 0; i < P.gjobs.size(); ++i)
     if (!P.gjob_accumulate[i]) tjobs.push_back(P.gjobs[i]);
   std::vector<unsigned long long> tprefix;
-  gather_prefix(tjobs, P.tune, tprefix);
-  gather_prefix(P.gjobs, P.tune, P.gprefix);
+  gather_prefix(tjobs, batch_tune(P.tune), tprefix);
+  gather_prefix(P.gjobs, batch_tune(P.tune), P.gprefix);
   size_t off = 0;
   uint8_t *base = static_cast<uint8_t *>(P.d_desc);
   P.d_gjobs = place<GatherJob>(base, off, P.gjobs.size());
@@ -466,9 +484,9 @@ fs_status enqueue(fs_plan &P, hipStream_t s) {
   PL_TRY(launch_repair_prep_batch(P.d_rpreps, (uint32_t)P.rpreps.size(), s));
   PL_TRY(launch_update_plan_batch(P.d_uplans, (uint32_t)P.uplans.size(), s));
   PL_TRY(launch_update_delta_batch(P.d_udeltas, P.d_uprefix, (uint32_t)P.udeltas.size(), P.uprefix.back(), s));
-  PL_TRY(launch_gather_batch(P.d_gjobs, P.d_gprefix, (uint32_t)P.gjobs.size(), P.d_counter, P.tune, P.gather_grid,
-                             P.gprefix.back(), s));
-  for (const GatherJob &j : P.solo) PL_TRY(launch_gather(j, P.tune, s));
+  PL_TRY(launch_gather_batch(P.d_gjobs, P.d_gprefix, (uint32_t)P.gjobs.size(), P.d_counter, batch_tune(P.tune),
+                             P.gather_grid, P.gprefix.back(), s));
+  for (size_t i = 0; i < P.solo.size(); ++i) PL_TRY(launch_gather(P.solo[i], tile_for(P.tune, P.solo_graph[i]), s));
   if (fork) {
     PL_TRY(hip_ok(hipEventRecord(P.join, P.side), "join"));
     PL_TRY(hip_ok(hipStreamWaitEvent(s, P.join, 0), "join wait"));
