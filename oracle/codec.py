@@ -19,6 +19,8 @@ Functions and the passage each follows
                 the same union of decoded sets).
   repair_from_inputs   conventional re-encoding of lost coded rows when the
                 inputs are at hand (§4, "re-run partial encoding").
+  extend        §2.9: new coded rows n_old..n-1 of a longer (prefix-stable)
+                graph, from the inputs or, as repair does, from the existing rows
   repair_conventional  §4: decode the survivors, then re-encode each lost row
                 whose neighbours were all recovered.
   update        replace some input blocks; the definition is re-encoding from
@@ -231,6 +233,30 @@ def repair_conventional(G, c, erased, lost, maxit=0):
             out[r] = _xor_rows(x[G.N(j)])
             ok[r] = 1
     return out, ok
+
+
+def extend(G, n_old, x=None, c_old=None, erased=None, maxit=0):
+    """The paper's update (§2.9): the code gains coded blocks n_old..n-1 of the
+    graph G (whose first n_old rows are those of the original graph: rows
+    depend only on their own index) without any change to the existing ones.
+
+    With the inputs x the new blocks are their encode.  Without them they are
+    made the way the repair engine makes missing blocks (§4): decode from the
+    existing blocks c_old[0:n_old] that are not erased, then encode each new
+    row whose neighbours were all recovered; the others stay zero.
+
+    Returns (blocks[n - n_old, t], made[n - n_old]).
+    """
+    new_rows = list(range(n_old, G.n))
+    if x is not None:
+        return encode(G, x, rows=new_rows), np.ones(len(new_rows), dtype=np.uint8)
+    t = c_old.shape[1]
+    c = np.zeros((G.n, t), dtype=np.uint8)
+    c[:n_old] = c_old[:n_old]
+    er = np.zeros(G.n, dtype=bool)
+    if erased is not None:
+        er[:n_old] = np.asarray(erased, dtype=bool)[:n_old]
+    return repair_conventional(G, c, er, new_rows, maxit)
 
 
 def update(G, x, ids, new_blocks):

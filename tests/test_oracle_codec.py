@@ -262,3 +262,49 @@ def test_workload_shapes():
     assert (t.k, t.n, t.t, t.n_erased) == (64, 96, 4096, 16)
     r = workloads.resident256(4)
     assert all(1 <= len(sp.extra["lost"]) <= 4 and len(sp.extra["update_ids"]) == 10 for sp in r)
+
+
+def _graph(k, n, seed=1, key=0, **kw):
+    kw.setdefault("dist", "rsd")
+    return graph.build(graph.GraphParams(k=k, n=n, seed=seed, stripe_key=key, **kw))
+
+
+def test_extension_keeps_existing_blocks_and_strengthens_the_code():
+    # the longer graph starts with the original rows, so the existing blocks
+    # are part of the extended code unchanged; the new rows make an erasure
+    # pattern decodable that the original code could not resolve
+    k, n_old, n_new, t = 200, 210, 300, 16
+    G0, G1 = _graph(k, n_old), _graph(k, n_new)
+    x = gen.payload(0, 5, k, t)
+    c_old = codec.encode(G0, x)
+    new, made = codec.extend(G1, n_old, x=x)
+    assert made.all() and new.shape == (n_new - n_old, t)
+    assert np.array_equal(np.concatenate([c_old, new]), codec.encode(G1, x))
+    er_old = gen.erasure_mask(2, 5, n_old, 10)
+    _, rec0, st0, _ = codec.decode(G0, c_old, er_old)
+    er_new = np.concatenate([er_old, np.zeros(n_new - n_old, np.uint8)])
+    x1, rec1, st1, _ = codec.decode(G1, np.concatenate([c_old, new]), er_new)
+    assert st0[0] == 0 and st1[0] == 1 and np.array_equal(x1, x)
+    assert rec1.sum() > rec0.sum()
+
+
+def test_extension_without_inputs_follows_the_recovered_set():
+    # generated from the existing blocks: a new row is made exactly when all
+    # its neighbours were recovered from the surviving old rows, and then it
+    # equals the encode of the inputs; the others stay zero
+    k, n_old, n_new, t = 150, 260, 320, 16
+    G0, G1 = _graph(k, n_old, key=5), _graph(k, n_new, key=5)
+    x = gen.payload(0, 6, k, t)
+    c_old = codec.encode(G0, x)
+    full, _ = codec.extend(G1, n_old, x=x)
+    for n_er in (0, 30):
+        er = gen.erasure_mask(2, 6, n_old, n_er)
+        new, made = codec.extend(G1, n_old, c_old=c_old, erased=er)
+        _, rec, _, _ = codec.decode(G0, c_old, er)
+        for r, j in enumerate(range(n_old, n_new)):
+            want = all(rec[i] for i in G1.N(j))
+            assert bool(made[r]) == want
+            assert np.array_equal(new[r], full[r] if want else np.zeros(t, np.uint8))
+        if n_er == 0:
+            assert rec.all() and made.all()
+    assert not made.all()   # 30 of 260 rows erased: the decode stalls early
