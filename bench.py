@@ -53,10 +53,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="large_stripe",
-                    choices=["large_stripe", "batch512", "resident256", "serve", "all"],
+                    choices=["large_stripe", "batch512", "resident256", "serve", "extend", "all"],
                     help="large_stripe: plain one-stripe path (the headline line); batch512 / "
                          "resident256: batched plans vs the plain loop; serve: the request loop "
-                         "on a Poisson mix; all: the headline line with the others attached")
+                         "on a Poisson mix; extend: code extension of the large stripe; all: the "
+                         "headline line with the others attached")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--batch-stripes", type=int, default=512)
@@ -122,9 +123,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.workload in ("batch512", "resident256", "serve"):
+    if args.workload in ("batch512", "resident256", "serve", "extend"):
         import bench_batch
-        if args.workload == "batch512":
+        if args.workload == "extend":
+            res = bench_batch.run_extend()
+        elif args.workload == "batch512":
             res = bench_batch.run_batch512(args.batch_stripes)
         elif args.workload == "resident256":
             res = bench_batch.run_resident256(args.resident_stripes)

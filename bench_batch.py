@@ -8,6 +8,9 @@ batch512     512 stripes, k log-uniform in [64, 8192), blocks 4 KiB..1 MiB,
 resident256  256 stripes k=1024 x 256 KiB, n=1126, RSD (c=0.1, delta=0.05),
              resident in HBM: repair of 1-4 lost coded blocks per stripe from
              the inputs, and an update of 10 inputs per stripe.
+extend       the large stripe (k=4096 x 64 KiB, finite16, n=1.1 k) grown to
+             n=1.2 k: 409 new coded blocks from the resident inputs, and from
+             the existing blocks with 5 % of them erased.
 """
 
 import sys
@@ -213,6 +216,44 @@ def run_resident256(count=256, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
         "update_batched_GBps_user": round(upd_user / (t_upd * 1e-3) / 1e9, 1),
         "update_hbm_frac_effective": round(upd_comp / (t_upd * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "repair_tune": rep.info()["tune"], "setup_s": round(time.perf_counter() - t0, 1),
+    }
+
+
+def run_extend(reps=20):
+    import torch
+    import paper_1702_07409_amd as fs
+    import synth.gpu as sg
+    from dataclasses import replace
+    from synth import gen, workloads
+
+    base = workloads.large_stripe()
+    sp = replace(base, n=gen.overhead_n(base.k, 0.20))
+    k, n_old, n, t = sp.k, base.n, sp.n, sp.t
+    g = fs.fs_graph_build(**sp.graph_kwargs())
+    x = torch.empty((k, t), dtype=torch.uint8, device="cuda")
+    sg.fill(x, sp.data_seed, sp.stripe, t)
+    c = torch.empty((n, t), dtype=torch.uint8, device="cuda")
+    fs.fs_encode(g, x, c, t)
+    er = torch.from_numpy(gen.erasure_mask(sp.erase_seed, sp.stripe, n_old, base.n_erased)).cuda()
+    made = torch.empty(n - n_old, dtype=torch.uint8, device="cuda")
+    st = torch.empty(3, dtype=torch.int32, device="cuda")
+    wa = fs.workspace(g, fs.FS_OP_EXTEND, t)
+    wb = fs.workspace(g, fs.FS_OP_EXTEND_CONVENTIONAL, t)
+    t_a = _time(lambda: fs.fs_extend(g, n_old, x, c, None, made, st, t, wa), reps)
+    made_a = int(made.sum())
+    t_b = _time(lambda: fs.fs_extend(g, n_old, None, c, er, made, st, t, wb), reps)
+    made_b = int(made.sum())
+    rp, col, _, _ = g.export()
+    touched = len(np.unique(col[rp[n_old]:rp[n]]))
+    new_bytes = (n - n_old) * t
+    return {
+        "workload": "extend", "k": k, "n_old": n_old, "n": n, "t": t, "erased_old": base.n_erased,
+        "from_inputs_ms": round(t_a, 3), "from_inputs_made": made_a,
+        "from_inputs_GBps_new": round(new_bytes / (t_a * 1e-3) / 1e9, 1),
+        "from_inputs_hbm_frac_effective": round((touched + n - n_old) * t / (t_a * 1e-3) / 1e9
+                                                / HBM_PEAK_GBPS, 4),
+        "conventional_ms": round(t_b, 3), "conventional_made": made_b,
+        "conventional_GBps_new": round(made_b * t / (t_b * 1e-3) / 1e9, 1),
     }
 
 

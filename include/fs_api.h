@@ -154,7 +154,8 @@ FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t
 
 /* Operations for fs_workspace_size. */
 enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
-       FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6 };
+       FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6, FS_OP_EXTEND = 7,
+       FS_OP_EXTEND_CONVENTIONAL = 8 };
 
 /*
  * Workspace bytes the operation needs for this graph and block size
@@ -238,6 +239,29 @@ FS_API fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint
 FS_API fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *ids, uint32_t n_ids,
                     const void *new_blocks, int32_t *status, uint64_t t, void *ws,
                     size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Code extension, the paper's update (§2.9): the code is made
+ * stronger by new coded blocks while no existing block changes.  g is the
+ * graph of the longer code (n rows); since a row depends only on its own
+ * index and the seeds, its first n_old rows are those of the original code.
+ * c: device uint8[n][t]; rows [0, n_old) hold the existing blocks, rows
+ * [n_old, n) are written and nothing else is.
+ *   x != NULL  the new rows are encoded from the resident inputs.
+ *   x == NULL  they are made the way the repair engine makes missing blocks:
+ *              peel + replay over the existing rows that are not erased,
+ *              then each new row whose neighbours were all recovered is
+ *              encoded; other new rows are zero-filled.  erased: device
+ *              uint8[n_old] (may be NULL = none).
+ * made: device uint8[n - n_old], 1 where the new block was made.
+ * status: device int32[3] {all made, rows not made, 0}.
+ * ws: FS_OP_EXTEND (x given) or FS_OP_EXTEND_CONVENTIONAL bytes; neither
+ * depends on n_old.  Making the code weaker (dropping coded rows) needs no
+ * call: the shorter code is the prefix of rows it keeps.
+ */
+FS_API fs_status fs_extend(const fs_graph *g, uint32_t n_old, const void *x, void *c,
+                    const uint8_t *erased, uint8_t *made, int32_t *status, uint64_t t,
+                    void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Decode in two halves.  fs_decode_plan runs the peeling schedule of fs_peel

@@ -1,6 +1,6 @@
 """MI355X (gfx950) implementation of the LDGM fountain-code XOR path of
 Founsure 1.0: seeded graph build, encode, level-synchronous peeling decode,
-repair and delta update, as HIP kernels behind the C ABI of libfs.so
+repair, delta update and code extension, as HIP kernels behind the C ABI of libfs.so
 (include/fs_api.h).  This package is the thin ctypes binding; PyTorch only
 supplies device memory and streams.
 
@@ -11,10 +11,12 @@ then raises ImportError.
 
 _BINDING = (
     "EXPORTED", "FS_DEFAULT_SEED", "FS_OP_DECODE", "FS_OP_ENCODE", "FS_OP_PEEL", "FS_OP_REPAIR",
-    "FS_OP_REPAIR_CONVENTIONAL", "FS_OP_REPLAY", "FS_OP_UPDATE", "FsError", "Graph", "fs_decode",
+    "FS_OP_REPAIR_CONVENTIONAL", "FS_OP_REPLAY", "FS_OP_UPDATE", "FS_OP_EXTEND",
+    "FS_OP_EXTEND_CONVENTIONAL", "FsError", "Graph", "fs_decode",
     "fs_decode_apply", "fs_decode_plan", "fs_degree_table", "fs_encode", "fs_get_tune",
     "fs_graph_build", "fs_peel", "fs_repair", "fs_replay", "fs_reset_tune", "fs_set_tune",
-    "fs_update", "fs_workspace_size", "version", "workspace", "Plan", "work", "plan_memory_size",
+    "fs_update", "fs_extend", "fs_workspace_size", "version", "workspace", "Plan", "work",
+    "plan_memory_size",
     "FS_WORK_ENCODE", "FS_WORK_DECODE", "FS_WORK_REPAIR", "FS_WORK_UPDATE",
 )
 

@@ -224,6 +224,15 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
       carve_update(cv, g, t, n_items, b);
       return cv.size();
     }
+    case FS_OP_EXTEND:
+    case FS_OP_EXTEND_CONVENTIONAL: {
+      const bool conventional = (op == FS_OP_EXTEND_CONVENTIONAL);
+      cv.take<uint32_t>(g->n);
+      if (conventional) cv.take<uint8_t>(g->n);
+      RepairBufs b;
+      carve_repair(cv, g, t, conventional, b);
+      return cv.size();
+    }
   }
   return 0;
 }
@@ -453,8 +462,9 @@ void fs_graph_free(fs_graph *g) {
 fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
-  if (op < FS_OP_ENCODE || op > FS_OP_REPLAY) return fail(FS_ERR_INVALID, "unknown operation");
-  if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_UPDATE) && (t == 0 || (t & 15)))
+  if (op < FS_OP_ENCODE || op > FS_OP_EXTEND_CONVENTIONAL) return fail(FS_ERR_INVALID, "unknown operation");
+  if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_EXTEND_CONVENTIONAL || op == FS_OP_UPDATE) &&
+      (t == 0 || (t & 15)))
     return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
   *bytes = workspace_bytes(g, op, t, n_items);
   return FS_OK;
@@ -586,19 +596,12 @@ fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uin
   return fs_decode_apply(g, c, x, t, ws, ws_bytes, stream);
 }
 
-fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *erased, const uint32_t *lost,
-                    uint32_t n_lost, uint8_t *repaired, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
-                    hipStream_t stream) {
-  clear_error();
-  FS_TRY(check_graph(g));
-  FS_TRY(check_payload(c, t, "c"));
-  if (x) FS_TRY(check_payload(x, t, "x"));
-  if ((n_lost && (!lost || !repaired)) || !status)
-    return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
+// Repair of the rows lost[0..n_lost) with the workspace already checked; cv
+// points at the part of it that carve_repair lays out.
+static fs_status repair_impl(const fs_graph *g, const void *x, void *c, const uint8_t *erased,
+                             const uint32_t *lost, uint32_t n_lost, uint8_t *repaired, int32_t *status,
+                             uint64_t t, Carver &cv, hipStream_t stream) {
   const bool conventional = (x == nullptr);
-  const int op = conventional ? FS_OP_REPAIR_CONVENTIONAL : FS_OP_REPAIR;
-  FS_TRY(check_ws(g, op, t, n_lost, ws, ws_bytes));
-  Carver cv(ws);
   RepairBufs b;
   carve_repair(cv, g, t, conventional, b);
 
@@ -669,6 +672,43 @@ fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *er
   gj.src = b.x;
   gj.row_ok = repaired;
   return launch_gather(gj, tile_for(current_tune(), g), stream);
+}
+
+fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *erased, const uint32_t *lost,
+                    uint32_t n_lost, uint8_t *repaired, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                    hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(c, t, "c"));
+  if (x) FS_TRY(check_payload(x, t, "x"));
+  if ((n_lost && (!lost || !repaired)) || !status)
+    return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
+  const int op = x ? FS_OP_REPAIR : FS_OP_REPAIR_CONVENTIONAL;
+  FS_TRY(check_ws(g, op, t, n_lost, ws, ws_bytes));
+  Carver cv(ws);
+  return repair_impl(g, x, c, erased, lost, n_lost, repaired, status, t, cv, stream);
+}
+
+fs_status fs_extend(const fs_graph *g, uint32_t n_old, const void *x, void *c, const uint8_t *erased,
+                    uint8_t *made, int32_t *status, uint64_t t, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_payload(c, t, "c"));
+  if (x) FS_TRY(check_payload(x, t, "x"));
+  if (n_old > g->n) return fail(FS_ERR_INVALID, "n_old exceeds the rows of the graph");
+  const uint32_t n_new = g->n - n_old;
+  if ((n_new && !made) || !status) return fail(FS_ERR_INVALID, "made and status must be non-null");
+  const int op = x ? FS_OP_EXTEND : FS_OP_EXTEND_CONVENTIONAL;
+  FS_TRY(check_ws(g, op, t, 0, ws, ws_bytes));
+  Carver cv(ws);
+  ExtendPrepJob ej{};
+  ej.n = g->n;
+  ej.n_old = n_old;
+  ej.erased = erased;
+  ej.ids = cv.take<uint32_t>(g->n);
+  ej.erased_full = x ? nullptr : cv.take<uint8_t>(g->n);
+  FS_TRY(launch_extend_prep(ej, stream));
+  return repair_impl(g, x, c, ej.erased_full, ej.ids, n_new, made, status, t, cv, stream);
 }
 
 fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *ids, uint32_t n_ids,

@@ -166,6 +166,16 @@ struct RepairPrepJob {
 };
 fs_status launch_repair_prep(const RepairPrepJob &job, hipStream_t s);
 
+// Lost-row list and erasure vector of a code extension: ids[i] = n_old + i
+// for i < n - n_old; erased_full (if non-null) = erased on [0, n_old), 0 above.
+struct ExtendPrepJob {
+  uint32_t n, n_old;
+  const uint8_t *erased;   // may be null: nothing erased
+  uint32_t *ids;           // uint32[n - n_old]
+  uint8_t *erased_full;    // uint8[n], may be null
+};
+fs_status launch_extend_prep(const ExtendPrepJob &job, hipStream_t s);
+
 struct RepairCheckJob {
   const int32_t *row_ptr, *col;
   uint32_t n;

@@ -1104,6 +1104,13 @@ __global__ __launch_bounds__(kPlanThreads) void repair_prep_batch_kernel(const R
   repair_prep_body(jobs[blockIdx.x], jobs[blockIdx.x].erased2 ? 0 : 1);
 }
 
+__global__ __launch_bounds__(256) void extend_prep_kernel(ExtendPrepJob J) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= J.n) return;
+  if (i < J.n - J.n_old) J.ids[i] = J.n_old + i;
+  if (J.erased_full) J.erased_full[i] = (i < J.n_old && J.erased && J.erased[i]) ? 1 : 0;
+}
+
 __global__ __launch_bounds__(kPlanThreads) void repair_check_kernel(RepairCheckJob J) {
   __shared__ int s_fail;
   const int tid = threadIdx.x;
@@ -1489,6 +1496,12 @@ fs_status launch_repair_prep(const RepairPrepJob &job, hipStream_t s) {
   const int default_ok = job.erased2 ? 0 : 1;
   hipLaunchKernelGGL(repair_prep_kernel, dim3(1), dim3(kPlanThreads), 0, s, job, default_ok);
   return hip_check(hipGetLastError(), "repair prep launch");
+}
+
+fs_status launch_extend_prep(const ExtendPrepJob &job, hipStream_t s) {
+  if (job.n == 0) return FS_OK;
+  hipLaunchKernelGGL(extend_prep_kernel, dim3((job.n + 255) / 256), dim3(256), 0, s, job);
+  return hip_check(hipGetLastError(), "extend prep launch");
 }
 
 fs_status launch_repair_check(const RepairCheckJob &job, hipStream_t s) {
