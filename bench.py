@@ -53,10 +53,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="large_stripe",
-                    choices=["large_stripe", "batch512", "resident256", "serve", "extend", "all"],
+                    choices=["large_stripe", "batch512", "resident256", "serve", "extend", "simdisk", "all"],
                     help="large_stripe: plain one-stripe path (the headline line); batch512 / "
                          "resident256: batched plans vs the plain loop; serve: the request loop "
-                         "on a Poisson mix; extend: code extension of the large stripe; all: the "
+                         "on a Poisson mix; extend: code extension of the large stripe; simdisk: "
+                         "disk-failure sweeps; all: the "
                          "headline line with the others attached")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
@@ -123,10 +124,12 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.workload in ("batch512", "resident256", "serve", "extend"):
+    if args.workload in ("batch512", "resident256", "serve", "extend", "simdisk"):
         import bench_batch
         if args.workload == "extend":
             res = bench_batch.run_extend()
+        elif args.workload == "simdisk":
+            res = bench_batch.run_simdisk()
         elif args.workload == "batch512":
             res = bench_batch.run_batch512(args.batch_stripes)
         elif args.workload == "resident256":

@@ -11,6 +11,9 @@ resident256  256 stripes k=1024 x 256 KiB, n=1126, RSD (c=0.1, delta=0.05),
 extend       the large stripe (k=4096 x 64 KiB, finite16, n=1.1 k) grown to
              n=1.2 k: 409 new coded blocks from the resident inputs, and from
              the existing blocks with 5 % of them erased.
+simdisk      disk-failure sweeps of the larger code of the paper's measurements
+             (k=10246, n=21800, finite Raptor table): every combination of 4
+             failed disks out of 24, and every failure count on 10 disks.
 """
 
 import sys
@@ -255,6 +258,34 @@ def run_extend(reps=20):
         "conventional_ms": round(t_b, 3), "conventional_made": made_b,
         "conventional_GBps_new": round(made_b * t / (t_b * 1e-3) / 1e9, 1),
     }
+
+
+def run_simdisk(reps=5):
+    import math
+    import torch
+    import paper_1702_07409_amd as fs
+
+    g = fs.fs_graph_build(k=10246, n=21800, dist="raptor", seed=1)
+    ws = fs.workspace(g, fs.FS_OP_SIM_DISKS)
+    out = {"workload": "simdisk", "k": 10246, "n": 21800, "dist": "raptor", "graph_seed": 1, "nnz": int(g.nnz)}
+    s, f = 24, 4
+    total = math.comb(s, f)
+    res = torch.empty((total, 3), dtype=torch.int32, device="cuda")
+    ms = _time(lambda: fs.fs_sim_disks(g, s, f, 0, total, 0, res, ws), reps)
+    r = res.cpu().numpy()
+    out.update({"s": s, "f": f, "combinations": total, "ms": round(ms, 3),
+                "combinations_per_s": round(total / (ms * 1e-3)),
+                "tolerable": int(r[:, 0].sum()), "mean_levels": round(float(r[:, 2].mean()), 1)})
+    per_f = []
+    t_all = 0.0
+    for f10 in range(0, 11):
+        c = math.comb(10, f10)
+        res10 = torch.empty((c, 3), dtype=torch.int32, device="cuda")
+        m = _time(lambda: fs.fs_sim_disks(g, 10, f10, 0, c, 0, res10, ws), reps)
+        t_all += m
+        per_f.append(int(res10[:, 0].sum().item()))
+    out.update({"ten_disks_tolerable_by_f": per_f, "ten_disks_all_ms": round(t_all, 3)})
+    return out
 
 
 def _fresh(reqs, Request):

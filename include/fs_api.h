@@ -155,7 +155,7 @@ FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t
 /* Operations for fs_workspace_size. */
 enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
        FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6, FS_OP_EXTEND = 7,
-       FS_OP_EXTEND_CONVENTIONAL = 8 };
+       FS_OP_EXTEND_CONVENTIONAL = 8, FS_OP_SIM_DISKS = 9 };
 
 /*
  * Workspace bytes the operation needs for this graph and block size
@@ -262,6 +262,27 @@ FS_API fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *
 FS_API fs_status fs_extend(const fs_graph *g, uint32_t n_old, const void *x, void *c,
                     const uint8_t *erased, uint8_t *made, int32_t *status, uint64_t t,
                     void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Disk-failure sweep, the simDisk utility (§2.1, §2.2): which combinations
+ * of f failed disks out of s the code tolerates.  The n coded rows are
+ * striped over the s disks equally and in order: disk d holds rows
+ * [floor(d n / s), floor((d+1) n / s)).  The f-subsets of the disks are
+ * ranked in lexicographic order of their sorted disk lists (rank 0 = disks
+ * 0..f-1); for each rank r in [first, first + count) the rows of the failed
+ * disks are erased and the peeling decode runs (maxit levels, 0 = no limit).
+ * result: device int32[count][3]; entry r - first is the status triple that
+ *   fs_peel gives for that erasure pattern: {ok (every input decoded),
+ *   undecoded inputs, levels}.  No payload is read.
+ * Requires 1 <= s <= min(64, n), f <= s and first + count <= C(s, f)
+ * (FS_ERR_INVALID otherwise, nothing launched).
+ * ws: FS_OP_SIM_DISKS bytes (a binomial table, the rows' initial state, and
+ *   per-workgroup state when it does not fit in LDS); t and n_items are
+ *   ignored for it.
+ */
+FS_API fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first,
+                       uint64_t count, uint32_t maxit, int32_t *result, void *ws,
+                       size_t ws_bytes, hipStream_t stream);
 
 /*
  * Decode in two halves.  fs_decode_plan runs the peeling schedule of fs_peel

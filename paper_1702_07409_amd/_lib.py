@@ -36,7 +36,7 @@ FS_DIST_RSD, FS_DIST_FINITE, FS_DIST_RAPTOR = 0, 1, 2
 FS_DEFAULT_SEED = 1389488782
 FS_GRAPH_HOST_ONLY = 1
 (FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE, FS_OP_REPLAY,
- FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL) = range(9)
+ FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS) = range(10)
 
 DIST_CODES = {"rsd": FS_DIST_RSD, "finite": FS_DIST_FINITE, "raptor": FS_DIST_RAPTOR}
 
@@ -95,6 +95,7 @@ _SIGS = {
     "fs_repair": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_extend": ([P, U32, P, P, P, P, P, U64, P, SZ, P], ST),
+    "fs_sim_disks": ([P, U32, U32, U64, U64, U32, P, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
     "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ST),
@@ -303,6 +304,12 @@ def fs_extend(g, n_old, x, c, erased, made, status, t, ws, stream=None):
     w, wb = _ws(ws)
     _check(_lib.fs_extend(g.handle, n_old, _ptr(x), _ptr(c), _ptr(erased), _ptr(made), _ptr(status),
                           t, w, wb, _stream(stream)), "fs_extend")
+
+
+def fs_sim_disks(g, s, f, first, count, maxit, result, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_sim_disks(g.handle, s, f, first, count, maxit, _ptr(result), w, wb, _stream(stream)),
+           "fs_sim_disks")
 
 
 def fs_set_tune(lanes_per_row=0, chunks=0, xcd_remap=1, nt_store=1, replay_prog_global=0, encode_slab=1):

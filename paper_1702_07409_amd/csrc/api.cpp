@@ -182,6 +182,19 @@ void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, Upd
   b.delta = cv.take<uint8_t>((size_t)n_ids * t);
 }
 
+SimDiskLayout simdisk_layout_for(const fs_graph *g) {
+  const int dev = g->device < 0 ? 0 : g->device;
+  return simdisk_layout(g->k, g->n, g->max_deg, (size_t)device_info(dev).max_lds_per_block);
+}
+
+void carve_simdisk(Carver &cv, const fs_graph *g, SimDiskJob &j) {
+  const SimDiskLayout L = simdisk_layout_for(g);
+  const bool global = (L.mode == kSimDiskGlobal);
+  j.binom = cv.take<uint64_t>(65 * 65);
+  j.rowinfo = cv.take<uint32_t>(L.image_bytes / 4);
+  j.slots = global ? cv.take<uint8_t>((size_t)kSimDiskSlots * L.bytes) : nullptr;
+}
+
 size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) {
   Carver cv(nullptr);
   switch (op) {
@@ -222,6 +235,11 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
     case FS_OP_UPDATE: {
       UpdateBufs b;
       carve_update(cv, g, t, n_items, b);
+      return cv.size();
+    }
+    case FS_OP_SIM_DISKS: {
+      SimDiskJob j{};
+      carve_simdisk(cv, g, j);
       return cv.size();
     }
     case FS_OP_EXTEND:
@@ -462,7 +480,7 @@ void fs_graph_free(fs_graph *g) {
 fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
-  if (op < FS_OP_ENCODE || op > FS_OP_EXTEND_CONVENTIONAL) return fail(FS_ERR_INVALID, "unknown operation");
+  if (op < FS_OP_ENCODE || op > FS_OP_SIM_DISKS) return fail(FS_ERR_INVALID, "unknown operation");
   if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_EXTEND_CONVENTIONAL || op == FS_OP_UPDATE) &&
       (t == 0 || (t & 15)))
     return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
@@ -768,6 +786,37 @@ fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *ids, ui
   gj.t = t;
   gj.accumulate = 1;
   return launch_gather(gj, tile_for(current_tune(), g), stream);
+}
+
+fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first, uint64_t count,
+                       uint32_t maxit, int32_t *result, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  if (s < 1 || s > 64 || s > g->n) return fail(FS_ERR_INVALID, "s must be in [1, min(64, n)]");
+  if (f > s) return fail(FS_ERR_INVALID, "f exceeds s");
+  // C(s, f) by the multiplicative formula, exact for s <= 64 in 128-bit
+  unsigned __int128 total = 1;
+  for (uint32_t i = 1; i <= f; ++i) total = total * (s - f + i) / i;
+  if (first > (uint64_t)total || count > (uint64_t)total - first)
+    return fail(FS_ERR_INVALID, "combination ranks beyond C(s, f) = " + std::to_string((uint64_t)total));
+  if (count && !result) return fail(FS_ERR_INVALID, "result is null");
+  FS_TRY(check_ws(g, FS_OP_SIM_DISKS, 0, 0, ws, ws_bytes));
+  Carver cv(ws);
+  SimDiskJob j{};
+  carve_simdisk(cv, g, j);
+  j.k = g->k;
+  j.n = g->n;
+  j.s = s;
+  j.f = f;
+  j.maxit = maxit;
+  j.first = first;
+  j.count = count;
+  j.row_ptr = g->d_row_ptr;
+  j.col = g->d_col;
+  j.col_ptr = g->d_col_ptr;
+  j.rowidx = g->d_rowidx;
+  j.result = result;
+  return launch_simdisk(j, simdisk_layout_for(g), stream);
 }
 
 }  // extern "C"

@@ -176,6 +176,30 @@ struct ExtendPrepJob {
 };
 fs_status launch_extend_prep(const ExtendPrepJob &job, hipStream_t s);
 
+// Disk-failure sweep (simdisk.hip).  Per-combination state lives in LDS
+// (byte counts + 16-bit index XORs, or one word a row) when it fits, else in
+// kSimDiskSlots per-workgroup slots of the workspace.
+enum { kSimDiskByte = 0, kSimDiskXor16 = 1, kSimDiskGlobal = 2 };
+constexpr uint32_t kSimDiskSlots = 256;
+struct SimDiskLayout {
+  int mode;
+  size_t image_bytes;                 // per-row state image (rowinfo and the copy in LDS / a slot)
+  size_t off_w, off_dec, off_fresh;   // byte offsets in LDS or in one slot
+  size_t bytes;                       // LDS bytes, or bytes of one slot
+};
+SimDiskLayout simdisk_layout(uint32_t k, uint32_t n, uint32_t max_deg, size_t max_lds);
+struct SimDiskJob {
+  uint32_t k, n, s, f, maxit;
+  uint64_t first, count;
+  const int32_t *row_ptr, *col, *col_ptr, *rowidx;
+  uint64_t *binom;      // uint64[65 * 65], C(a, b) at a * 65 + b (written by the setup)
+  uint32_t *rowinfo;    // the initial per-row state image (written by the setup)
+  uint8_t *slots;       // global mode: kSimDiskSlots slots of slot_bytes
+  size_t slot_bytes, off_w, off_dec, off_fresh;
+  int32_t *result;      // int32[count][3]
+};
+fs_status launch_simdisk(const SimDiskJob &job, const SimDiskLayout &layout, hipStream_t s);
+
 struct RepairCheckJob {
   const int32_t *row_ptr, *col;
   uint32_t n;

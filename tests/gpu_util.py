@@ -32,8 +32,10 @@ def empty_i32(*shape):
 
 
 def graphs(**kw):
-    """(library graph, oracle graph) for the same parameters."""
+    """(library graph, oracle graph) for the same parameters.  The seed is
+    always passed explicitly: the two builders' defaults differ."""
     import paper_1702_07409_amd as fs
+    kw.setdefault("seed", graph.GraphParams(k=1, n=1).seed)
     g = fs.fs_graph_build(**kw)
     G = graph.build(graph.GraphParams(**kw))
     return g, G
