@@ -285,6 +285,25 @@ def run_simdisk(reps=5):
         t_all += m
         per_f.append(int(res10[:, 0].sum().item()))
     out.update({"ten_disks_tolerable_by_f": per_f, "ten_disks_all_ms": round(t_all, 3)})
+    # The sweep is bound by instruction issue, not HBM: the roofline is the
+    # VALU issue rate (256 CUs x 2.4 GHz x one wave64 VALU instruction per CU
+    # per cycle) against the VALU instructions per pattern that the committed
+    # counter profile recorded for this kernel source (null once it changed).
+    peak = 256 * 2.4e9
+    valu = None
+    try:
+        import json, os
+        import bench
+        prof = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                           "simdisk_counters.json")))
+        if prof.get("kernel_source_sha256_16") == bench.kernel_source_hash():
+            valu = prof["valu_per_pattern"]
+    except (OSError, ValueError, KeyError):
+        valu = None
+    achieved = valu * total / (ms * 1e-3) if valu else None
+    out["roofline"] = {"bound": "alu", "unit": "wave64 VALU instructions/s", "peak": peak,
+                       "achieved": achieved, "frac": round(achieved / peak, 4) if achieved else None,
+                       "valu_per_pattern": valu, "kernel": "simdisk_kernel"}
     return out
 
 
