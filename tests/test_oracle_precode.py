@@ -1,0 +1,141 @@
+"""Pins of the precode oracle (oracle/precode.py): Algorithm 2's checks against
+the circulant block structure of array LDPC codes, encodability, and the
+two-stage decode against direct checks and an independent check peel."""
+
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import codec, graph, precode
+from synth import gen
+
+# (b, k): Table 2's k values with j' = 3, and small codes
+CODES = [(28, 49), (21, 35), (55, 77), (10, 15), (925, 1036), (9919, 10246), (110, 121)]
+
+
+def is_prime(q):
+    return q >= 2 and all(q % d for d in range(2, int(q ** 0.5) + 1))
+
+
+@pytest.mark.parametrize("k", [2, 15, 49, 97, 1024, 1036, 10246, 2 * 3 * 5 * 7 * 11, 121])
+def test_largest_prime_factor(k):
+    p = precode.largest_prime_factor(k)
+    assert is_prime(p) and k % p == 0
+    assert not any(k % q == 0 and is_prime(q) for q in range(p + 1, k + 1))
+
+
+@pytest.mark.parametrize("b,k", CODES)
+def test_checks_are_the_circulant_array_structure(b, k):
+    # Array LDPC codes are built from powers of the p x p cyclic shift: here
+    # block row j covers block columns j .. j + k' - j', ends in the identity
+    # (its parity block, column c_j = j + k' - j') and carries the shift
+    # (j' - 1 - j)(c - c_j) mod p at block column c.
+    p, kp, jp = precode.array_params(b, k)
+    C = precode.checks(b, k)
+    assert len(C) == k - b == jp * p
+    for j in range(jp):
+        cj = j + kp - jp
+        for i in range(p):
+            want = sorted(c * p + (i + (jp - 1 - j) * (c - cj)) % p for c in range(j, cj + 1))
+            assert C[i + j * p] == want, (j, i)
+
+
+@pytest.mark.parametrize("b,k", [c for c in CODES if c[1] <= 1100])
+def test_no_two_checks_share_two_blocks(b, k):
+    # girth at least 6 (k' <= p): the property array codes are chosen for
+    p, kp, jp = precode.array_params(b, k)
+    assert kp <= p
+    C = [set(c) for c in precode.checks(b, k)]
+    assert all(len(a & c) <= 1 for a, c in itertools.combinations(C, 2))
+
+
+@pytest.mark.parametrize("b,k", CODES)
+def test_parity_rows_only_use_earlier_block_rows(b, k):
+    p, _, _ = precode.array_params(b, k)
+    for r, row in enumerate(precode.check_one(b, k)):
+        assert len(set(row)) == len(row)
+        assert all(0 <= i < b + p * (r // p) for i in row)
+
+
+@pytest.mark.parametrize("b,k", [(28, 49), (925, 1036)])
+def test_encode_satisfies_every_check(b, k):
+    data = gen.payload(0, 3, b, 16)
+    x = precode.encode(b, k, data)
+    assert np.array_equal(x[:b], data)
+    for members in precode.checks(b, k):
+        acc = np.zeros(16, np.uint8)
+        for m in members:
+            acc ^= x[m]
+        assert not acc.any()
+    # linearity: the parity of a sum is the sum of the parities
+    d2 = gen.payload(0, 4, b, 16)
+    assert np.array_equal(precode.encode(b, k, data ^ d2), x ^ precode.encode(b, k, d2))
+
+
+def queue_check_peel(C, known):
+    """Independent reference: recovered set of a queue-driven peel over the checks."""
+    known = set(np.flatnonzero(known).tolist())
+    changed = True
+    while changed:
+        changed = False
+        for members in C:
+            unknown = [s for s in members if s not in known]
+            if len(unknown) == 1:
+                known.add(unknown[0])
+                changed = True
+    return known
+
+
+def test_precode_recovers_what_the_ldgm_decode_misses():
+    b, k = 925, 1036
+    G = graph.build(graph.GraphParams(k=k, n=1500, dist="raptor", seed=3))
+    data = gen.payload(0, 9, b, 32)
+    x = precode.encode(b, k, data)
+    c = codec.encode(G, x)
+    # erase every coded row on three data blocks: the LDGM decode cannot get them
+    lost = [5, 400, 900]
+    er = np.zeros(G.n, np.uint8)
+    for i in lost:
+        er[G.NT(i)] = 1
+    xd, rec, st, _ = codec.decode(G, c, er)
+    assert not rec[lost].any()
+    got, ok, status = precode.decode_two_stage(G, b, c, er)
+    assert status[0] == 1 and ok.all() and np.array_equal(got, data)
+    assert status[2] == st[2] and status[3] >= 1
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_two_stage_decode_is_exact_and_matches_a_queue_peel(seed):
+    b, k = 28, 49
+    G = graph.build(graph.GraphParams(k=k, n=60, dist="rsd", seed=seed + 1))
+    data = gen.payload(1, seed, b, 16)
+    x = precode.encode(b, k, data)
+    c = codec.encode(G, x)
+    C = precode.checks(b, k)
+    rng = np.random.default_rng(seed)
+    for trial in range(20):
+        er = (rng.random(G.n) < rng.uniform(0.0, 0.5)).astype(np.uint8)
+        got, ok, status = precode.decode_two_stage(G, b, c, er)
+        okb = ok.astype(bool)
+        assert np.array_equal(got[okb], data[okb]) and not got[~okb].any()
+        _, rec, _, _ = codec.decode(G, c, er)
+        want = queue_check_peel(C, rec) if not rec[:b].all() else set(np.flatnonzero(rec).tolist())
+        assert set(np.flatnonzero(okb).tolist()) == {s for s in want if s < b}
+        assert status[0] == int(okb.all()) and status[1] == b - okb.sum()
+
+
+def test_no_erasures_and_level_limit():
+    b, k = 55, 77
+    G = graph.build(graph.GraphParams(k=k, n=130, dist="rsd", seed=2))
+    data = gen.payload(2, 0, b, 16)
+    c = codec.encode(G, precode.encode(b, k, data))
+    got, ok, status = precode.decode_two_stage(G, b, c, np.zeros(G.n, np.uint8))
+    assert np.array_equal(got, data) and status[:2] == (1, 0)
+    # stage two one level at a time ends where the unbounded run ends
+    x, rec, _, _ = codec.decode(G, c, np.zeros(G.n, np.uint8))
+    rec[:3] = 0
+    full_x, full_known, L = precode.precode_bp(b, k, x, rec)
+    one_x, one_known, L1 = precode.precode_bp(b, k, x, rec, maxit=1)
+    assert L1 == min(L, 1) and one_known.sum() <= full_known.sum()
+    assert full_known[:b].all() and np.array_equal(full_x[:b], data)
