@@ -84,6 +84,7 @@ typedef struct fs_graph_params {
 } fs_graph_params;
 
 typedef struct fs_graph fs_graph;   /* opaque; owns host + device CSR and CSC */
+typedef struct fs_precode fs_precode;   /* opaque; owns host + device check sets */
 
 /*
  * Degree table: the integer inverse-CDF thresholds used
@@ -155,7 +156,7 @@ FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t
 /* Operations for fs_workspace_size. */
 enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
        FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6, FS_OP_EXTEND = 7,
-       FS_OP_EXTEND_CONVENTIONAL = 8, FS_OP_SIM_DISKS = 9 };
+       FS_OP_EXTEND_CONVENTIONAL = 8, FS_OP_SIM_DISKS = 9, FS_OP_DECODE_PRECODED = 10 };
 
 /*
  * Workspace bytes the operation needs for this graph and block size
@@ -283,6 +284,55 @@ FS_API fs_status fs_extend(const fs_graph *g, uint32_t n_old, const void *x, voi
 FS_API fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first,
                        uint64_t count, uint32_t maxit, int32_t *result, void *ws,
                        size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Array-LDPC precode, check #1 (§2.4, Algorithm 2).  A (b, k, n) code first
+ * extends b data blocks to k with k - b parity blocks, then encodes the k
+ * blocks with an LDGM graph of k inputs (§2.2).  With p the largest prime
+ * factor of k, k' = k / p and j' = k' - b / p, b must be a multiple of p and
+ * 1 <= j' < k' (FS_ERR_INVALID otherwise).  Row r of L(1) lists the k' - j'
+ * blocks whose XOR is parity block b + r; they lie in the data or in earlier
+ * block rows of p checks.  Check r is that row together with block b + r
+ * (its members XOR to zero).
+ * host_only != 0 builds the host tables only (for export; no device use).
+ * Errors: FS_ERR_INVALID, FS_ERR_NOMEM, FS_ERR_HIP.
+ */
+FS_API fs_status fs_precode_build(uint32_t b, uint32_t k, int host_only, hipStream_t stream,
+                           fs_precode **out);
+FS_API fs_status fs_precode_info(const fs_precode *pc, uint32_t *b, uint32_t *k, uint32_t *p,
+                          uint32_t *kp, uint32_t *jp);
+/* L(1) on the host: row_ptr int32[k - b + 1], col int32[(k - b)(k' - j')],
+ * each row ascending. */
+FS_API fs_status fs_precode_export(const fs_precode *pc, int32_t *row_ptr, int32_t *col);
+FS_API void fs_precode_free(fs_precode *pc);
+
+/*
+ * Precode encode: x device uint8[k][t] with the b data blocks in rows
+ * 0..b-1; rows b..k-1 are written with the parity blocks, block row by block
+ * row (j' launches).  Then fs_encode with the LDGM graph of k inputs makes
+ * the coded blocks.
+ */
+FS_API fs_status fs_precode_encode(const fs_precode *pc, void *x, uint64_t t, hipStream_t stream);
+
+/*
+ * Two-stage decode (§2.2: BP at most twice, on the LDGM graph and then on
+ * the precode).  The first pass is fs_decode into x (device uint8[k][t]) and
+ * recovered (device uint8[k]).  If data blocks (rows < b) are still missing,
+ * the second pass runs BP over the checks: at each level every check with
+ * exactly one unknown member names it, and each named block becomes the XOR
+ * of the other members of one of its naming checks; it ends when no check
+ * names anything.  The second pass does not feed back into the first.
+ * Blocks left unknown are zero, recovered[] marks the others.
+ * status: device int32[4] {all b data blocks recovered, data blocks not
+ *   recovered, levels of the first pass, levels of the second}.
+ * g->k must equal the precode's k.  ws: FS_OP_DECODE_PRECODED bytes.
+ * FS_ERR_UNSUPPORTED when the second pass's state (8 bytes per check plus a
+ * bit per block) exceeds one workgroup's LDS.
+ */
+FS_API fs_status fs_decode_precoded(const fs_graph *g, const fs_precode *pc, const void *c,
+                             const uint8_t *erased, uint32_t maxit, void *x, uint8_t *recovered,
+                             int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                             hipStream_t stream);
 
 /*
  * Decode in two halves.  fs_decode_plan runs the peeling schedule of fs_peel

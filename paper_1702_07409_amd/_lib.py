@@ -36,7 +36,7 @@ FS_DIST_RSD, FS_DIST_FINITE, FS_DIST_RAPTOR = 0, 1, 2
 FS_DEFAULT_SEED = 1389488782
 FS_GRAPH_HOST_ONLY = 1
 (FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE, FS_OP_REPLAY,
- FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS) = range(10)
+ FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS, FS_OP_DECODE_PRECODED) = range(11)
 
 DIST_CODES = {"rsd": FS_DIST_RSD, "finite": FS_DIST_FINITE, "raptor": FS_DIST_RAPTOR}
 
@@ -96,6 +96,13 @@ _SIGS = {
     "fs_update": ([P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_extend": ([P, U32, P, P, P, P, P, U64, P, SZ, P], ST),
     "fs_sim_disks": ([P, U32, U32, U64, U64, U32, P, P, SZ, P], ST),
+    "fs_precode_build": ([U32, U32, I32, P, ctypes.POINTER(P)], ST),
+    "fs_precode_info": ([P, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32),
+                         ctypes.POINTER(U32)], ST),
+    "fs_precode_export": ([P, P, P], ST),
+    "fs_precode_free": ([P], None),
+    "fs_precode_encode": ([P, P, U64, P], ST),
+    "fs_decode_precoded": ([P, P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
     "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ST),
@@ -304,6 +311,54 @@ def fs_extend(g, n_old, x, c, erased, made, status, t, ws, stream=None):
     w, wb = _ws(ws)
     _check(_lib.fs_extend(g.handle, n_old, _ptr(x), _ptr(c), _ptr(erased), _ptr(made), _ptr(status),
                           t, w, wb, _stream(stream)), "fs_extend")
+
+
+class Precode:
+    """Owner of an fs_precode handle (array-LDPC check #1 of a (b, k) code)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        b, k, p, kp, jp = U32(), U32(), U32(), U32(), U32()
+        _check(_lib.fs_precode_info(handle, ctypes.byref(b), ctypes.byref(k), ctypes.byref(p), ctypes.byref(kp),
+                                    ctypes.byref(jp)), "fs_precode_info")
+        self.b, self.k, self.p, self.kp, self.jp = b.value, k.value, p.value, kp.value, jp.value
+
+    def export(self):
+        """L(1) as (row_ptr, col) numpy arrays, each row ascending."""
+        import numpy as np
+        m, w = self.k - self.b, self.kp - self.jp
+        rp = np.zeros(m + 1, np.int32)
+        col = np.zeros(max(m * w, 1), np.int32)
+        _check(_lib.fs_precode_export(self.handle, rp.ctypes.data, col.ctypes.data), "fs_precode_export")
+        return rp, col[:m * w]
+
+    def free(self):
+        if self.handle:
+            _lib.fs_precode_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fs_precode_build(b, k, host_only=False, stream=None):
+    h = P()
+    _check(_lib.fs_precode_build(b, k, 1 if host_only else 0, None if host_only else _stream(stream),
+                                 ctypes.byref(h)), "fs_precode_build")
+    return Precode(h)
+
+
+def fs_precode_encode(pc, x, t, stream=None):
+    _check(_lib.fs_precode_encode(pc.handle, _ptr(x), t, _stream(stream)), "fs_precode_encode")
+
+
+def fs_decode_precoded(g, pc, c, erased, maxit, x, recovered, status, t, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_decode_precoded(g.handle, pc.handle, _ptr(c), _ptr(erased), maxit, _ptr(x), _ptr(recovered),
+                                   _ptr(status), t, w, wb, _stream(stream)), "fs_decode_precoded")
 
 
 def fs_sim_disks(g, s, f, first, count, maxit, result, ws, stream=None):

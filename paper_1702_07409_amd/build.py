@@ -28,6 +28,7 @@ HOST = ["-x", "c++", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include"]
 SOURCES = [
     ("kernels.hip", DEVICE),
     ("simdisk.hip", DEVICE),
+    ("precode.hip", DEVICE),
     ("api.cpp", DEVICE),
     ("plan.cpp", DEVICE),
     ("graph_host.cpp", HOST),

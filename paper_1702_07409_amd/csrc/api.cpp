@@ -182,6 +182,20 @@ void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, Upd
   b.delta = cv.take<uint8_t>((size_t)n_ids * t);
 }
 
+struct PrecodeBufs {
+  int32_t *status1, *pair_sym, *pair_chk, *level_ptr, *meta;
+};
+
+void carve_precode(Carver &cv, uint32_t k, PrecodeBufs &b) {
+  b.status1 = cv.take<int32_t>(4);
+  b.pair_sym = cv.take<int32_t>(k);
+  b.pair_chk = cv.take<int32_t>(k);
+  b.level_ptr = cv.take<int32_t>((size_t)k + 1);
+  b.meta = cv.take<int32_t>(4);
+}
+
+size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items);
+
 SimDiskLayout simdisk_layout_for(const fs_graph *g) {
   const int dev = g->device < 0 ? 0 : g->device;
   return simdisk_layout(g->k, g->n, g->max_deg, (size_t)device_info(dev).max_lds_per_block);
@@ -240,6 +254,12 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
     case FS_OP_SIM_DISKS: {
       SimDiskJob j{};
       carve_simdisk(cv, g, j);
+      return cv.size();
+    }
+    case FS_OP_DECODE_PRECODED: {
+      cv.take<uint8_t>(workspace_bytes(g, FS_OP_DECODE, t, 0));
+      PrecodeBufs b;
+      carve_precode(cv, g->k, b);
       return cv.size();
     }
     case FS_OP_EXTEND:
@@ -480,7 +500,7 @@ void fs_graph_free(fs_graph *g) {
 fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
-  if (op < FS_OP_ENCODE || op > FS_OP_SIM_DISKS) return fail(FS_ERR_INVALID, "unknown operation");
+  if (op < FS_OP_ENCODE || op > FS_OP_DECODE_PRECODED) return fail(FS_ERR_INVALID, "unknown operation");
   if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_EXTEND_CONVENTIONAL || op == FS_OP_UPDATE) &&
       (t == 0 || (t & 15)))
     return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
@@ -817,6 +837,158 @@ fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first
   j.rowidx = g->d_rowidx;
   j.result = result;
   return launch_simdisk(j, simdisk_layout_for(g), stream);
+}
+
+fs_status fs_precode_build(uint32_t b, uint32_t k, int host_only, hipStream_t stream, fs_precode **out) {
+  clear_error();
+  if (!out) return fail(FS_ERR_INVALID, "out is null");
+  *out = nullptr;
+  fs_precode *pc = new (std::nothrow) fs_precode();
+  if (!pc) return fail(FS_ERR_NOMEM, "host allocation failed");
+  fs_status st = build_precode_host(b, k, *pc);
+  if (st != FS_OK) {
+    delete pc;
+    return st;
+  }
+  if (!host_only) {
+    if (const hipError_t e = hipGetDevice(&pc->device); e != hipSuccess) {
+      delete pc;
+      return fail(FS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+    }
+    const std::vector<int32_t> *parts[6] = {&pc->enc_ptr, &pc->enc_col, &pc->chk_ptr,
+                                            &pc->chk_col, &pc->sym_ptr, &pc->sym_chk};
+    size_t off[6], total = 0;
+    for (int i = 0; i < 6; ++i) {
+      off[i] = total;
+      total += (parts[i]->size() * sizeof(int32_t) + 255) & ~size_t(255);
+    }
+    void *base = nullptr;
+    if (hipMalloc(&base, total) != hipSuccess) {
+      delete pc;
+      return fail(FS_ERR_NOMEM, "device allocation for the precode failed");
+    }
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 6; ++i)
+      if (e == hipSuccess && !parts[i]->empty())
+        e = hipMemcpyAsync(static_cast<uint8_t *>(base) + off[i], parts[i]->data(), parts[i]->size() * sizeof(int32_t),
+                           hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      (void)hipFree(base);
+      delete pc;
+      return fail(FS_ERR_HIP, std::string("precode upload: ") + hipGetErrorString(e));
+    }
+    pc->d_base = base;
+    const int32_t **dst[6] = {&pc->d_enc_ptr, &pc->d_enc_col, &pc->d_chk_ptr,
+                              &pc->d_chk_col, &pc->d_sym_ptr, &pc->d_sym_chk};
+    for (int i = 0; i < 6; ++i) *dst[i] = reinterpret_cast<const int32_t *>(static_cast<uint8_t *>(base) + off[i]);
+  }
+  *out = pc;
+  return FS_OK;
+}
+
+fs_status fs_precode_info(const fs_precode *pc, uint32_t *b, uint32_t *k, uint32_t *p, uint32_t *kp, uint32_t *jp) {
+  clear_error();
+  if (!pc) return fail(FS_ERR_INVALID, "precode is null");
+  if (b) *b = pc->b;
+  if (k) *k = pc->k;
+  if (p) *p = pc->p;
+  if (kp) *kp = pc->kp;
+  if (jp) *jp = pc->jp;
+  return FS_OK;
+}
+
+fs_status fs_precode_export(const fs_precode *pc, int32_t *row_ptr, int32_t *col) {
+  clear_error();
+  if (!pc || !row_ptr || !col) return fail(FS_ERR_INVALID, "precode, row_ptr and col must be non-null");
+  std::copy(pc->enc_ptr.begin(), pc->enc_ptr.end(), row_ptr);
+  std::copy(pc->enc_col.begin(), pc->enc_col.end(), col);
+  return FS_OK;
+}
+
+void fs_precode_free(fs_precode *pc) {
+  if (!pc) return;
+  if (pc->d_base) (void)hipFree(pc->d_base);
+  delete pc;
+}
+
+static fs_status check_precode(const fs_precode *pc) {
+  if (!pc) return fail(FS_ERR_INVALID, "precode is null");
+  if (!pc->d_base) return fail(FS_ERR_INVALID, "precode was built host-only");
+  return FS_OK;
+}
+
+fs_status fs_precode_encode(const fs_precode *pc, void *x, uint64_t t, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_precode(pc));
+  FS_TRY(check_payload(x, t, "x"));
+  fs_tune tune = current_tune();
+  if (tune.lanes_per_row == 0) {
+    tune.lanes_per_row = 64;
+    tune.chunks = 4;
+  }
+  for (uint32_t j = 0; j < pc->jp; ++j) {
+    GatherJob gj{};
+    gj.src = static_cast<const uint8_t *>(x);
+    gj.src_stride = t;
+    gj.dst = static_cast<uint8_t *>(x) + (uint64_t)(pc->b + j * pc->p) * t;
+    gj.dst_stride = t;
+    gj.ptr = pc->d_enc_ptr + (size_t)j * pc->p;
+    gj.idx = pc->d_enc_col;
+    gj.nrows = pc->p;
+    gj.csr_rows = pc->p;
+    gj.t = t;
+    FS_TRY(launch_gather(gj, tune, stream));
+  }
+  return FS_OK;
+}
+
+fs_status fs_decode_precoded(const fs_graph *g, const fs_precode *pc, const void *c, const uint8_t *erased,
+                             uint32_t maxit, void *x, uint8_t *recovered, int32_t *status, uint64_t t, void *ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_precode(pc));
+  if (pc->k != g->k) return fail(FS_ERR_INVALID, "the graph's k differs from the precode's");
+  if (!erased || !recovered || !status) return fail(FS_ERR_INVALID, "erased, recovered and status must be non-null");
+  FS_TRY(check_payload(c, t, "c"));
+  FS_TRY(check_payload(x, t, "x"));
+  const int dev = g->device < 0 ? 0 : g->device;
+  if (precode_peel_lds(pc->k, pc->m) > (size_t)device_info(dev).max_lds_per_block)
+    return fail(FS_ERR_UNSUPPORTED, "the precode's check state exceeds one workgroup's LDS");
+  FS_TRY(check_ws(g, FS_OP_DECODE_PRECODED, t, 0, ws, ws_bytes));
+  const size_t dec = workspace_bytes(g, FS_OP_DECODE, t, 0);
+  Carver cv(ws);
+  uint8_t *dws = cv.take<uint8_t>(dec);
+  PrecodeBufs b;
+  carve_precode(cv, g->k, b);
+  FS_TRY(fs_decode(g, c, erased, maxit, x, recovered, b.status1, t, dws, dec, stream));
+  PrecodePeelJob pj{};
+  pj.b = pc->b;
+  pj.k = pc->k;
+  pj.m = pc->m;
+  pj.chk_ptr = pc->d_chk_ptr;
+  pj.chk_col = pc->d_chk_col;
+  pj.sym_ptr = pc->d_sym_ptr;
+  pj.sym_chk = pc->d_sym_chk;
+  pj.recovered = recovered;
+  pj.status1 = b.status1;
+  pj.status = status;
+  pj.pair_sym = b.pair_sym;
+  pj.pair_chk = b.pair_chk;
+  pj.level_ptr = b.level_ptr;
+  pj.meta = b.meta;
+  FS_TRY(launch_precode_peel(pj, stream));
+  PrecodeReplayJob rj{};
+  rj.x = static_cast<uint8_t *>(x);
+  rj.t = t;
+  rj.chk_ptr = pc->d_chk_ptr;
+  rj.chk_col = pc->d_chk_col;
+  rj.pair_sym = b.pair_sym;
+  rj.pair_chk = b.pair_chk;
+  rj.level_ptr = b.level_ptr;
+  rj.meta = b.meta;
+  return launch_precode_replay(rj, stream);
 }
 
 }  // extern "C"

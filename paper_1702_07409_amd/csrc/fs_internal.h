@@ -33,6 +33,18 @@ struct fs_graph {
   const uint8_t *d_seg_atomic = nullptr;
 };
 
+// An array-LDPC precode (check #1, Algorithm 2) on the host and the device.
+struct fs_precode {
+  uint32_t b = 0, k = 0, p = 0, kp = 0, jp = 0, m = 0;   // m = k - b checks
+  std::vector<int32_t> enc_ptr, enc_col;   // row r of L(1): the blocks whose XOR is parity b + r
+  std::vector<int32_t> chk_ptr, chk_col;   // members of check r: its row and b + r
+  std::vector<int32_t> sym_ptr, sym_chk;   // the checks of every block
+  int device = -1;
+  void *d_base = nullptr;
+  const int32_t *d_enc_ptr = nullptr, *d_enc_col = nullptr, *d_chk_ptr = nullptr, *d_chk_col = nullptr,
+                *d_sym_ptr = nullptr, *d_sym_chk = nullptr;
+};
+
 namespace fs {
 
 constexpr uint32_t kSegMax = 64;
@@ -199,6 +211,29 @@ struct SimDiskJob {
   int32_t *result;      // int32[count][3]
 };
 fs_status launch_simdisk(const SimDiskJob &job, const SimDiskLayout &layout, hipStream_t s);
+
+// Precode (precode.hip): host construction of the checks and the second BP
+// pass of the two-stage decode.
+uint32_t largest_prime_factor(uint32_t k);
+fs_status build_precode_host(uint32_t b, uint32_t k, fs_precode &pc);
+size_t precode_peel_lds(uint32_t k, uint32_t m);
+struct PrecodePeelJob {
+  uint32_t b, k, m;
+  const int32_t *chk_ptr, *chk_col, *sym_ptr, *sym_chk;
+  uint8_t *recovered;        // uint8[k]: in, the LDGM pass; out, both passes
+  const int32_t *status1;    // int32[3] of the LDGM pass
+  int32_t *status;           // int32[4] out
+  int32_t *pair_sym, *pair_chk;   // int32[k]: (block, check) in level order
+  int32_t *level_ptr;        // int32[k + 1]
+  int32_t *meta;             // int32[2]: levels, pairs
+};
+fs_status launch_precode_peel(const PrecodePeelJob &job, hipStream_t s);
+struct PrecodeReplayJob {
+  uint8_t *x;
+  uint64_t t;
+  const int32_t *chk_ptr, *chk_col, *pair_sym, *pair_chk, *level_ptr, *meta;
+};
+fs_status launch_precode_replay(const PrecodeReplayJob &job, hipStream_t s);
 
 struct RepairCheckJob {
   const int32_t *row_ptr, *col;

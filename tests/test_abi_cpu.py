@@ -122,3 +122,23 @@ def test_graph_image_size_covers_every_array():
     assert size % 256 == 0 and size >= base + 256
     segs = sum(-(-int(rp[j + 1] - rp[j]) // 64) for j in range(g.n))
     assert size <= base + al(4 * (segs + 1)) + al(4 * segs) + al(4 * g.n) + al(segs) + 256
+
+
+@pytest.mark.parametrize("b,k", [(28, 49), (925, 1036), (9919, 10246), (10, 15), (110, 121)])
+def test_host_precode_matches_oracle(b, k):
+    import paper_1702_07409_amd as fs
+    from oracle import precode
+    pc = fs.fs_precode_build(b, k, host_only=True)
+    p, kp, jp = precode.array_params(b, k)
+    assert (pc.b, pc.k, pc.p, pc.kp, pc.jp) == (b, k, p, kp, jp)
+    rp, col = pc.export()
+    L = precode.check_one(b, k)
+    assert rp.tolist() == [r * (kp - jp) for r in range(k - b + 1)]
+    assert [sorted(row) for row in L] == [col[rp[r]:rp[r + 1]].tolist() for r in range(k - b)]
+
+
+@pytest.mark.parametrize("b,k", [(27, 49), (49, 49), (0, 49), (3, 7), (5, 1)])
+def test_precode_rejects_bad_parameters(b, k):
+    import paper_1702_07409_amd as fs
+    with pytest.raises(fs.FsError):
+        fs.fs_precode_build(b, k, host_only=True)
