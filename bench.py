@@ -53,11 +53,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="large_stripe",
-                    choices=["large_stripe", "batch512", "resident256", "serve", "extend", "simdisk", "all"],
+                    choices=["large_stripe", "batch512", "resident256", "serve", "extend", "simdisk", "precode", "all"],
                     help="large_stripe: plain one-stripe path (the headline line); batch512 / "
                          "resident256: batched plans vs the plain loop; serve: the request loop "
                          "on a Poisson mix; extend: code extension of the large stripe; simdisk: "
-                         "disk-failure sweeps; all: the "
+                         "disk-failure sweeps; precode: Table 2's set-up with the precode; all: the "
                          "headline line with the others attached")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
@@ -124,9 +124,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.workload in ("batch512", "resident256", "serve", "extend", "simdisk"):
+    if args.workload in ("batch512", "resident256", "serve", "extend", "simdisk", "precode"):
         import bench_batch
-        if args.workload == "extend":
+        if args.workload == "precode":
+            res = bench_batch.run_precode()
+        elif args.workload == "extend":
             res = bench_batch.run_extend()
         elif args.workload == "simdisk":
             res = bench_batch.run_simdisk()

@@ -439,11 +439,18 @@ constexpr unsigned long long kSumMask = kCountOne - 1;
 // their inputs never brings it near 2, so they never enter a frontier and the
 // propagation step needs no erasure test.
 constexpr unsigned long long kErasedAcc = 1ull << 63;
+// The same state packed in 32 bits (count << 24 | sum of ids) when degrees
+// are at most 127 and every sum of ids stays below 2^24: erased rows start at
+// count 255 and never come down to 128.
+constexpr uint32_t kCountOne32 = 1u << 24;
+constexpr uint32_t kSumMask32 = kCountOne32 - 1u;
+constexpr uint32_t kErasedAcc32 = 255u << 24;
 
 __device__ __forceinline__ uint32_t words_of(uint32_t k) { return (k + 31) / 32; }
 
 struct PeelState {
   unsigned long long *acc, *best;
+  uint32_t *acc32;    // packed row state (kPeelLdsRows32 only)
   int32_t *fa, *fb, *dl;
   uint32_t *mask, *decm;
   int32_t *cptr;      // column pointers (LDS copy, or the graph's)
@@ -504,8 +511,10 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
 
 // Where the peel keeps its state: kPeelLds all of it in LDS, kPeelLdsRows
 // only the per-row counters (the one array every edge updates atomically;
-// for stripes whose full state does not fit), kPeelGlobal none of it.
-constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2;
+// for stripes whose full state does not fit), kPeelLdsRows32 the counters
+// packed in 32 bits (for stripes whose 64-bit counters do not fit either),
+// kPeelGlobal none of it.
+constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2, kPeelLdsRows32 = 3;
 
 template <int MODE>
 __device__ __forceinline__ void peel_body(const PeelJob &J) {
@@ -529,6 +538,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.deg = reinterpret_cast<uint16_t *>(p);
   } else {
     S.acc = MODE == kPeelLdsRows ? reinterpret_cast<unsigned long long *>(smem) : J.acc;
+    S.acc32 = MODE == kPeelLdsRows32 ? reinterpret_cast<uint32_t *>(smem) : nullptr;
     S.best = J.best; S.fa = J.front_a; S.fb = J.front_b; S.dl = J.dlist;
     S.mask = J.mask; S.decm = J.decmask;
     S.cptr = const_cast<int32_t *>(J.col_ptr);
@@ -556,10 +566,16 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     const int d = J.row_ptr[g + 1] - J.row_ptr[g];
     if constexpr (MODE == kPeelLds) S.deg[g] = (uint16_t)d;
     if (J.erased[g]) {
-      S.acc[g] = kErasedAcc;
+      if constexpr (MODE == kPeelLdsRows32)
+        S.acc32[g] = kErasedAcc32;
+      else
+        S.acc[g] = kErasedAcc;
       continue;
     }
-    S.acc[g] = (unsigned long long)d << 40;
+    if constexpr (MODE == kPeelLdsRows32)
+      S.acc32[g] = (uint32_t)d << 24;
+    else
+      S.acc[g] = (unsigned long long)d << 40;
     if (d == 1) S.fa[atomicAdd(&s_nA, 1)] = (int32_t)g;
   }
   __syncthreads();
@@ -573,8 +589,13 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
 #pragma unroll
       for (int u = 0; u < kPeelBatch; ++u) h[u] = e + u < c1 ? J.rowidx[e + u] : -1;
 #pragma unroll
-      for (int u = 0; u < kPeelBatch; ++u)
-        if (h[u] >= 0) atomicAdd(&S.acc[h[u]], (unsigned long long)i);
+      for (int u = 0; u < kPeelBatch; ++u) {
+        if (h[u] < 0) continue;
+        if constexpr (MODE == kPeelLdsRows32)
+          atomicAdd(&S.acc32[h[u]], i);
+        else
+          atomicAdd(&S.acc[h[u]], (unsigned long long)i);
+      }
     }
   }
   __syncthreads();
@@ -588,9 +609,16 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     // keep the namer of least (original degree, row)
     for (int q = tid; q < nA; q += kPeelThreads) {
       const int32_t g = cur[q];
-      const unsigned long long a = S.acc[g];
-      if ((a >> 40) != 1ull) continue;
-      const uint32_t f = (uint32_t)(a & kSumMask);
+      uint32_t f;
+      if constexpr (MODE == kPeelLdsRows32) {
+        const uint32_t a = S.acc32[g];
+        if ((a >> 24) != 1u) continue;
+        f = a & kSumMask32;
+      } else {
+        const unsigned long long a = S.acc[g];
+        if ((a >> 40) != 1ull) continue;
+        f = (uint32_t)(a & kSumMask);
+      }
       uint32_t d;
       if constexpr (MODE == kPeelLds)
         d = S.deg[g];
@@ -613,6 +641,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
       for (int q = tid - 64; q < nD; q += kPeelThreads - 64) {
         const uint32_t f = (uint32_t)S.dl[q];
         const unsigned long long dec = 0ull - (kCountOne | f);
+        const uint32_t dec32 = 0u - (kCountOne32 | f);
         const int c1 = S.cptr[f + 1];
         for (int e = S.cptr[f]; e < c1; e += kPeelBatch) {
           // the column's row ids are loaded together, then applied
@@ -622,8 +651,12 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
 #pragma unroll
           for (int u = 0; u < kPeelBatch; ++u) {
             if (h[u] < 0) continue;
-            const unsigned long long old = atomicAdd(&S.acc[h[u]], dec);
-            if ((old >> 40) == 2ull) nxt[atomicAdd(&s_nB, 1)] = h[u];
+            bool two;
+            if constexpr (MODE == kPeelLdsRows32)
+              two = (atomicAdd(&S.acc32[h[u]], dec32) >> 24) == 2u;
+            else
+              two = (atomicAdd(&S.acc[h[u]], dec) >> 40) == 2ull;
+            if (two) nxt[atomicAdd(&s_nB, 1)] = h[u];
           }
         }
       }
@@ -1350,6 +1383,8 @@ int peel_mode(uint32_t k, uint32_t n, uint32_t max_deg) {
   const size_t budget = (size_t)device_info(dev).max_lds_per_block - 64;
   if (max_deg < 65536 && peel_lds_bytes(k, n) <= budget) return kPeelLds;
   if (8ull * n <= budget) return kPeelLdsRows;
+  if (4ull * n <= budget && max_deg <= 127 && (uint64_t)max_deg * (k ? k - 1 : 0) < (1ull << 24))
+    return kPeelLdsRows32;
   return kPeelGlobal;
 }
 
@@ -1370,6 +1405,10 @@ fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg) {
       static bool done[64] = {false};
       set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLdsRows>), dev, budget - (int)static_lds, done);
       hipLaunchKernelGGL(peel_kernel<kPeelLdsRows>, dim3(1), dim3(kPeelThreads), 8ull * job.n, s, job);
+    } else if (mode == kPeelLdsRows32) {
+      static bool done[64] = {false};
+      set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLdsRows32>), dev, budget - (int)static_lds, done);
+      hipLaunchKernelGGL(peel_kernel<kPeelLdsRows32>, dim3(1), dim3(kPeelThreads), 4ull * job.n, s, job);
     } else {
       hipLaunchKernelGGL(peel_kernel<kPeelGlobal>, dim3(1), dim3(kPeelThreads), 0, s, job);
     }
@@ -1580,6 +1619,11 @@ fs_status launch_peel_batch(const PeelJob *d_jobs, uint32_t njobs, int mode, siz
     set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLdsRows>), dev,
                 device_info(dev).max_lds_per_block - 64, done);
     hipLaunchKernelGGL(peel_batch_kernel<kPeelLdsRows>, dim3(njobs), dim3(kPeelThreads), lds_bytes, s, d_jobs);
+  } else if (mode == kPeelLdsRows32) {
+    static bool done[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLdsRows32>), dev,
+                device_info(dev).max_lds_per_block - 64, done);
+    hipLaunchKernelGGL(peel_batch_kernel<kPeelLdsRows32>, dim3(njobs), dim3(kPeelThreads), lds_bytes, s, d_jobs);
   } else {
     hipLaunchKernelGGL(peel_batch_kernel<kPeelGlobal>, dim3(njobs), dim3(kPeelThreads), 0, s, d_jobs);
   }
@@ -1634,9 +1678,11 @@ void prepare_batch_kernels() {
   int dev = 0;
   (void)hipGetDevice(&dev);
   const int budget = device_info(dev).max_lds_per_block;
-  static bool d1[64] = {false}, d2[64] = {false};
+  static bool d1[64] = {false}, d2[64] = {false}, d3[64] = {false}, d4[64] = {false};
   set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLds>), dev, budget - 64, d1);
   set_max_lds(reinterpret_cast<const void *>(&replay_batch_kernel<kBatchReplayLanes>), dev, budget, d2);
+  set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLdsRows>), dev, budget - 64, d3);
+  set_max_lds(reinterpret_cast<const void *>(&peel_batch_kernel<kPeelLdsRows32>), dev, budget - 64, d4);
 }
 
 fs_status launch_zero_batch(const ZeroEntry *d_rows, uint32_t nrows, uint64_t max_t, hipStream_t s) {

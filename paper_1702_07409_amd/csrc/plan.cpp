@@ -48,6 +48,8 @@ struct fs_plan {
   std::vector<ProgJob> replay_progs;   // programs of the batched replays, in their order
   std::vector<PeelJob> peels_rows;     // schedules whose row counters alone fit LDS
   size_t peel_rows_bytes = 0;
+  size_t peel_rows32_bytes = 0;
+  std::vector<PeelJob> peels_rows32;   // schedules whose row counters fit LDS packed in 32 bits
   std::vector<PeelJob> peels_global;   // schedules too large for LDS
   bool peel_lds = true;
   size_t peel_lds_bytes = 0;
@@ -64,6 +66,7 @@ struct fs_plan {
   unsigned long long *d_gprefix = nullptr;
   PeelJob *d_peels = nullptr;
   PeelJob *d_peels_rows = nullptr;
+  PeelJob *d_peels_rows32 = nullptr;
   PeelJob *d_peels_global = nullptr;
   ProgJob *d_progs = nullptr;
   ReplayJob *d_replays = nullptr;
@@ -213,7 +216,9 @@ void build_descriptors(fs_plan &P) {
   P.replay_progs.clear();
   P.peels_global.clear();
   P.peels_rows.clear();
+  P.peels_rows32.clear();
   P.peel_rows_bytes = 0;
+  P.peel_rows32_bytes = 0;
   P.peel_lds = true;
   P.peel_lds_bytes = 0;
   P.replay_lds = 256;
@@ -249,6 +254,9 @@ void build_descriptors(fs_plan &P) {
         } else if (mode == 1) {
           P.peel_rows_bytes = std::max<size_t>(P.peel_rows_bytes, 8ull * g->n);
           P.peels_rows.push_back(pj);
+        } else if (mode == 3) {
+          P.peel_rows32_bytes = std::max<size_t>(P.peel_rows32_bytes, 4ull * g->n);
+          P.peels_rows32.push_back(pj);
         } else {
           P.peels_global.push_back(pj);
         }
@@ -403,6 +411,7 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   P.d_gprefix = place<unsigned long long>(base, off, P.gprefix.size());
   P.d_peels = place<PeelJob>(base, off, P.peels.size());
   P.d_peels_rows = place<PeelJob>(base, off, P.peels_rows.size());
+  P.d_peels_rows32 = place<PeelJob>(base, off, P.peels_rows32.size());
   P.d_peels_global = place<PeelJob>(base, off, P.peels_global.size());
   P.d_progs = place<ProgJob>(base, off, P.progs.size());
   P.d_replays = place<ReplayJob>(base, off, P.replays.size());
@@ -437,6 +446,7 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   put(P.d_gprefix, P.gprefix.data(), P.gprefix.size() * sizeof(unsigned long long));
   put(P.d_peels, P.peels.data(), P.peels.size() * sizeof(PeelJob));
   put(P.d_peels_rows, P.peels_rows.data(), P.peels_rows.size() * sizeof(PeelJob));
+  put(P.d_peels_rows32, P.peels_rows32.data(), P.peels_rows32.size() * sizeof(PeelJob));
   put(P.d_peels_global, P.peels_global.data(), P.peels_global.size() * sizeof(PeelJob));
   put(P.d_progs, P.progs.data(), P.progs.size() * sizeof(ProgJob));
   put(P.d_replays, P.replays.data(), P.replays.size() * sizeof(ReplayJob));
@@ -463,7 +473,7 @@ uint32_t gather_grid_for(uint64_t items) {
 
 // The whole plan as launches on s (branch A on P.side when it exists).
 fs_status enqueue(fs_plan &P, hipStream_t s) {
-  const bool fork = P.side != nullptr && !(P.peels.empty() && P.peels_rows.empty() && P.peels_global.empty());
+  const bool fork = P.side != nullptr && !(P.peels.empty() && P.peels_rows.empty() && P.peels_rows32.empty() && P.peels_global.empty());
   hipStream_t a = fork ? P.side : s;
   if (fork) {
     PL_TRY(hip_ok(hipEventRecord(P.fork, s), "fork"));
@@ -472,6 +482,7 @@ fs_status enqueue(fs_plan &P, hipStream_t s) {
   // branch A: decodes (schedule, program, replay)
   PL_TRY(launch_peel_batch(P.d_peels, (uint32_t)P.peels.size(), 2, P.peel_lds_bytes, a));
   PL_TRY(launch_peel_batch(P.d_peels_rows, (uint32_t)P.peels_rows.size(), 1, P.peel_rows_bytes, a));
+  PL_TRY(launch_peel_batch(P.d_peels_rows32, (uint32_t)P.peels_rows32.size(), 3, P.peel_rows32_bytes, a));
   PL_TRY(launch_peel_batch(P.d_peels_global, (uint32_t)P.peels_global.size(), 0, 0, a));
   PL_TRY(launch_prog_batch(P.d_progs, (uint32_t)P.progs.size(), a));
   // replays[i] runs the program replay_progs[i] (built above for every decode)
@@ -688,7 +699,7 @@ fs_status fs_plan_create(const fs_work *items, uint32_t count, const char *tune_
   }
   P->gather_grid = gather_grid_for(P->gprefix.back());
   if (hipStreamSynchronize(stream) != hipSuccess) return bail(fail(FS_ERR_HIP, "plan upload failed"));
-  if (!P->peels.empty() || !P->peels_rows.empty() || !P->peels_global.empty()) {
+  if (!P->peels.empty() || !P->peels_rows.empty() || !P->peels_rows32.empty() || !P->peels_global.empty()) {
     if (hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&P->fork, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&P->join, hipEventDisableTiming) != hipSuccess)

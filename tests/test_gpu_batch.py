@@ -288,3 +288,29 @@ def test_plan_with_large_items_and_rebind():
     torch.cuda.synchronize()
     bad = [i for i, ok in enumerate(checks2) if not ok()]
     assert not bad, bad
+
+
+def test_plan_peels_in_every_state_layout():
+    """Decodes whose peel state fits LDS whole, by its 64-bit row counters,
+    by its 32-bit row counters, and not at all, in one plan."""
+    import paper_1702_07409_amd as fs
+    specs = [S(stripe=80, k=64, n=96, t=64, dist="rsd", stripe_key=80, n_erased=10),
+             S(stripe=81, k=16384, n=18022, t=16, dist="rsd", stripe_key=81, n_erased=900),
+             S(stripe=82, k=10246, n=21800, t=32, dist="raptor", stripe_key=82, n_erased=1090),
+             S(stripe=83, k=20000, n=22000, t=16, dist="rsd", stripe_key=83, n_erased=1100)]
+    items, wants, outs = [], [], []
+    for sp in specs:
+        g, G = graphs(**sp.graph_kwargs())
+        x = sp.x()
+        c = codec.encode(G, x)
+        er = sp.erased_mask()
+        xo, rec, st = empty_u8(sp.k, sp.t), empty_u8(sp.k), empty_i32(3)
+        items.append(fs.work("decode", g, sp.t, x=xo, c=dev(c), erased=dev(er), recovered=rec, status=st))
+        wants.append(codec.decode(G, c, er)[:3])
+        outs.append((xo, rec, st))
+    plan = fs.Plan(items)
+    for _ in range(2):
+        plan.launch()
+        for (xo, rec, st), (xw, recw, stw) in zip(outs, wants):
+            assert host(st).tolist() == list(stw)
+            assert np.array_equal(host(rec), recw) and np.array_equal(host(xo), xw)

@@ -237,12 +237,16 @@ def test_decode_k1_t16():
     decode_case(sp)
 
 
-@pytest.mark.parametrize("k,n", [(16384, 18022), (20000, 22000)])
-def test_peel_state_beyond_lds_uses_workspace(k, n):
+@pytest.mark.parametrize("k,n,dist", [(16384, 18022, "rsd"), (20000, 22000, "rsd"), (10246, 21800, "raptor"),
+                                      (20000, 32000, "finite")])
+def test_peel_state_beyond_lds_uses_workspace(k, n, dist):
     # k = 16384: the full peel state does not fit LDS, its per-row counters
-    # (8 n bytes) do; n = 22000: not even those, everything stays in the
-    # workspace
-    sp = workloads.StripeSpec(stripe=0, k=k, n=n, t=16, dist="rsd", stripe_key=1, n_erased=round(0.05 * n))
+    # (8 n bytes) do; n = 22000 Robust Soliton: not even those, everything
+    # stays in the workspace; n = 21800 and 32000 with degrees <= 65 or 16:
+    # the counters fit packed in 32 bits
+    w = workloads.finite16_weights() if dist == "finite" else ()
+    sp = workloads.StripeSpec(stripe=0, k=k, n=n, t=16, dist=dist, finite_w=w, stripe_key=1,
+                              n_erased=round(0.05 * n))
     decode_case(sp)
 
 
