@@ -27,6 +27,10 @@ Functions
   erased_mask     the erasure vector of one combination.
   sim_disks       status triples of the combinations of ranks
                   [first, first + count).
+  sim_disks_precoded  the same with the array-LDPC precode of b data blocks:
+                  tolerable means every data block recovered by the two-stage
+                  decode (§2.2); status {ok, data blocks missing, LDGM levels,
+                  precode levels}, as precode.decode_two_stage reports it.
 """
 
 import itertools
@@ -34,7 +38,7 @@ import math
 
 import numpy as np
 
-from . import codec
+from . import codec, precode
 
 
 def disk_rows(n, s, d):
@@ -65,4 +69,24 @@ def sim_disks(G, s, f, first=0, count=None, maxit=0):
     for r, failed in enumerate(combos):
         sched = codec.peel_schedule(G, erased_mask(G.n, s, failed), maxit)
         out[r] = sched.status()
+    return out
+
+
+def sim_disks_precoded(G, b, s, f, first=0, count=None, maxit=0):
+    """int32[count, 4]: the two-stage decoder's status for each combination."""
+    total = math.comb(s, f)
+    count = total - first if count is None else count
+    assert 0 <= first and first + count <= total
+    combos = combinations(s, f)[first:first + count]
+    out = np.zeros((count, 4), dtype=np.int32)
+    for r, failed in enumerate(combos):
+        sched = codec.peel_schedule(G, erased_mask(G.n, s, failed), maxit)
+        known = np.ones(G.k, dtype=bool)
+        known[sched.F] = False
+        levels2 = 0
+        if not known[:b].all():
+            # the second pass on the symbols alone (zero-width blocks)
+            _, known, levels2 = precode.precode_bp(b, G.k, np.zeros((G.k, 0), np.uint8), known)
+        miss = int(b - known[:b].sum())
+        out[r] = (int(miss == 0), miss, int(sched.L), int(levels2))
     return out

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from oracle import codec, gf2, graph, simdisk
+from synth import gen
 
 
 def G_of(k, n, **kw):
@@ -95,3 +96,38 @@ def test_level_limit():
     assert (one[:, 2] <= 1).all() and (one[:, 1] >= full[:, 1]).all()
     L = int(full[:, 2].max())
     assert np.array_equal(simdisk.sim_disks(G, 7, 2, maxit=L), full)
+
+
+def test_precoded_sweep_matches_the_two_stage_decode_on_payloads():
+    # the symbolic sweep against the numeric two-stage decode of a real
+    # payload, pattern by pattern; the precode only ever adds tolerable patterns
+    from oracle import precode
+    b, k = 28, 49
+    G = graph.build(graph.GraphParams(k=k, n=84, dist="rsd", seed=2))
+    data = gen.payload(3, 1, b, 16)
+    c = codec.encode(G, precode.encode(b, k, data))
+    s = 7
+    for f in range(s + 1):
+        got = simdisk.sim_disks_precoded(G, b, s, f)
+        plain = simdisk.sim_disks(G, s, f)
+        for r, failed in enumerate(simdisk.combinations(s, f)):
+            out, ok, status = precode.decode_two_stage(G, b, c, simdisk.erased_mask(G.n, s, failed))
+            assert got[r].tolist() == list(status)
+            assert np.array_equal(out[ok.astype(bool)], data[ok.astype(bool)])
+            assert got[r][0] >= plain[r][0]
+    assert simdisk.sim_disks_precoded(G, b, s, 2, first=5, count=3).tolist() == \
+        simdisk.sim_disks_precoded(G, b, s, 2)[5:8].tolist()
+
+
+def test_precoded_sweep_monotone():
+    b, k = 28, 49
+    G = graph.build(graph.GraphParams(k=k, n=70, dist="rsd", seed=4))
+    s = 7
+    res = {}
+    for f in range(s + 1):
+        for cmb, st in zip(simdisk.combinations(s, f), simdisk.sim_disks_precoded(G, b, s, f)):
+            res[cmb] = st
+    for a in res:
+        for bb in res:
+            if set(a) < set(bb):
+                assert res[bb][0] <= res[a][0] and res[a][1] <= res[bb][1]
