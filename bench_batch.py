@@ -290,6 +290,20 @@ def run_simdisk(reps=5):
         t_all += m
         per_f.append(int(res10[:, 0].sum().item()))
     out.update({"ten_disks_tolerable_by_f": per_f, "ten_disks_all_ms": round(t_all, 3)})
+    # the same code with its array-LDPC precode (b = 9919, j' = 3): a pattern
+    # is tolerable when the two-stage decode recovers every data block
+    pc = fs.fs_precode_build(9919, 10246)
+    wsp = fs.workspace(g, fs.FS_OP_SIM_DISKS, 16, pc.k - pc.b)
+    resp = torch.empty((total, 4), dtype=torch.int32, device="cuda")
+    msp = _time(lambda: fs.fs_sim_disks_precoded(g, pc, s, f, 0, total, 0, resp, wsp), reps)
+    per_fp = []
+    for f10 in range(0, 11):
+        c = math.comb(10, f10)
+        r10 = torch.empty((c, 4), dtype=torch.int32, device="cuda")
+        fs.fs_sim_disks_precoded(g, pc, 10, f10, 0, c, 0, r10, wsp)
+        per_fp.append(int(r10[:, 0].sum().item()))
+    out["precoded"] = {"b": 9919, "ms": round(msp, 3), "combinations_per_s": round(total / (msp * 1e-3)),
+                       "tolerable": int(resp[:, 0].sum().item()), "ten_disks_tolerable_by_f": per_fp}
     # The sweep is bound by instruction issue, not HBM: the roofline is the
     # VALU issue rate (256 CUs x 2.4 GHz x one wave64 VALU instruction per CU
     # per cycle) against the VALU instructions per pattern that the committed

@@ -277,9 +277,9 @@ FS_API fs_status fs_extend(const fs_graph *g, uint32_t n_old, const void *x, voi
  *   undecoded inputs, levels}.  No payload is read.
  * Requires 1 <= s <= min(64, n), f <= s and first + count <= C(s, f)
  * (FS_ERR_INVALID otherwise, nothing launched).
- * ws: FS_OP_SIM_DISKS bytes (a binomial table, the rows' initial state, and
- *   per-workgroup state when it does not fit in LDS); t and n_items are
- *   ignored for it.
+ * ws: FS_OP_SIM_DISKS bytes with n_items = 0 (a binomial table, the rows'
+ *   initial state, and per-workgroup state when it does not fit in LDS); t
+ *   is ignored for it.
  */
 FS_API fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first,
                        uint64_t count, uint32_t maxit, int32_t *result, void *ws,
@@ -333,6 +333,18 @@ FS_API fs_status fs_decode_precoded(const fs_graph *g, const fs_precode *pc, con
                              const uint8_t *erased, uint32_t maxit, void *x, uint8_t *recovered,
                              int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
                              hipStream_t stream);
+
+/*
+ * Disk-failure sweep of a precoded code: as fs_sim_disks, with a
+ * combination tolerable when the two-stage decode of fs_decode_precoded
+ * recovers all b data blocks (maxit limits the first pass).  result: device
+ * int32[count][4], each {ok, data blocks missing, levels of the first pass,
+ * levels of the second}.  g->k must equal the precode's k.  ws:
+ * FS_OP_SIM_DISKS bytes with n_items = k - b (the precode's checks).
+ */
+FS_API fs_status fs_sim_disks_precoded(const fs_graph *g, const fs_precode *pc, uint32_t s,
+                                uint32_t f, uint64_t first, uint64_t count, uint32_t maxit,
+                                int32_t *result, void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Decode in two halves.  fs_decode_plan runs the peeling schedule of fs_peel

@@ -17,7 +17,7 @@ _BINDING = (
     "fs_decode",
     "fs_decode_apply", "fs_decode_plan", "fs_degree_table", "fs_encode", "fs_get_tune",
     "fs_graph_build", "fs_peel", "fs_repair", "fs_replay", "fs_reset_tune", "fs_set_tune",
-    "fs_update", "fs_extend", "fs_sim_disks", "fs_precode_build", "fs_precode_encode",
+    "fs_update", "fs_extend", "fs_sim_disks", "fs_sim_disks_precoded", "fs_precode_build", "fs_precode_encode",
     "fs_decode_precoded", "Precode", "fs_workspace_size", "version", "workspace", "Plan",
     "work", "plan_memory_size",
     "FS_WORK_ENCODE", "FS_WORK_DECODE", "FS_WORK_REPAIR", "FS_WORK_UPDATE",

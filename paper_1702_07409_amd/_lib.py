@@ -103,6 +103,7 @@ _SIGS = {
     "fs_precode_free": ([P], None),
     "fs_precode_encode": ([P, P, U64, P], ST),
     "fs_decode_precoded": ([P, P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
+    "fs_sim_disks_precoded": ([P, P, U32, U32, U64, U64, U32, P, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
     "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ST),
@@ -359,6 +360,12 @@ def fs_decode_precoded(g, pc, c, erased, maxit, x, recovered, status, t, ws, str
     w, wb = _ws(ws)
     _check(_lib.fs_decode_precoded(g.handle, pc.handle, _ptr(c), _ptr(erased), maxit, _ptr(x), _ptr(recovered),
                                    _ptr(status), t, w, wb, _stream(stream)), "fs_decode_precoded")
+
+
+def fs_sim_disks_precoded(g, pc, s, f, first, count, maxit, result, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_sim_disks_precoded(g.handle, pc.handle, s, f, first, count, maxit, _ptr(result), w, wb,
+                                      _stream(stream)), "fs_sim_disks_precoded")
 
 
 def fs_sim_disks(g, s, f, first, count, maxit, result, ws, stream=None):

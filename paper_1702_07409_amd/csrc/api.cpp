@@ -196,13 +196,13 @@ void carve_precode(Carver &cv, uint32_t k, PrecodeBufs &b) {
 
 size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items);
 
-SimDiskLayout simdisk_layout_for(const fs_graph *g) {
+SimDiskLayout simdisk_layout_for(const fs_graph *g, uint32_t checks) {
   const int dev = g->device < 0 ? 0 : g->device;
-  return simdisk_layout(g->k, g->n, g->max_deg, (size_t)device_info(dev).max_lds_per_block);
+  return simdisk_layout(g->k, g->n, g->max_deg, checks, (size_t)device_info(dev).max_lds_per_block);
 }
 
-void carve_simdisk(Carver &cv, const fs_graph *g, SimDiskJob &j) {
-  const SimDiskLayout L = simdisk_layout_for(g);
+void carve_simdisk(Carver &cv, const fs_graph *g, uint32_t checks, SimDiskJob &j) {
+  const SimDiskLayout L = simdisk_layout_for(g, checks);
   const bool global = (L.mode == kSimDiskGlobal);
   j.binom = cv.take<uint64_t>(65 * 65);
   j.rowinfo = cv.take<uint32_t>(L.image_bytes / 4);
@@ -253,7 +253,7 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
     }
     case FS_OP_SIM_DISKS: {
       SimDiskJob j{};
-      carve_simdisk(cv, g, j);
+      carve_simdisk(cv, g, n_items, j);
       return cv.size();
     }
     case FS_OP_DECODE_PRECODED: {
@@ -808,10 +808,15 @@ fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *ids, ui
   return launch_gather(gj, tile_for(current_tune(), g), stream);
 }
 
-fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first, uint64_t count,
-                       uint32_t maxit, int32_t *result, void *ws, size_t ws_bytes, hipStream_t stream) {
+static fs_status sim_disks_impl(const fs_graph *g, const fs_precode *pc, uint32_t s, uint32_t f, uint64_t first,
+                                uint64_t count, uint32_t maxit, int32_t *result, void *ws, size_t ws_bytes,
+                                hipStream_t stream) {
   clear_error();
   FS_TRY(check_graph(g));
+  if (pc) {
+    if (!pc->d_base) return fail(FS_ERR_INVALID, "precode was built host-only");
+    if (pc->k != g->k) return fail(FS_ERR_INVALID, "the graph's k differs from the precode's");
+  }
   if (s < 1 || s > 64 || s > g->n) return fail(FS_ERR_INVALID, "s must be in [1, min(64, n)]");
   if (f > s) return fail(FS_ERR_INVALID, "f exceeds s");
   // C(s, f) by the multiplicative formula, exact for s <= 64 in 128-bit
@@ -820,10 +825,11 @@ fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first
   if (first > (uint64_t)total || count > (uint64_t)total - first)
     return fail(FS_ERR_INVALID, "combination ranks beyond C(s, f) = " + std::to_string((uint64_t)total));
   if (count && !result) return fail(FS_ERR_INVALID, "result is null");
-  FS_TRY(check_ws(g, FS_OP_SIM_DISKS, 0, 0, ws, ws_bytes));
+  const uint32_t checks = pc ? pc->m : 0;
+  FS_TRY(check_ws(g, FS_OP_SIM_DISKS, 0, checks, ws, ws_bytes));
   Carver cv(ws);
   SimDiskJob j{};
-  carve_simdisk(cv, g, j);
+  carve_simdisk(cv, g, checks, j);
   j.k = g->k;
   j.n = g->n;
   j.s = s;
@@ -836,7 +842,30 @@ fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first
   j.col_ptr = g->d_col_ptr;
   j.rowidx = g->d_rowidx;
   j.result = result;
-  return launch_simdisk(j, simdisk_layout_for(g), stream);
+  if (pc) {
+    j.pc_b = pc->b;
+    j.pc_m = pc->m;
+    j.chk_ptr = pc->d_chk_ptr;
+    j.chk_col = pc->d_chk_col;
+    j.sym_ptr = pc->d_sym_ptr;
+    j.sym_chk = pc->d_sym_chk;
+  }
+  return launch_simdisk(j, simdisk_layout_for(g, checks), stream);
+}
+
+fs_status fs_sim_disks(const fs_graph *g, uint32_t s, uint32_t f, uint64_t first, uint64_t count,
+                       uint32_t maxit, int32_t *result, void *ws, size_t ws_bytes, hipStream_t stream) {
+  return sim_disks_impl(g, nullptr, s, f, first, count, maxit, result, ws, ws_bytes, stream);
+}
+
+fs_status fs_sim_disks_precoded(const fs_graph *g, const fs_precode *pc, uint32_t s, uint32_t f, uint64_t first,
+                                uint64_t count, uint32_t maxit, int32_t *result, void *ws, size_t ws_bytes,
+                                hipStream_t stream) {
+  if (!pc) {
+    clear_error();
+    return fail(FS_ERR_INVALID, "precode is null");
+  }
+  return sim_disks_impl(g, pc, s, f, first, count, maxit, result, ws, ws_bytes, stream);
 }
 
 fs_status fs_precode_build(uint32_t b, uint32_t k, int host_only, hipStream_t stream, fs_precode **out) {

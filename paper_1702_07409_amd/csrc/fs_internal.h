@@ -196,10 +196,10 @@ constexpr uint32_t kSimDiskSlots = 256;
 struct SimDiskLayout {
   int mode;
   size_t image_bytes;                 // per-row state image (rowinfo and the copy in LDS / a slot)
-  size_t off_w, off_dec, off_fresh;   // byte offsets in LDS or in one slot
+  size_t off_w, off_dec, off_fresh, off_chk;   // byte offsets in LDS or in one slot
   size_t bytes;                       // LDS bytes, or bytes of one slot
 };
-SimDiskLayout simdisk_layout(uint32_t k, uint32_t n, uint32_t max_deg, size_t max_lds);
+SimDiskLayout simdisk_layout(uint32_t k, uint32_t n, uint32_t max_deg, uint32_t checks, size_t max_lds);
 struct SimDiskJob {
   uint32_t k, n, s, f, maxit;
   uint64_t first, count;
@@ -207,8 +207,10 @@ struct SimDiskJob {
   uint64_t *binom;      // uint64[65 * 65], C(a, b) at a * 65 + b (written by the setup)
   uint32_t *rowinfo;    // the initial per-row state image (written by the setup)
   uint8_t *slots;       // global mode: kSimDiskSlots slots of slot_bytes
-  size_t slot_bytes, off_w, off_dec, off_fresh;
-  int32_t *result;      // int32[count][3]
+  size_t slot_bytes, off_w, off_dec, off_fresh, off_chk;
+  uint32_t pc_b, pc_m;  // precode: data blocks and checks (pc_m = 0: none)
+  const int32_t *chk_ptr, *chk_col, *sym_ptr, *sym_chk;   // precode check sets
+  int32_t *result;      // int32[count][3], or [count][4] with a precode
 };
 fs_status launch_simdisk(const SimDiskJob &job, const SimDiskLayout &layout, hipStream_t s);
 

@@ -23,6 +23,8 @@
 // of each level is that of the schedule, so |F| and the level count agree
 // with it; which row decodes an input is not needed here and not recorded.
 // An erased row carries an offset in its count that keeps it above one.
+// With a precode the same workgroup then runs the second BP pass over the
+// check equations (8 bytes of state per check) when data blocks are missing.
 
 #include <hip/hip_runtime.h>
 
@@ -198,11 +200,30 @@ __device__ __forceinline__ void fence_for_barrier() {
   if (MODE == kSimDiskGlobal) __threadfence();
 }
 
+// Data blocks (inputs below b) not decoded; every thread of the workgroup
+// calls it and gets the same count.
+template <int MODE>
+__device__ __forceinline__ uint32_t missing_data(const State<MODE> &S, uint32_t b, uint32_t *s_miss) {
+  const uint32_t tid = threadIdx.x, nt = blockDim.x, bw = (b + 31) / 32;
+  __syncthreads();
+  if (tid == 0) *s_miss = 0;
+  __syncthreads();
+  uint32_t miss = 0;
+  for (uint32_t w = tid; w < bw; w += nt) {
+    uint32_t bits = ~S.ld(S.dec + w);
+    if (w == bw - 1 && (b & 31)) bits &= (1u << (b & 31)) - 1u;
+    miss += (uint32_t)__popc(bits);
+  }
+  if (miss) atomicAdd(s_miss, miss);
+  __syncthreads();
+  return *s_miss;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(1024) void simdisk_kernel(SimDiskJob J) {
   extern __shared__ __align__(16) uint8_t lds[];
   __shared__ unsigned long long s_rev;
-  __shared__ uint32_t s_dec;
+  __shared__ uint32_t s_dec, s_miss;
 
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t n = J.n, k = J.k;
@@ -351,7 +372,74 @@ __global__ __launch_bounds__(1024) void simdisk_kernel(SimDiskJob J) {
       __syncthreads();
       decoded = now;
     }
-    if (tid == 0) {
+    if (J.pc_m) {
+      // precoded: the second BP pass over the checks when data blocks are
+      // still missing, then the data blocks missing after both
+      uint32_t levels2 = 0;
+      uint32_t missing = missing_data(S, J.pc_b, &s_miss);
+      if (missing) {
+        uint32_t *ccnt = reinterpret_cast<uint32_t *>(base + J.off_chk), *cxs = ccnt + J.pc_m;
+        for (uint32_t c = tid; c < J.pc_m; c += nt) {
+          uint32_t u = 0, x = 0;
+          for (int32_t e = J.chk_ptr[c]; e < J.chk_ptr[c + 1]; ++e) {
+            const uint32_t sb = (uint32_t)J.chk_col[e];
+            if (!((S.ld(S.dec + (sb >> 5)) >> (sb & 31)) & 1u)) {
+              ++u;
+              x ^= sb;
+            }
+          }
+          S.st(ccnt + c, u);
+          S.st(cxs + c, x);
+        }
+        if (tid == 0) s_dec = 0;
+        fence_for_barrier<MODE>();
+        __syncthreads();
+        uint32_t prev = 0;
+        for (;;) {
+          uint32_t mine = 0;
+          for (uint32_t c = tid; c < J.pc_m; c += nt) {
+            if (S.ld(ccnt + c) != 1u) continue;
+            const uint32_t f = S.ld(cxs + c), bit = 1u << (f & 31);
+            if (!(atomicOr(S.dec + (f >> 5), bit) & bit)) {
+              atomicOr(S.fresh + (f >> 5), bit);
+              ++mine;
+            }
+          }
+          for (int o = 32; o > 0; o >>= 1) mine += __shfl_xor(mine, o, 64);
+          if (lane == 0 && mine) atomicAdd(&s_dec, mine);
+          fence_for_barrier<MODE>();
+          __syncthreads();
+          const uint32_t now = s_dec;
+          if (now == prev) break;
+          ++levels2;
+          for (uint32_t wi = tid; wi < kw; wi += nt) {
+            uint32_t bits = S.ld(S.fresh + wi);
+            if (!bits) continue;
+            S.st(S.fresh + wi, 0u);
+            while (bits) {
+              const uint32_t f = 32 * wi + (uint32_t)__builtin_ctz(bits);
+              bits &= bits - 1u;
+              for (int32_t e = J.sym_ptr[f]; e < J.sym_ptr[f + 1]; ++e) {
+                const uint32_t h = (uint32_t)J.sym_chk[e];
+                atomicSub(ccnt + h, 1u);
+                atomicXor(cxs + h, f);
+              }
+            }
+          }
+          fence_for_barrier<MODE>();
+          __syncthreads();
+          prev = now;
+        }
+        missing = missing_data(S, J.pc_b, &s_miss);
+      }
+      if (tid == 0) {
+        int32_t *out = J.result + r * 4;
+        out[0] = missing == 0 ? 1 : 0;
+        out[1] = (int32_t)missing;
+        out[2] = (int32_t)levels;
+        out[3] = (int32_t)levels2;
+      }
+    } else if (tid == 0) {
       int32_t *out = J.result + r * 3;
       out[0] = decoded == k ? 1 : 0;
       out[1] = (int32_t)(k - decoded);
@@ -364,7 +452,7 @@ __global__ __launch_bounds__(1024) void simdisk_kernel(SimDiskJob J) {
 
 }  // namespace
 
-SimDiskLayout simdisk_layout(uint32_t k, uint32_t n, uint32_t max_deg, size_t max_lds) {
+SimDiskLayout simdisk_layout(uint32_t k, uint32_t n, uint32_t max_deg, uint32_t checks, size_t max_lds) {
   SimDiskLayout L{};
   auto up = [](size_t v) { return (v + 15) & ~size_t(15); };
   const size_t n16 = ((size_t)n + kChunk - 1) & ~size_t(kChunk - 1), kw = (k + 31) / 32;
@@ -374,7 +462,8 @@ SimDiskLayout simdisk_layout(uint32_t k, uint32_t n, uint32_t max_deg, size_t ma
     L.off_w = 0;
     L.off_dec = up(L.image_bytes);
     L.off_fresh = up(L.off_dec + 4 * kw);
-    L.bytes = up(L.off_fresh + 4 * kw);
+    L.off_chk = up(L.off_fresh + 4 * kw);
+    L.bytes = up(L.off_chk + 8ull * checks);
     if (L.bytes <= max_lds) return L;
   }
   // per-workgroup slots in global memory
@@ -384,7 +473,8 @@ SimDiskLayout simdisk_layout(uint32_t k, uint32_t n, uint32_t max_deg, size_t ma
   L.off_w = 0;
   L.off_dec = al(L.image_bytes);
   L.off_fresh = al(L.off_dec + 4 * kw);
-  L.bytes = al(L.off_fresh + 4 * kw);
+  L.off_chk = al(L.off_fresh + 4 * kw);
+  L.bytes = al(L.off_chk + 8ull * checks);
   return L;
 }
 
@@ -436,6 +526,7 @@ fs_status launch_simdisk(const SimDiskJob &job_in, const SimDiskLayout &L, hipSt
   job.off_w = L.off_w;
   job.off_dec = L.off_dec;
   job.off_fresh = L.off_fresh;
+  job.off_chk = L.off_chk;
   job.slot_bytes = L.bytes;
   int dev = 0;
   (void)hipGetDevice(&dev);

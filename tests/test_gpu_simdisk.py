@@ -109,3 +109,39 @@ def test_sweep_large_code_sampled():
     assert ((got[:, 0] == 1) == (got[:, 1] == 0)).all()
     for r in (0, 1, total // 3, total // 2, total - 2, total - 1):
         assert np.array_equal(got[r], simdisk.sim_disks(G, s, f, first=r, count=1)[0]), r
+
+
+def gpu_sweep_precoded(g, pc, s, f, first=0, count=None, maxit=0):
+    import paper_1702_07409_amd as fs
+    count = math.comb(s, f) - first if count is None else count
+    res = empty_i32(max(count, 1), 4)
+    res.fill_(-7)
+    ws = fs.workspace(g, fs.FS_OP_SIM_DISKS, 16, pc.k - pc.b)
+    fs.fs_sim_disks_precoded(g, pc, s, f, first, count, maxit, res, ws)
+    return host(res)[:count]
+
+
+@pytest.mark.parametrize("b,k,n,dist,s,fs_", [(925, 1036, 2180, "raptor", 10, (0, 2, 3, 4, 5)),
+                                             (28, 49, 84, "rsd", 7, range(0, 8))])
+def test_precoded_sweep(b, k, n, dist, s, fs_):
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=k, n=n, dist=dist)
+    pc = fs.fs_precode_build(b, k)
+    for f in fs_:
+        got = gpu_sweep_precoded(g, pc, s, f)
+        want = simdisk.sim_disks_precoded(G, b, s, f)
+        assert np.array_equal(got, want), (s, f, np.flatnonzero((got != want).any(axis=1))[:5])
+
+
+def test_precoded_sweep_large_code_sampled_and_slots():
+    # the k = 10246 code on 24 disks: sampled ranks; and a code whose state
+    # lives in workgroup slots (3 bytes a row for n = 56000 exceed LDS)
+    import paper_1702_07409_amd as fs
+    for b, k, n, s, f in ((9919, 10246, 21800, 24, 4), (21854, 22523, 56000, 20, 1)):
+        g, G = graphs(k=k, n=n, dist="raptor")
+        pc = fs.fs_precode_build(b, k)
+        total = math.comb(s, f)
+        got = gpu_sweep_precoded(g, pc, s, f)
+        assert got.shape == (total, 4)
+        for r in sorted({0, 1, total // 2, total - 1}):
+            assert np.array_equal(got[r], simdisk.sim_disks_precoded(G, b, s, f, first=r, count=1)[0]), r
