@@ -1,0 +1,125 @@
+"""Check #2 / check #3 generation (CGA) and local-group repair (oracle copy).
+
+Test infrastructure: only the tests, the smoke check and the CPU baseline of
+the benchmark use this module; the library never does.
+
+Functions and the passage each follows
+  cga            Algorithm 4 (§2.6): columns of the generator matrix B (k x n,
+                 column j = the inputs of coded block j) are XORed into each
+                 other while that lowers their weight; L(2,3) (n x n, the
+                 identity at the start) records which coded blocks each
+                 column has become the sum of.  The sweep over (j, i) repeats
+                 until B has n - k zero columns or a sweep changes nothing.
+  split          §2.6: a column of weight one is a check #2 equation (input i
+                 = XOR of the coded blocks of its L column), a column of
+                 weight zero a check #3 group (its coded blocks XOR to zero);
+                 groups ordered by cardinality, smallest first, ties by
+                 column.
+  set_xor        §2.5, Eqs. (1)-(4): check #3 groups from a check #1 group
+                 and the check #2 sets of its members (symmetric difference).
+  local_repair   the repair engine's fast path (§2.7, §4): each lost coded
+                 block is the XOR of the other members of the first (smallest)
+                 check #3 group holding it whose other members are all
+                 available; lost blocks without such a group are left for
+                 the conventional repair.
+
+Readings:
+  * Columns are bitsets of the k inputs; w() is their number of ones.  The
+    pair test is 2 w(b_j) > w(b_i), then w(b_j ^ b_i) < w(b_j), both with the
+    current b_j (it changes inside the i loop).
+  * zero_columns counts the zero columns (the text's "nonzero" contradicts
+    the loop bound n - k).
+  * Local repair takes groups in the stored order (smallest first) and uses
+    only blocks that are neither erased nor lost; a block repaired in the same
+    call is not reused (one pass).
+"""
+
+import numpy as np
+
+
+def _w(x):
+    return bin(x).count("1")
+
+
+def cga(G, max_sweeps=0):
+    """Algorithm 4.  Returns (B columns after, L columns after, sweeps), each
+    column an int bitset (B over inputs, L over coded blocks)."""
+    k, n = G.k, G.n
+    b = [sum(1 << int(i) for i in G.N(j)) for j in range(n)]
+    L = [1 << j for j in range(n)]
+    sweeps = 0
+    while sum(1 for x in b if x == 0) < n - k:
+        if max_sweeps and sweeps == max_sweeps:
+            break
+        changed = False
+        for j in range(n):
+            for i in range(n):
+                if j != i and 2 * _w(b[j]) > _w(b[i]):
+                    if _w(b[j] ^ b[i]) < _w(b[j]):
+                        b[j] ^= b[i]
+                        L[j] ^= L[i]
+                        changed = True
+        sweeps += 1
+        if not changed:
+            break
+    return b, L, sweeps
+
+
+def _members(x):
+    out, s = [], 0
+    while x:
+        if x & 1:
+            out.append(s)
+        x >>= 1
+        s += 1
+    return out
+
+
+def split(b, L):
+    """(check2, check3): check2 maps input i to the coded blocks of the first
+    column whose weight-one b is input i; check3 lists coded-block groups,
+    smallest first (ties by column index)."""
+    check2 = {}
+    groups = []
+    for j, (bj, lj) in enumerate(zip(b, L)):
+        if bj == 0:
+            groups.append((_w(lj), j, _members(lj)))
+        elif bj & (bj - 1) == 0:
+            i = bj.bit_length() - 1
+            check2.setdefault(i, _members(lj))
+    groups.sort()
+    return check2, [g for _, _, g in groups]
+
+
+def set_xor(sets):
+    """Symmetric difference of the given sets (sorted list)."""
+    acc = set()
+    for s in sets:
+        acc ^= set(s)
+    return sorted(acc)
+
+
+def local_repair(groups, c, lost, erased=None):
+    """Returns (blocks[len(lost), t], repaired[len(lost)], group used per lost
+    block or -1)."""
+    n, t = c.shape
+    unavailable = np.zeros(n, dtype=bool)
+    if erased is not None:
+        unavailable |= np.asarray(erased, dtype=bool)
+    unavailable[list(lost)] = True
+    out = np.zeros((len(lost), t), dtype=np.uint8)
+    ok = np.zeros(len(lost), dtype=np.uint8)
+    used = np.full(len(lost), -1, dtype=np.int64)
+    for r, s in enumerate(lost):
+        for gi, grp in enumerate(groups):
+            if s not in grp:
+                continue
+            others = [m for m in grp if m != s]
+            if any(unavailable[m] for m in others):
+                continue
+            acc = np.zeros(t, dtype=np.uint8)
+            for m in others:
+                acc ^= c[m]
+            out[r], ok[r], used[r] = acc, 1, gi
+            break
+    return out, ok, used
