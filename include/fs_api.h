@@ -85,6 +85,7 @@ typedef struct fs_graph_params {
 
 typedef struct fs_graph fs_graph;   /* opaque; owns host + device CSR and CSC */
 typedef struct fs_precode fs_precode;   /* opaque; owns host + device check sets */
+typedef struct fs_checks fs_checks;     /* opaque; check #2 / #3 equations of a graph */
 
 /*
  * Degree table: the integer inverse-CDF thresholds used
@@ -156,7 +157,8 @@ FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t
 /* Operations for fs_workspace_size. */
 enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
        FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6, FS_OP_EXTEND = 7,
-       FS_OP_EXTEND_CONVENTIONAL = 8, FS_OP_SIM_DISKS = 9, FS_OP_DECODE_PRECODED = 10 };
+       FS_OP_EXTEND_CONVENTIONAL = 8, FS_OP_SIM_DISKS = 9, FS_OP_DECODE_PRECODED = 10,
+       FS_OP_REPAIR_LOCAL = 11 };
 
 /*
  * Workspace bytes the operation needs for this graph and block size
@@ -345,6 +347,49 @@ FS_API fs_status fs_decode_precoded(const fs_graph *g, const fs_precode *pc, con
 FS_API fs_status fs_sim_disks_precoded(const fs_graph *g, const fs_precode *pc, uint32_t s,
                                 uint32_t f, uint64_t first, uint64_t count, uint32_t maxit,
                                 int32_t *result, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Check #2 and check #3 generation (§2.6, Algorithm 4 "CGA"), on the device.
+ * Columns of the generator matrix B (column j = the inputs of coded block j)
+ * are XORed into each other while that lowers their weight: for j = 0..n-1
+ * and i = 0..n-1 (i != j), if 2 w(b_j) > w(b_i) and w(b_j ^ b_i) < w(b_j)
+ * then b_j ^= b_i and l_j ^= l_i, with L the n x n identity at the start.
+ * Sweeps repeat until B has n - k zero columns, a sweep changes nothing, or
+ * max_sweeps sweeps ran (0 = no limit).  Then a column of weight one is a
+ * check #2 equation (its input = XOR of the coded blocks of l_j; the first
+ * such column per input is kept) and a column of weight zero a check #3
+ * group (its coded blocks XOR to zero), groups ordered by size, smallest
+ * first, ties by column.  Runs on the stream, waits for it, and keeps the
+ * groups on the host and the device.  Errors: FS_ERR_NOMEM, FS_ERR_HIP.
+ */
+FS_API fs_status fs_checks_generate(const fs_graph *g, uint32_t max_sweeps, hipStream_t stream,
+                             fs_checks **out);
+FS_API fs_status fs_checks_info(const fs_checks *ch, uint32_t *n_check2, uint32_t *n_check3,
+                         uint32_t *sweeps, uint32_t *zero_columns, uint64_t *check2_entries,
+                         uint64_t *check3_entries);
+/* Host copies: check #3 groups c3_ptr int32[n_check3 + 1], c3_col
+ * int32[check3_entries]; check #2 equations by ascending input, c2_input
+ * int32[n_check2], c2_ptr int32[n_check2 + 1], c2_col int32[check2_entries].
+ * Members ascending. */
+FS_API fs_status fs_checks_export(const fs_checks *ch, int32_t *c3_ptr, int32_t *c3_col,
+                           int32_t *c2_input, int32_t *c2_ptr, int32_t *c2_col);
+FS_API void fs_checks_free(fs_checks *ch);
+
+/*
+ * Local-group repair, the repair engine's fast path (§2.7, §4): each lost
+ * coded row s is rebuilt in place in c as the XOR of the other members of
+ * the first (smallest) check #3 group holding s whose other members are
+ * neither erased nor lost; rows without such a group are zero-filled and
+ * left for fs_repair.  lost: device uint32[n_lost]; erased: device uint8[n]
+ * or NULL.  repaired: device uint8[n_lost].  status: device int32[3] {all
+ * rebuilt, rows not rebuilt, 0 or FS_ERR_INVALID for a bad lost id (>= n or
+ * repeated; nothing is written)}.  ws: FS_OP_REPAIR_LOCAL bytes with
+ * n_items = n_lost.
+ */
+FS_API fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c,
+                          const uint8_t *erased, const uint32_t *lost, uint32_t n_lost,
+                          uint8_t *repaired, int32_t *status, uint64_t t, void *ws,
+                          size_t ws_bytes, hipStream_t stream);
 
 /*
  * Decode in two halves.  fs_decode_plan runs the peeling schedule of fs_peel

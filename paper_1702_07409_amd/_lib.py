@@ -36,7 +36,7 @@ FS_DIST_RSD, FS_DIST_FINITE, FS_DIST_RAPTOR = 0, 1, 2
 FS_DEFAULT_SEED = 1389488782
 FS_GRAPH_HOST_ONLY = 1
 (FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE, FS_OP_REPLAY,
- FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS, FS_OP_DECODE_PRECODED) = range(11)
+ FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS, FS_OP_DECODE_PRECODED, FS_OP_REPAIR_LOCAL) = range(12)
 
 DIST_CODES = {"rsd": FS_DIST_RSD, "finite": FS_DIST_FINITE, "raptor": FS_DIST_RAPTOR}
 
@@ -104,6 +104,12 @@ _SIGS = {
     "fs_precode_encode": ([P, P, U64, P], ST),
     "fs_decode_precoded": ([P, P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
     "fs_sim_disks_precoded": ([P, P, U32, U32, U64, U64, U32, P, P, SZ, P], ST),
+    "fs_checks_generate": ([P, U32, P, ctypes.POINTER(P)], ST),
+    "fs_checks_info": ([P, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32),
+                        ctypes.POINTER(U64), ctypes.POINTER(U64)], ST),
+    "fs_checks_export": ([P, P, P, P, P, P], ST),
+    "fs_checks_free": ([P], None),
+    "fs_repair_local": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
     "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ST),
@@ -360,6 +366,55 @@ def fs_decode_precoded(g, pc, c, erased, maxit, x, recovered, status, t, ws, str
     w, wb = _ws(ws)
     _check(_lib.fs_decode_precoded(g.handle, pc.handle, _ptr(c), _ptr(erased), maxit, _ptr(x), _ptr(recovered),
                                    _ptr(status), t, w, wb, _stream(stream)), "fs_decode_precoded")
+
+
+class Checks:
+    """Owner of an fs_checks handle (check #2 / #3 equations of a graph)."""
+
+    def __init__(self, handle):
+        self.handle = handle
+        a, b_, c, d, e, f = U32(), U32(), U32(), U32(), U64(), U64()
+        _check(_lib.fs_checks_info(handle, ctypes.byref(a), ctypes.byref(b_), ctypes.byref(c), ctypes.byref(d),
+                                   ctypes.byref(e), ctypes.byref(f)), "fs_checks_info")
+        self.n_check2, self.n_check3, self.sweeps, self.zero_columns = a.value, b_.value, c.value, d.value
+        self.check2_entries, self.check3_entries = e.value, f.value
+
+    def export(self):
+        """(check2 {input: [coded blocks]}, check3 [[coded blocks], ...])."""
+        import numpy as np
+        c3p = np.zeros(self.n_check3 + 1, np.int32)
+        c3c = np.zeros(max(self.check3_entries, 1), np.int32)
+        c2i = np.zeros(max(self.n_check2, 1), np.int32)
+        c2p = np.zeros(self.n_check2 + 1, np.int32)
+        c2c = np.zeros(max(self.check2_entries, 1), np.int32)
+        _check(_lib.fs_checks_export(self.handle, c3p.ctypes.data, c3c.ctypes.data, c2i.ctypes.data,
+                                     c2p.ctypes.data, c2c.ctypes.data), "fs_checks_export")
+        check2 = {int(c2i[q]): c2c[c2p[q]:c2p[q + 1]].tolist() for q in range(self.n_check2)}
+        check3 = [c3c[c3p[q]:c3p[q + 1]].tolist() for q in range(self.n_check3)]
+        return check2, check3
+
+    def free(self):
+        if self.handle:
+            _lib.fs_checks_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def fs_checks_generate(g, max_sweeps=0, stream=None):
+    h = P()
+    _check(_lib.fs_checks_generate(g.handle, max_sweeps, _stream(stream), ctypes.byref(h)), "fs_checks_generate")
+    return Checks(h)
+
+
+def fs_repair_local(g, ch, c, erased, lost, n_lost, repaired, status, t, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_repair_local(g.handle, ch.handle, _ptr(c), _ptr(erased), _ptr(lost), n_lost, _ptr(repaired),
+                                _ptr(status), t, w, wb, _stream(stream)), "fs_repair_local")
 
 
 def fs_sim_disks_precoded(g, pc, s, f, first, count, maxit, result, ws, stream=None):

@@ -29,6 +29,7 @@ SOURCES = [
     ("kernels.hip", DEVICE),
     ("simdisk.hip", DEVICE),
     ("precode.hip", DEVICE),
+    ("checks.hip", DEVICE),
     ("api.cpp", DEVICE),
     ("plan.cpp", DEVICE),
     ("graph_host.cpp", HOST),

@@ -182,6 +182,20 @@ void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, Upd
   b.delta = cv.take<uint8_t>((size_t)n_ids * t);
 }
 
+struct LocalBufs {
+  uint32_t *down;
+  int32_t *chosen, *item_ptr, *item_col, *flag;
+};
+
+// the XOR lists are bounded by n blocks per lost row
+void carve_local(Carver &cv, const fs_graph *g, uint32_t n_lost, LocalBufs &b) {
+  b.down = cv.take<uint32_t>((g->n + 31) / 32);
+  b.chosen = cv.take<int32_t>(std::max<uint32_t>(n_lost, 1));
+  b.item_ptr = cv.take<int32_t>((size_t)n_lost + 1);
+  b.item_col = cv.take<int32_t>(std::max<uint64_t>((uint64_t)n_lost * g->n, 1));
+  b.flag = cv.take<int32_t>(4);
+}
+
 struct PrecodeBufs {
   int32_t *status1, *pair_sym, *pair_chk, *level_ptr, *meta;
 };
@@ -254,6 +268,11 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
     case FS_OP_SIM_DISKS: {
       SimDiskJob j{};
       carve_simdisk(cv, g, n_items, j);
+      return cv.size();
+    }
+    case FS_OP_REPAIR_LOCAL: {
+      LocalBufs b;
+      carve_local(cv, g, n_items, b);
       return cv.size();
     }
     case FS_OP_DECODE_PRECODED: {
@@ -500,7 +519,7 @@ void fs_graph_free(fs_graph *g) {
 fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
-  if (op < FS_OP_ENCODE || op > FS_OP_DECODE_PRECODED) return fail(FS_ERR_INVALID, "unknown operation");
+  if (op < FS_OP_ENCODE || op > FS_OP_REPAIR_LOCAL) return fail(FS_ERR_INVALID, "unknown operation");
   if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_EXTEND_CONVENTIONAL || op == FS_OP_UPDATE) &&
       (t == 0 || (t & 15)))
     return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
@@ -1018,6 +1037,211 @@ fs_status fs_decode_precoded(const fs_graph *g, const fs_precode *pc, const void
   rj.level_ptr = b.level_ptr;
   rj.meta = b.meta;
   return launch_precode_replay(rj, stream);
+}
+
+fs_status fs_checks_generate(const fs_graph *g, uint32_t max_sweeps, hipStream_t stream, fs_checks **out) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  if (!out) return fail(FS_ERR_INVALID, "out is null");
+  *out = nullptr;
+  const uint32_t k = g->k, n = g->n, kw = (k + 31) / 32, nw = (n + 31) / 32;
+  const size_t b_bytes = 4ull * n * kw, l_bytes = 4ull * n * nw, w_bytes = 4ull * n;
+  const size_t o_l = (b_bytes + 255) & ~size_t(255), o_w = o_l + ((l_bytes + 255) & ~size_t(255)),
+               o_m = o_w + ((w_bytes + 255) & ~size_t(255)), total = o_m + 256;
+  void *scratch = nullptr;
+  if (hipMalloc(&scratch, total) != hipSuccess) return fail(FS_ERR_NOMEM, "device allocation for the checks failed");
+  uint8_t *base = static_cast<uint8_t *>(scratch);
+  CgaJob j{};
+  j.k = k;
+  j.n = n;
+  j.kw = kw;
+  j.nw = nw;
+  j.max_sweeps = max_sweeps;
+  j.row_ptr = g->d_row_ptr;
+  j.col = g->d_col;
+  j.bcol = reinterpret_cast<uint32_t *>(base);
+  j.lcol = reinterpret_cast<uint32_t *>(base + o_l);
+  j.w = reinterpret_cast<uint32_t *>(base + o_w);
+  j.meta = reinterpret_cast<int32_t *>(base + o_m);
+  std::vector<uint32_t> hb((size_t)n * kw), hl((size_t)n * nw), hw(n);
+  int32_t meta[2] = {0, 0};
+  fs_status st = run_cga(j, stream);
+  hipError_t e = hipSuccess;
+  if (st == FS_OK) {
+    e = hipMemcpyAsync(hb.data(), j.bcol, b_bytes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hl.data(), j.lcol, l_bytes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hw.data(), j.w, w_bytes, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(meta, j.meta, sizeof(meta), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  }
+  (void)hipFree(scratch);
+  if (st != FS_OK) return st;
+  if (e != hipSuccess) return fail(FS_ERR_HIP, std::string("check generation: ") + hipGetErrorString(e));
+  fs_checks *ch = new (std::nothrow) fs_checks();
+  if (!ch) return fail(FS_ERR_NOMEM, "host allocation failed");
+  ch->k = k;
+  ch->n = n;
+  ch->sweeps = (uint32_t)meta[0];
+  ch->zero_columns = (uint32_t)meta[1];
+  // check #3 groups (weight zero), smallest first, ties by column; check #2
+  // equations (weight one), the first column per input
+  struct Grp {
+    uint32_t size, col;
+  };
+  std::vector<Grp> groups;
+  std::vector<int32_t> c2_of(k, -1);
+  auto members = [&](uint32_t col, std::vector<int32_t> &dst) {
+    const uint32_t *l = hl.data() + (size_t)col * nw;
+    for (uint32_t q = 0; q < nw; ++q)
+      for (uint32_t x = l[q]; x; x &= x - 1) dst.push_back((int32_t)(32 * q + (uint32_t)__builtin_ctz(x)));
+  };
+  for (uint32_t c = 0; c < n; ++c) {
+    if (hw[c] == 0) {
+      uint32_t size = 0;
+      for (uint32_t q = 0; q < nw; ++q) size += (uint32_t)__builtin_popcount(hl[(size_t)c * nw + q]);
+      groups.push_back({size, c});
+    } else if (hw[c] == 1) {
+      const uint32_t *b = hb.data() + (size_t)c * kw;
+      for (uint32_t q = 0; q < kw; ++q)
+        if (b[q]) {
+          const uint32_t i = 32 * q + (uint32_t)__builtin_ctz(b[q]);
+          if (i < k && c2_of[i] < 0) c2_of[i] = (int32_t)c;
+          break;
+        }
+    }
+  }
+  std::stable_sort(groups.begin(), groups.end(), [](const Grp &a, const Grp &b) { return a.size < b.size; });
+  ch->grp_ptr.assign(1, 0);
+  for (const Grp &gr : groups) {
+    members(gr.col, ch->grp_col);
+    ch->grp_ptr.push_back((int32_t)ch->grp_col.size());
+    ch->max_group = std::max(ch->max_group, gr.size);
+  }
+  ch->c2_ptr.assign(1, 0);
+  for (uint32_t i = 0; i < k; ++i)
+    if (c2_of[i] >= 0) {
+      ch->c2_input.push_back((int32_t)i);
+      members((uint32_t)c2_of[i], ch->c2_col);
+      ch->c2_ptr.push_back((int32_t)ch->c2_col.size());
+    }
+  ch->sym_ptr.assign(n + 1, 0);
+  for (int32_t v : ch->grp_col) ++ch->sym_ptr[v + 1];
+  for (uint32_t u = 0; u < n; ++u) ch->sym_ptr[u + 1] += ch->sym_ptr[u];
+  ch->sym_grp.assign(ch->grp_col.size(), 0);
+  {
+    std::vector<int32_t> fill(ch->sym_ptr.begin(), ch->sym_ptr.end() - 1);
+    for (size_t q = 0; q + 1 < ch->grp_ptr.size(); ++q)
+      for (int32_t m = ch->grp_ptr[q]; m < ch->grp_ptr[q + 1]; ++m) ch->sym_grp[fill[ch->grp_col[m]]++] = (int32_t)q;
+  }
+  // device copies of the groups and their transpose
+  const std::vector<int32_t> *parts[4] = {&ch->grp_ptr, &ch->grp_col, &ch->sym_ptr, &ch->sym_grp};
+  size_t off[4], dtotal = 0;
+  for (int q = 0; q < 4; ++q) {
+    off[q] = dtotal;
+    dtotal += (std::max<size_t>(parts[q]->size(), 1) * sizeof(int32_t) + 255) & ~size_t(255);
+  }
+  (void)hipGetDevice(&ch->device);
+  void *dbase = nullptr;
+  if (hipMalloc(&dbase, dtotal) != hipSuccess) {
+    delete ch;
+    return fail(FS_ERR_NOMEM, "device allocation for the checks failed");
+  }
+  e = hipSuccess;
+  for (int q = 0; q < 4; ++q)
+    if (e == hipSuccess && !parts[q]->empty())
+      e = hipMemcpyAsync(static_cast<uint8_t *>(dbase) + off[q], parts[q]->data(), parts[q]->size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    (void)hipFree(dbase);
+    delete ch;
+    return fail(FS_ERR_HIP, std::string("checks upload: ") + hipGetErrorString(e));
+  }
+  ch->d_base = dbase;
+  const int32_t **dst[4] = {&ch->d_grp_ptr, &ch->d_grp_col, &ch->d_sym_ptr, &ch->d_sym_grp};
+  for (int q = 0; q < 4; ++q) *dst[q] = reinterpret_cast<const int32_t *>(static_cast<uint8_t *>(dbase) + off[q]);
+  *out = ch;
+  return FS_OK;
+}
+
+fs_status fs_checks_info(const fs_checks *ch, uint32_t *n_check2, uint32_t *n_check3, uint32_t *sweeps,
+                         uint32_t *zero_columns, uint64_t *check2_entries, uint64_t *check3_entries) {
+  clear_error();
+  if (!ch) return fail(FS_ERR_INVALID, "checks is null");
+  if (n_check2) *n_check2 = (uint32_t)ch->c2_input.size();
+  if (n_check3) *n_check3 = (uint32_t)(ch->grp_ptr.size() - 1);
+  if (sweeps) *sweeps = ch->sweeps;
+  if (zero_columns) *zero_columns = ch->zero_columns;
+  if (check2_entries) *check2_entries = ch->c2_col.size();
+  if (check3_entries) *check3_entries = ch->grp_col.size();
+  return FS_OK;
+}
+
+fs_status fs_checks_export(const fs_checks *ch, int32_t *c3_ptr, int32_t *c3_col, int32_t *c2_input, int32_t *c2_ptr,
+                           int32_t *c2_col) {
+  clear_error();
+  if (!ch || !c3_ptr || !c3_col || !c2_input || !c2_ptr || !c2_col)
+    return fail(FS_ERR_INVALID, "checks and every array must be non-null");
+  std::copy(ch->grp_ptr.begin(), ch->grp_ptr.end(), c3_ptr);
+  std::copy(ch->grp_col.begin(), ch->grp_col.end(), c3_col);
+  std::copy(ch->c2_input.begin(), ch->c2_input.end(), c2_input);
+  std::copy(ch->c2_ptr.begin(), ch->c2_ptr.end(), c2_ptr);
+  std::copy(ch->c2_col.begin(), ch->c2_col.end(), c2_col);
+  return FS_OK;
+}
+
+void fs_checks_free(fs_checks *ch) {
+  if (!ch) return;
+  if (ch->d_base) (void)hipFree(ch->d_base);
+  delete ch;
+}
+
+fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const uint8_t *erased, const uint32_t *lost,
+                          uint32_t n_lost, uint8_t *repaired, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  if (!ch || !ch->d_base) return fail(FS_ERR_INVALID, "checks is null");
+  if (ch->n != g->n || ch->k != g->k) return fail(FS_ERR_INVALID, "the checks belong to another graph shape");
+  FS_TRY(check_payload(c, t, "c"));
+  if ((n_lost && (!lost || !repaired)) || !status)
+    return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
+  FS_TRY(check_ws(g, FS_OP_REPAIR_LOCAL, t, n_lost, ws, ws_bytes));
+  Carver cv(ws);
+  LocalBufs b;
+  carve_local(cv, g, n_lost, b);
+  LocalPlanJob pj{};
+  pj.n = g->n;
+  pj.n_lost = n_lost;
+  pj.lost = lost;
+  pj.erased = erased;
+  pj.grp_ptr = ch->d_grp_ptr;
+  pj.grp_col = ch->d_grp_col;
+  pj.sym_ptr = ch->d_sym_ptr;
+  pj.sym_grp = ch->d_sym_grp;
+  pj.down = b.down;
+  pj.chosen = b.chosen;
+  pj.item_ptr = b.item_ptr;
+  pj.item_col = b.item_col;
+  pj.flag = b.flag;
+  pj.repaired = repaired;
+  pj.status = status;
+  FS_TRY(launch_local_plan(pj, stream));
+  if (n_lost == 0) return FS_OK;
+  GatherJob gj{};
+  gj.src = static_cast<const uint8_t *>(c);
+  gj.src_stride = t;
+  gj.dst = static_cast<uint8_t *>(c);
+  gj.dst_stride = t;
+  gj.ptr = b.item_ptr;
+  gj.idx = b.item_col;
+  gj.out_map = reinterpret_cast<const int32_t *>(lost);
+  gj.row_ok = repaired;
+  gj.skip_flag = b.flag;
+  gj.nrows = n_lost;
+  gj.csr_rows = n_lost;
+  gj.t = t;
+  return launch_gather(gj, tile_for(current_tune(), g), stream);
 }
 
 }  // extern "C"

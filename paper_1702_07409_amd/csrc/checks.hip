@@ -1,0 +1,238 @@
+// Check #2 / check #3 generation (CGA) and local-group repair for gfx950.
+//
+//   cga_setup_kernel   columns of B (the inputs of each coded block) and of
+//                      L (the identity) as bitsets, and their weights
+//   cga_kernel         one workgroup runs the sweeps in the exact order of
+//                      the algorithm: for column j it finds, among i = cursor
+//                      .. n-1 (i != j) in parallel, the first i with
+//                      2 w(b_j) > w(b_i) and w(b_j ^ b_i) < w(b_j), applies
+//                      it to b_j and l_j, and continues from i + 1.  Column
+//                      j is the only one that changes while it is processed,
+//                      so this visits the same (j, i) pairs as the sequential
+//                      loops and takes the same steps.
+//   local_plan_kernel  for each lost coded block the first check #3 group
+//                      holding it whose other members are all available;
+//                      writes the XOR lists the gather then runs.
+//
+// The bitsets live in a workspace the generation call allocates; the columns
+// of the workgroup's current j are copied to LDS.  Reads after a barrier of
+// what the same workgroup wrote before it are ordered by that barrier.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "fs_internal.h"
+
+namespace fs {
+
+namespace {
+
+constexpr int kCgaThreads = 1024;
+constexpr uint32_t kNoCol = 0xffffffffu;
+
+__global__ __launch_bounds__(256) void cga_setup_kernel(CgaJob J) {
+  const uint32_t j = blockIdx.x * 256u + threadIdx.x;
+  if (j >= J.n) return;
+  uint32_t *b = J.bcol + (size_t)j * J.kw;
+  uint32_t *l = J.lcol + (size_t)j * J.nw;
+  for (uint32_t q = 0; q < J.kw; ++q) b[q] = 0;
+  for (uint32_t q = 0; q < J.nw; ++q) l[q] = 0;
+  const int32_t lo = J.row_ptr[j], hi = J.row_ptr[j + 1];
+  for (int32_t e = lo; e < hi; ++e) {
+    const uint32_t i = (uint32_t)J.col[e];
+    b[i >> 5] |= 1u << (i & 31);
+  }
+  l[j >> 5] |= 1u << (j & 31);
+  J.w[j] = (uint32_t)(hi - lo);
+}
+
+__global__ __launch_bounds__(kCgaThreads) void cga_kernel(CgaJob J) {
+  extern __shared__ __align__(16) uint32_t cga_lds[];
+  uint32_t *bj = cga_lds;            // [kw]
+  uint32_t *lj = cga_lds + J.kw;     // [nw]
+  __shared__ uint32_t s_zero, s_best, s_bestw;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t n = J.n, k = J.k, kw = J.kw, nw = J.nw;
+  uint32_t sweeps = 0, zero = 0;
+  for (;;) {
+    __syncthreads();
+    if (tid == 0) s_zero = 0;
+    __syncthreads();
+    uint32_t cnt = 0;
+    for (uint32_t j = tid; j < n; j += nt) cnt += J.w[j] == 0 ? 1u : 0u;
+    if (cnt) atomicAdd(&s_zero, cnt);
+    __syncthreads();
+    zero = s_zero;
+    if (zero + k >= n || (J.max_sweeps && sweeps == J.max_sweeps)) break;
+    bool changed = false;
+    for (uint32_t j = 0; j < n; ++j) {
+      for (uint32_t q = tid; q < kw; q += nt) bj[q] = J.bcol[(size_t)j * kw + q];
+      for (uint32_t q = tid; q < nw; q += nt) lj[q] = J.lcol[(size_t)j * nw + q];
+      uint32_t wj = J.w[j];
+      __syncthreads();
+      uint32_t cursor = 0;
+      for (;;) {
+        // the first qualifying i >= cursor, one round of nt candidates at a time
+        uint32_t found = kNoCol, mine = kNoCol, minew = 0;
+        for (uint32_t base = cursor; base < n; base += nt) {
+          const uint32_t i = base + tid;
+          if (i < n && i != j) {
+            const uint32_t wi = J.w[i];
+            if (2 * wj > wi) {
+              const uint32_t *bi = J.bcol + (size_t)i * kw;
+              uint32_t x = 0;
+              for (uint32_t q = 0; q < kw; ++q) x += (uint32_t)__popc(bj[q] ^ bi[q]);
+              if (x < wj) {
+                mine = i;
+                minew = x;
+              }
+            }
+          }
+          __syncthreads();
+          if (tid == 0) s_best = kNoCol;
+          __syncthreads();
+          if (mine != kNoCol) atomicMin(&s_best, mine);
+          __syncthreads();
+          found = s_best;
+          if (found != kNoCol) break;
+        }
+        if (found == kNoCol) break;
+        if (mine == found) s_bestw = minew;
+        __syncthreads();
+        for (uint32_t q = tid; q < kw; q += nt) bj[q] ^= J.bcol[(size_t)found * kw + q];
+        for (uint32_t q = tid; q < nw; q += nt) lj[q] ^= J.lcol[(size_t)found * nw + q];
+        wj = s_bestw;
+        changed = true;
+        cursor = found + 1;
+        __syncthreads();
+      }
+      for (uint32_t q = tid; q < kw; q += nt) J.bcol[(size_t)j * kw + q] = bj[q];
+      for (uint32_t q = tid; q < nw; q += nt) J.lcol[(size_t)j * nw + q] = lj[q];
+      if (tid == 0) J.w[j] = wj;
+      __syncthreads();
+    }
+    ++sweeps;
+    if (!changed) {
+      // zero columns are unchanged since the count above
+      break;
+    }
+  }
+  if (tid == 0) {
+    J.meta[0] = (int32_t)sweeps;
+    J.meta[1] = (int32_t)zero;
+  }
+}
+
+// inclusive prefix sums of one value per thread (kCgaThreads threads)
+__device__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *sh) {
+  const uint32_t tid = threadIdx.x;
+  sh[tid] = v;
+  __syncthreads();
+  for (uint32_t o = 1; o < kCgaThreads; o <<= 1) {
+    const uint32_t add = tid >= o ? sh[tid - o] : 0u;
+    __syncthreads();
+    sh[tid] += add;
+    __syncthreads();
+  }
+  return sh[tid];
+}
+
+__global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J) {
+  __shared__ uint32_t s_bad, s_fail;
+  __shared__ uint32_t scan_sh[kCgaThreads];
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  const uint32_t nw = (J.n + 31) / 32;
+  if (tid == 0) {
+    s_bad = 0;
+    s_fail = 0;
+  }
+  for (uint32_t w = tid; w < nw; w += nt) J.down[w] = 0;
+  __syncthreads();
+  for (uint32_t r = tid; r < J.n_lost; r += nt) {
+    const uint32_t s = J.lost[r];
+    if (s >= J.n) {
+      atomicOr(&s_bad, 1u);
+      continue;
+    }
+    const uint32_t bit = 1u << (s & 31);
+    if (atomicOr(&J.down[s >> 5], bit) & bit) atomicOr(&s_bad, 1u);
+  }
+  if (J.erased)
+    for (uint32_t s = tid; s < J.n; s += nt)
+      if (J.erased[s]) atomicOr(&J.down[s >> 5], 1u << (s & 31));
+  __syncthreads();
+  const bool bad = s_bad != 0;
+  // each thread plans a contiguous run of lost blocks
+  const uint32_t per = (J.n_lost + nt - 1) / nt;
+  const uint32_t r0 = min(J.n_lost, tid * per), r1 = min(J.n_lost, r0 + per);
+  uint32_t total = 0;
+  for (uint32_t r = r0; r < r1; ++r) {
+    int32_t pick = -1;
+    if (!bad) {
+      const uint32_t s = J.lost[r];
+      for (int32_t e = J.sym_ptr[s]; e < J.sym_ptr[s + 1] && pick < 0; ++e) {
+        const int32_t g = J.sym_grp[e];
+        bool ok = true;
+        for (int32_t m = J.grp_ptr[g]; m < J.grp_ptr[g + 1] && ok; ++m) {
+          const uint32_t u = (uint32_t)J.grp_col[m];
+          if (u != s && ((J.down[u >> 5] >> (u & 31)) & 1u)) ok = false;
+        }
+        if (ok) pick = g;
+      }
+    }
+    J.chosen[r] = pick;
+    J.repaired[r] = pick >= 0 ? 1 : 0;
+    if (pick >= 0) total += (uint32_t)(J.grp_ptr[pick + 1] - J.grp_ptr[pick] - 1);
+    else atomicAdd(&s_fail, 1u);
+  }
+  const uint32_t incl = block_inclusive_scan(total, scan_sh);
+  uint32_t off = incl - total;
+  for (uint32_t r = r0; r < r1; ++r) {
+    J.item_ptr[r] = (int32_t)off;
+    const int32_t g = J.chosen[r];
+    if (g >= 0) {
+      const uint32_t s = J.lost[r];
+      for (int32_t m = J.grp_ptr[g]; m < J.grp_ptr[g + 1]; ++m)
+        if ((uint32_t)J.grp_col[m] != s) J.item_col[off++] = J.grp_col[m];
+    }
+  }
+  if (tid == nt - 1) J.item_ptr[J.n_lost] = (int32_t)incl;
+  __syncthreads();
+  if (tid == 0) {
+    J.flag[0] = bad ? FS_ERR_INVALID : 0;
+    J.status[0] = (!bad && s_fail == 0) ? 1 : 0;
+    J.status[1] = bad ? (int32_t)J.n_lost : (int32_t)s_fail;
+    J.status[2] = bad ? FS_ERR_INVALID : 0;
+  }
+  if (bad)
+    for (uint32_t r = tid; r < J.n_lost; r += nt) J.repaired[r] = 0;
+}
+
+fs_status ck_hip(hipError_t e, const char *what) {
+  if (e == hipSuccess) return FS_OK;
+  return fail(FS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+}  // namespace
+
+fs_status run_cga(const CgaJob &job, hipStream_t s) {
+  if (job.n == 0) return FS_OK;
+  hipLaunchKernelGGL(cga_setup_kernel, dim3((job.n + 255) / 256), dim3(256), 0, s, job);
+  const fs_status st = ck_hip(hipGetLastError(), "check generation setup launch");
+  if (st != FS_OK) return st;
+  const size_t lds = 4ull * (job.kw + job.nw);
+  const void *fn = reinterpret_cast<const void *>(&cga_kernel);
+  if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(cga_kernel, dim3(1), dim3(kCgaThreads), lds, s, job);
+  return ck_hip(hipGetLastError(), "check generation launch");
+}
+
+fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s) {
+  hipLaunchKernelGGL(local_plan_kernel, dim3(1), dim3(kCgaThreads), 0, s, job);
+  return ck_hip(hipGetLastError(), "local repair plan launch");
+}
+
+}  // namespace fs

@@ -45,6 +45,18 @@ struct fs_precode {
                 *d_sym_ptr = nullptr, *d_sym_chk = nullptr;
 };
 
+// Check #2 / check #3 equations of a graph (Algorithm 4) on the host and the
+// device.
+struct fs_checks {
+  uint32_t k = 0, n = 0, sweeps = 0, zero_columns = 0, max_group = 0;
+  std::vector<int32_t> grp_ptr, grp_col;          // check #3 groups, smallest first
+  std::vector<int32_t> c2_input, c2_ptr, c2_col;  // check #2: input and its coded blocks
+  std::vector<int32_t> sym_ptr, sym_grp;          // the groups of every coded block, in group order
+  int device = -1;
+  void *d_base = nullptr;
+  const int32_t *d_grp_ptr = nullptr, *d_grp_col = nullptr, *d_sym_ptr = nullptr, *d_sym_grp = nullptr;
+};
+
 namespace fs {
 
 constexpr uint32_t kSegMax = 64;
@@ -236,6 +248,31 @@ struct PrecodeReplayJob {
   const int32_t *chk_ptr, *chk_col, *pair_sym, *pair_chk, *level_ptr, *meta;
 };
 fs_status launch_precode_replay(const PrecodeReplayJob &job, hipStream_t s);
+
+// Check generation and local repair (checks.hip).
+struct CgaJob {
+  uint32_t k, n, kw, nw;     // 32-bit words per B column (k bits) and per L column (n bits)
+  uint32_t max_sweeps;       // 0: until converged or unchanged
+  const int32_t *row_ptr, *col;
+  uint32_t *bcol;            // [n][kw]
+  uint32_t *lcol;            // [n][nw]
+  uint32_t *w;               // [n] column weights of B
+  int32_t *meta;             // [2] sweeps, zero columns
+};
+fs_status run_cga(const CgaJob &job, hipStream_t s);
+struct LocalPlanJob {
+  uint32_t n, n_lost;
+  const uint32_t *lost;
+  const uint8_t *erased;     // may be null
+  const int32_t *grp_ptr, *grp_col, *sym_ptr, *sym_grp;
+  uint32_t *down;            // ws: [ceil(n / 32)] erased or lost
+  int32_t *chosen;           // ws: [n_lost] group per lost block, -1 none
+  int32_t *item_ptr, *item_col;   // ws: the blocks each repaired block is the XOR of
+  int32_t *flag;             // ws: non-zero = bad ids, nothing written
+  uint8_t *repaired;         // out [n_lost]
+  int32_t *status;           // out [3]
+};
+fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s);
 
 struct RepairCheckJob {
   const int32_t *row_ptr, *col;

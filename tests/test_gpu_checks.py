@@ -1,0 +1,116 @@
+"""GPU parity of check #2/#3 generation (Algorithm 4) and local-group repair:
+the equations equal the oracle's exactly, and repaired blocks equal the
+oracle's bit for bit.
+
+Run on an MI355X: pytest -m gpu.
+"""
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, empty_i32, empty_u8, graphs, host
+from oracle import checks, codec
+from synth import gen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.mark.parametrize("k,n,dist,seed", [(2, 3, "rsd", 1), (20, 30, "rsd", 1), (64, 96, "rsd", 1),
+                                           (200, 400, "raptor", 1), (100, 130, "raptor", 4)])
+def test_checks_equal_the_oracle(k, n, dist, seed):
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=k, n=n, dist=dist, seed=seed)
+    ch = fs.fs_checks_generate(g)
+    b, L, sweeps = checks.cga(G)
+    want2, want3 = checks.split(b, L)
+    got2, got3 = ch.export()
+    assert ch.sweeps == sweeps and ch.zero_columns == sum(1 for x in b if x == 0)
+    assert got3 == want3 and got2 == want2
+
+
+def test_sweep_limit():
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor", seed=2)
+    for m in (1, 2):
+        ch = fs.fs_checks_generate(g, max_sweeps=m)
+        b, L, sweeps = checks.cga(G, max_sweeps=m)
+        assert ch.sweeps == sweeps == m
+        assert ch.export() == tuple(checks.split(b, L))
+
+
+def test_paper_example_scale_identities():
+    # the paper's illustrative code size (k = 500, n = 1000): every check #3
+    # group XORs to zero and every check #2 equation gives its input, on
+    # encoded payloads; the groups equal the oracle's
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=500, n=1000, dist="raptor")
+    ch = fs.fs_checks_generate(g)
+    c2, c3 = ch.export()
+    assert ch.n_check3 == 500 and ch.n_check2 == 500
+    x = gen.payload(0, 13, 500, 32)
+    c = codec.encode(G, x)
+    for grp in c3:
+        assert not np.bitwise_xor.reduce(c[grp], axis=0).any()
+    for i, members in c2.items():
+        assert np.array_equal(np.bitwise_xor.reduce(c[members], axis=0), x[i])
+    b, L, _ = checks.cga(G)
+    assert (c2, c3) == checks.split(b, L)
+
+
+def local_case(g, G, ch, c3, lost, er, t, seed=0):
+    import paper_1702_07409_amd as fs
+    x = gen.payload(1, seed, G.k, t)
+    c_host = codec.encode(G, x)
+    want, ok, _ = checks.local_repair(c3, c_host, lost, er)
+    c = dev(c_host)
+    c[dev(np.array(lost, np.int64))] = 0x6D
+    rep, st = empty_u8(max(len(lost), 1)), empty_i32(3)
+    ws = fs.workspace(g, fs.FS_OP_REPAIR_LOCAL, t, len(lost))
+    fs.fs_repair_local(g, ch, c, dev(er) if er is not None else None, dev(np.array(lost, np.uint32)), len(lost),
+                       rep, st, t, ws)
+    got = host(c)
+    assert np.array_equal(host(rep)[:len(lost)], ok)
+    assert np.array_equal(got[lost], want)
+    others = [j for j in range(G.n) if j not in set(lost)]
+    assert np.array_equal(got[others], c_host[others])
+    assert host(st).tolist() == [int(ok.all()), int(len(lost) - ok.sum()), 0]
+    return ok
+
+
+def test_local_repair_random_losses():
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor")
+    ch = fs.fs_checks_generate(g)
+    _, c3 = ch.export()
+    rng = np.random.default_rng(7)
+    some, none_ = 0, 0
+    for trial in range(12):
+        lost = sorted(rng.choice(400, size=int(rng.integers(1, 9)), replace=False).tolist())
+        er = (rng.random(400) < 0.05).astype(np.uint8)
+        er[lost] = 0
+        ok = local_case(g, G, ch, c3, lost, er if trial % 2 else None, 512 * 3 + 16, trial)
+        some += int(ok.sum())
+        none_ += int(len(ok) - ok.sum())
+    assert some > 0
+
+
+def test_local_repair_rejects_bad_ids_without_writing():
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor")
+    ch = fs.fs_checks_generate(g)
+    x = gen.payload(1, 2, 200, 64)
+    c_host = codec.encode(G, x)
+    for lost in ([3, 400], [5, 9, 5]):
+        c = dev(c_host)
+        rep, st = empty_u8(len(lost)), empty_i32(3)
+        ws = fs.workspace(g, fs.FS_OP_REPAIR_LOCAL, 64, len(lost))
+        fs.fs_repair_local(g, ch, c, None, dev(np.array(lost, np.uint32)), len(lost), rep, st, 64, ws)
+        assert np.array_equal(host(c), c_host)
+        assert host(st).tolist() == [0, len(lost), fs._lib.FS_ERR_INVALID] and not host(rep).any()
