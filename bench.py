@@ -53,11 +53,13 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--workload", default="large_stripe",
-                    choices=["large_stripe", "batch512", "resident256", "serve", "extend", "simdisk", "precode", "all"],
+                    choices=["large_stripe", "batch512", "resident256", "serve", "extend", "simdisk", "precode", "checks",
+                             "all"],
                     help="large_stripe: plain one-stripe path (the headline line); batch512 / "
                          "resident256: batched plans vs the plain loop; serve: the request loop "
                          "on a Poisson mix; extend: code extension of the large stripe; simdisk: "
-                         "disk-failure sweeps; precode: Table 2's set-up with the precode; all: the "
+                         "disk-failure sweeps; precode: Table 2's set-up with the precode; checks: check "
+                         "generation and local-group repair of a lost disk; all: the "
                          "headline line with the others attached")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
@@ -124,9 +126,11 @@ def main():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
     torch.cuda.set_device(0)
-    if args.workload in ("batch512", "resident256", "serve", "extend", "simdisk", "precode"):
+    if args.workload in ("batch512", "resident256", "serve", "extend", "simdisk", "precode", "checks"):
         import bench_batch
-        if args.workload == "precode":
+        if args.workload == "checks":
+            res = bench_batch.run_checks()
+        elif args.workload == "precode":
             res = bench_batch.run_precode()
         elif args.workload == "extend":
             res = bench_batch.run_extend()
