@@ -52,7 +52,8 @@ class fs_graph_params(ctypes.Structure):
 class fs_tune(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
                 ("xcd_remap", ctypes.c_uint32), ("nt_store", ctypes.c_uint32),
-                ("replay_prog_global", ctypes.c_uint32), ("encode_slab", ctypes.c_uint32)]
+                ("replay_prog_global", ctypes.c_uint32), ("encode_slab", ctypes.c_uint32),
+                ("replay_lookahead", ctypes.c_uint32)]
 
 
 class fs_work(ctypes.Structure):
@@ -429,8 +430,9 @@ def fs_sim_disks(g, s, f, first, count, maxit, result, ws, stream=None):
            "fs_sim_disks")
 
 
-def fs_set_tune(lanes_per_row=0, chunks=0, xcd_remap=1, nt_store=1, replay_prog_global=0, encode_slab=1):
-    tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store, replay_prog_global, encode_slab)
+def fs_set_tune(lanes_per_row=0, chunks=0, xcd_remap=1, nt_store=1, replay_prog_global=0, encode_slab=1,
+                replay_lookahead=0):
+    tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store, replay_prog_global, encode_slab, replay_lookahead)
     _check(_lib.fs_set_tune(ctypes.byref(tu)), "fs_set_tune")
 
 
@@ -442,7 +444,8 @@ def fs_get_tune():
     tu = fs_tune()
     _check(_lib.fs_get_tune(ctypes.byref(tu)), "fs_get_tune")
     return dict(lanes_per_row=tu.lanes_per_row, chunks=tu.chunks, xcd_remap=tu.xcd_remap,
-                nt_store=tu.nt_store, replay_prog_global=tu.replay_prog_global, encode_slab=tu.encode_slab)
+                nt_store=tu.nt_store, replay_prog_global=tu.replay_prog_global, encode_slab=tu.encode_slab,
+                replay_lookahead=tu.replay_lookahead)
 
 
 FS_WORK_ENCODE, FS_WORK_DECODE, FS_WORK_REPAIR, FS_WORK_UPDATE = range(4)

@@ -37,7 +37,7 @@ const DeviceInfo &device_info(int dev) {
 
 namespace {
 std::mutex g_tune_mu;
-fs_tune g_tune = {0, 0, 1, 1, 0, 1};
+fs_tune g_tune = {0, 0, 1, 1, 0, 1, 0};
 
 }  // namespace
 
@@ -79,7 +79,8 @@ static bool tune_ok(const fs_tune &t) {
   const bool auto_tile = t.lanes_per_row == 0 && t.chunks == 0;
   const bool lpr = auto_tile || t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64;
   const bool ch = auto_tile || t.chunks == 1 || t.chunks == 2 || t.chunks == 4;
-  return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1 && t.encode_slab <= 1;
+  return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1 && t.encode_slab <= 1 &&
+         t.replay_lookahead <= 1;
 }
 
 // The device copy of a graph: nine arrays, each 256-byte aligned, in one buffer.
@@ -384,7 +385,7 @@ fs_status fs_set_tune(const fs_tune *tune) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_tune_mu);
   if (!tune) {
-    g_tune = fs_tune{0, 0, 1, 1, 0, 1};
+    g_tune = fs_tune{0, 0, 1, 1, 0, 1, 0};
     return FS_OK;
   }
   if (!tune_ok(*tune)) return fail(FS_ERR_INVALID, "tuning out of range");

@@ -166,8 +166,18 @@ struct ProgJob {
   int32_t *meta;       // int32[4]
   uint32_t pidx_cap;
   const int32_t *skip_flag;
+  // dependency-slab form of the program (graphs with k, n <= 65535): per
+  // input 2 + its slab slot when some pair reads it (la_slot); per pair a
+  // prefix count (la_pre) and a record {f, g, entries offset, 1 + slot of f}
+  // (la_pair); la_idx holds the slots of each pair's other inputs; la_meta =
+  // {usable, slots, largest level}
+  int32_t *la_slot, *la_pre, *la_idx, *la_meta;
+  int32_t *la_pair;    // int32[4 k]
 };
 void prog_carve(Carver &cv, ProgJob &p, uint64_t nnz);
+// whether launch_prog also builds the lookahead form for this graph
+bool prog_has_lookahead(const ProgJob &p);
+fs_status launch_prog_lookahead(const ProgJob &prog, hipStream_t s);
 
 // prog: workspace for the replay program (null: global-memory replay only).
 // launch_replay builds the program then replays; launch_prog and

@@ -363,7 +363,8 @@ __global__ __launch_bounds__(kSlabThreads) void slab_encode_kernel(GatherJob j, 
 
 // Lanes per slab row for k inputs (0: the slab does not apply).  Slices
 // narrower than 256 bytes (k > 512) read memory in pieces too short to
-// keep up with the gather, which wins there.
+// keep up with the gather, which wins there (the finite-degree k = 4096
+// stripe: 0.25 ms with 32-byte slices against 0.157 ms for the gather).
 int slab_lanes(uint32_t k) {
   for (int lps = 64; lps >= 16; lps /= 2)
     if ((uint64_t)k * lps <= kSlabEntries) return lps;
@@ -711,6 +712,8 @@ __device__ __forceinline__ void prog_body(const ProgJob &P) {
   constexpr int G = 8;
   const int tid = threadIdx.x;
   const int k = (int)P.k;
+  // the dependency-slab form is unusable until prog_lookahead_kernel says otherwise
+  if (tid == 0 && P.la_meta) P.la_meta[0] = 0;
   if (P.skip_flag && *P.skip_flag) {
     if (tid == 0) P.meta[3] = 0;
     return;
@@ -809,6 +812,91 @@ __device__ __forceinline__ void prog_body(const ProgJob &P) {
 __global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) { prog_body(P); }
 
 __global__ __launch_bounds__(kPlanThreads) void prog_batch_kernel(const ProgJob *jobs) { prog_body(jobs[blockIdx.x]); }
+
+// Dependency-slab form of a replay program (one workgroup, after
+// prog_body).  Every input that some pair reads (a dependency) gets its own
+// slot, numbered in decode order, in an LDS slab that the lookahead replay
+// keeps for the whole slice; the pair records then name slots only.  Per
+// pair q: {f, g, entries offset, 1 + slot of f (0: nobody reads f)}; la_idx
+// holds the slots of the pair's other inputs; la_meta = {usable, slots,
+// largest level}.  A schedule whose pairs read an input no pair decodes, or
+// whose level pointers do not run from 0 to nR, is marked unusable.
+__global__ __launch_bounds__(kPlanThreads) void prog_lookahead_kernel(ProgJob P) {
+  __shared__ uint32_t scan_sh[kPlanThreads / 64 + 1];
+  __shared__ int s_bad, s_max;
+  const int tid = threadIdx.x;
+  const int k = (int)P.k;
+  if ((P.skip_flag && *P.skip_flag) || !P.meta[3]) {
+    if (tid == 0) P.la_meta[0] = 0;
+    return;
+  }
+  const int nR = P.meta[0], L = P.meta[1];
+  if (tid == 0) {
+    s_bad = 0;
+    s_max = 0;
+  }
+  __syncthreads();
+  int mx = 0;
+  for (int l = tid; l <= L; l += kPlanThreads) {
+    const int v = P.level_ptr[l];
+    if (v < 0 || v > nR || (l == 0 && v != 0) || (l == L && v != nR) || (l < L && v > P.level_ptr[l + 1]))
+      atomicOr(&s_bad, 1);
+    else if (l < L)
+      mx = max(mx, P.level_ptr[l + 1] - v);
+  }
+  if (mx) atomicMax(&s_max, mx);
+  for (int i = tid; i < k; i += kPlanThreads) P.la_slot[i] = 0;
+  __syncthreads();
+  if (s_bad) {
+    if (tid == 0) P.la_meta[0] = 0;
+    return;
+  }
+  // mark the dependencies
+  for (int o = tid; o < P.meta[2]; o += kPlanThreads) {
+    const int i = P.pidx[o];
+    if ((uint32_t)i < (uint32_t)k) P.la_slot[i] = 1;
+  }
+  __syncthreads();
+  // number them in decode order (a contiguous run of pairs per thread)
+  const int cpt = (nR + kPlanThreads - 1) / kPlanThreads;
+  const int p0 = min(nR, tid * cpt), p1 = min(nR, p0 + cpt);
+  uint32_t cnt = 0;
+  for (int q = p0; q < p1; ++q) cnt += P.la_slot[P.dp_f[q]] != 0;
+  uint32_t marked;
+  uint32_t run = block_exclusive_scan<kPlanThreads>(cnt, scan_sh, marked);
+  for (int q = p0; q < p1; ++q) {
+    P.la_pre[q] = (int32_t)run;
+    run += P.la_slot[P.dp_f[q]] != 0;
+  }
+  __syncthreads();
+  for (int q = tid; q < nR; q += kPlanThreads) {
+    const int f = P.dp_f[q];
+    if (P.la_slot[f]) P.la_slot[f] = 2 + P.la_pre[q];   // 2 + slot until every pair is numbered
+  }
+  __syncthreads();
+  int bad = 0;
+  for (int o = tid; o < P.meta[2]; o += kPlanThreads) {
+    const int i = P.pidx[o];
+    const int v = (uint32_t)i < (uint32_t)k ? P.la_slot[i] : 0;
+    if (v < 2) bad = 1;   // read but never decoded
+    P.la_idx[o] = v - 2;
+  }
+  for (int q = tid; q < nR; q += kPlanThreads) {
+    const int f = P.dp_f[q];
+    int32_t *rec = P.la_pair + 4 * (size_t)q;
+    rec[0] = f;
+    rec[1] = P.dp_g[q];
+    rec[2] = P.poff[q];
+    rec[3] = P.la_slot[f] ? P.la_slot[f] - 1 : 0;
+  }
+  if (bad) atomicOr(&s_bad, 1);
+  __syncthreads();
+  if (tid == 0) {
+    P.la_meta[0] = s_bad ? 0 : 1;
+    P.la_meta[1] = (int32_t)marked;
+    P.la_meta[2] = s_max;
+  }
+}
 
 // One workgroup per CU walks byte slices of T = 16 LPS bytes.  For each slice
 // the k x T slab of x lives in LDS: x_f starts as c_{g(f)} (zero for the
@@ -1037,6 +1125,162 @@ template <int LPS>
 __global__ __launch_bounds__(kReplayThreads) __attribute__((amdgpu_waves_per_eu(LPS <= 16 ? 8 : 1)))
 void replay_wide_kernel(ReplayJob J, ProgJob P, uint32_t nslices, uint32_t lds_bytes, uint32_t prog_lds) {
   replay_wide_body<LPS>(J, P, nslices, lds_bytes, prog_lds, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// Lookahead replay with a dependency slab.  One workgroup per CU walks byte
+// slices of W = 16 lps bytes.  Every decoded input that a later pair reads
+// keeps its slice in an LDS slab slot for the whole slice, so a level
+// reads LDS only: x_f = c_g ^ (slab entries of g's other inputs), stored to
+// x and, when read later, to f's slot.  The coded blocks are the only loads;
+// each thread holds one pair per level and loads c_g PD steps ahead (steps
+// run level by level and continue into the workgroup's next slice), so a
+// level never waits on a round trip of its own.  Loads and stores go through
+// buffer resources: an absent operand has an offset past the end, which
+// reads zero and drops the store, so every step issues the same memory
+// instructions and the compiler keeps the later loads in flight.  lps is the
+// widest of 8, 4, 2, 1 whose slab fits LDS beside the 16-bit program; pairs
+// past 1024 / lps in a level load their block when they run.
+typedef __amdgpu_buffer_rsrc_t bufrsrc;
+constexpr uint32_t kBufOob = 0x80000000u;   // offsets at or past this read zero
+
+__device__ __forceinline__ bufrsrc make_rsrc(const uint8_t *p, uint64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(p), (short)0,
+                                           (int)(uint32_t)min<uint64_t>(bytes, (uint64_t)kBufOob - 1), 0x00020000);
+}
+
+__device__ __forceinline__ v4u bld16(bufrsrc r, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+}
+
+__device__ __forceinline__ void bst16(bufrsrc r, uint32_t off, v4u v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)off, 0, 0);
+}
+
+// byte offset of (block b, byte off) as a buffer offset; past the end reads
+// zero and drops stores
+__device__ __forceinline__ uint32_t boff(uint32_t b, uint64_t t, uint32_t off) {
+  const uint64_t o = (uint64_t)b * t + off;
+  return o < kBufOob ? (uint32_t)o : kBufOob;
+}
+
+// 16-bit program in LDS: lp[L+1], pf[nR], pg[nR], po[nR+1], ps[nR], pidx[total]
+__host__ __device__ inline size_t replay_la_prog_bytes(size_t L, size_t nR, size_t total) {
+  return ((2 * ((L + 1) + 4 * nR + 1 + total)) + 15) & ~size_t(15);
+}
+
+template <int PD>
+__global__ __launch_bounds__(kReplayThreads) void replay_la_kernel(ReplayJob J, ProgJob P, uint32_t lds_bytes) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  if (J.skip_flag && *J.skip_flag) return;
+  if (!P.meta[3]) return;
+  const int nR = P.meta[0], L = P.meta[1], total = P.meta[2];
+  const uint32_t k = J.k;
+  const uint64_t t = J.t;
+  const uint32_t vb = xcd_remap(blockIdx.x, gridDim.x), stride = gridDim.x;
+  const size_t progb = replay_la_prog_bytes(L, nR, total);
+  const int nslots = P.la_meta[1];
+  const bool usable = P.la_meta[0] && total <= 65535 && nslots >= 0 && nslots <= nR;
+  uint32_t lsh = 4;
+  for (uint32_t c = 3; c <= 3; --c)
+    if (usable && progb + (size_t)nslots * (16u << c) <= lds_bytes) {
+      lsh = c;
+      break;
+    }
+  const uint32_t lps = 1u << lsh, W = 16u * lps;
+  const uint32_t nslices = lsh < 4 ? (uint32_t)((t + W - 1) / W) : 0u;
+  const uint32_t nmine = vb < nslices ? (nslices - 1 - vb) / stride + 1 : 0u;
+  if (lsh == 4 || (uint64_t)nmine * (uint64_t)max(L, 1) >= (1ull << 31)) {
+    const uint32_t ns8 = (uint32_t)((t + 127) / 128);
+    replay_wide_body<8>(J, P, ns8, lds_bytes, 1u, vb, stride);
+    return;
+  }
+  uint16_t *q16 = reinterpret_cast<uint16_t *>(smem);
+  uint16_t *lp = q16; q16 += L + 1;
+  uint16_t *pf = q16; q16 += nR;
+  uint16_t *pg = q16; q16 += nR;
+  uint16_t *po = q16; q16 += nR + 1;
+  uint16_t *ps = q16; q16 += nR;
+  uint16_t *pidx = q16;
+  for (int i = threadIdx.x; i <= L; i += kReplayThreads) lp[i] = (uint16_t)min(max(J.level_ptr[i], 0), nR);
+  for (int i = threadIdx.x; i < nR; i += kReplayThreads) {
+    const int32_t *rec = P.la_pair + 4 * (size_t)i;
+    pf[i] = (uint16_t)rec[0];
+    pg[i] = (uint16_t)rec[1];
+    po[i] = (uint16_t)rec[2];
+    ps[i] = (uint16_t)rec[3];
+  }
+  if (threadIdx.x == 0) po[nR] = (uint16_t)total;
+  for (int i = threadIdx.x; i < total; i += kReplayThreads) pidx[i] = (uint16_t)P.la_idx[i];
+  v4u *slab = reinterpret_cast<v4u *>(smem + progb);
+  __syncthreads();
+
+  const uint32_t lane = threadIdx.x & (lps - 1), sym = threadIdx.x >> lsh;
+  const int NS = (int)(kReplayThreads >> lsh);
+  const v4u zero = {0u, 0u, 0u, 0u};
+  const bufrsrc rc = make_rsrc(J.c, (uint64_t)J.n * J.t);
+  const bufrsrc rx = make_rsrc(J.x, (uint64_t)J.k * J.t);
+  const uint32_t steps = nmine * (uint32_t)L;
+  // inputs no pair decodes are zero in every slice
+  auto zero_fill = [&](uint32_t off) {
+    if (off < t)
+      for (int q = nR + (int)sym; q < (int)k; q += NS) {
+        const int32_t f = J.dp_f[q];
+        if ((uint32_t)f < k) bst16(rx, boff((uint32_t)f, t, off), zero);
+      }
+  };
+  if (L == 0) {
+    for (uint32_t s = vb; s < nslices; s += stride) zero_fill(s * W + lane * 16u);
+    return;
+  }
+  // coded block of this thread's pair at step j (zero when there is none)
+  auto load_step = [&](uint32_t j) -> v4u {
+    const uint32_t jj = min(j, steps - 1);
+    const uint32_t sl = vb + stride * (jj / (uint32_t)L), l = jj % (uint32_t)L;
+    const uint32_t off = sl * W + lane * 16u;
+    const int q = (int)lp[l] + (int)sym;
+    const bool valid = j < steps && off < t && q < (int)lp[l + 1];
+    return bld16(rc, valid ? boff(pg[valid ? q : 0], t, off) : kBufOob);
+  };
+  v4u C[PD];
+#pragma unroll
+  for (int d = 0; d < PD; ++d) C[d] = load_step((uint32_t)d);
+  for (uint32_t j0 = 0; j0 < steps; j0 += PD) {
+#pragma unroll
+    for (int d = 0; d < PD; ++d) {
+      const uint32_t j = j0 + (uint32_t)d;
+      const v4u cur = C[d];
+      C[d] = load_step(j + PD);
+      const uint32_t jj = min(j, steps - 1);
+      const uint32_t sl = vb + stride * (jj / (uint32_t)L), l = jj % (uint32_t)L;
+      const uint32_t off = sl * W + lane * 16u;
+      const bool run = j < steps;
+      const bool live = run && off < t;
+      const int q0 = lp[l], q1 = lp[l + 1];
+      const int q = q0 + (int)sym;
+      const bool valid = live && q < q1;
+      v4u acc = cur;
+      const int qv = valid ? q : 0;
+      if (valid) {
+        const int o1 = po[qv + 1];
+        for (int o = po[qv]; o < o1; ++o) acc ^= slab[((uint32_t)pidx[o] << lsh) + lane];
+      }
+      const uint32_t f = pf[qv];
+      bst16(rx, valid && f < k ? boff(f, t, off) : kBufOob, acc);
+      const uint32_t s1 = ps[qv];
+      if (valid && s1) slab[((s1 - 1u) << lsh) + lane] = acc;
+      // pairs past one per thread: their block is loaded here
+      if (live)
+        for (int qq = q + NS; qq < q1; qq += NS) {
+          v4u a2 = bld16(rc, boff(pg[qq], t, off));
+          for (int o = po[qq]; o < po[qq + 1]; ++o) a2 ^= slab[((uint32_t)pidx[o] << lsh) + lane];
+          const uint32_t f2 = pf[qq];
+          bst16(rx, f2 < k ? boff(f2, t, off) : kBufOob, a2);
+          if (ps[qq]) slab[(((uint32_t)ps[qq] - 1u) << lsh) + lane] = a2;
+        }
+      if (run && l == 0) zero_fill(off);
+      __syncthreads();
+    }
+  }
 }
 
 // Replays of a batch: stripe i owns workgroups [wg_prefix[i], wg_prefix[i+1])
@@ -1425,6 +1669,19 @@ void prog_carve(Carver &cv, ProgJob &p, uint64_t nnz) {
   p.pidx = cv.take<int32_t>(nnz ? nnz : 1);
   p.meta = cv.take<int32_t>(4);
   p.pidx_cap = (uint32_t)(nnz ? nnz : 1);
+  if (p.k <= 65535 && p.n <= 65535) {
+    p.la_slot = cv.take<int32_t>(p.k);
+    p.la_pre = cv.take<int32_t>((size_t)p.k + 1);
+    p.la_idx = cv.take<int32_t>(nnz ? nnz : 1);
+    p.la_pair = cv.take<int32_t>(4ull * p.k);
+    p.la_meta = cv.take<int32_t>(4);
+  } else {
+    p.la_slot = p.la_pre = p.la_idx = p.la_pair = p.la_meta = nullptr;
+  }
+}
+
+bool prog_has_lookahead(const ProgJob &p) {
+  return p.k <= 65535 && p.n <= 65535 && p.la_meta != nullptr && p.la_pair != nullptr;
 }
 
 // LDS layout of the slab replay: the widest row slice (16 LPS bytes, LPS in
@@ -1475,7 +1732,31 @@ static hipError_t run_replay_lds_m(const ReplayJob &job, const ProgJob &prog, ui
 
 fs_status launch_prog(const ProgJob &prog, hipStream_t s) {
   FS_TRY_LAUNCH(prog_build, prog, s);
-  return FS_OK;
+  return launch_prog_lookahead(prog, s);
+}
+
+fs_status launch_prog_lookahead(const ProgJob &prog, hipStream_t s) {
+  if (!prog_has_lookahead(prog) || !tune_snapshot().replay_lookahead || tune_snapshot().replay_prog_global)
+    return FS_OK;
+  hipLaunchKernelGGL(prog_lookahead_kernel, dim3(1), dim3(kPlanThreads), 0, s, prog);
+  return hip_check(hipGetLastError(), "lookahead program launch");
+}
+
+// Lookahead replay: one workgroup per CU with the whole LDS (program and
+// dependency slab), coded blocks loaded eight steps ahead.
+template <int PD>
+static hipError_t run_replay_la(const ReplayJob &job, const ProgJob &prog, int budget, int dev, int cu,
+                                hipStream_t s) {
+  static bool done[64] = {false};
+  set_max_lds(reinterpret_cast<const void *>(&replay_la_kernel<PD>), dev, budget, done);
+  hipLaunchKernelGGL(replay_la_kernel<PD>, dim3(cu), dim3(kReplayThreads), budget, s, job, prog, (uint32_t)budget);
+  return hipGetLastError();
+}
+
+static bool use_lookahead(const ReplayJob &job, const ProgJob &prog) {
+  const fs_tune tu = tune_snapshot();
+  return tu.replay_lookahead && !tu.replay_prog_global && prog_has_lookahead(prog) &&
+         (uint64_t)job.n * job.t < kBufOob && (uint64_t)job.k * job.t < kBufOob;
 }
 
 fs_status launch_replay(const ReplayJob &job, const ProgJob *prog, hipStream_t s) {
@@ -1516,6 +1797,8 @@ fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStrea
       case 16: e = run_replay_lds_m<16>(job, *prog, mneed, nslices, grid, budget, dev, s); break;
       default: e = run_replay_lds_m<8>(job, *prog, mneed, nslices, grid, budget, dev, s); break;
     }
+  } else if (use_lookahead(job, *prog)) {
+    e = run_replay_la<8>(job, *prog, budget, dev, cu, s);
   } else {
     // large k: wide slices in global memory, about two workgroups per CU
     const uint64_t per = (job.t + 2ull * cu - 1) / (2ull * cu);

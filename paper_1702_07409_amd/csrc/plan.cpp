@@ -488,8 +488,10 @@ fs_status enqueue(fs_plan &P, hipStream_t s) {
   // replays[i] runs the program replay_progs[i] (built above for every decode)
   PL_TRY(launch_replay_batch(P.d_replays, P.d_replay_progs, P.d_rprefix, (uint32_t)P.replays.size(),
                              P.rprefix.back(), P.replay_lds, a));
-  for (size_t i = 0; i < P.solo_replays.size(); ++i)
+  for (size_t i = 0; i < P.solo_replays.size(); ++i) {
+    PL_TRY(launch_prog_lookahead(P.progs[P.solo_replay_prog[i]], a));
     PL_TRY(launch_replay_prog(P.solo_replays[i], &P.progs[P.solo_replay_prog[i]], a));
+  }
   // branch B: zeroing, checks, update planning, then the persistent gather
   PL_TRY(launch_zero_batch(P.d_zeros, (uint32_t)P.zeros.size(), P.zero_max_t, s));
   PL_TRY(launch_repair_prep_batch(P.d_rpreps, (uint32_t)P.rpreps.size(), s));

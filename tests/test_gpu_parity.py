@@ -280,6 +280,88 @@ def test_decode_wide_replay_program_placement(prog_global):
     assert got.status[0] == 1
 
 
+FIN16 = workloads.finite16_weights()
+LOOKAHEAD_CASES = {
+    # 1585 inputs in the dependency slab: 64-byte slices, at most 215 pairs a
+    # level (one per thread), ragged t (1072 = 16 slices + 48 bytes)
+    "prefetched": dict(stripe=6, k=2000, n=2600, t=1024 + 48, dist="finite", finite_w=FIN16, stripe_key=5,
+                       n_erased=50),
+    # 32-byte slices and a first level of 741 pairs: past 512 a level's pairs
+    # load their block when they run
+    "wide_levels": dict(stripe=6, k=3000, n=3600, t=2048 + 128 + 32, dist="finite",
+                        finite_w=tuple([0.3] + list(FIN16[1:])), stripe_key=5, n_erased=100),
+    # 342 slab inputs: 128-byte slices
+    "rsd": dict(stripe=7, k=2500, n=3000, t=4096 + 48, dist="rsd", stripe_key=6, n_erased=60),
+    # 3619 slab inputs and 15203 program entries: 16-byte slices, a level of
+    # 3339 pairs, no erasures
+    "degree_one_heavy": dict(stripe=4, k=4000, n=16000, t=800, dist="finite",
+                             finite_w=tuple([0.45] + [0.0] * 22 + [0.55]), stripe_key=2, n_erased=0),
+    # 9907 slab inputs do not fit LDS beside the program: the kernel runs the
+    # wide replay instead
+    "slab_too_large": dict(stripe=8, k=12000, n=13500, t=160, dist="finite", finite_w=FIN16, stripe_key=7,
+                           n_erased=300),
+}
+
+
+@pytest.mark.parametrize("lookahead", [1, 0])
+@pytest.mark.parametrize("case", sorted(LOOKAHEAD_CASES))
+def test_decode_lookahead_replay(case, lookahead):
+    # large k: the lookahead replay (coded blocks loaded steps ahead, the
+    # inputs later pairs read kept in an LDS slab) and the wide replay both
+    # equal the oracle
+    import paper_1702_07409_amd as fs
+    fs.fs_set_tune(replay_lookahead=lookahead)
+    try:
+        decode_case(workloads.StripeSpec(**LOOKAHEAD_CASES[case]))
+    finally:
+        fs.fs_reset_tune()
+
+
+@pytest.mark.parametrize("maxit", [1, 3, 7])
+def test_decode_lookahead_replay_maxit(maxit):
+    import paper_1702_07409_amd as fs
+    fs.fs_set_tune(replay_lookahead=1)
+    try:
+        decode_case(workloads.StripeSpec(**LOOKAHEAD_CASES["prefetched"]), maxit)
+    finally:
+        fs.fs_reset_tune()
+
+
+def test_decode_lookahead_replay_large_stripe():
+    # the full-size stripe through the lookahead replay (32-byte slices; the
+    # default wide replay is covered by the full-size test above)
+    import paper_1702_07409_amd as fs
+    fs.fs_set_tune(replay_lookahead=1)
+    try:
+        decode_case(workloads.large_stripe())
+    finally:
+        fs.fs_reset_tune()
+
+
+def test_decode_lookahead_plan_without_its_program():
+    # a plan made without the lookahead program, applied with the lookahead
+    # replay asked for: the kernel finds the program unusable and runs the
+    # wide replay
+    import paper_1702_07409_amd as fs
+    sp = workloads.StripeSpec(**LOOKAHEAD_CASES["rsd"])
+    g, G = spec_graphs(sp)
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    er = sp.erased_mask()
+    xo, reco, sto, _ = oracle_decode(G, c_host, er, 0)
+    ws = fs.workspace(g, fs.FS_OP_DECODE, sp.t)
+    rec, st = empty_u8(sp.k), empty_i32(3)
+    out = empty_u8((sp.k, sp.t))
+    fs.fs_decode_plan(g, dev(er), 0, rec, st, ws)
+    fs.fs_set_tune(replay_lookahead=1)
+    try:
+        fs.fs_decode_apply(g, dev(c_host), out, sp.t, ws)
+    finally:
+        fs.fs_reset_tune()
+    assert host(st).tolist() == list(sto)
+    assert np.array_equal(host(out), xo)
+
+
 def test_decode_wide_replay_with_more_than_65535_rows():
     # n > 65535: no 16-bit program, the replay reads its program from global memory
     sp = workloads.StripeSpec(stripe=5, k=2000, n=70000, t=32, dist="rsd", stripe_key=3, n_erased=7000)
