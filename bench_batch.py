@@ -390,35 +390,54 @@ def run_precode(reps=10):
     return out
 
 
-def _first_usable_group(groups, lost):
-    """Per lost block, the group local repair takes (the first one, smallest
-    first, holding it with no other member lost), or None."""
+def _local_reads(groups, lost):
+    """Coded blocks read by local repair (BP over the groups, the rule the
+    library applies): (blocks rebuilt, block reads, distinct surviving blocks
+    read, levels).  Bandwidth accounting for the report; the rebuilt count
+    and levels are checked against the library's status."""
     down = set(lost)
+    lost_set = set(lost)
     by_block = {}
     for q, grp in enumerate(groups):
         for m in grp:
             by_block.setdefault(m, []).append(q)
-    out = []
-    for s in lost:
-        pick = None
-        for q in by_block.get(s, ()):
-            if not any(m in down for m in groups[q] if m != s):
-                pick = q
-                break
-        out.append(pick)
-    return out
+    todo = list(lost)
+    rebuilt = reads = levels = 0
+    fetched = set()
+    while todo:
+        picks = []
+        for s in todo:
+            for q in by_block.get(s, ()):
+                if not any(m in down for m in groups[q] if m != s):
+                    picks.append((s, q))
+                    break
+        if not picks:
+            break
+        for s, q in picks:
+            reads += len(groups[q]) - 1
+            fetched.update(m for m in groups[q] if m not in lost_set)
+        for s, _ in picks:
+            down.discard(s)
+        rebuilt += len(picks)
+        done = {s for s, _ in picks}
+        todo = [s for s in todo if s not in done]
+        levels += 1
+    return rebuilt, reads, len(fetched), levels
 
 
 def run_checks(reps=10):
     """Check #2/#3 generation (Algorithm 4) and repair of one lost disk by
-    local groups against the conventional repair (decode, then re-encode).
+    local groups (BP over the check #3 groups) against the conventional
+    repair (decode, then re-encode).
 
     Codes: the paper's illustrative one (k=500, n=1000, t=512; §4) and Table
     2's smaller one (k=1036, n=2180) with a 64 MiB object, both Raptor Omega
     graphs striped over 10 disks; disk 0 (rows 0 .. n/10-1) is lost.  Repair
     bandwidth is the bytes of coded blocks read: for local repair the other
     members of each block's group, for the conventional repair the coded
-    blocks the decode uses (one per recovered input)."""
+    blocks the decode uses (one per recovered input).  bytes_read counts every
+    source of every XOR; bytes_transferred counts each surviving block once
+    (what a repair would fetch over the network, the paper's measure)."""
     import torch
     import paper_1702_07409_amd as fs
     import synth.gpu as sg
@@ -446,9 +465,9 @@ def run_checks(reps=10):
         t_loc = _time(lambda: fs.fs_repair_local(g, ch, c, None, lost, m, rep, st, t, ws_l), reps)
         n_loc = int(rep.sum().item())
         loc_ok = bool(torch.equal(c[:m][rep.bool()], c_ref[rep.bool()]))
-        picks = _first_usable_group(c3, lost_h.tolist())
-        loc_blocks = sum(len(c3[q]) - 1 for q in picks if q is not None)
-        assert sum(q is not None for q in picks) == n_loc
+        st_h = st.cpu().tolist()
+        n_acc, loc_blocks, loc_fetched, loc_levels = _local_reads(c3, lost_h.tolist())
+        assert n_acc == n_loc and loc_levels == st_h[2]
         # conventional repair of the same disk: decode from the other rows, re-encode
         rep2 = torch.empty(m, dtype=torch.uint8, device="cuda")
         st2 = torch.empty(3, dtype=torch.int32, device="cuda")
@@ -467,10 +486,11 @@ def run_checks(reps=10):
             "k": k, "n": n, "t": t, "object_bytes": k * t,
             "generate_ms": round(gen_ms, 2), "sweeps": ch.sweeps, "check2": ch.n_check2, "check3": ch.n_check3,
             "lost_blocks": m,
-            "local": {"ms": round(t_loc, 4), "repaired": n_loc, "exact": loc_ok,
-                      "bytes_read": loc_blocks * t, "mean_group_read": round(loc_blocks / max(n_loc, 1), 2)},
+            "local": {"ms": round(t_loc, 4), "repaired": n_loc, "levels": loc_levels, "exact": loc_ok,
+                      "bytes_read": loc_blocks * t, "bytes_transferred": loc_fetched * t,
+                      "mean_group_read": round(loc_blocks / max(n_loc, 1), 2)},
             "conventional": {"ms": round(t_conv, 4), "repaired": n_conv, "exact": conv_ok,
-                             "decode_recovered": n_rec, "bytes_read": n_rec * t},
+                             "decode_recovered": n_rec, "bytes_read": n_rec * t, "bytes_transferred": n_rec * t},
         })
         _progress("checks: k=%d n=%d generated in %.1f ms, local repair %d/%d in %.3f ms" %
                   (k, n, gen_ms, n_loc, m, t_loc))

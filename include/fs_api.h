@@ -376,15 +376,18 @@ FS_API fs_status fs_checks_export(const fs_checks *ch, int32_t *c3_ptr, int32_t 
 FS_API void fs_checks_free(fs_checks *ch);
 
 /*
- * Local-group repair, the repair engine's fast path (§2.7, §4): each lost
- * coded row s is rebuilt in place in c as the XOR of the other members of
- * the first (smallest) check #3 group holding s whose other members are
- * neither erased nor lost; rows without such a group are zero-filled and
- * left for fs_repair.  lost: device uint32[n_lost]; erased: device uint8[n]
- * or NULL.  repaired: device uint8[n_lost].  status: device int32[3] {all
- * rebuilt, rows not rebuilt, 0 or FS_ERR_INVALID for a bad lost id (>= n or
- * repeated; nothing is written)}.  ws: FS_OP_REPAIR_LOCAL bytes with
- * n_items = n_lost.
+ * Local-group repair, the repair engine's fast path (§2.7, §2.8, §4): BP
+ * over the check #3 groups.  At each level every lost coded row s still
+ * unknown is rebuilt in place in c as the XOR of the other members of the
+ * first (smallest) group holding s whose other members are all known:
+ * neither erased nor lost, or rebuilt at an earlier level.  The loop ends at
+ * a level that rebuilds nothing; rows left unknown are zero-filled for
+ * fs_repair.  lost: device uint32[n_lost]; erased: device uint8[n] or NULL.
+ * repaired: device uint8[n_lost].  status: device int32[3] {all rebuilt,
+ * rows not rebuilt, levels run}, or {0, n_lost, -FS_ERR_INVALID} for a bad
+ * lost id (>= n or repeated; then nothing is written).  ws:
+ * FS_OP_REPAIR_LOCAL bytes with n_items = n_lost.  FS_ERR_UNSUPPORTED for
+ * codes of more than 786432 rows.
  */
 FS_API fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c,
                           const uint8_t *erased, const uint32_t *lost, uint32_t n_lost,

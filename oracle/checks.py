@@ -17,11 +17,14 @@ Functions and the passage each follows
                  column.
   set_xor        §2.5, Eqs. (1)-(4): check #3 groups from a check #1 group
                  and the check #2 sets of its members (symmetric difference).
-  local_repair   the repair engine's fast path (§2.7, §4): each lost coded
-                 block is the XOR of the other members of the first (smallest)
-                 check #3 group holding it whose other members are all
-                 available; lost blocks without such a group are left for
-                 the conventional repair.
+  local_repair   the repair engine's fast path (§2.7, §2.8, §4): BP over the
+                 check #3 groups.  At each level every lost coded block
+                 still unknown is rebuilt as the XOR of the other members of
+                 the first (smallest) group holding it whose other members
+                 are all known (neither erased nor lost, or rebuilt at an
+                 earlier level); the loop ends when a level rebuilds
+                 nothing.  Blocks left unknown are for the conventional
+                 repair.
 
 Readings:
   * Columns are bitsets of the k inputs; w() is their number of ones.  The
@@ -29,9 +32,12 @@ Readings:
     current b_j (it changes inside the i loop).
   * zero_columns counts the zero columns (the text's "nonzero" contradicts
     the loop bound n - k).
-  * Local repair takes groups in the stored order (smallest first) and uses
-    only blocks that are neither erased nor lost; a block repaired in the same
-    call is not reused (one pass).
+  * Local repair takes groups in the stored order (smallest first).  The
+    repair engine searches the local sets for one unknown in a loop, as BP
+    does (§2.8); here the loop is level-synchronous: a block rebuilt at level
+    l becomes known for level l + 1.  The set of blocks rebuilt at the end
+    does not depend on the order (it is the closure of the one-unknown
+    rule); the group chosen per block does.
 """
 
 import numpy as np
@@ -99,27 +105,41 @@ def set_xor(sets):
     return sorted(acc)
 
 
-def local_repair(groups, c, lost, erased=None):
-    """Returns (blocks[len(lost), t], repaired[len(lost)], group used per lost
-    block or -1)."""
+def local_repair(groups, c, lost, erased=None, max_levels=0):
+    """Returns (blocks[len(lost), t], repaired[len(lost)], group used per
+    lost block or -1, level per lost block or -1, levels run).  max_levels
+    > 0 stops after that many levels."""
     n, t = c.shape
-    unavailable = np.zeros(n, dtype=bool)
+    lost = [int(s) for s in lost]
+    known = np.ones(n, dtype=bool)
     if erased is not None:
-        unavailable |= np.asarray(erased, dtype=bool)
-    unavailable[list(lost)] = True
+        known &= ~np.asarray(erased, dtype=bool)
+    known[lost] = False
+    work = np.array(c, dtype=np.uint8, copy=True)
     out = np.zeros((len(lost), t), dtype=np.uint8)
     ok = np.zeros(len(lost), dtype=np.uint8)
     used = np.full(len(lost), -1, dtype=np.int64)
-    for r, s in enumerate(lost):
-        for gi, grp in enumerate(groups):
-            if s not in grp:
+    level_of = np.full(len(lost), -1, dtype=np.int64)
+    levels = 0
+    while not ok.all() and (max_levels == 0 or levels < max_levels):
+        picks = []
+        for r, s in enumerate(lost):
+            if ok[r]:
                 continue
-            others = [m for m in grp if m != s]
-            if any(unavailable[m] for m in others):
-                continue
-            acc = np.zeros(t, dtype=np.uint8)
-            for m in others:
-                acc ^= c[m]
-            out[r], ok[r], used[r] = acc, 1, gi
+            for gi, grp in enumerate(groups):
+                if s in grp and all(known[m] for m in grp if m != s):
+                    picks.append((r, gi))
+                    break
+        if not picks:
             break
-    return out, ok, used
+        for r, gi in picks:
+            acc = np.zeros(t, dtype=np.uint8)
+            for m in groups[gi]:
+                if m != lost[r]:
+                    acc ^= work[m]
+            out[r], ok[r], used[r], level_of[r] = acc, 1, gi, levels
+        for r, _ in picks:
+            known[lost[r]] = True
+            work[lost[r]] = out[r]
+        levels += 1
+    return out, ok, used, level_of, levels

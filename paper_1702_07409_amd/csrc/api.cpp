@@ -184,16 +184,20 @@ void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, Upd
 }
 
 struct LocalBufs {
-  uint32_t *down;
-  int32_t *chosen, *item_ptr, *item_col, *flag;
+  int32_t *chosen, *level, *pos, *item_ptr, *item_col, *item_dst, *lvl_ptr, *meta, *flag;
 };
 
 // the XOR lists are bounded by n blocks per lost row
 void carve_local(Carver &cv, const fs_graph *g, uint32_t n_lost, LocalBufs &b) {
-  b.down = cv.take<uint32_t>((g->n + 31) / 32);
-  b.chosen = cv.take<int32_t>(std::max<uint32_t>(n_lost, 1));
+  const size_t m = std::max<uint32_t>(n_lost, 1);
+  b.chosen = cv.take<int32_t>(m);
+  b.level = cv.take<int32_t>(m);
+  b.pos = cv.take<int32_t>(m);
   b.item_ptr = cv.take<int32_t>((size_t)n_lost + 1);
   b.item_col = cv.take<int32_t>(std::max<uint64_t>((uint64_t)n_lost * g->n, 1));
+  b.item_dst = cv.take<int32_t>(m);
+  b.lvl_ptr = cv.take<int32_t>((size_t)n_lost + 2);
+  b.meta = cv.take<int32_t>(4);
   b.flag = cv.take<int32_t>(4);
 }
 
@@ -1204,6 +1208,7 @@ fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const
   FS_TRY(check_graph(g));
   if (!ch || !ch->d_base) return fail(FS_ERR_INVALID, "checks is null");
   if (ch->n != g->n || ch->k != g->k) return fail(FS_ERR_INVALID, "the checks belong to another graph shape");
+  if (g->n > kLocalMaxN) return fail(FS_ERR_UNSUPPORTED, "local repair plans codes of at most 786432 blocks");
   FS_TRY(check_payload(c, t, "c"));
   if ((n_lost && (!lost || !repaired)) || !status)
     return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
@@ -1220,29 +1225,20 @@ fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const
   pj.grp_col = ch->d_grp_col;
   pj.sym_ptr = ch->d_sym_ptr;
   pj.sym_grp = ch->d_sym_grp;
-  pj.down = b.down;
   pj.chosen = b.chosen;
+  pj.level = b.level;
+  pj.pos = b.pos;
   pj.item_ptr = b.item_ptr;
   pj.item_col = b.item_col;
+  pj.item_dst = b.item_dst;
+  pj.lvl_ptr = b.lvl_ptr;
+  pj.meta = b.meta;
   pj.flag = b.flag;
   pj.repaired = repaired;
   pj.status = status;
   FS_TRY(launch_local_plan(pj, stream));
   if (n_lost == 0) return FS_OK;
-  GatherJob gj{};
-  gj.src = static_cast<const uint8_t *>(c);
-  gj.src_stride = t;
-  gj.dst = static_cast<uint8_t *>(c);
-  gj.dst_stride = t;
-  gj.ptr = b.item_ptr;
-  gj.idx = b.item_col;
-  gj.out_map = reinterpret_cast<const int32_t *>(lost);
-  gj.row_ok = repaired;
-  gj.skip_flag = b.flag;
-  gj.nrows = n_lost;
-  gj.csr_rows = n_lost;
-  gj.t = t;
-  return launch_gather(gj, tile_for(current_tune(), g), stream);
+  return launch_local_apply(pj, static_cast<uint8_t *>(c), t, stream);
 }
 
 }  // extern "C"

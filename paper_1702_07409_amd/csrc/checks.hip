@@ -10,9 +10,12 @@
 //                      j is the only one that changes while it is processed,
 //                      so this visits the same (j, i) pairs as the sequential
 //                      loops and takes the same steps.
-//   local_plan_kernel  for each lost coded block the first check #3 group
-//                      holding it whose other members are all available;
-//                      writes the XOR lists the gather then runs.
+//   local_plan_kernel  BP over the check #3 groups: level by level, each lost
+//                      coded block still unknown takes the first group
+//                      holding it whose other members are all known; writes
+//                      the XOR lists in level order
+//   local_apply_kernel rebuilds the blocks level by level, one workgroup per
+//                      256-byte slice of every block
 //
 // The bitsets live in a workspace the generation call allocates; the columns
 // of the workgroup's current j are copied to LDS.  Reads after a barrier of
@@ -29,6 +32,8 @@
 namespace fs {
 
 namespace {
+
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
 
 constexpr int kCgaThreads = 1024;
 constexpr uint32_t kNoCol = 0xffffffffu;
@@ -140,75 +145,169 @@ __device__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *sh) {
   return sh[tid];
 }
 
+// BP over the check #3 groups.  The unknown blocks (erased or lost) are a
+// bitset in LDS.  At each level every lost block still unknown takes the
+// first group on its list whose other members are all known; after a
+// barrier the blocks taken become known, and the loop ends at a level that
+// takes none.  The items are then laid out level by level (blocks in lost
+// order within a level, the unrebuilt ones last with no sources).
 __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J) {
-  __shared__ uint32_t s_bad, s_fail;
+  extern __shared__ uint32_t down[];   // [ceil(n / 32)]
+  __shared__ uint32_t s_bad, s_picked, s_fail;
   __shared__ uint32_t scan_sh[kCgaThreads];
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t nw = (J.n + 31) / 32;
+  const uint32_t nw = (J.n + 31) / 32, m = J.n_lost;
   if (tid == 0) {
     s_bad = 0;
     s_fail = 0;
   }
-  for (uint32_t w = tid; w < nw; w += nt) J.down[w] = 0;
+  for (uint32_t w = tid; w < nw; w += nt) down[w] = 0;
   __syncthreads();
-  for (uint32_t r = tid; r < J.n_lost; r += nt) {
+  for (uint32_t r = tid; r < m; r += nt) {
     const uint32_t s = J.lost[r];
     if (s >= J.n) {
       atomicOr(&s_bad, 1u);
       continue;
     }
     const uint32_t bit = 1u << (s & 31);
-    if (atomicOr(&J.down[s >> 5], bit) & bit) atomicOr(&s_bad, 1u);
+    if (atomicOr(&down[s >> 5], bit) & bit) atomicOr(&s_bad, 1u);
   }
   if (J.erased)
     for (uint32_t s = tid; s < J.n; s += nt)
-      if (J.erased[s]) atomicOr(&J.down[s >> 5], 1u << (s & 31));
+      if (J.erased[s]) atomicOr(&down[s >> 5], 1u << (s & 31));
   __syncthreads();
-  const bool bad = s_bad != 0;
-  // each thread plans a contiguous run of lost blocks
-  const uint32_t per = (J.n_lost + nt - 1) / nt;
-  const uint32_t r0 = min(J.n_lost, tid * per), r1 = min(J.n_lost, r0 + per);
-  uint32_t total = 0;
-  for (uint32_t r = r0; r < r1; ++r) {
-    int32_t pick = -1;
-    if (!bad) {
+  if (s_bad) {
+    for (uint32_t r = tid; r < m; r += nt) J.repaired[r] = 0;
+    if (tid == 0) {
+      J.flag[0] = FS_ERR_INVALID;
+      J.status[0] = 0;
+      J.status[1] = (int32_t)m;
+      J.status[2] = -FS_ERR_INVALID;
+    }
+    return;
+  }
+  for (uint32_t r = tid; r < m; r += nt) {
+    J.chosen[r] = -1;
+    J.level[r] = -1;
+  }
+  int level = 0;
+  for (;;) {
+    if (tid == 0) s_picked = 0;
+    __syncthreads();
+    uint32_t cnt = 0;
+    for (uint32_t r = tid; r < m; r += nt) {
+      if (J.level[r] >= 0) continue;
       const uint32_t s = J.lost[r];
+      int32_t pick = -1;
       for (int32_t e = J.sym_ptr[s]; e < J.sym_ptr[s + 1] && pick < 0; ++e) {
         const int32_t g = J.sym_grp[e];
         bool ok = true;
-        for (int32_t m = J.grp_ptr[g]; m < J.grp_ptr[g + 1] && ok; ++m) {
-          const uint32_t u = (uint32_t)J.grp_col[m];
-          if (u != s && ((J.down[u >> 5] >> (u & 31)) & 1u)) ok = false;
+        for (int32_t q = J.grp_ptr[g]; q < J.grp_ptr[g + 1] && ok; ++q) {
+          const uint32_t u = (uint32_t)J.grp_col[q];
+          if (u != s && ((down[u >> 5] >> (u & 31)) & 1u)) ok = false;
         }
         if (ok) pick = g;
       }
+      if (pick >= 0) {
+        J.chosen[r] = pick;
+        J.level[r] = level;
+        ++cnt;
+      }
     }
-    J.chosen[r] = pick;
-    J.repaired[r] = pick >= 0 ? 1 : 0;
-    if (pick >= 0) total += (uint32_t)(J.grp_ptr[pick + 1] - J.grp_ptr[pick] - 1);
-    else atomicAdd(&s_fail, 1u);
+    if (cnt) atomicAdd(&s_picked, cnt);
+    __syncthreads();
+    if (s_picked == 0) break;
+    // the blocks rebuilt at this level are known from the next one on
+    for (uint32_t r = tid; r < m; r += nt)
+      if (J.level[r] == level) {
+        const uint32_t s = J.lost[r];
+        atomicAnd(&down[s >> 5], ~(1u << (s & 31)));
+      }
+    ++level;
+    __syncthreads();
   }
-  const uint32_t incl = block_inclusive_scan(total, scan_sh);
-  uint32_t off = incl - total;
+  // level order: a contiguous run of lost blocks per thread, one scan per
+  // level (the unrebuilt blocks form the last one)
+  const uint32_t per = (m + nt - 1) / nt;
+  const uint32_t r0 = min(m, tid * per), r1 = min(m, r0 + per);
+  uint32_t base = 0;
+  for (int l = 0; l <= level; ++l) {
+    const int want = l < level ? l : -1;
+    uint32_t c = 0;
+    for (uint32_t r = r0; r < r1; ++r) c += J.level[r] == want;
+    const uint32_t incl = block_inclusive_scan(c, scan_sh);
+    const uint32_t tot = scan_sh[nt - 1];
+    uint32_t p = base + incl - c;
+    for (uint32_t r = r0; r < r1; ++r)
+      if (J.level[r] == want) J.pos[r] = (int32_t)p++;
+    if (tid == 0) J.lvl_ptr[l] = (int32_t)base;
+    base += tot;
+    __syncthreads();
+  }
+  if (tid == 0) J.lvl_ptr[level + 1] = (int32_t)m;
+  // sources per item (at the item's place), then their offsets by a scan
+  // over item places, each thread rewriting only its own run of places
+  uint32_t fail = 0;
   for (uint32_t r = r0; r < r1; ++r) {
-    J.item_ptr[r] = (int32_t)off;
     const int32_t g = J.chosen[r];
-    if (g >= 0) {
-      const uint32_t s = J.lost[r];
-      for (int32_t m = J.grp_ptr[g]; m < J.grp_ptr[g + 1]; ++m)
-        if ((uint32_t)J.grp_col[m] != s) J.item_col[off++] = J.grp_col[m];
-    }
+    J.item_ptr[J.pos[r]] = g >= 0 ? J.grp_ptr[g + 1] - J.grp_ptr[g] - 1 : 0;
+    J.item_dst[J.pos[r]] = (int32_t)J.lost[r];
+    J.repaired[r] = g >= 0 ? 1 : 0;
+    fail += g < 0;
   }
-  if (tid == nt - 1) J.item_ptr[J.n_lost] = (int32_t)incl;
+  if (fail) atomicAdd(&s_fail, fail);
   __syncthreads();
-  if (tid == 0) {
-    J.flag[0] = bad ? FS_ERR_INVALID : 0;
-    J.status[0] = (!bad && s_fail == 0) ? 1 : 0;
-    J.status[1] = bad ? (int32_t)J.n_lost : (int32_t)s_fail;
-    J.status[2] = bad ? FS_ERR_INVALID : 0;
+  uint32_t c = 0;
+  for (uint32_t p = r0; p < r1; ++p) c += (uint32_t)J.item_ptr[p];
+  const uint32_t incl = block_inclusive_scan(c, scan_sh);
+  uint32_t off = incl - c;
+  for (uint32_t p = r0; p < r1; ++p) {
+    const uint32_t sz = (uint32_t)J.item_ptr[p];
+    J.item_ptr[p] = (int32_t)off;
+    off += sz;
   }
-  if (bad)
-    for (uint32_t r = tid; r < J.n_lost; r += nt) J.repaired[r] = 0;
+  if (tid == nt - 1) J.item_ptr[m] = (int32_t)incl;
+  __syncthreads();
+  for (uint32_t r = r0; r < r1; ++r) {
+    const int32_t g = J.chosen[r];
+    if (g < 0) continue;
+    const uint32_t s = J.lost[r];
+    int32_t o = J.item_ptr[J.pos[r]];
+    for (int32_t q = J.grp_ptr[g]; q < J.grp_ptr[g + 1]; ++q)
+      if ((uint32_t)J.grp_col[q] != s) J.item_col[o++] = J.grp_col[q];
+  }
+  if (tid == 0) {
+    J.flag[0] = 0;
+    J.meta[0] = level;
+    J.status[0] = s_fail == 0 ? 1 : 0;
+    J.status[1] = (int32_t)s_fail;
+    J.status[2] = level;
+  }
+}
+
+// One workgroup per 256-byte slice of every block walks the levels: sixteen
+// items at a time, sixteen lanes each, XOR their sources and store the
+// result; a barrier between levels orders a level's stores before the next
+// level's loads (blocks rebuilt earlier are sources later).
+__global__ __launch_bounds__(256) void local_apply_kernel(LocalPlanJob J, uint8_t *c, uint64_t t) {
+  if (J.flag[0]) return;
+  const int levels = J.meta[0];
+  const uint32_t lane = threadIdx.x & 15u, it = threadIdx.x >> 4;
+  const uint64_t off = (uint64_t)blockIdx.x * 256u + lane * 16u;
+  const bool live = off < t;
+  const v4u zero = {0u, 0u, 0u, 0u};
+  for (int l = 0; l <= levels; ++l) {
+    const int p1 = J.lvl_ptr[l + 1];
+    if (live)
+      for (int p = J.lvl_ptr[l] + (int)it; p < p1; p += 16) {
+        v4u acc = zero;
+        const int e1 = J.item_ptr[p + 1];
+        for (int e = J.item_ptr[p]; e < e1; ++e)
+          acc ^= *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
+        *reinterpret_cast<v4u *>(c + (uint64_t)(uint32_t)J.item_dst[p] * t + off) = acc;
+      }
+    __syncthreads();
+  }
 }
 
 fs_status ck_hip(hipError_t e, const char *what) {
@@ -231,8 +330,19 @@ fs_status run_cga(const CgaJob &job, hipStream_t s) {
 }
 
 fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s) {
-  hipLaunchKernelGGL(local_plan_kernel, dim3(1), dim3(kCgaThreads), 0, s, job);
+  const size_t lds = 4ull * ((job.n + 31) / 32);
+  const void *fn = reinterpret_cast<const void *>(&local_plan_kernel);
+  if (lds > 32 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(local_plan_kernel, dim3(1), dim3(kCgaThreads), lds, s, job);
   return ck_hip(hipGetLastError(), "local repair plan launch");
+}
+
+fs_status launch_local_apply(const LocalPlanJob &plan, uint8_t *c, uint64_t t, hipStream_t s) {
+  const uint64_t nslices = (t + 255) / 256;
+  if (nslices == 0) return FS_OK;
+  if (nslices > 0x7fffffffull) return fail(FS_ERR_UNSUPPORTED, "block too large for the local repair");
+  hipLaunchKernelGGL(local_apply_kernel, dim3((uint32_t)nslices), dim3(256), 0, s, plan, c, t);
+  return ck_hip(hipGetLastError(), "local repair launch");
 }
 
 }  // namespace fs

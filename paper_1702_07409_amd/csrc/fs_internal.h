@@ -275,14 +275,23 @@ struct LocalPlanJob {
   const uint32_t *lost;
   const uint8_t *erased;     // may be null
   const int32_t *grp_ptr, *grp_col, *sym_ptr, *sym_grp;
-  uint32_t *down;            // ws: [ceil(n / 32)] erased or lost
   int32_t *chosen;           // ws: [n_lost] group per lost block, -1 none
-  int32_t *item_ptr, *item_col;   // ws: the blocks each repaired block is the XOR of
+  int32_t *level;            // ws: [n_lost] BP level that rebuilds it, -1 none
+  int32_t *pos;              // ws: [n_lost] its place in level order
+  // ws: items in level order (unrebuilt blocks last, with no sources): the
+  // blocks item p is the XOR of, item_col[item_ptr[p] .. item_ptr[p+1]),
+  // its destination item_dst[p]; items of level l at [lvl_ptr[l], lvl_ptr[l+1])
+  int32_t *item_ptr, *item_col, *item_dst, *lvl_ptr;
+  int32_t *meta;             // ws: [4] {levels}
   int32_t *flag;             // ws: non-zero = bad ids, nothing written
   uint8_t *repaired;         // out [n_lost]
   int32_t *status;           // out [3]
 };
 fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s);
+// the rebuild of the lost blocks in c, level by level, from a local plan
+fs_status launch_local_apply(const LocalPlanJob &plan, uint8_t *c, uint64_t t, hipStream_t s);
+// the largest n local repair plans for (its unknown-block bitset sits in LDS)
+constexpr uint32_t kLocalMaxN = 786432;
 
 struct RepairCheckJob {
   const int32_t *row_ptr, *col;

@@ -68,7 +68,7 @@ def local_case(g, G, ch, c3, lost, er, t, seed=0):
     import paper_1702_07409_amd as fs
     x = gen.payload(1, seed, G.k, t)
     c_host = codec.encode(G, x)
-    want, ok, _ = checks.local_repair(c3, c_host, lost, er)
+    want, ok, _, _, levels = checks.local_repair(c3, c_host, lost, er)
     c = dev(c_host)
     c[dev(np.array(lost, np.int64))] = 0x6D
     rep, st = empty_u8(max(len(lost), 1)), empty_i32(3)
@@ -80,8 +80,8 @@ def local_case(g, G, ch, c3, lost, er, t, seed=0):
     assert np.array_equal(got[lost], want)
     others = [j for j in range(G.n) if j not in set(lost)]
     assert np.array_equal(got[others], c_host[others])
-    assert host(st).tolist() == [int(ok.all()), int(len(lost) - ok.sum()), 0]
-    return ok
+    assert host(st).tolist() == [int(ok.all()), int(len(lost) - ok.sum()), levels]
+    return ok, levels
 
 
 def test_local_repair_random_losses():
@@ -90,15 +90,35 @@ def test_local_repair_random_losses():
     ch = fs.fs_checks_generate(g)
     _, c3 = ch.export()
     rng = np.random.default_rng(7)
-    some, none_ = 0, 0
+    some = 0
     for trial in range(12):
         lost = sorted(rng.choice(400, size=int(rng.integers(1, 9)), replace=False).tolist())
         er = (rng.random(400) < 0.05).astype(np.uint8)
         er[lost] = 0
-        ok = local_case(g, G, ch, c3, lost, er if trial % 2 else None, 512 * 3 + 16, trial)
+        ok, _ = local_case(g, G, ch, c3, lost, er if trial % 2 else None, 512 * 3 + 16, trial)
         some += int(ok.sum())
-        none_ += int(len(ok) - ok.sum())
     assert some > 0
+
+
+@pytest.mark.parametrize("disk", [0, 3])
+def test_local_repair_of_a_whole_disk_takes_several_levels(disk):
+    # a tenth of the rows lost at once: blocks rebuilt at one level complete
+    # the groups of others at the next
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor")
+    ch = fs.fs_checks_generate(g)
+    _, c3 = ch.export()
+    lost = list(range(disk * 40, disk * 40 + 40))
+    ok, levels = local_case(g, G, ch, c3, lost, None, 256 + 48, disk)
+    assert levels >= 2 and ok.sum() > 0
+
+
+def test_local_repair_nothing_lost():
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor")
+    ch = fs.fs_checks_generate(g)
+    _, c3 = ch.export()
+    local_case(g, G, ch, c3, [], None, 64)
 
 
 def test_local_repair_rejects_bad_ids_without_writing():
@@ -113,4 +133,4 @@ def test_local_repair_rejects_bad_ids_without_writing():
         ws = fs.workspace(g, fs.FS_OP_REPAIR_LOCAL, 64, len(lost))
         fs.fs_repair_local(g, ch, c, None, dev(np.array(lost, np.uint32)), len(lost), rep, st, 64, ws)
         assert np.array_equal(host(c), c_host)
-        assert host(st).tolist() == [0, len(lost), fs._lib.FS_ERR_INVALID] and not host(rep).any()
+        assert host(st).tolist() == [0, len(lost), -fs._lib.FS_ERR_INVALID] and not host(rep).any()

@@ -81,21 +81,71 @@ def test_checks_hold_on_payloads():
         assert not acc.any()
 
 
+def _usable(grp, s, known):
+    return s in grp and not [m for m in grp if m != s and not known[m]]
+
+
 def test_local_repair_against_brute_force():
+    # each level's choice is checked against a direct search of the groups
+    # usable with what is known at that level
     G = G_of(40, 70, seed=2)
     x = gen.payload(0, 6, 40, 16)
     c = codec.encode(G, x)
     _, check3 = checks.split(*checks.cga(G)[:2])
     rng = np.random.default_rng(3)
-    for trial in range(30):
-        lost = sorted(rng.choice(70, size=int(rng.integers(1, 6)), replace=False).tolist())
+    deeper = 0
+    for trial in range(40):
+        lost = sorted(rng.choice(70, size=int(rng.integers(1, 12)), replace=False).tolist())
         er = (rng.random(70) < 0.1).astype(np.uint8)
         er[lost] = 0
-        out, ok, used = checks.local_repair(check3, c, lost, er)
-        down = set(lost) | set(np.flatnonzero(er).tolist())
+        out, ok, used, lev, levels = checks.local_repair(check3, c, lost, er)
+        known0 = np.ones(70, dtype=bool)
+        known0[np.flatnonzero(er)] = False
+        known0[lost] = False
+        for l in range(levels + 1):
+            known = known0.copy()
+            for r, s in enumerate(lost):
+                if ok[r] and lev[r] < l:
+                    known[s] = True
+            for r, s in enumerate(lost):
+                usable = [q for q, grp in enumerate(check3) if _usable(grp, s, known)]
+                if ok[r] and lev[r] == l:
+                    # the first group usable at this level, and none before it
+                    assert used[r] == usable[0] and np.array_equal(out[r], c[s])
+                elif not ok[r] or lev[r] > l:
+                    # unknown at this level: nothing usable yet (else it would be rebuilt here)
+                    assert not usable or (ok[r] and lev[r] == l)
         for r, s in enumerate(lost):
-            usable = [q for q, grp in enumerate(check3) if s in grp and not (set(grp) - {s}) & down]
-            if usable:
-                assert ok[r] == 1 and used[r] == usable[0] and np.array_equal(out[r], c[s])
-            else:
-                assert ok[r] == 0 and used[r] == -1 and not out[r].any()
+            if not ok[r]:
+                assert used[r] == -1 and lev[r] == -1 and not out[r].any()
+        deeper += int(levels > 1)
+    assert deeper > 0
+
+
+def test_local_repair_closure_is_order_independent():
+    # the rebuilt set equals that of a queue-driven sequential search in any
+    # order (the closure of the one-unknown rule), and the one-level run is
+    # the first step of it
+    G = G_of(60, 110, seed=5, dist="raptor")
+    x = gen.payload(0, 8, 60, 16)
+    c = codec.encode(G, x)
+    _, check3 = checks.split(*checks.cga(G)[:2])
+    rng = np.random.default_rng(11)
+    for trial in range(25):
+        lost = sorted(rng.choice(110, size=int(rng.integers(2, 30)), replace=False).tolist())
+        _, ok, _, _, levels = checks.local_repair(check3, c, lost)
+        known = np.ones(110, dtype=bool)
+        known[lost] = False
+        todo = list(lost)
+        rng.shuffle(todo)
+        progress = True
+        while progress:
+            progress = False
+            for s in list(todo):
+                if any(_usable(grp, s, known) for grp in check3):
+                    known[s] = True
+                    todo.remove(s)
+                    progress = True
+        assert sorted(set(lost) - set(todo)) == [s for r, s in enumerate(lost) if ok[r]]
+        _, ok1, _, lev1, levels1 = checks.local_repair(check3, c, lost, max_levels=1)
+        assert levels1 == min(levels, 1) and set(np.flatnonzero(ok1)) == set(np.flatnonzero(lev1 == 0))
