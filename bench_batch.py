@@ -430,9 +430,11 @@ def run_checks(reps=10):
     local groups (BP over the check #3 groups) against the conventional
     repair (decode, then re-encode).
 
-    Codes: the paper's illustrative one (k=500, n=1000, t=512; §4) and Table
-    2's smaller one (k=1036, n=2180) with a 64 MiB object, both Raptor Omega
-    graphs striped over 10 disks; disk 0 (rows 0 .. n/10-1) is lost.  Repair
+    Codes, Raptor Omega graphs striped over 10 disks: the paper's
+    illustrative one (k=500, n=1000, t=512; §4) and Table 2's smaller one
+    (k=1036, n=2180, a 64 MiB object) with disk 0 (rows 0 .. n/10-1) lost;
+    the §5 repair case (k=10246, n=21800, 10240-byte blocks: 100 MiB) with
+    disks 0 and 1 lost.  Repair
     bandwidth is the bytes of coded blocks read: for local repair the other
     members of each block's group, for the conventional repair the coded
     blocks the decode uses (one per recovered input).  bytes_read counts every
@@ -443,7 +445,7 @@ def run_checks(reps=10):
     import synth.gpu as sg
 
     out = {"workload": "checks", "disks": 10, "codes": []}
-    for k, n, t in ((500, 1000, 512), (1036, 2180, 65536)):
+    for k, n, t, disks in ((500, 1000, 512, 1), (1036, 2180, 65536, 1), (10246, 21800, 10240, 2)):
         g = fs.fs_graph_build(k=k, n=n, dist="raptor", seed=1)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -455,7 +457,7 @@ def run_checks(reps=10):
         sg.fill(x, 0, 0, t)
         c = torch.empty((n, t), dtype=torch.uint8, device="cuda")
         fs.fs_encode(g, x, c, t)
-        lost_h = np.arange(0, n // 10, dtype=np.uint32)
+        lost_h = np.arange(0, disks * n // 10, dtype=np.uint32)
         m = len(lost_h)
         lost = torch.from_numpy(lost_h).cuda()
         c_ref = c[:m].clone()
@@ -485,7 +487,7 @@ def run_checks(reps=10):
         out["codes"].append({
             "k": k, "n": n, "t": t, "object_bytes": k * t,
             "generate_ms": round(gen_ms, 2), "sweeps": ch.sweeps, "check2": ch.n_check2, "check3": ch.n_check3,
-            "lost_blocks": m,
+            "disks_lost": disks, "lost_blocks": m,
             "local": {"ms": round(t_loc, 4), "repaired": n_loc, "levels": loc_levels, "exact": loc_ok,
                       "bytes_read": loc_blocks * t, "bytes_transferred": loc_fetched * t,
                       "mean_group_read": round(loc_blocks / max(n_loc, 1), 2)},

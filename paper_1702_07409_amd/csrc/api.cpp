@@ -1050,9 +1050,12 @@ fs_status fs_checks_generate(const fs_graph *g, uint32_t max_sweeps, hipStream_t
   if (!out) return fail(FS_ERR_INVALID, "out is null");
   *out = nullptr;
   const uint32_t k = g->k, n = g->n, kw = (k + 31) / 32, nw = (n + 31) / 32;
-  const size_t b_bytes = 4ull * n * kw, l_bytes = 4ull * n * nw, w_bytes = 4ull * n;
+  const size_t b_bytes = 4ull * n * kw, l_bytes = 4ull * n * nw, w_bytes = 4ull * n, r_bytes = 4ull * k * nw;
   const size_t o_l = (b_bytes + 255) & ~size_t(255), o_w = o_l + ((l_bytes + 255) & ~size_t(255)),
-               o_m = o_w + ((w_bytes + 255) & ~size_t(255)), total = o_m + 256;
+               o_r = o_w + ((w_bytes + 255) & ~size_t(255)), o_m = o_r + ((r_bytes + 255) & ~size_t(255)),
+               total = o_m + 256;
+  if (4ull * (kw + nw + g->max_deg) + 64 > 160ull * 1024)
+    return fail(FS_ERR_UNSUPPORTED, "check generation keeps a column of B and of L in LDS: k + n too large");
   void *scratch = nullptr;
   if (hipMalloc(&scratch, total) != hipSuccess) return fail(FS_ERR_NOMEM, "device allocation for the checks failed");
   uint8_t *base = static_cast<uint8_t *>(scratch);
@@ -1062,11 +1065,15 @@ fs_status fs_checks_generate(const fs_graph *g, uint32_t max_sweeps, hipStream_t
   j.kw = kw;
   j.nw = nw;
   j.max_sweeps = max_sweeps;
+  j.max_w = g->max_deg;
   j.row_ptr = g->d_row_ptr;
   j.col = g->d_col;
+  j.col_ptr = g->d_col_ptr;
+  j.rowidx = g->d_rowidx;
   j.bcol = reinterpret_cast<uint32_t *>(base);
   j.lcol = reinterpret_cast<uint32_t *>(base + o_l);
   j.w = reinterpret_cast<uint32_t *>(base + o_w);
+  j.rrow = reinterpret_cast<uint32_t *>(base + o_r);
   j.meta = reinterpret_cast<int32_t *>(base + o_m);
   std::vector<uint32_t> hb((size_t)n * kw), hl((size_t)n * nw), hw(n);
   int32_t meta[2] = {0, 0};

@@ -2,6 +2,7 @@
 //
 //   cga_setup_kernel   columns of B (the inputs of each coded block) and of
 //                      L (the identity) as bitsets, and their weights
+//   cga_rows_kernel    rows of B as bitsets (the columns holding each input)
 //   cga_kernel         one workgroup runs the sweeps in the exact order of
 //                      the algorithm: for column j it finds, among i = cursor
 //                      .. n-1 (i != j) in parallel, the first i with
@@ -54,11 +55,33 @@ __global__ __launch_bounds__(256) void cga_setup_kernel(CgaJob J) {
   J.w[j] = (uint32_t)(hi - lo);
 }
 
+// Rows of B: R_r holds the columns whose coded block has input r (from the
+// graph's column lists), one thread per input.
+__global__ __launch_bounds__(256) void cga_rows_kernel(CgaJob J) {
+  const uint32_t r = blockIdx.x * 256u + threadIdx.x;
+  if (r >= J.k) return;
+  uint32_t *row = J.rrow + (size_t)r * J.nw;
+  for (uint32_t q = 0; q < J.nw; ++q) row[q] = 0;
+  for (int32_t e = J.col_ptr[r]; e < J.col_ptr[r + 1]; ++e) {
+    const uint32_t j = (uint32_t)J.rowidx[e];
+    row[j >> 5] |= 1u << (j & 31);
+  }
+}
+
+// The sweeps of Algorithm 4 in their sequential order, on one workgroup.
+// For column j the next i (from the cursor on) must satisfy 2 w_j > w_i and
+// w(b_j ^ b_i) < w_j; since w(b_j ^ b_i) = w_j + w_i - 2 |b_j & b_i|, the
+// second test is w_i < 2 |b_j & b_i|, so only columns sharing an input with
+// b_j can pass.  Those are found from the rows of b_j's inputs: per 32
+// columns, the OR of those rows' words names the candidates and a count
+// over them gives |b_j & b_i|; a block minimum picks the first passing i.
+// b_j ^= b_i then also flips column j in the rows of b_i's inputs.
 __global__ __launch_bounds__(kCgaThreads) void cga_kernel(CgaJob J) {
   extern __shared__ __align__(16) uint32_t cga_lds[];
-  uint32_t *bj = cga_lds;            // [kw]
-  uint32_t *lj = cga_lds + J.kw;     // [nw]
-  __shared__ uint32_t s_zero, s_best, s_bestw;
+  uint32_t *bj = cga_lds;                 // [kw]
+  uint32_t *lj = cga_lds + J.kw;          // [nw]
+  uint32_t *sj = cga_lds + J.kw + J.nw;   // [max_w] inputs of b_j
+  __shared__ uint32_t s_zero, s_best, s_bestw, s_cnt;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
   const uint32_t n = J.n, k = J.k, kw = J.kw, nw = J.nw;
   uint32_t sweeps = 0, zero = 0;
@@ -77,42 +100,67 @@ __global__ __launch_bounds__(kCgaThreads) void cga_kernel(CgaJob J) {
       for (uint32_t q = tid; q < kw; q += nt) bj[q] = J.bcol[(size_t)j * kw + q];
       for (uint32_t q = tid; q < nw; q += nt) lj[q] = J.lcol[(size_t)j * nw + q];
       uint32_t wj = J.w[j];
-      __syncthreads();
       uint32_t cursor = 0;
       for (;;) {
-        // the first qualifying i >= cursor, one round of nt candidates at a time
-        uint32_t found = kNoCol, mine = kNoCol, minew = 0;
-        for (uint32_t base = cursor; base < n; base += nt) {
-          const uint32_t i = base + tid;
-          if (i < n && i != j) {
-            const uint32_t wi = J.w[i];
-            if (2 * wj > wi) {
-              const uint32_t *bi = J.bcol + (size_t)i * kw;
-              uint32_t x = 0;
-              for (uint32_t q = 0; q < kw; ++q) x += (uint32_t)__popc(bj[q] ^ bi[q]);
-              if (x < wj) {
-                mine = i;
-                minew = x;
-              }
+        // the inputs of b_j (their order does not matter)
+        if (tid == 0) {
+          s_cnt = 0;
+          s_best = kNoCol;
+        }
+        __syncthreads();
+        for (uint32_t q = tid; q < kw; q += nt) {
+          uint32_t x = bj[q];
+          if (x) {
+            uint32_t at = atomicAdd(&s_cnt, (uint32_t)__popc(x));
+            for (; x; x &= x - 1) {
+              if (at < J.max_w) sj[at] = 32u * q + (uint32_t)__ffs(x) - 1u;
+              ++at;
             }
           }
-          __syncthreads();
-          if (tid == 0) s_best = kNoCol;
-          __syncthreads();
-          if (mine != kNoCol) atomicMin(&s_best, mine);
-          __syncthreads();
-          found = s_best;
-          if (found != kNoCol) break;
         }
+        __syncthreads();
+        const uint32_t m = min(s_cnt, J.max_w);
+        // each thread scans its words in increasing order; its first passing
+        // column is its smallest
+        uint32_t mine = kNoCol, minew = 0;
+        for (uint32_t q = (cursor >> 5) + tid; q < nw && mine == kNoCol; q += nt) {
+          uint32_t cand = 0;
+          for (uint32_t e = 0; e < m; ++e) cand |= J.rrow[(size_t)sj[e] * nw + q];
+          if (q == (cursor >> 5)) cand &= ~0u << (cursor & 31);
+          if (q == (j >> 5)) cand &= ~(1u << (j & 31));
+          for (; cand; cand &= cand - 1) {
+            const uint32_t bit = (uint32_t)__ffs(cand) - 1u, i = 32u * q + bit;
+            if (i >= n) break;
+            const uint32_t wi = J.w[i];
+            if (!(2 * wj > wi)) continue;
+            uint32_t both = 0;
+            for (uint32_t e = 0; e < m; ++e) both += (J.rrow[(size_t)sj[e] * nw + q] >> bit) & 1u;
+            if (wi < 2 * both) {
+              mine = i;
+              minew = wj + wi - 2 * both;
+              break;
+            }
+          }
+        }
+        if (mine != kNoCol) atomicMin(&s_best, mine);
+        __syncthreads();
+        const uint32_t found = s_best;
         if (found == kNoCol) break;
         if (mine == found) s_bestw = minew;
-        __syncthreads();
-        for (uint32_t q = tid; q < kw; q += nt) bj[q] ^= J.bcol[(size_t)found * kw + q];
+        // b_j ^= b_found (flipping column j in the rows of b_found's inputs), l_j ^= l_found
+        for (uint32_t q = tid; q < kw; q += nt) {
+          const uint32_t x = J.bcol[(size_t)found * kw + q];
+          bj[q] ^= x;
+          for (uint32_t y = x; y; y &= y - 1) {
+            const uint32_t r = 32u * q + (uint32_t)__ffs(y) - 1u;
+            J.rrow[(size_t)r * nw + (j >> 5)] ^= 1u << (j & 31);
+          }
+        }
         for (uint32_t q = tid; q < nw; q += nt) lj[q] ^= J.lcol[(size_t)found * nw + q];
+        __syncthreads();
         wj = s_bestw;
         changed = true;
         cursor = found + 1;
-        __syncthreads();
       }
       for (uint32_t q = tid; q < kw; q += nt) J.bcol[(size_t)j * kw + q] = bj[q];
       for (uint32_t q = tid; q < nw; q += nt) J.lcol[(size_t)j * nw + q] = lj[q];
@@ -320,9 +368,12 @@ fs_status ck_hip(hipError_t e, const char *what) {
 fs_status run_cga(const CgaJob &job, hipStream_t s) {
   if (job.n == 0) return FS_OK;
   hipLaunchKernelGGL(cga_setup_kernel, dim3((job.n + 255) / 256), dim3(256), 0, s, job);
-  const fs_status st = ck_hip(hipGetLastError(), "check generation setup launch");
+  fs_status st = ck_hip(hipGetLastError(), "check generation setup launch");
   if (st != FS_OK) return st;
-  const size_t lds = 4ull * (job.kw + job.nw);
+  hipLaunchKernelGGL(cga_rows_kernel, dim3((job.k + 255) / 256), dim3(256), 0, s, job);
+  st = ck_hip(hipGetLastError(), "check generation rows launch");
+  if (st != FS_OK) return st;
+  const size_t lds = 4ull * (job.kw + job.nw + job.max_w);
   const void *fn = reinterpret_cast<const void *>(&cga_kernel);
   if (lds > 64 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(cga_kernel, dim3(1), dim3(kCgaThreads), lds, s, job);

@@ -263,9 +263,11 @@ fs_status launch_precode_replay(const PrecodeReplayJob &job, hipStream_t s);
 struct CgaJob {
   uint32_t k, n, kw, nw;     // 32-bit words per B column (k bits) and per L column (n bits)
   uint32_t max_sweeps;       // 0: until converged or unchanged
-  const int32_t *row_ptr, *col;
+  uint32_t max_w;            // largest column weight of B (its largest row degree)
+  const int32_t *row_ptr, *col, *col_ptr, *rowidx;
   uint32_t *bcol;            // [n][kw]
   uint32_t *lcol;            // [n][nw]
+  uint32_t *rrow;            // [k][nw] rows of B: the columns holding each input
   uint32_t *w;               // [n] column weights of B
   int32_t *meta;             // [2] sweeps, zero columns
 };
