@@ -325,6 +325,7 @@ PeelJob peel_job(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8
   j.level_ptr = level_ptr;
   j.dp_f = dp_f;
   j.dp_g = dp_g;
+  j.nnz = g->nnz;
   return j;
 }
 
@@ -623,8 +624,7 @@ fs_status fs_decode_plan(const fs_graph *g, const uint8_t *erased, uint32_t maxi
   j.dlist = b.peel.dlist;
   j.mask = b.peel.mask;
   j.decmask = b.peel.decmask;
-  FS_TRY(launch_peel(j, stream, g->max_deg));
-  FS_TRY(launch_prog(b.prog, stream));
+  FS_TRY(launch_plan(j, b.prog, stream, g->max_deg));
   if (status) {
     const hipError_t e = hipMemcpyAsync(status, b.sched.status, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice, stream);
     if (e != hipSuccess) return fail(FS_ERR_HIP, std::string("status copy: ") + hipGetErrorString(e));

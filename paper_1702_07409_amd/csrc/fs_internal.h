@@ -136,6 +136,7 @@ struct PeelJob {
   int32_t *front_a, *front_b, *dlist;
   uint32_t *mask, *decmask;
   const int32_t *skip_flag;  // non-zero: write status only
+  uint64_t nnz;              // edges (0: unknown; the compact all-LDS variant needs it)
 };
 
 size_t peel_ws_bytes(uint32_t k, uint32_t n);
@@ -185,6 +186,8 @@ fs_status launch_prog_lookahead(const ProgJob &prog, hipStream_t s);
 fs_status launch_replay(const ReplayJob &job, const ProgJob *prog, hipStream_t s);
 fs_status launch_prog(const ProgJob &prog, hipStream_t s);
 fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStream_t s);
+// the peel and the replay program in one launch (one workgroup): a decode plan
+fs_status launch_plan(const PeelJob &job, const ProgJob &prog, hipStream_t s, uint32_t max_deg);
 
 // lost-row validation / masks for repair
 struct RepairPrepJob {

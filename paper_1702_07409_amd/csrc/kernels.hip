@@ -451,11 +451,12 @@ __device__ __forceinline__ uint32_t words_of(uint32_t k) { return (k + 31) / 32;
 
 struct PeelState {
   unsigned long long *acc, *best;
-  uint32_t *acc32;    // packed row state (kPeelLdsRows32 only)
+  uint32_t *acc32;    // packed row state (kPeelLdsRows32, kPeelLds16)
   int32_t *fa, *fb, *dl;
+  uint16_t *fa16, *fb16, *dl16, *ridx;   // kPeelLds16: 16-bit frontiers, list and column rows
   uint32_t *mask, *decm;
   int32_t *cptr;      // column pointers (LDS copy, or the graph's)
-  uint16_t *deg;      // row degrees (LDS variant only)
+  uint16_t *deg;      // row degrees (LDS variants only)
 };
 
 // Wave 0 lists the set bits of mask (one k-bit set) in ascending order: each
@@ -515,7 +516,19 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
 // for stripes whose full state does not fit), kPeelLdsRows32 the counters
 // packed in 32 bits (for stripes whose 64-bit counters do not fit either),
 // kPeelGlobal none of it.
-constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2, kPeelLdsRows32 = 3;
+// kPeelLds16 keeps everything in LDS in compact form (k, n <= 65535, degrees
+// <= 127): packed 32-bit counters, 16-bit frontiers and input list, and the
+// graph's column lists as 16-bit row ids, so a level touches no global
+// memory but the schedule it writes.
+constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2, kPeelLdsRows32 = 3, kPeelLds16 = 4;
+
+__host__ __device__ inline size_t peel_lds16_bytes(uint32_t k, uint32_t n, uint64_t nnz) {
+  const size_t kw = (k + 31) / 32;
+  size_t b = 8ull * k;                                  // best
+  b += 4ull * n + 8ull * kw + 4ull * (k + 1);           // acc32, mask, decm, cptr
+  b += 2ull * n + 2ull * n + 2ull * k + 2ull * n;       // fa16, fb16, dl16, deg
+  return b + 2ull * nnz;                                // ridx
+}
 
 template <int MODE>
 __device__ __forceinline__ void peel_body(const PeelJob &J) {
@@ -525,8 +538,24 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   const uint32_t k = J.k, n = J.n, kw = words_of(k);
   const int tid = threadIdx.x;
   const int wid = tid >> 6;
+  constexpr bool PACKED = MODE == kPeelLdsRows32 || MODE == kPeelLds16;   // 32-bit counters
+  constexpr bool ALL = MODE == kPeelLds || MODE == kPeelLds16;             // degrees, column pointers in LDS
+  constexpr bool SHORT = MODE == kPeelLds16;                               // 16-bit lists
   PeelState S;
-  if constexpr (MODE == kPeelLds) {
+  if constexpr (MODE == kPeelLds16) {
+    unsigned char *p = smem;
+    S.best = reinterpret_cast<unsigned long long *>(p); p += 8ull * k;
+    S.acc32 = reinterpret_cast<uint32_t *>(p); p += 4ull * n;
+    S.mask = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
+    S.decm = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
+    S.cptr = reinterpret_cast<int32_t *>(p); p += 4ull * (k + 1);
+    S.fa16 = reinterpret_cast<uint16_t *>(p); p += 2ull * n;
+    S.fb16 = reinterpret_cast<uint16_t *>(p); p += 2ull * n;
+    S.dl16 = reinterpret_cast<uint16_t *>(p); p += 2ull * k;
+    S.deg = reinterpret_cast<uint16_t *>(p); p += 2ull * n;
+    S.ridx = reinterpret_cast<uint16_t *>(p);
+    S.acc = nullptr; S.fa = S.fb = S.dl = nullptr;
+  } else if constexpr (MODE == kPeelLds) {
     unsigned char *p = smem;
     S.acc = reinterpret_cast<unsigned long long *>(p); p += 8ull * n;
     S.best = reinterpret_cast<unsigned long long *>(p); p += 8ull * k;
@@ -553,8 +582,11 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.mask[w] = 0;
     S.decm[w] = 0;
   }
-  if constexpr (MODE == kPeelLds) {
+  if constexpr (ALL) {
     for (uint32_t i = tid; i <= k; i += kPeelThreads) S.cptr[i] = J.col_ptr[i];
+  }
+  if constexpr (SHORT) {
+    for (uint64_t e = tid; e < J.nnz; e += kPeelThreads) S.ridx[e] = (uint16_t)J.rowidx[e];
   }
   if (tid == 0) {
     s_nA = 0;
@@ -565,19 +597,24 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   __syncthreads();
   for (uint32_t g = tid; g < n; g += kPeelThreads) {
     const int d = J.row_ptr[g + 1] - J.row_ptr[g];
-    if constexpr (MODE == kPeelLds) S.deg[g] = (uint16_t)d;
+    if constexpr (ALL) S.deg[g] = (uint16_t)d;
     if (J.erased[g]) {
-      if constexpr (MODE == kPeelLdsRows32)
+      if constexpr (PACKED)
         S.acc32[g] = kErasedAcc32;
       else
         S.acc[g] = kErasedAcc;
       continue;
     }
-    if constexpr (MODE == kPeelLdsRows32)
+    if constexpr (PACKED)
       S.acc32[g] = (uint32_t)d << 24;
     else
       S.acc[g] = (unsigned long long)d << 40;
-    if (d == 1) S.fa[atomicAdd(&s_nA, 1)] = (int32_t)g;
+    if (d == 1) {
+      if constexpr (SHORT)
+        S.fa16[atomicAdd(&s_nA, 1)] = (uint16_t)g;
+      else
+        S.fa[atomicAdd(&s_nA, 1)] = (int32_t)g;
+    }
   }
   __syncthreads();
   // sums of neighbour ids, accumulated by input over the CSC: the work per
@@ -588,11 +625,16 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     for (int e = S.cptr[i]; e < c1; e += kPeelBatch) {
       int32_t h[kPeelBatch];
 #pragma unroll
-      for (int u = 0; u < kPeelBatch; ++u) h[u] = e + u < c1 ? J.rowidx[e + u] : -1;
+      for (int u = 0; u < kPeelBatch; ++u) {
+        if constexpr (SHORT)
+          h[u] = e + u < c1 ? (int32_t)S.ridx[e + u] : -1;
+        else
+          h[u] = e + u < c1 ? J.rowidx[e + u] : -1;
+      }
 #pragma unroll
       for (int u = 0; u < kPeelBatch; ++u) {
         if (h[u] < 0) continue;
-        if constexpr (MODE == kPeelLdsRows32)
+        if constexpr (PACKED)
           atomicAdd(&S.acc32[h[u]], i);
         else
           atomicAdd(&S.acc[h[u]], (unsigned long long)i);
@@ -602,6 +644,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   __syncthreads();
 
   int32_t *cur = S.fa, *nxt = S.fb;
+  uint16_t *cur16 = S.fa16, *nxt16 = S.fb16;
   uint32_t level = 0, npairs = 0;
   while (true) {
     const int nA = s_nA;
@@ -609,9 +652,13 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     // every surviving row of residual weight 1 names its last unknown input;
     // keep the namer of least (original degree, row)
     for (int q = tid; q < nA; q += kPeelThreads) {
-      const int32_t g = cur[q];
+      int32_t g;
+      if constexpr (SHORT)
+        g = (int32_t)cur16[q];
+      else
+        g = cur[q];
       uint32_t f;
-      if constexpr (MODE == kPeelLdsRows32) {
+      if constexpr (PACKED) {
         const uint32_t a = S.acc32[g];
         if ((a >> 24) != 1u) continue;
         f = a & kSumMask32;
@@ -621,14 +668,19 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
         f = (uint32_t)(a & kSumMask);
       }
       uint32_t d;
-      if constexpr (MODE == kPeelLds)
+      if constexpr (ALL)
         d = S.deg[g];
       else
         d = (uint32_t)(J.row_ptr[g + 1] - J.row_ptr[g]);
       atomicMin(&S.best[f], ((unsigned long long)d << 32) | (uint32_t)g);
       const uint32_t bit = 1u << (f & 31);
       const uint32_t old = atomicOr(&S.mask[f >> 5], bit);
-      if (!(old & bit)) S.dl[atomicAdd(&s_nD, 1)] = (int32_t)f;
+      if (!(old & bit)) {
+        if constexpr (SHORT)
+          S.dl16[atomicAdd(&s_nD, 1)] = (uint16_t)f;
+        else
+          S.dl[atomicAdd(&s_nD, 1)] = (int32_t)f;
+      }
     }
     __syncthreads();
     const int nD = s_nD;
@@ -640,7 +692,11 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
       // remove the decoded inputs from every row they touch; a row whose
       // residual weight drops to 1 joins the next frontier
       for (int q = tid - 64; q < nD; q += kPeelThreads - 64) {
-        const uint32_t f = (uint32_t)S.dl[q];
+        uint32_t f;
+        if constexpr (SHORT)
+          f = S.dl16[q];
+        else
+          f = (uint32_t)S.dl[q];
         const unsigned long long dec = 0ull - (kCountOne | f);
         const uint32_t dec32 = 0u - (kCountOne32 | f);
         const int c1 = S.cptr[f + 1];
@@ -648,16 +704,26 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
           // the column's row ids are loaded together, then applied
           int32_t h[kPeelBatch];
 #pragma unroll
-          for (int u = 0; u < kPeelBatch; ++u) h[u] = e + u < c1 ? J.rowidx[e + u] : -1;
+          for (int u = 0; u < kPeelBatch; ++u) {
+            if constexpr (SHORT)
+              h[u] = e + u < c1 ? (int32_t)S.ridx[e + u] : -1;
+            else
+              h[u] = e + u < c1 ? J.rowidx[e + u] : -1;
+          }
 #pragma unroll
           for (int u = 0; u < kPeelBatch; ++u) {
             if (h[u] < 0) continue;
             bool two;
-            if constexpr (MODE == kPeelLdsRows32)
+            if constexpr (PACKED)
               two = (atomicAdd(&S.acc32[h[u]], dec32) >> 24) == 2u;
             else
               two = (atomicAdd(&S.acc[h[u]], dec) >> 40) == 2ull;
-            if (two) nxt[atomicAdd(&s_nB, 1)] = h[u];
+            if (two) {
+              if constexpr (SHORT)
+                nxt16[atomicAdd(&s_nB, 1)] = (uint16_t)h[u];
+              else
+                nxt[atomicAdd(&s_nB, 1)] = h[u];
+            }
           }
         }
       }
@@ -674,6 +740,9 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     int32_t *tmp = cur;
     cur = nxt;
     nxt = tmp;
+    uint16_t *tmp16 = cur16;
+    cur16 = nxt16;
+    nxt16 = tmp16;
     __syncthreads();
   }
   // the unrecovered inputs follow the schedule, ascending, with row -1
@@ -812,6 +881,15 @@ __device__ __forceinline__ void prog_body(const ProgJob &P) {
 __global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) { prog_body(P); }
 
 __global__ __launch_bounds__(kPlanThreads) void prog_batch_kernel(const ProgJob *jobs) { prog_body(jobs[blockIdx.x]); }
+
+// A decode plan in one launch: the peel, then (after a barrier, reading the
+// schedule the same workgroup just wrote) the replay program.
+template <int MODE>
+__global__ __launch_bounds__(kPeelThreads) void plan_kernel(PeelJob J, ProgJob P) {
+  peel_body<MODE>(J);
+  __syncthreads();
+  prog_body(P);
+}
 
 // Dependency-slab form of a replay program (one workgroup, after
 // prog_body).  Every input that some pair reads (a dependency) gets its own
@@ -1632,6 +1710,36 @@ int peel_mode(uint32_t k, uint32_t n, uint32_t max_deg) {
   return kPeelGlobal;
 }
 
+// the compact all-LDS peel applies: 16-bit ids, packed counters, and its
+// state with the column lists fits LDS beside the static arrays
+static bool peel16_ok(const PeelJob &job, uint32_t max_deg, int budget) {
+  return job.nnz > 0 && job.k <= 65535 && job.n <= 65535 && max_deg <= 127 &&
+         (uint64_t)max_deg * (job.k ? job.k - 1 : 0) < (1ull << 24) &&
+         peel_lds16_bytes(job.k, job.n, job.nnz) + 256 <= (size_t)budget;
+}
+
+fs_status launch_plan(const PeelJob &job, const ProgJob &prog, hipStream_t s, uint32_t max_deg) {
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int budget = device_info(dev).max_lds_per_block;
+  if (peel16_ok(job, max_deg, budget)) {
+    static bool done[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&plan_kernel<kPeelLds16>), dev, budget - 256, done);
+    hipLaunchKernelGGL(plan_kernel<kPeelLds16>, dim3(1), dim3(kPeelThreads),
+                       peel_lds16_bytes(job.k, job.n, job.nnz), s, job, prog);
+  } else if (peel_mode(job.k, job.n, max_deg) == kPeelLds) {
+    static bool done[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&plan_kernel<kPeelLds>), dev, budget - 256, done);
+    hipLaunchKernelGGL(plan_kernel<kPeelLds>, dim3(1), dim3(kPeelThreads), peel_lds_bytes(job.k, job.n), s, job,
+                       prog);
+  } else {
+    const fs_status st = launch_peel(job, s, max_deg);
+    return st != FS_OK ? st : launch_prog(prog, s);
+  }
+  const fs_status st = hip_check(hipGetLastError(), "decode plan launch");
+  return st != FS_OK ? st : launch_prog_lookahead(prog, s);
+}
+
 fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg) {
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -1639,7 +1747,12 @@ fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg) {
   const size_t static_lds = 64;
   const int budget = device_info(dev).max_lds_per_block;
   const int mode = peel_mode(job.k, job.n, max_deg);
-  if (mode == kPeelLds) {
+  if (peel16_ok(job, max_deg, budget)) {
+    static bool done[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLds16>), dev, budget - 256, done);
+    hipLaunchKernelGGL(peel_kernel<kPeelLds16>, dim3(1), dim3(kPeelThreads), peel_lds16_bytes(job.k, job.n, job.nnz),
+                       s, job);
+  } else if (mode == kPeelLds) {
     static bool done[64] = {false};
     set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLds>), dev, budget - (int)static_lds, done);
     hipLaunchKernelGGL(peel_kernel<kPeelLds>, dim3(1), dim3(kPeelThreads), lds, s, job);
