@@ -624,12 +624,8 @@ fs_status fs_decode_plan(const fs_graph *g, const uint8_t *erased, uint32_t maxi
   j.dlist = b.peel.dlist;
   j.mask = b.peel.mask;
   j.decmask = b.peel.decmask;
-  FS_TRY(launch_plan(j, b.prog, stream, g->max_deg));
-  if (status) {
-    const hipError_t e = hipMemcpyAsync(status, b.sched.status, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice, stream);
-    if (e != hipSuccess) return fail(FS_ERR_HIP, std::string("status copy: ") + hipGetErrorString(e));
-  }
-  return FS_OK;
+  j.status_out = status;   // the peel writes the caller's copy too: no extra dispatch
+  return launch_plan(j, b.prog, stream, g->max_deg);
 }
 
 fs_status fs_decode_apply(const fs_graph *g, const void *c, void *x, uint64_t t, const void *ws, size_t ws_bytes,

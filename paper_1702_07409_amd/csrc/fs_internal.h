@@ -137,6 +137,7 @@ struct PeelJob {
   uint32_t *mask, *decmask;
   const int32_t *skip_flag;  // non-zero: write status only
   uint64_t nnz;              // edges (0: unknown; the compact all-LDS variant needs it)
+  int32_t *status_out;       // int32[3] or null: a second copy of status (the caller's)
 };
 
 size_t peel_ws_bytes(uint32_t k, uint32_t n);

@@ -751,6 +751,11 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     J.status[0] = npairs == k ? 1 : 0;
     J.status[1] = (int32_t)(k - npairs);
     J.status[2] = (int32_t)level;
+    if (J.status_out) {
+      J.status_out[0] = npairs == k ? 1 : 0;
+      J.status_out[1] = (int32_t)(k - npairs);
+      J.status_out[2] = (int32_t)level;
+    }
   }
 }
 
