@@ -376,6 +376,28 @@ FS_API fs_status fs_checks_export(const fs_checks *ch, int32_t *c3_ptr, int32_t 
 FS_API void fs_checks_free(fs_checks *ch);
 
 /*
+ * The check data file (§2.8): one integer array.  A check #2 equation is the
+ * record 1, input, L, then the L coded blocks whose XOR is that input; a
+ * check #3 group is the record 0, L, then its L coded blocks.
+ *
+ * fs_checks_serialize writes the check #2 records by ascending input, then
+ * the check #3 groups in their stored order (smallest first), into out
+ * (host int32[cap]); *len is the number of integers (with out == NULL only
+ * *len is set).  FS_ERR_INVALID, nothing written, when cap is too small.
+ *
+ * fs_checks_load reads such an array (host int32[len]) for graph g: the
+ * first check #2 record of each input is kept, the check #3 groups are
+ * ordered by cardinality with ties in file order, as the repair engine sorts
+ * them, and members become ascending sets.  The groups are uploaded on
+ * stream (the call waits for the copy).  FS_ERR_INVALID for an unknown
+ * flag, a record running past the end or an index out of range (input >= k,
+ * coded block >= n).  The result serves fs_repair_local like a generated one.
+ */
+FS_API fs_status fs_checks_serialize(const fs_checks *ch, int32_t *out, uint64_t cap, uint64_t *len);
+FS_API fs_status fs_checks_load(const fs_graph *g, const int32_t *data, uint64_t len, hipStream_t stream,
+                                fs_checks **out);
+
+/*
  * Local-group repair, the repair engine's fast path (§2.7, §2.8, §4): BP
  * over the check #3 groups.  At each level every lost coded row s still
  * unknown is rebuilt in place in c as the XOR of the other members of the

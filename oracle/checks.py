@@ -17,6 +17,14 @@ Functions and the passage each follows
                  column.
   set_xor        §2.5, Eqs. (1)-(4): check #3 groups from a check #1 group
                  and the check #2 sets of its members (symmetric difference).
+  check_data     §2.8: the integer array of the check data file.  A check #2
+                 equation is the record 1, input, L, then the L coded blocks
+                 whose XOR is that input; a check #3 group is 0, L, then its
+                 L coded blocks.
+  parse_check_data  the records of such an array, in file order.
+  from_check_data   what the repair engine keeps from it: the first check #2
+                 record per input, and the check #3 groups ordered by
+                 cardinality (ties in file order), members as sets.
   local_repair   the repair engine's fast path (§2.7, §2.8, §4): BP over the
                  check #3 groups.  At each level every lost coded block
                  still unknown is rebuilt as the XOR of the other members of
@@ -32,6 +40,9 @@ Readings:
     current b_j (it changes inside the i loop).
   * zero_columns counts the zero columns (the text's "nonzero" contradicts
     the loop bound n - k).
+  * The check data array is written check #2 records first (ascending
+    input), then the check #3 groups in their stored order; the paper leaves
+    the record order open.
   * Local repair takes groups in the stored order (smallest first).  The
     repair engine searches the local sets for one unknown in a loop, as BP
     does (§2.8); here the loop is level-synchronous: a block rebuilt at level
@@ -103,6 +114,58 @@ def set_xor(sets):
     for s in sets:
         acc ^= set(s)
     return sorted(acc)
+
+
+def check_data(check2, check3):
+    """The check data integer array of check #2 equations {input: [coded
+    blocks]} and check #3 groups [[coded blocks], ...]."""
+    out = []
+    for i in sorted(check2):
+        out += [1, int(i), len(check2[i])] + [int(m) for m in check2[i]]
+    for grp in check3:
+        out += [0, len(grp)] + [int(m) for m in grp]
+    return out
+
+
+def parse_check_data(arr):
+    """(check #2 records [(input, [coded blocks])], check #3 groups) in file
+    order; ValueError for an unknown flag or a record past the end."""
+    arr = [int(v) for v in arr]
+    c2, c3 = [], []
+    p = 0
+    while p < len(arr):
+        flag = arr[p]
+        if flag == 1:
+            if p + 3 > len(arr):
+                raise ValueError("check #2 record header past the end")
+            i, L = arr[p + 1], arr[p + 2]
+            if L < 0 or p + 3 + L > len(arr):
+                raise ValueError("check #2 record past the end")
+            c2.append((i, arr[p + 3:p + 3 + L]))
+            p += 3 + L
+        elif flag == 0:
+            if p + 2 > len(arr):
+                raise ValueError("check #3 record header past the end")
+            L = arr[p + 1]
+            if L < 0 or p + 2 + L > len(arr):
+                raise ValueError("check #3 record past the end")
+            c3.append(arr[p + 2:p + 2 + L])
+            p += 2 + L
+        else:
+            raise ValueError("unknown record flag %d" % flag)
+    return c2, c3
+
+
+def from_check_data(arr):
+    """(check2 {input: sorted coded blocks}, check3 sorted groups ordered by
+    size, ties in file order): the equations as the repair engine holds
+    them (§2.8 sorts the check #3 groups by cardinality)."""
+    c2, c3 = parse_check_data(arr)
+    check2 = {}
+    for i, members in c2:
+        check2.setdefault(i, sorted(members))
+    groups = sorted((sorted(g) for g in c3), key=len)
+    return check2, groups
 
 
 def local_repair(groups, c, lost, erased=None, max_levels=0):

@@ -110,6 +110,8 @@ _SIGS = {
                         ctypes.POINTER(U64), ctypes.POINTER(U64)], ST),
     "fs_checks_export": ([P, P, P, P, P, P], ST),
     "fs_checks_free": ([P], None),
+    "fs_checks_serialize": ([P, P, U64, ctypes.POINTER(U64)], ST),
+    "fs_checks_load": ([P, P, U64, P, ctypes.POINTER(P)], ST),
     "fs_repair_local": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
@@ -394,6 +396,16 @@ class Checks:
         check3 = [c3c[c3p[q]:c3p[q + 1]].tolist() for q in range(self.n_check3)]
         return check2, check3
 
+    def serialize(self):
+        """The check data integer array (numpy int32)."""
+        import numpy as np
+        n = U64()
+        _check(_lib.fs_checks_serialize(self.handle, None, 0, ctypes.byref(n)), "fs_checks_serialize")
+        out = np.zeros(max(n.value, 1), np.int32)
+        _check(_lib.fs_checks_serialize(self.handle, out.ctypes.data, out.size, ctypes.byref(n)),
+               "fs_checks_serialize")
+        return out[:n.value]
+
     def free(self):
         if self.handle:
             _lib.fs_checks_free(self.handle)
@@ -409,6 +421,16 @@ class Checks:
 def fs_checks_generate(g, max_sweeps=0, stream=None):
     h = P()
     _check(_lib.fs_checks_generate(g.handle, max_sweeps, _stream(stream), ctypes.byref(h)), "fs_checks_generate")
+    return Checks(h)
+
+
+def fs_checks_load(g, data, stream=None):
+    """Checks from a check data integer array (anything numpy turns into int32)."""
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(data, dtype=np.int32))
+    h = P()
+    _check(_lib.fs_checks_load(g.handle, arr.ctypes.data if arr.size else None, arr.size, _stream(stream),
+                               ctypes.byref(h)), "fs_checks_load")
     return Checks(h)
 
 

@@ -604,6 +604,52 @@ void carve_decode(Carver &cv, const fs_graph *g, DecodeBufs &b) {
 
 using namespace fs;
 
+
+namespace fs {
+
+// The groups of every coded block (the transpose of the check #3 groups),
+// the largest group, and the device copies the local repair reads.
+fs_status finish_checks(fs_checks *ch, hipStream_t stream) {
+  const uint32_t n = ch->n;
+  ch->max_group = 0;
+  for (size_t q = 0; q + 1 < ch->grp_ptr.size(); ++q)
+    ch->max_group = std::max<uint32_t>(ch->max_group, (uint32_t)(ch->grp_ptr[q + 1] - ch->grp_ptr[q]));
+  ch->sym_ptr.assign(n + 1, 0);
+  for (int32_t v : ch->grp_col) ++ch->sym_ptr[v + 1];
+  for (uint32_t u = 0; u < n; ++u) ch->sym_ptr[u + 1] += ch->sym_ptr[u];
+  ch->sym_grp.assign(ch->grp_col.size(), 0);
+  {
+    std::vector<int32_t> fill(ch->sym_ptr.begin(), ch->sym_ptr.end() - 1);
+    for (size_t q = 0; q + 1 < ch->grp_ptr.size(); ++q)
+      for (int32_t m = ch->grp_ptr[q]; m < ch->grp_ptr[q + 1]; ++m) ch->sym_grp[fill[ch->grp_col[m]]++] = (int32_t)q;
+  }
+  const std::vector<int32_t> *parts[4] = {&ch->grp_ptr, &ch->grp_col, &ch->sym_ptr, &ch->sym_grp};
+  size_t off[4], dtotal = 0;
+  for (int q = 0; q < 4; ++q) {
+    off[q] = dtotal;
+    dtotal += (std::max<size_t>(parts[q]->size(), 1) * sizeof(int32_t) + 255) & ~size_t(255);
+  }
+  (void)hipGetDevice(&ch->device);
+  void *dbase = nullptr;
+  if (hipMalloc(&dbase, dtotal) != hipSuccess) return fail(FS_ERR_NOMEM, "device allocation for the checks failed");
+  hipError_t e = hipSuccess;
+  for (int q = 0; q < 4; ++q)
+    if (e == hipSuccess && !parts[q]->empty())
+      e = hipMemcpyAsync(static_cast<uint8_t *>(dbase) + off[q], parts[q]->data(), parts[q]->size() * sizeof(int32_t),
+                         hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    (void)hipFree(dbase);
+    return fail(FS_ERR_HIP, std::string("checks upload: ") + hipGetErrorString(e));
+  }
+  ch->d_base = dbase;
+  const int32_t **dst[4] = {&ch->d_grp_ptr, &ch->d_grp_col, &ch->d_sym_ptr, &ch->d_sym_grp};
+  for (int q = 0; q < 4; ++q) *dst[q] = reinterpret_cast<const int32_t *>(static_cast<uint8_t *>(dbase) + off[q]);
+  return FS_OK;
+}
+
+}  // namespace fs
+
 extern "C" {
 
 fs_status fs_decode_plan(const fs_graph *g, const uint8_t *erased, uint32_t maxit, uint8_t *recovered,
@@ -1132,42 +1178,11 @@ fs_status fs_checks_generate(const fs_graph *g, uint32_t max_sweeps, hipStream_t
       members((uint32_t)c2_of[i], ch->c2_col);
       ch->c2_ptr.push_back((int32_t)ch->c2_col.size());
     }
-  ch->sym_ptr.assign(n + 1, 0);
-  for (int32_t v : ch->grp_col) ++ch->sym_ptr[v + 1];
-  for (uint32_t u = 0; u < n; ++u) ch->sym_ptr[u + 1] += ch->sym_ptr[u];
-  ch->sym_grp.assign(ch->grp_col.size(), 0);
-  {
-    std::vector<int32_t> fill(ch->sym_ptr.begin(), ch->sym_ptr.end() - 1);
-    for (size_t q = 0; q + 1 < ch->grp_ptr.size(); ++q)
-      for (int32_t m = ch->grp_ptr[q]; m < ch->grp_ptr[q + 1]; ++m) ch->sym_grp[fill[ch->grp_col[m]]++] = (int32_t)q;
-  }
-  // device copies of the groups and their transpose
-  const std::vector<int32_t> *parts[4] = {&ch->grp_ptr, &ch->grp_col, &ch->sym_ptr, &ch->sym_grp};
-  size_t off[4], dtotal = 0;
-  for (int q = 0; q < 4; ++q) {
-    off[q] = dtotal;
-    dtotal += (std::max<size_t>(parts[q]->size(), 1) * sizeof(int32_t) + 255) & ~size_t(255);
-  }
-  (void)hipGetDevice(&ch->device);
-  void *dbase = nullptr;
-  if (hipMalloc(&dbase, dtotal) != hipSuccess) {
+  const fs_status fin = finish_checks(ch, stream);
+  if (fin != FS_OK) {
     delete ch;
-    return fail(FS_ERR_NOMEM, "device allocation for the checks failed");
+    return fin;
   }
-  e = hipSuccess;
-  for (int q = 0; q < 4; ++q)
-    if (e == hipSuccess && !parts[q]->empty())
-      e = hipMemcpyAsync(static_cast<uint8_t *>(dbase) + off[q], parts[q]->data(), parts[q]->size() * sizeof(int32_t),
-                         hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) {
-    (void)hipFree(dbase);
-    delete ch;
-    return fail(FS_ERR_HIP, std::string("checks upload: ") + hipGetErrorString(e));
-  }
-  ch->d_base = dbase;
-  const int32_t **dst[4] = {&ch->d_grp_ptr, &ch->d_grp_col, &ch->d_sym_ptr, &ch->d_sym_grp};
-  for (int q = 0; q < 4; ++q) *dst[q] = reinterpret_cast<const int32_t *>(static_cast<uint8_t *>(dbase) + off[q]);
   *out = ch;
   return FS_OK;
 }
@@ -1195,6 +1210,107 @@ fs_status fs_checks_export(const fs_checks *ch, int32_t *c3_ptr, int32_t *c3_col
   std::copy(ch->c2_input.begin(), ch->c2_input.end(), c2_input);
   std::copy(ch->c2_ptr.begin(), ch->c2_ptr.end(), c2_ptr);
   std::copy(ch->c2_col.begin(), ch->c2_col.end(), c2_col);
+  return FS_OK;
+}
+
+fs_status fs_checks_serialize(const fs_checks *ch, int32_t *out, uint64_t cap, uint64_t *len) {
+  clear_error();
+  if (!ch || !len) return fail(FS_ERR_INVALID, "checks and len must be non-null");
+  const uint64_t ngroups = ch->grp_ptr.empty() ? 0 : ch->grp_ptr.size() - 1;
+  const uint64_t need = 3ull * ch->c2_input.size() + ch->c2_col.size() + 2ull * ngroups + ch->grp_col.size();
+  if (out) {
+    if (cap < need) return fail(FS_ERR_INVALID, "the output holds fewer integers than the check data");
+    uint64_t p = 0;
+    for (size_t q = 0; q < ch->c2_input.size(); ++q) {
+      out[p++] = 1;
+      out[p++] = ch->c2_input[q];
+      out[p++] = ch->c2_ptr[q + 1] - ch->c2_ptr[q];
+      for (int32_t m = ch->c2_ptr[q]; m < ch->c2_ptr[q + 1]; ++m) out[p++] = ch->c2_col[m];
+    }
+    for (uint64_t q = 0; q < ngroups; ++q) {
+      out[p++] = 0;
+      out[p++] = ch->grp_ptr[q + 1] - ch->grp_ptr[q];
+      for (int32_t m = ch->grp_ptr[q]; m < ch->grp_ptr[q + 1]; ++m) out[p++] = ch->grp_col[m];
+    }
+  }
+  *len = need;
+  return FS_OK;
+}
+
+fs_status fs_checks_load(const fs_graph *g, const int32_t *data, uint64_t len, hipStream_t stream,
+                         fs_checks **out) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  if (!out || (len && !data)) return fail(FS_ERR_INVALID, "out and data must be non-null");
+  *out = nullptr;
+  const uint32_t k = g->k, n = g->n;
+  struct Grp {
+    std::vector<int32_t> m;
+  };
+  std::vector<Grp> groups;
+  std::vector<std::vector<int32_t>> c2(k);
+  std::vector<uint8_t> c2_seen(k, 0);
+  uint64_t p = 0;
+  auto members = [&](uint64_t at, int64_t L, std::vector<int32_t> &dst) -> bool {
+    if (L < 0 || at + (uint64_t)L > len) return false;
+    for (int64_t q = 0; q < L; ++q) {
+      const int32_t v = data[at + q];
+      if (v < 0 || (uint32_t)v >= n) return false;
+      dst.push_back(v);
+    }
+    std::sort(dst.begin(), dst.end());
+    return true;
+  };
+  while (p < len) {
+    const int32_t flag = data[p];
+    if (flag == 1) {
+      if (p + 3 > len) return fail(FS_ERR_INVALID, "check data: a check #2 record runs past the end");
+      const int32_t i = data[p + 1], L = data[p + 2];
+      if (i < 0 || (uint32_t)i >= k) return fail(FS_ERR_INVALID, "check data: input index out of range");
+      std::vector<int32_t> m;
+      if (!members(p + 3, L, m)) return fail(FS_ERR_INVALID, "check data: a check #2 record is past the end or out of range");
+      if (!c2_seen[i]) {
+        c2_seen[i] = 1;
+        c2[i] = std::move(m);
+      }
+      p += 3 + (uint64_t)L;
+    } else if (flag == 0) {
+      if (p + 2 > len) return fail(FS_ERR_INVALID, "check data: a check #3 record runs past the end");
+      const int32_t L = data[p + 1];
+      Grp gr;
+      if (!members(p + 2, L, gr.m)) return fail(FS_ERR_INVALID, "check data: a check #3 record is past the end or out of range");
+      groups.push_back(std::move(gr));
+      p += 2 + (uint64_t)L;
+    } else {
+      return fail(FS_ERR_INVALID, "check data: unknown record flag");
+    }
+  }
+  // the repair engine takes the smallest groups first (ties in file order)
+  std::stable_sort(groups.begin(), groups.end(), [](const Grp &a, const Grp &b) { return a.m.size() < b.m.size(); });
+  fs_checks *ch = new (std::nothrow) fs_checks();
+  if (!ch) return fail(FS_ERR_NOMEM, "host allocation failed");
+  ch->k = k;
+  ch->n = n;
+  ch->sweeps = 0;
+  ch->zero_columns = (uint32_t)groups.size();
+  ch->grp_ptr.assign(1, 0);
+  for (const Grp &gr : groups) {
+    ch->grp_col.insert(ch->grp_col.end(), gr.m.begin(), gr.m.end());
+    ch->grp_ptr.push_back((int32_t)ch->grp_col.size());
+  }
+  ch->c2_ptr.assign(1, 0);
+  for (uint32_t i = 0; i < k; ++i)
+    if (c2_seen[i]) {
+      ch->c2_input.push_back((int32_t)i);
+      ch->c2_col.insert(ch->c2_col.end(), c2[i].begin(), c2[i].end());
+      ch->c2_ptr.push_back((int32_t)ch->c2_col.size());
+    }
+  const fs_status fin = finish_checks(ch, stream);
+  if (fin != FS_OK) {
+    delete ch;
+    return fin;
+  }
+  *out = ch;
   return FS_OK;
 }
 

@@ -134,3 +134,53 @@ def test_local_repair_rejects_bad_ids_without_writing():
         fs.fs_repair_local(g, ch, c, None, dev(np.array(lost, np.uint32)), len(lost), rep, st, 64, ws)
         assert np.array_equal(host(c), c_host)
         assert host(st).tolist() == [0, len(lost), -fs._lib.FS_ERR_INVALID] and not host(rep).any()
+
+
+@pytest.mark.parametrize("k,n,dist", [(64, 96, "rsd"), (200, 400, "raptor")])
+def test_check_data_equals_the_oracle_and_loads_back(k, n, dist):
+    # the library's check data array equals the oracle's (§2.8 records), and
+    # loading it back gives the same equations
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=k, n=n, dist=dist)
+    ch = fs.fs_checks_generate(g)
+    arr = ch.serialize()
+    want2, want3 = checks.split(*checks.cga(G)[:2])
+    assert arr.tolist() == checks.check_data(want2, want3)
+    back = fs.fs_checks_load(g, arr)
+    assert back.export() == (want2, want3)
+    assert back.serialize().tolist() == arr.tolist()
+
+
+def test_check_data_of_the_paper_example_loads():
+    # §2.8's example array on a code with at least 89 coded and 20 data blocks
+    import json
+    import os
+    import paper_1702_07409_amd as fs
+    with open(os.path.join(os.path.dirname(__file__), "golden", "paper_check_data.json")) as fh:
+        ex = json.load(fh)
+    g, G = graphs(k=64, n=96)
+    ch = fs.fs_checks_load(g, ex["array"])
+    assert ch.export() == checks.from_check_data(ex["array"])
+    assert ch.n_check2 == 1 and ch.n_check3 == 2
+
+
+def test_local_repair_with_loaded_checks_equals_generated():
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor")
+    ch = fs.fs_checks_generate(g)
+    loaded = fs.fs_checks_load(g, ch.serialize())
+    _, c3 = ch.export()
+    rng = np.random.default_rng(21)
+    for trial in range(3):
+        lost = sorted(rng.choice(400, size=30, replace=False).tolist())
+        for which in (ch, loaded):
+            local_case(g, G, which, c3, lost, None, 256 + 32, trial)
+
+
+@pytest.mark.parametrize("arr", [[2, 1, 5], [0, 3, 1, 2], [1, 4, 2, 7], [1, 64, 1, 0], [0, 1, 96], [0, -1]])
+def test_check_data_load_rejects_malformed_arrays(arr):
+    # unknown flag, records past the end, input >= k, coded block >= n, a negative size
+    import paper_1702_07409_amd as fs
+    g, _ = graphs(k=64, n=96)
+    with pytest.raises(fs.FsError):
+        fs.fs_checks_load(g, arr)

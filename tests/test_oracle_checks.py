@@ -149,3 +149,38 @@ def test_local_repair_closure_is_order_independent():
         assert sorted(set(lost) - set(todo)) == [s for r, s in enumerate(lost) if ok[r]]
         _, ok1, _, lev1, levels1 = checks.local_repair(check3, c, lost, max_levels=1)
         assert levels1 == min(levels, 1) and set(np.flatnonzero(ok1)) == set(np.flatnonzero(lev1 == 0))
+
+
+def test_check_data_reads_the_papers_example():
+    # §2.8's example array: #3{13, 56, 17, 66}, #2(19; 11, 13), #3{39, 88}
+    with open(os.path.join(GOLDEN, "paper_check_data.json")) as fh:
+        g = json.load(fh)
+    c2, c3 = checks.parse_check_data(g["array"])
+    assert c3 == g["check3"]
+    assert [[i, m] for i, m in c2] == g["check2"]
+    check2, groups = checks.from_check_data(g["array"])
+    assert check2 == {19: [11, 13]} and groups == [[39, 88], [13, 17, 56, 66]]
+
+
+def test_check_data_size_formula_and_round_trip():
+    # a converged run stores N = sum L_c + k + 2n integers (§2.8): k check #2
+    # records of L + 3 and n - k check #3 records of L + 2
+    G = graph.from_rows(2, [[0], [1], [0, 1]])
+    check2, check3 = checks.split(*checks.cga(G)[:2])
+    arr = checks.check_data(check2, check3)
+    L = sum(len(v) for v in check2.values()) + sum(len(gr) for gr in check3)
+    assert len(arr) == L + G.k + 2 * G.n == 13
+    assert arr == [1, 0, 1, 0, 1, 1, 1, 1, 0, 3, 0, 1, 2]
+    for k, n, seed in ((40, 70, 2), (30, 45, 3)):
+        G = G_of(k, n, seed=seed)
+        check2, check3 = checks.split(*checks.cga(G)[:2])
+        arr = checks.check_data(check2, check3)
+        L = sum(len(v) for v in check2.values()) + sum(len(gr) for gr in check3)
+        assert len(arr) == L + 3 * len(check2) + 2 * len(check3)
+        assert checks.from_check_data(arr) == (check2, check3)
+
+
+@pytest.mark.parametrize("arr", [[2, 1, 5], [0, 3, 1, 2], [1, 4, 2, 7], [1, 4], [0]])
+def test_check_data_rejects_malformed_arrays(arr):
+    with pytest.raises(ValueError):
+        checks.parse_check_data(arr)
