@@ -426,15 +426,16 @@ def _local_reads(groups, lost):
 
 
 def run_checks(reps=10):
-    """Check #2/#3 generation (Algorithm 4) and repair of one lost disk by
-    local groups (BP over the check #3 groups) against the conventional
-    repair (decode, then re-encode).
+    """Check #2/#3 generation (Algorithm 4) and repair of lost disks by local
+    groups (BP over the check #3 groups) against the conventional repair
+    (decode, then re-encode), before and after adding §2.5's groups from
+    degree-one blocks and from the precode's check #1 sets.
 
-    Codes, Raptor Omega graphs striped over 10 disks: the paper's
-    illustrative one (k=500, n=1000, t=512; §4) and Table 2's smaller one
-    (k=1036, n=2180, a 64 MiB object) with disk 0 (rows 0 .. n/10-1) lost;
-    the §5 repair case (k=10246, n=21800, 10240-byte blocks: 100 MiB) with
-    disks 0 and 1 lost.  Repair
+    Codes, Raptor Omega graphs over precoded objects (array code with j' = 3)
+    striped over 10 disks: the paper's illustrative one (k=500, n=1000,
+    t=512; §4) and Table 2's smaller one (k=1036, n=2180, a 64 MiB object)
+    with disk 0 (rows 0 .. n/10-1) lost; the §5 repair case (k=10246,
+    n=21800, 10240-byte blocks: 100 MiB) with disks 0 and 1 lost.  Repair
     bandwidth is the bytes of coded blocks read: for local repair the other
     members of each block's group, for the conventional repair the coded
     blocks the decode uses (one per recovered input).  bytes_read counts every
@@ -446,15 +447,18 @@ def run_checks(reps=10):
 
     out = {"workload": "checks", "disks": 10, "codes": []}
     for k, n, t, disks in ((500, 1000, 512, 1), (1036, 2180, 65536, 1), (10246, 21800, 10240, 2)):
+        lp = _largest_prime_factor(k)
+        b = (k // lp - 3) * lp
         g = fs.fs_graph_build(k=k, n=n, dist="raptor", seed=1)
+        pc = fs.fs_precode_build(b, k)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ch = fs.fs_checks_generate(g)
         torch.cuda.synchronize()
         gen_ms = (time.perf_counter() - t0) * 1e3
-        _, c3 = ch.export()
         x = torch.empty((k, t), dtype=torch.uint8, device="cuda")
-        sg.fill(x, 0, 0, t)
+        sg.fill(x[:b], 0, 0, t)
+        fs.fs_precode_encode(pc, x, t)
         c = torch.empty((n, t), dtype=torch.uint8, device="cuda")
         fs.fs_encode(g, x, c, t)
         lost_h = np.arange(0, disks * n // 10, dtype=np.uint32)
@@ -464,13 +468,28 @@ def run_checks(reps=10):
         rep = torch.empty(m, dtype=torch.uint8, device="cuda")
         st = torch.empty(3, dtype=torch.int32, device="cuda")
         ws_l = fs.workspace(g, fs.FS_OP_REPAIR_LOCAL, t, m)
-        t_loc = _time(lambda: fs.fs_repair_local(g, ch, c, None, lost, m, rep, st, t, ws_l), reps)
-        n_loc = int(rep.sum().item())
-        loc_ok = bool(torch.equal(c[:m][rep.bool()], c_ref[rep.bool()]))
-        st_h = st.cpu().tolist()
-        n_acc, loc_blocks, loc_fetched, loc_levels = _local_reads(c3, lost_h.tolist())
-        assert n_acc == n_loc and loc_levels == st_h[2]
-        # conventional repair of the same disk: decode from the other rows, re-encode
+
+        def local(tag):
+            t_loc = _time(lambda: fs.fs_repair_local(g, ch, c, None, lost, m, rep, st, t, ws_l), reps)
+            n_loc = int(rep.sum().item())
+            ok = bool(torch.equal(c[:m][rep.bool()], c_ref[rep.bool()]))
+            _, c3 = ch.export()
+            n_acc, reads, fetched, levels = _local_reads(c3, lost_h.tolist())
+            assert n_acc == n_loc and levels == st.cpu().tolist()[2]
+            _progress("checks: k=%d n=%d %s: local repair %d/%d in %.3f ms" % (k, n, tag, n_loc, m, t_loc))
+            return {"groups": ch.n_check3, "ms": round(t_loc, 4), "repaired": n_loc, "levels": levels, "exact": ok,
+                    "bytes_read": reads * t, "bytes_transferred": fetched * t,
+                    "mean_group_read": round(reads / max(n_loc, 1), 2)}
+
+        row = {"k": k, "n": n, "t": t, "b": b, "object_bytes": b * t, "generate_ms": round(gen_ms, 2),
+               "sweeps": ch.sweeps, "check2": ch.n_check2, "check3": ch.n_check3, "disks_lost": disks,
+               "lost_blocks": m}
+        row["local"] = local("generated groups")
+        t0 = time.perf_counter()
+        row["added_groups"] = ch.add_groups(g, pc)
+        row["add_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+        row["local_with_added"] = local("with added groups")
+        # conventional repair of the same disks: decode from the other rows, re-encode
         rep2 = torch.empty(m, dtype=torch.uint8, device="cuda")
         st2 = torch.empty(3, dtype=torch.int32, device="cuda")
         ws_c = fs.workspace(g, fs.FS_OP_REPAIR_CONVENTIONAL, t, m)
@@ -484,18 +503,9 @@ def run_checks(reps=10):
         st3 = torch.empty(3, dtype=torch.int32, device="cuda")
         fs.fs_decode(g, c, er, 0, xd, rec, st3, t, fs.workspace(g, fs.FS_OP_DECODE, t))
         n_rec = int(rec.sum().item())
-        out["codes"].append({
-            "k": k, "n": n, "t": t, "object_bytes": k * t,
-            "generate_ms": round(gen_ms, 2), "sweeps": ch.sweeps, "check2": ch.n_check2, "check3": ch.n_check3,
-            "disks_lost": disks, "lost_blocks": m,
-            "local": {"ms": round(t_loc, 4), "repaired": n_loc, "levels": loc_levels, "exact": loc_ok,
-                      "bytes_read": loc_blocks * t, "bytes_transferred": loc_fetched * t,
-                      "mean_group_read": round(loc_blocks / max(n_loc, 1), 2)},
-            "conventional": {"ms": round(t_conv, 4), "repaired": n_conv, "exact": conv_ok,
-                             "decode_recovered": n_rec, "bytes_read": n_rec * t, "bytes_transferred": n_rec * t},
-        })
-        _progress("checks: k=%d n=%d generated in %.1f ms, local repair %d/%d in %.3f ms" %
-                  (k, n, gen_ms, n_loc, m, t_loc))
+        row["conventional"] = {"ms": round(t_conv, 4), "repaired": n_conv, "exact": conv_ok,
+                               "decode_recovered": n_rec, "bytes_read": n_rec * t, "bytes_transferred": n_rec * t}
+        out["codes"].append(row)
         del x, c, xd, c_ref
         torch.cuda.empty_cache()
     out["paper_context"] = ("§5: k=10246, n=21800, 100 MiB, two disks lost: conventional repair 108,267,520 "

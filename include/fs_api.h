@@ -393,6 +393,20 @@ FS_API void fs_checks_free(fs_checks *ch);
  * flag, a record running past the end or an index out of range (input >= k,
  * coded block >= n).  The result serves fs_repair_local like a generated one.
  */
+/*
+ * More check #3 groups (§2.5), added to ch for graph g:
+ *   (1) for each coded block j of degree one whose input i has a check #2
+ *       set S_i, the group S_i xor {j} (c_j = x_i);
+ *   (2) with pc non-null (the precode of g's inputs, pc's k = g's k), for each
+ *       check #1 set D whose members all have check #2 sets, the symmetric
+ *       difference of those sets (Eqs. (1)-(4)).
+ * Empty groups and groups equal to one already held are skipped; all groups
+ * are then ordered by cardinality, held ones first on ties.  added (may be
+ * NULL): the number of groups added.  The device copies are replaced (the
+ * call waits for the upload); on an error ch is left as it was.
+ */
+FS_API fs_status fs_checks_add_groups(fs_checks *ch, const fs_graph *g, const fs_precode *pc,
+                                      hipStream_t stream, uint32_t *added);
 FS_API fs_status fs_checks_serialize(const fs_checks *ch, int32_t *out, uint64_t cap, uint64_t *len);
 FS_API fs_status fs_checks_load(const fs_graph *g, const int32_t *data, uint64_t len, hipStream_t stream,
                                 fs_checks **out);

@@ -17,6 +17,14 @@ Functions and the passage each follows
                  column.
   set_xor        §2.5, Eqs. (1)-(4): check #3 groups from a check #1 group
                  and the check #2 sets of its members (symmetric difference).
+  extra_groups   §2.5: more check #3 groups from check #2 equations: for a
+                 coded block j of degree one with input i, S_i xor {j}
+                 (c_j = x_i); for a check #1 set D of precoded blocks (XOR
+                 zero) whose members all have check #2 sets, the symmetric
+                 difference of those sets (Eqs. (1)-(4)).
+  with_extra_groups  the groups held with them: new ones that are empty or
+                 equal to a held group are skipped, then all are ordered by
+                 cardinality (held ones first on ties).
   check_data     §2.8: the integer array of the check data file.  A check #2
                  equation is the record 1, input, L, then the L coded blocks
                  whose XOR is that input; a check #3 group is 0, L, then its
@@ -114,6 +122,35 @@ def set_xor(sets):
     for s in sets:
         acc ^= set(s)
     return sorted(acc)
+
+
+def extra_groups(G, check2, check1=None):
+    """Groups from degree-one coded blocks (coded block order), then from the
+    check #1 sets in check1 (their order), each a sorted list; empty ones are
+    left out."""
+    out = []
+    for j in range(G.n):
+        N = [int(i) for i in G.N(j)]
+        if len(N) == 1 and N[0] in check2:
+            grp = set_xor([check2[N[0]], [j]])
+            if grp:
+                out.append(grp)
+    for D in check1 or ():
+        if all(int(i) in check2 for i in D):
+            grp = set_xor([check2[int(i)] for i in D])
+            if grp:
+                out.append(grp)
+    return out
+
+
+def with_extra_groups(check3, extra):
+    groups = [list(g) for g in check3]
+    seen = {tuple(g) for g in groups}
+    for g in extra:
+        if tuple(g) not in seen:
+            seen.add(tuple(g))
+            groups.append(list(g))
+    return sorted(groups, key=len)
 
 
 def check_data(check2, check3):

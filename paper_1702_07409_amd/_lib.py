@@ -112,6 +112,7 @@ _SIGS = {
     "fs_checks_free": ([P], None),
     "fs_checks_serialize": ([P, P, U64, ctypes.POINTER(U64)], ST),
     "fs_checks_load": ([P, P, U64, P, ctypes.POINTER(P)], ST),
+    "fs_checks_add_groups": ([P, P, P, P, ctypes.POINTER(U32)], ST),
     "fs_repair_local": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
@@ -395,6 +396,19 @@ class Checks:
         check2 = {int(c2i[q]): c2c[c2p[q]:c2p[q + 1]].tolist() for q in range(self.n_check2)}
         check3 = [c3c[c3p[q]:c3p[q + 1]].tolist() for q in range(self.n_check3)]
         return check2, check3
+
+    def add_groups(self, g, precode=None, stream=None):
+        """Check #3 groups from degree-one coded blocks and from the
+        precode's check #1 sets (§2.5); returns how many were added."""
+        a = U32()
+        _check(_lib.fs_checks_add_groups(self.handle, g.handle, precode.handle if precode is not None else None,
+                                         _stream(stream), ctypes.byref(a)), "fs_checks_add_groups")
+        n2, n3, sw, zc, e2, e3 = U32(), U32(), U32(), U32(), U64(), U64()
+        _check(_lib.fs_checks_info(self.handle, ctypes.byref(n2), ctypes.byref(n3), ctypes.byref(sw),
+                                   ctypes.byref(zc), ctypes.byref(e2), ctypes.byref(e3)), "fs_checks_info")
+        self.n_check2, self.n_check3 = n2.value, n3.value
+        self.check2_entries, self.check3_entries = e2.value, e3.value
+        return a.value
 
     def serialize(self):
         """The check data integer array (numpy int32)."""

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstring>
 #include <mutex>
+#include <set>
 
 #include "fs_internal.h"
 
@@ -607,9 +608,9 @@ using namespace fs;
 
 namespace fs {
 
-// The groups of every coded block (the transpose of the check #3 groups),
-// the largest group, and the device copies the local repair reads.
-fs_status finish_checks(fs_checks *ch, hipStream_t stream) {
+// The groups of every coded block (the transpose of the check #3 groups)
+// and the largest group, on the host.
+void checks_transpose(fs_checks *ch) {
   const uint32_t n = ch->n;
   ch->max_group = 0;
   for (size_t q = 0; q + 1 < ch->grp_ptr.size(); ++q)
@@ -623,6 +624,12 @@ fs_status finish_checks(fs_checks *ch, hipStream_t stream) {
     for (size_t q = 0; q + 1 < ch->grp_ptr.size(); ++q)
       for (int32_t m = ch->grp_ptr[q]; m < ch->grp_ptr[q + 1]; ++m) ch->sym_grp[fill[ch->grp_col[m]]++] = (int32_t)q;
   }
+}
+
+// The transpose, then the device copies the local repair reads; the device
+// pointers change only on success.
+fs_status finish_checks(fs_checks *ch, hipStream_t stream) {
+  checks_transpose(ch);
   const std::vector<int32_t> *parts[4] = {&ch->grp_ptr, &ch->grp_col, &ch->sym_ptr, &ch->sym_grp};
   size_t off[4], dtotal = 0;
   for (int q = 0; q < 4; ++q) {
@@ -1311,6 +1318,99 @@ fs_status fs_checks_load(const fs_graph *g, const int32_t *data, uint64_t len, h
     return fin;
   }
   *out = ch;
+  return FS_OK;
+}
+
+fs_status fs_checks_add_groups(fs_checks *ch, const fs_graph *g, const fs_precode *pc, hipStream_t stream,
+                               uint32_t *added) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  if (!ch) return fail(FS_ERR_INVALID, "checks is null");
+  if (ch->n != g->n || ch->k != g->k) return fail(FS_ERR_INVALID, "the checks belong to another graph shape");
+  if (pc) {
+    FS_TRY(check_precode(pc));
+    if (pc->k != g->k) return fail(FS_ERR_INVALID, "the precode's k differs from the graph's");
+  }
+  // check #2 set of every input (-1: none)
+  std::vector<int32_t> c2_of(g->k, -1);
+  for (size_t q = 0; q < ch->c2_input.size(); ++q) c2_of[ch->c2_input[q]] = (int32_t)q;
+  auto set_of = [&](int32_t i, std::vector<int32_t> &dst) {
+    const int32_t q = c2_of[i];
+    dst.assign(ch->c2_col.begin() + ch->c2_ptr[q], ch->c2_col.begin() + ch->c2_ptr[q + 1]);
+  };
+  // symmetric difference of two ascending sets
+  auto sym_xor = [](const std::vector<int32_t> &a, const std::vector<int32_t> &b, std::vector<int32_t> &out) {
+    out.clear();
+    size_t i = 0, j = 0;
+    while (i < a.size() || j < b.size()) {
+      if (j == b.size() || (i < a.size() && a[i] < b[j])) out.push_back(a[i++]);
+      else if (i == a.size() || b[j] < a[i]) out.push_back(b[j++]);
+      else { ++i; ++j; }
+    }
+  };
+  std::vector<std::vector<int32_t>> groups;
+  const size_t held = ch->grp_ptr.empty() ? 0 : ch->grp_ptr.size() - 1;
+  for (size_t q = 0; q < held; ++q) groups.emplace_back(ch->grp_col.begin() + ch->grp_ptr[q], ch->grp_col.begin() + ch->grp_ptr[q + 1]);
+  std::set<std::vector<int32_t>> seen(groups.begin(), groups.end());
+  uint32_t count = 0;
+  auto offer = [&](std::vector<int32_t> &&grp) {
+    if (grp.empty() || seen.count(grp)) return;
+    seen.insert(grp);
+    groups.push_back(std::move(grp));
+    ++count;
+  };
+  std::vector<int32_t> acc, tmp, set;
+  // (1) coded blocks of degree one: c_j = x_i, so S_i xor {j} XORs to zero
+  for (uint32_t j = 0; j < g->n; ++j) {
+    if (g->row_ptr[j + 1] - g->row_ptr[j] != 1) continue;
+    const int32_t i = g->col[g->row_ptr[j]];
+    if (c2_of[i] < 0) continue;
+    set_of(i, set);
+    sym_xor(set, std::vector<int32_t>{(int32_t)j}, acc);
+    offer(std::move(acc));
+    acc = {};
+  }
+  // (2) check #1 sets whose members all have check #2 sets (Eqs. (1)-(4))
+  if (pc) {
+    for (uint32_t r = 0; r < pc->m; ++r) {
+      bool all = true;
+      for (int32_t e = pc->chk_ptr[r]; e < pc->chk_ptr[r + 1] && all; ++e) all = c2_of[pc->chk_col[e]] >= 0;
+      if (!all) continue;
+      acc.clear();
+      for (int32_t e = pc->chk_ptr[r]; e < pc->chk_ptr[r + 1]; ++e) {
+        set_of(pc->chk_col[e], set);
+        sym_xor(acc, set, tmp);
+        acc.swap(tmp);
+      }
+      offer(std::move(acc));
+      acc = {};
+    }
+  }
+  // smallest first, the held groups before new ones of the same size
+  std::stable_sort(groups.begin(), groups.end(),
+                   [](const std::vector<int32_t> &a, const std::vector<int32_t> &b) { return a.size() < b.size(); });
+  std::vector<int32_t> ptr(1, 0), col;
+  for (const auto &gr : groups) {
+    col.insert(col.end(), gr.begin(), gr.end());
+    ptr.push_back((int32_t)col.size());
+  }
+  void *old = ch->d_base;
+  const int old_dev = ch->device;
+  ch->grp_ptr.swap(ptr);
+  ch->grp_col.swap(col);
+  ch->d_base = nullptr;
+  const fs_status fin = finish_checks(ch, stream);
+  if (fin != FS_OK) {
+    // keep the object as it was
+    ch->grp_ptr.swap(ptr);
+    ch->grp_col.swap(col);
+    ch->d_base = old;
+    ch->device = old_dev;
+    checks_transpose(ch);
+    return fin;
+  }
+  if (old) (void)hipFree(old);
+  if (added) *added = count;
   return FS_OK;
 }
 

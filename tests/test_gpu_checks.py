@@ -184,3 +184,37 @@ def test_check_data_load_rejects_malformed_arrays(arr):
     g, _ = graphs(k=64, n=96)
     with pytest.raises(fs.FsError):
         fs.fs_checks_load(g, arr)
+
+
+@pytest.mark.parametrize("with_precode", [False, True])
+def test_added_groups_equal_the_oracle(with_precode):
+    # §2.5's extra check #3 groups (degree-one blocks; check #1 sets combined
+    # through check #2, Eqs. (1)-(4)) equal the oracle's, in order, and serve
+    # the local repair
+    import paper_1702_07409_amd as fs
+    from oracle import precode
+    b, k, n = 85, 100, 170
+    g, G = graphs(k=k, n=n, dist="raptor", seed=3)
+    ch = fs.fs_checks_generate(g)
+    pc = fs.fs_precode_build(b, k) if with_precode else None
+    added = ch.add_groups(g, pc)
+    check2, check3 = checks.split(*checks.cga(G)[:2])
+    extra = checks.extra_groups(G, check2, precode.checks(b, k) if with_precode else None)
+    want = checks.with_extra_groups(check3, extra)
+    got2, got3 = ch.export()
+    assert got2 == check2 and got3 == want
+    assert added == len(want) - len(check3) and (added > 0 or not with_precode)
+    rng = np.random.default_rng(5)
+    for trial in range(3):
+        lost = sorted(rng.choice(n, size=25, replace=False).tolist())
+        local_case(g, G, ch, want, lost, None, 128 + 16, trial)
+
+
+def test_added_groups_reject_a_precode_of_another_size():
+    import paper_1702_07409_amd as fs
+    g, _ = graphs(k=100, n=170, dist="raptor", seed=3)
+    ch = fs.fs_checks_generate(g)
+    before = ch.export()
+    with pytest.raises(fs.FsError):
+        ch.add_groups(g, fs.fs_precode_build(75, 90))
+    assert ch.export() == before

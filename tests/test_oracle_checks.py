@@ -184,3 +184,37 @@ def test_check_data_size_formula_and_round_trip():
 def test_check_data_rejects_malformed_arrays(arr):
     with pytest.raises(ValueError):
         checks.parse_check_data(arr)
+
+
+def test_extra_groups_from_a_degree_one_block():
+    # coded block 3 has degree one (input 0) while input 0's check #2 set is
+    # {0, 1}: c_3 = x_0 = c_0 ^ c_1, so {0, 1, 3} XORs to zero
+    G = graph.from_rows(2, [[0, 1], [1], [0, 1], [0]])
+    extra = checks.extra_groups(G, {0: [0, 1], 1: [1]})
+    assert extra == [[0, 1, 3]]
+    # a degree-one block that is itself input 0's check #2 set adds nothing
+    assert checks.extra_groups(G, {0: [3], 1: [1]}) == []
+
+
+def test_extra_groups_hold_on_precoded_payloads():
+    # every group from degree-one blocks and from the precode's check #1 sets
+    # (Eqs. (1)-(4)) XORs to zero on an encoded precoded object
+    from oracle import precode
+    b, k, n = 85, 100, 170
+    G = G_of(k, n, seed=3, dist="raptor")
+    check2, check3 = checks.split(*checks.cga(G)[:2])
+    c1 = precode.checks(b, k)
+    data = gen.payload(0, 9, b, 32)
+    x = precode.encode(b, k, data)
+    c = codec.encode(G, x)
+    extra = checks.extra_groups(G, check2, c1)
+    from_c1 = checks.extra_groups(G, check2, c1)[len(checks.extra_groups(G, check2)):]
+    assert from_c1, "no check #1 set had every member in check #2"
+    for grp in extra:
+        acc = np.zeros(32, np.uint8)
+        for s in grp:
+            acc ^= c[s]
+        assert not acc.any()
+    merged = checks.with_extra_groups(check3, extra)
+    assert [len(gr) for gr in merged] == sorted(len(gr) for gr in merged)
+    assert len({tuple(gr) for gr in merged}) == len(merged) >= len(check3)
