@@ -423,7 +423,7 @@ FS_API fs_status fs_checks_load(const fs_graph *g, const int32_t *data, uint64_t
  * rows not rebuilt, levels run}, or {0, n_lost, -FS_ERR_INVALID} for a bad
  * lost id (>= n or repeated; then nothing is written).  ws:
  * FS_OP_REPAIR_LOCAL bytes with n_items = n_lost.  FS_ERR_UNSUPPORTED for
- * codes of more than 786432 rows.
+ * codes of more than 524288 rows or checks with more than 2n groups.
  */
 FS_API fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c,
                           const uint8_t *erased, const uint32_t *lost, uint32_t n_lost,

@@ -186,6 +186,8 @@ void carve_update(Carver &cv, const fs_graph *g, uint64_t t, uint32_t n_ids, Upd
 
 struct LocalBufs {
   int32_t *chosen, *level, *pos, *item_ptr, *item_col, *item_dst, *lvl_ptr, *meta, *flag;
+  unsigned long long *gacc;
+  int32_t *rof, *best, *fa, *fb;
 };
 
 // the XOR lists are bounded by n blocks per lost row
@@ -200,6 +202,12 @@ void carve_local(Carver &cv, const fs_graph *g, uint32_t n_lost, LocalBufs &b) {
   b.lvl_ptr = cv.take<int32_t>((size_t)n_lost + 2);
   b.meta = cv.take<int32_t>(4);
   b.flag = cv.take<int32_t>(4);
+  // group peel: at most 2n groups (n - k from the generation, at most n + k added)
+  b.gacc = cv.take<unsigned long long>(2ull * g->n + 1);
+  b.rof = cv.take<int32_t>((size_t)g->n + 1);
+  b.best = cv.take<int32_t>((size_t)g->n + 1);
+  b.fa = cv.take<int32_t>(4ull * g->n + 2);
+  b.fb = cv.take<int32_t>(4ull * g->n + 2);
 }
 
 struct PrecodeBufs {
@@ -1427,7 +1435,7 @@ fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const
   FS_TRY(check_graph(g));
   if (!ch || !ch->d_base) return fail(FS_ERR_INVALID, "checks is null");
   if (ch->n != g->n || ch->k != g->k) return fail(FS_ERR_INVALID, "the checks belong to another graph shape");
-  if (g->n > kLocalMaxN) return fail(FS_ERR_UNSUPPORTED, "local repair plans codes of at most 786432 blocks");
+  if (g->n > kLocalMaxN) return fail(FS_ERR_UNSUPPORTED, "local repair plans codes of at most 524288 blocks");
   FS_TRY(check_payload(c, t, "c"));
   if ((n_lost && (!lost || !repaired)) || !status)
     return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
@@ -1455,6 +1463,13 @@ fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const
   pj.flag = b.flag;
   pj.repaired = repaired;
   pj.status = status;
+  pj.n_groups = (uint32_t)(ch->grp_ptr.size() - 1);
+  pj.gacc = b.gacc;
+  pj.rof = b.rof;
+  pj.best = b.best;
+  pj.fa = b.fa;
+  pj.fb = b.fb;
+  if ((uint64_t)pj.n_groups > 2ull * g->n) return fail(FS_ERR_UNSUPPORTED, "more than 2n check #3 groups");
   FS_TRY(launch_local_plan(pj, stream));
   if (n_lost == 0) return FS_OK;
   return launch_local_apply(pj, static_cast<uint8_t *>(c), t, stream);

@@ -16,7 +16,7 @@
 //                      holding it whose other members are all known; writes
 //                      the XOR lists in level order
 //   local_apply_kernel rebuilds the blocks level by level, one workgroup per
-//                      256-byte slice of every block
+//                      16- to 256-byte slice of every block
 //
 // The bitsets live in a workspace the generation call allocates; the columns
 // of the workgroup's current j are copied to LDS.  Reads after a barrier of
@@ -193,23 +193,38 @@ __device__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *sh) {
   return sh[tid];
 }
 
-// BP over the check #3 groups.  The unknown blocks (erased or lost) are a
-// bitset in LDS.  At each level every lost block still unknown takes the
-// first group on its list whose other members are all known; after a
-// barrier the blocks taken become known, and the loop ends at a level that
-// takes none.  The items are then laid out level by level (blocks in lost
-// order within a level, the unrebuilt ones last with no sources).
+// BP over the check #3 groups, run as a peel over them.  The unknown blocks
+// (erased or lost) are a bitset in LDS.  Every group carries (unknown
+// members << 40 | sum of their ids), so a group with one unknown names it.
+// A level takes the frontier of such groups; each lost block still unknown
+// that one of them names keeps the smallest such group index (the first
+// group in the stored order whose other members are all known).  After a
+// barrier the blocks taken become known and every group holding one loses
+// it; a group left with one unknown joins the next frontier.  The loop ends
+// at a level that takes none.  The items are then laid out level by level
+// (blocks in lost order within a level, the unrebuilt ones last with no
+// sources).
+constexpr unsigned long long kGrpOne = 1ull << 40;
+
 __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J) {
-  extern __shared__ uint32_t down[];   // [ceil(n / 32)]
-  __shared__ uint32_t s_bad, s_picked, s_fail;
+  extern __shared__ uint32_t lds[];
+  uint32_t *down = lds;                                // [ceil(n / 32)] unknown blocks
+  uint32_t *took = lds + (J.n + 31) / 32;              // [ceil(n / 32)] taken at this level
+  __shared__ uint32_t s_bad, s_fail, s_nA, s_nB, s_nT;
   __shared__ uint32_t scan_sh[kCgaThreads];
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t nw = (J.n + 31) / 32, m = J.n_lost;
+  const uint32_t nw = (J.n + 31) / 32, m = J.n_lost, ng = J.n_groups;
   if (tid == 0) {
     s_bad = 0;
     s_fail = 0;
+    s_nA = 0;
+    s_nB = 0;
+    s_nT = 0;
   }
-  for (uint32_t w = tid; w < nw; w += nt) down[w] = 0;
+  for (uint32_t w = tid; w < nw; w += nt) {
+    down[w] = 0;
+    took[w] = 0;
+  }
   __syncthreads();
   for (uint32_t r = tid; r < m; r += nt) {
     const uint32_t s = J.lost[r];
@@ -234,44 +249,94 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
     }
     return;
   }
+  // lost index of every block, smallest usable group per lost block
+  for (uint32_t s = tid; s < J.n; s += nt) {
+    J.rof[s] = -1;
+    J.best[s] = 0x7fffffff;
+  }
+  __syncthreads();
   for (uint32_t r = tid; r < m; r += nt) {
     J.chosen[r] = -1;
     J.level[r] = -1;
+    J.rof[J.lost[r]] = (int32_t)r;
   }
+  // unknown members of every group; the groups with one form the first frontier
+  for (uint32_t q = tid; q < ng; q += nt) {
+    unsigned long long acc = 0;
+    for (int32_t e = J.grp_ptr[q]; e < J.grp_ptr[q + 1]; ++e) {
+      const uint32_t u = (uint32_t)J.grp_col[e];
+      if ((down[u >> 5] >> (u & 31)) & 1u) acc += kGrpOne | u;
+    }
+    J.gacc[q] = acc;
+    if ((acc >> 40) == 1ull) {
+      const uint32_t at = atomicAdd(&s_nA, 1u);
+      J.fa[2 * at] = (int32_t)q;
+      J.fa[2 * at + 1] = (int32_t)(acc & (kGrpOne - 1));
+    }
+  }
+  __syncthreads();
+  int32_t *cur = J.fa, *nxt = J.fb;
   int level = 0;
   for (;;) {
-    if (tid == 0) s_picked = 0;
+    const uint32_t nA = s_nA;
+    // each frontier group offers its unknown block, if that block is lost
+    // and still unknown; the block keeps the smallest group index
+    for (uint32_t a = tid; a < nA; a += nt) {
+      const int32_t q = cur[2 * a];
+      const uint32_t u = (uint32_t)cur[2 * a + 1];
+      if (u >= J.n || J.rof[u] < 0 || !((down[u >> 5] >> (u & 31)) & 1u)) continue;
+      atomicMin(&J.best[u], q);
+      const uint32_t bit = 1u << (u & 31);
+      if (!(atomicOr(&took[u >> 5], bit) & bit)) atomicAdd(&s_nT, 1u);
+    }
     __syncthreads();
-    uint32_t cnt = 0;
-    for (uint32_t r = tid; r < m; r += nt) {
-      if (J.level[r] >= 0) continue;
-      const uint32_t s = J.lost[r];
-      int32_t pick = -1;
-      for (int32_t e = J.sym_ptr[s]; e < J.sym_ptr[s + 1] && pick < 0; ++e) {
-        const int32_t g = J.sym_grp[e];
-        bool ok = true;
-        for (int32_t q = J.grp_ptr[g]; q < J.grp_ptr[g + 1] && ok; ++q) {
-          const uint32_t u = (uint32_t)J.grp_col[q];
-          if (u != s && ((down[u >> 5] >> (u & 31)) & 1u)) ok = false;
-        }
-        if (ok) pick = g;
-      }
-      if (pick >= 0) {
-        J.chosen[r] = pick;
+    const uint32_t taken = s_nT;
+    __syncthreads();   // every thread has read the count before it is reused
+    if (taken == 0) break;
+    // the blocks taken at this level, listed (J.pos serves as the list until
+    // the layout below), then one wave per block: record it, make it known,
+    // and remove it from every group holding it, the lanes splitting its
+    // groups
+    if (tid == 0) s_nT = 0;
+    __syncthreads();
+    for (uint32_t w = tid; w < nw; w += nt) {
+      const uint32_t x = took[w];
+      if (!x) continue;
+      uint32_t at = atomicAdd(&s_nT, (uint32_t)__popc(x));
+      for (uint32_t y = x; y; y &= y - 1) J.pos[at++] = (int32_t)(32u * w + (uint32_t)__ffs(y) - 1u);
+      took[w] = 0;
+    }
+    __syncthreads();
+    const uint32_t nT = s_nT, lane = tid & 63u, wave = tid >> 6, nwave = nt >> 6;
+    for (uint32_t i = wave; i < nT; i += nwave) {
+      const uint32_t u = (uint32_t)J.pos[i];
+      if (lane == 0) {
+        const int32_t r = J.rof[u];
+        J.chosen[r] = atomicAdd(&J.best[u], 0);
         J.level[r] = level;
-        ++cnt;
+        atomicAnd(&down[u >> 5], ~(1u << (u & 31)));
+      }
+      const unsigned long long dec = 0ull - (kGrpOne | u);
+      for (int32_t e = J.sym_ptr[u] + (int32_t)lane; e < J.sym_ptr[u + 1]; e += 64) {
+        const int32_t q = J.sym_grp[e];
+        const unsigned long long after = atomicAdd(&J.gacc[q], dec) + dec;
+        if ((after >> 40) == 1ull) {
+          const uint32_t at = atomicAdd(&s_nB, 1u);
+          nxt[2 * at] = q;
+          nxt[2 * at + 1] = (int32_t)(after & (kGrpOne - 1));
+        }
       }
     }
-    if (cnt) atomicAdd(&s_picked, cnt);
-    __syncthreads();
-    if (s_picked == 0) break;
-    // the blocks rebuilt at this level are known from the next one on
-    for (uint32_t r = tid; r < m; r += nt)
-      if (J.level[r] == level) {
-        const uint32_t s = J.lost[r];
-        atomicAnd(&down[s >> 5], ~(1u << (s & 31)));
-      }
     ++level;
+    __syncthreads();
+    if (tid == 0) {
+      s_nA = s_nB;
+      s_nB = 0;
+      s_nT = 0;
+    }
+    int32_t *tmp = cur;
+    cur = nxt;
+    nxt = tmp;
     __syncthreads();
   }
   // level order: a contiguous run of lost blocks per thread, one scan per
@@ -333,25 +398,34 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
   }
 }
 
-// One workgroup per 256-byte slice of every block walks the levels: sixteen
-// items at a time, sixteen lanes each, XOR their sources and store the
+// One workgroup per slice of 16 LPS bytes of every block walks the levels:
+// 256 / LPS items at a time, LPS lanes each, XOR their sources and store the
 // result; a barrier between levels orders a level's stores before the next
 // level's loads (blocks rebuilt earlier are sources later).
+template <int LPS>
 __global__ __launch_bounds__(256) void local_apply_kernel(LocalPlanJob J, uint8_t *c, uint64_t t) {
   if (J.flag[0]) return;
+  constexpr int IPW = 256 / LPS;
   const int levels = J.meta[0];
-  const uint32_t lane = threadIdx.x & 15u, it = threadIdx.x >> 4;
-  const uint64_t off = (uint64_t)blockIdx.x * 256u + lane * 16u;
+  const uint32_t lane = threadIdx.x % LPS, it = threadIdx.x / LPS;
+  const uint64_t off = (uint64_t)blockIdx.x * (16u * LPS) + lane * 16u;
   const bool live = off < t;
   const v4u zero = {0u, 0u, 0u, 0u};
   for (int l = 0; l <= levels; ++l) {
     const int p1 = J.lvl_ptr[l + 1];
     if (live)
-      for (int p = J.lvl_ptr[l] + (int)it; p < p1; p += 16) {
+      for (int p = J.lvl_ptr[l] + (int)it; p < p1; p += IPW) {
         v4u acc = zero;
         const int e1 = J.item_ptr[p + 1];
-        for (int e = J.item_ptr[p]; e < e1; ++e)
-          acc ^= *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
+        int e = J.item_ptr[p];
+        for (; e + 4 <= e1; e += 4) {
+          const v4u a0 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
+          const v4u a1 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 1] * t + off);
+          const v4u a2 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 2] * t + off);
+          const v4u a3 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 3] * t + off);
+          acc ^= (a0 ^ a1) ^ (a2 ^ a3);
+        }
+        for (; e < e1; ++e) acc ^= *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
         *reinterpret_cast<v4u *>(c + (uint64_t)(uint32_t)J.item_dst[p] * t + off) = acc;
       }
     __syncthreads();
@@ -381,7 +455,7 @@ fs_status run_cga(const CgaJob &job, hipStream_t s) {
 }
 
 fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s) {
-  const size_t lds = 4ull * ((job.n + 31) / 32);
+  const size_t lds = 8ull * ((job.n + 31) / 32);
   const void *fn = reinterpret_cast<const void *>(&local_plan_kernel);
   if (lds > 32 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(local_plan_kernel, dim3(1), dim3(kCgaThreads), lds, s, job);
@@ -389,11 +463,25 @@ fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s) {
 }
 
 fs_status launch_local_apply(const LocalPlanJob &plan, uint8_t *c, uint64_t t, hipStream_t s) {
-  const uint64_t nslices = (t + 255) / 256;
+  // the widest slice (16 to 256 bytes) that still gives every CU two workgroups
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const uint64_t want = 2ull * (uint64_t)device_info(dev).cu_count;
+  int lps = 16;
+  while (lps > 1 && (t + 16ull * lps - 1) / (16ull * lps) < want) lps /= 2;
+  const uint64_t nslices = (t + 16ull * lps - 1) / (16ull * lps);
   if (nslices == 0) return FS_OK;
   if (nslices > 0x7fffffffull) return fail(FS_ERR_UNSUPPORTED, "block too large for the local repair");
-  hipLaunchKernelGGL(local_apply_kernel, dim3((uint32_t)nslices), dim3(256), 0, s, plan, c, t);
+  const dim3 grid((uint32_t)nslices), block(256);
+  switch (lps) {
+    case 16: hipLaunchKernelGGL(local_apply_kernel<16>, grid, block, 0, s, plan, c, t); break;
+    case 8: hipLaunchKernelGGL(local_apply_kernel<8>, grid, block, 0, s, plan, c, t); break;
+    case 4: hipLaunchKernelGGL(local_apply_kernel<4>, grid, block, 0, s, plan, c, t); break;
+    case 2: hipLaunchKernelGGL(local_apply_kernel<2>, grid, block, 0, s, plan, c, t); break;
+    default: hipLaunchKernelGGL(local_apply_kernel<1>, grid, block, 0, s, plan, c, t); break;
+  }
   return ck_hip(hipGetLastError(), "local repair launch");
 }
+
 
 }  // namespace fs

@@ -292,12 +292,19 @@ struct LocalPlanJob {
   int32_t *flag;             // ws: non-zero = bad ids, nothing written
   uint8_t *repaired;         // out [n_lost]
   int32_t *status;           // out [3]
+  // group peel state: per group (unknown members << 40 | sum of their ids),
+  // per block its lost index (-1) and smallest usable group, two frontiers of
+  // (group, unknown block) pairs
+  uint32_t n_groups;
+  unsigned long long *gacc;  // ws: [2n]
+  int32_t *rof, *best;       // ws: [n] each
+  int32_t *fa, *fb;          // ws: [2 * 2n] each
 };
 fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s);
 // the rebuild of the lost blocks in c, level by level, from a local plan
 fs_status launch_local_apply(const LocalPlanJob &plan, uint8_t *c, uint64_t t, hipStream_t s);
 // the largest n local repair plans for (its unknown-block bitset sits in LDS)
-constexpr uint32_t kLocalMaxN = 786432;
+constexpr uint32_t kLocalMaxN = 524288;
 
 struct RepairCheckJob {
   const int32_t *row_ptr, *col;
