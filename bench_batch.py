@@ -505,6 +505,12 @@ def run_checks(reps=10):
         n_rec = int(rec.sum().item())
         row["conventional"] = {"ms": round(t_conv, 4), "repaired": n_conv, "exact": conv_ok,
                                "decode_recovered": n_rec, "bytes_read": n_rec * t, "bytes_transferred": n_rec * t}
+        # the same with the two-stage decode (the precode's BP after the LDGM one)
+        ws_p = fs.workspace(g, fs.FS_OP_REPAIR_PRECODED, t, m)
+        t_pre = _time(lambda: fs.fs_repair_precoded(g, pc, c, None, lost, m, rep2, st2, t, ws_p), reps)
+        n_pre = int(rep2.sum().item())
+        row["conventional_precoded"] = {"ms": round(t_pre, 4), "repaired": n_pre,
+                                        "exact": bool(torch.equal(c[:m][rep2.bool()], c_ref[rep2.bool()]))}
         out["codes"].append(row)
         del x, c, xd, c_ref
         torch.cuda.empty_cache()

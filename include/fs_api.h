@@ -158,7 +158,7 @@ FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t
 enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
        FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6, FS_OP_EXTEND = 7,
        FS_OP_EXTEND_CONVENTIONAL = 8, FS_OP_SIM_DISKS = 9, FS_OP_DECODE_PRECODED = 10,
-       FS_OP_REPAIR_LOCAL = 11 };
+       FS_OP_REPAIR_LOCAL = 11, FS_OP_REPAIR_PRECODED = 12 };
 
 /*
  * Workspace bytes the operation needs for this graph and block size
@@ -335,6 +335,20 @@ FS_API fs_status fs_decode_precoded(const fs_graph *g, const fs_precode *pc, con
                              const uint8_t *erased, uint32_t maxit, void *x, uint8_t *recovered,
                              int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
                              hipStream_t stream);
+
+/*
+ * Conventional repair of a precoded code (§4: decode the entire data, then
+ * re-run the encoding of the lost chunks): the two-stage decode of
+ * fs_decode_precoded from the rows neither erased nor lost; if every data
+ * block comes back, the parity blocks are encoded again from it, so every
+ * input is known.  A lost row is rebuilt in c when all its inputs are known,
+ * else zero-filled.  lost, repaired, status and the id checks are as in
+ * fs_repair.  ws: FS_OP_REPAIR_PRECODED bytes.  g->k must equal pc's k.
+ */
+FS_API fs_status fs_repair_precoded(const fs_graph *g, const fs_precode *pc, void *c, const uint8_t *erased,
+                                    const uint32_t *lost, uint32_t n_lost, uint8_t *repaired,
+                                    int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                                    hipStream_t stream);
 
 /*
  * Disk-failure sweep of a precoded code: as fs_sim_disks, with a

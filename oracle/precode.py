@@ -23,6 +23,12 @@ Functions and the passage each follows
                  over the checks: at each level every check with exactly one
                  unknown member names it; the named blocks are recovered from
                  their check of lowest index.
+  repair_two_stage  the conventional repair of a precoded code (§4: decode
+                 the entire data, then re-run the encoding of the lost
+                 chunks): the two-stage decode from the rows neither erased
+                 nor lost; with every data block back, the parity blocks are
+                 encoded again, so every input is known; a lost row is
+                 rebuilt when all its inputs are known.
 
 Readings (the paper states neither explicitly):
   * Row r of L(1) lists the blocks whose XOR is parity block b + r.  The
@@ -128,3 +134,29 @@ def decode_two_stage(G, b, c, erased, maxit=0):
         x[~known] = 0
     data_ok = known[:b]
     return x[:b], data_ok.astype(np.uint8), (int(data_ok.all()), int(b - data_ok.sum()), int(st[2]), int(levels2))
+
+
+def repair_two_stage(G, b, c, erased, lost, maxit=0):
+    """Returns (blocks[m, t], repaired[m]); rows that cannot be rebuilt are
+    zero."""
+    k = G.k
+    erased2 = np.asarray(erased, dtype=bool).copy()
+    erased2[list(lost)] = True
+    x, rec, _, _ = codec.decode(G, c, erased2, maxit)
+    known = rec.astype(bool)
+    if not known[:b].all():
+        x, known, _ = precode_bp(b, k, x, known)
+    if known[:b].all():
+        x = encode(b, k, x[:b])
+        known[:] = True
+    t = c.shape[1]
+    out = np.zeros((len(lost), t), dtype=np.uint8)
+    ok = np.zeros(len(lost), dtype=np.uint8)
+    for r, j in enumerate(lost):
+        N = [int(i) for i in G.N(j)]
+        if all(known[i] for i in N):
+            acc = np.zeros(t, dtype=np.uint8)
+            for i in N:
+                acc ^= x[i]
+            out[r], ok[r] = acc, 1
+    return out, ok

@@ -36,7 +36,8 @@ FS_DIST_RSD, FS_DIST_FINITE, FS_DIST_RAPTOR = 0, 1, 2
 FS_DEFAULT_SEED = 1389488782
 FS_GRAPH_HOST_ONLY = 1
 (FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE, FS_OP_REPLAY,
- FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS, FS_OP_DECODE_PRECODED, FS_OP_REPAIR_LOCAL) = range(12)
+ FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS, FS_OP_DECODE_PRECODED, FS_OP_REPAIR_LOCAL,
+ FS_OP_REPAIR_PRECODED) = range(13)
 
 DIST_CODES = {"rsd": FS_DIST_RSD, "finite": FS_DIST_FINITE, "raptor": FS_DIST_RAPTOR}
 
@@ -104,6 +105,7 @@ _SIGS = {
     "fs_precode_free": ([P], None),
     "fs_precode_encode": ([P, P, U64, P], ST),
     "fs_decode_precoded": ([P, P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
+    "fs_repair_precoded": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
     "fs_sim_disks_precoded": ([P, P, U32, U32, U64, U64, U32, P, P, SZ, P], ST),
     "fs_checks_generate": ([P, U32, P, ctypes.POINTER(P)], ST),
     "fs_checks_info": ([P, ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32), ctypes.POINTER(U32),
@@ -452,6 +454,12 @@ def fs_repair_local(g, ch, c, erased, lost, n_lost, repaired, status, t, ws, str
     w, wb = _ws(ws)
     _check(_lib.fs_repair_local(g.handle, ch.handle, _ptr(c), _ptr(erased), _ptr(lost), n_lost, _ptr(repaired),
                                 _ptr(status), t, w, wb, _stream(stream)), "fs_repair_local")
+
+
+def fs_repair_precoded(g, pc, c, erased, lost, n_lost, repaired, status, t, ws, stream=None):
+    w, wb = _ws(ws)
+    _check(_lib.fs_repair_precoded(g.handle, pc.handle, _ptr(c), _ptr(erased), _ptr(lost), n_lost, _ptr(repaired),
+                                   _ptr(status), t, w, wb, _stream(stream)), "fs_repair_precoded")
 
 
 def fs_sim_disks_precoded(g, pc, s, f, first, count, maxit, result, ws, stream=None):

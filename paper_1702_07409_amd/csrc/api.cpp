@@ -295,6 +295,13 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
       carve_precode(cv, g->k, b);
       return cv.size();
     }
+    case FS_OP_REPAIR_PRECODED: {
+      RepairBufs b;
+      carve_repair(cv, g, t, true, b);
+      cv.take<uint8_t>(workspace_bytes(g, FS_OP_DECODE_PRECODED, t, 0));
+      cv.take<int32_t>(4);
+      return cv.size();
+    }
     case FS_OP_EXTEND:
     case FS_OP_EXTEND_CONVENTIONAL: {
       const bool conventional = (op == FS_OP_EXTEND_CONVENTIONAL);
@@ -534,8 +541,9 @@ void fs_graph_free(fs_graph *g) {
 fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
-  if (op < FS_OP_ENCODE || op > FS_OP_REPAIR_LOCAL) return fail(FS_ERR_INVALID, "unknown operation");
-  if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_EXTEND_CONVENTIONAL || op == FS_OP_UPDATE) &&
+  if (op < FS_OP_ENCODE || op > FS_OP_REPAIR_PRECODED) return fail(FS_ERR_INVALID, "unknown operation");
+  if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_EXTEND_CONVENTIONAL || op == FS_OP_UPDATE ||
+       op == FS_OP_REPAIR_PRECODED) &&
       (t == 0 || (t & 15)))
     return fail(FS_ERR_ALIGN, "t must be a positive multiple of 16");
   *bytes = workspace_bytes(g, op, t, n_items);
@@ -717,12 +725,42 @@ fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *erased, uin
 
 // Repair of the rows lost[0..n_lost) with the workspace already checked; cv
 // points at the part of it that carve_repair lays out.
+static fs_status precode_encode_impl(const fs_precode *pc, void *x, uint64_t t, const int32_t *skip_flag,
+                                     hipStream_t stream);
+
+// The end of a conventional repair: a lost row is rebuilt when all its
+// inputs were recovered into b.x, else zero-filled.
+static fs_status repair_finish(const fs_graph *g, const uint32_t *lost, uint32_t n_lost, uint8_t *repaired,
+                               int32_t *status, RepairBufs &b, GatherJob &gj, hipStream_t stream) {
+  RepairCheckJob cj{};
+  cj.row_ptr = g->d_row_ptr;
+  cj.col = g->d_col;
+  cj.n = g->n;
+  cj.lost = lost;
+  cj.n_lost = n_lost;
+  cj.recovered = b.sched.recovered;
+  cj.flag = b.flag;
+  cj.repaired = repaired;
+  cj.status = status;
+  FS_TRY(launch_repair_check(cj, stream));
+  gj.src = b.x;
+  gj.row_ok = repaired;
+  return launch_gather(gj, tile_for(current_tune(), g), stream);
+}
+
 static fs_status repair_impl(const fs_graph *g, const void *x, void *c, const uint8_t *erased,
                              const uint32_t *lost, uint32_t n_lost, uint8_t *repaired, int32_t *status,
-                             uint64_t t, Carver &cv, hipStream_t stream) {
+                             uint64_t t, Carver &cv, hipStream_t stream, const fs_precode *pc = nullptr) {
   const bool conventional = (x == nullptr);
   RepairBufs b;
   carve_repair(cv, g, t, conventional, b);
+  uint8_t *pws = nullptr;
+  int32_t *skip = nullptr;
+  const size_t pws_bytes = pc ? workspace_bytes(g, FS_OP_DECODE_PRECODED, t, 0) : 0;
+  if (pc) {
+    pws = cv.take<uint8_t>(pws_bytes);
+    skip = cv.take<int32_t>(4);
+  }
 
   RepairPrepJob pj{};
   pj.n = g->n;
@@ -754,6 +792,14 @@ static fs_status repair_impl(const fs_graph *g, const void *x, void *c, const ui
     gj.src = static_cast<const uint8_t *>(x);
     return launch_gather(gj, tile_for(current_tune(), g), stream);
   }
+  if (pc) {
+    // two-stage decode of everything, then the parity again when the data is complete
+    FS_TRY(fs_decode_precoded(g, pc, c, b.erased2, 0, b.x, b.sched.recovered, b.sched.status, t, pws, pws_bytes,
+                              stream));
+    FS_TRY(launch_parity_known(b.sched.status, b.sched.recovered, pc->b, pc->k, b.flag, skip, stream));
+    FS_TRY(precode_encode_impl(pc, b.x, t, skip, stream));
+    return repair_finish(g, lost, n_lost, repaired, status, b, gj, stream);
+  }
   PeelJob j = peel_job(g, b.erased2, 0, b.sched.recovered, b.sched.status, b.sched.level_ptr, b.sched.dp_f,
                        b.sched.dp_g);
   j.acc = b.peel.acc;
@@ -777,20 +823,7 @@ static fs_status repair_impl(const fs_graph *g, const void *x, void *c, const ui
   p.dp_g = b.sched.dp_g;
   p.skip_flag = b.flag;
   FS_TRY(launch_replay(r, &p, stream));
-  RepairCheckJob cj{};
-  cj.row_ptr = g->d_row_ptr;
-  cj.col = g->d_col;
-  cj.n = g->n;
-  cj.lost = lost;
-  cj.n_lost = n_lost;
-  cj.recovered = b.sched.recovered;
-  cj.flag = b.flag;
-  cj.repaired = repaired;
-  cj.status = status;
-  FS_TRY(launch_repair_check(cj, stream));
-  gj.src = b.x;
-  gj.row_ok = repaired;
-  return launch_gather(gj, tile_for(current_tune(), g), stream);
+  return repair_finish(g, lost, n_lost, repaired, status, b, gj, stream);
 }
 
 fs_status fs_repair(const fs_graph *g, const void *x, void *c, const uint8_t *erased, const uint32_t *lost,
@@ -1032,6 +1065,12 @@ fs_status fs_precode_encode(const fs_precode *pc, void *x, uint64_t t, hipStream
   clear_error();
   FS_TRY(check_precode(pc));
   FS_TRY(check_payload(x, t, "x"));
+  return precode_encode_impl(pc, x, t, nullptr, stream);
+}
+
+// The parity block rows of the precode as gathers (skip_flag: as GatherJob's).
+static fs_status precode_encode_impl(const fs_precode *pc, void *x, uint64_t t, const int32_t *skip_flag,
+                                     hipStream_t stream) {
   fs_tune tune = current_tune();
   if (tune.lanes_per_row == 0) {
     tune.lanes_per_row = 64;
@@ -1048,9 +1087,25 @@ fs_status fs_precode_encode(const fs_precode *pc, void *x, uint64_t t, hipStream
     gj.nrows = pc->p;
     gj.csr_rows = pc->p;
     gj.t = t;
+    gj.skip_flag = skip_flag;
     FS_TRY(launch_gather(gj, tune, stream));
   }
   return FS_OK;
+}
+
+fs_status fs_repair_precoded(const fs_graph *g, const fs_precode *pc, void *c, const uint8_t *erased,
+                             const uint32_t *lost, uint32_t n_lost, uint8_t *repaired, int32_t *status, uint64_t t,
+                             void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_graph(g));
+  FS_TRY(check_precode(pc));
+  if (pc->k != g->k) return fail(FS_ERR_INVALID, "the graph's k differs from the precode's");
+  FS_TRY(check_payload(c, t, "c"));
+  if ((n_lost && (!lost || !repaired)) || !status)
+    return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
+  FS_TRY(check_ws(g, FS_OP_REPAIR_PRECODED, t, n_lost, ws, ws_bytes));
+  Carver cv(ws);
+  return repair_impl(g, nullptr, c, erased, lost, n_lost, repaired, status, t, cv, stream, pc);
 }
 
 fs_status fs_decode_precoded(const fs_graph *g, const fs_precode *pc, const void *c, const uint8_t *erased,

@@ -262,6 +262,10 @@ struct PrecodeReplayJob {
   const int32_t *chk_ptr, *chk_col, *pair_sym, *pair_chk, *level_ptr, *meta;
 };
 fs_status launch_precode_replay(const PrecodeReplayJob &job, hipStream_t s);
+// after a two-stage decode: mark the parity blocks known when every data
+// block came back, else set skip[0] (also when bad[0] is set)
+fs_status launch_parity_known(const int32_t *status, uint8_t *recovered, uint32_t b, uint32_t k, const int32_t *bad,
+                              int32_t *skip, hipStream_t s);
 
 // Check generation and local repair (checks.hip).
 struct CgaJob {

@@ -220,6 +220,25 @@ fs_status build_precode_host(uint32_t b, uint32_t k, fs_precode &pc) {
 
 size_t precode_peel_lds(uint32_t k, uint32_t m) { return 4ull * (2ull * m + (k + 31) / 32); }
 
+// After a two-stage decode for a repair: with every data block back
+// (status[0]) the parity blocks count as known, since they are encoded again
+// from the data; skip[0] tells that encode to write nothing otherwise, or
+// when the repair's ids were rejected (bad[0]).
+__global__ __launch_bounds__(256) void parity_known_kernel(const int32_t *status, uint8_t *recovered, uint32_t b,
+                                                           uint32_t k, const int32_t *bad, int32_t *skip) {
+  const bool all = status[0] != 0 && bad[0] == 0;
+  for (uint32_t i = b + blockIdx.x * 256u + threadIdx.x; all && i < k; i += gridDim.x * 256u) recovered[i] = 1;
+  if (blockIdx.x == 0 && threadIdx.x == 0) skip[0] = all ? 0 : 1;
+}
+
+fs_status launch_parity_known(const int32_t *status, uint8_t *recovered, uint32_t b, uint32_t k, const int32_t *bad,
+                              int32_t *skip, hipStream_t s) {
+  const uint32_t grid = std::max<uint32_t>(1, std::min<uint32_t>(64, (k - b + 255) / 256));
+  hipLaunchKernelGGL(parity_known_kernel, dim3(grid), dim3(256), 0, s, status, recovered, b, k, bad, skip);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FS_OK : fail(FS_ERR_HIP, std::string("parity launch: ") + hipGetErrorString(e));
+}
+
 fs_status launch_precode_peel(const PrecodePeelJob &job, hipStream_t s) {
   const size_t lds = precode_peel_lds(job.k, job.m);
   const void *fn = reinterpret_cast<const void *>(&precode_peel_kernel);

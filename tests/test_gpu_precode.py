@@ -121,3 +121,52 @@ def test_precode_arguments_are_checked():
     hpc = fs.fs_precode_build(28, 49, host_only=True)
     with pytest.raises(fs.FsError):
         fs.fs_precode_encode(hpc, empty_u8(49, 16), 16)
+
+
+@pytest.mark.parametrize("disks,erase", [(2, False), (3, False), (3, True), (6, False)])
+def test_precoded_repair_equals_the_oracle(disks, erase):
+    # the conventional repair of Table 2's smaller code: two-stage decode,
+    # parity encoded again when the data is complete, lost rows re-encoded;
+    # with six of ten disks lost the data stays incomplete
+    import paper_1702_07409_amd as fs
+    b, k, n, t = 925, 1036, 2180, 256 + 48
+    g, G = graphs(k=k, n=n, dist="raptor", seed=1)
+    pc = fs.fs_precode_build(b, k)
+    x = precode.encode(b, k, gen.payload(0, 7, b, t))
+    c_host = codec.encode(G, x)
+    # disks 0 .. disks-1 lost, or with disk 0 erased the next ones
+    first = n // 10 if erase else 0
+    lost = list(range(first, first + disks * n // 10))
+    er = np.zeros(n, np.uint8)
+    if erase:
+        er[:n // 10] = 1
+    want, ok = precode.repair_two_stage(G, b, c_host, er, lost)
+    c = dev(c_host)
+    c[dev(np.array(lost, np.int64))] = 0x5A
+    rep, st = empty_u8(len(lost)), empty_i32(3)
+    ws = fs.workspace(g, fs.FS_OP_REPAIR_PRECODED, t, len(lost))
+    fs.fs_repair_precoded(g, pc, c, dev(er), dev(np.array(lost, np.uint32)), len(lost), rep, st, t, ws)
+    got = host(c)
+    assert np.array_equal(host(rep), ok)
+    assert np.array_equal(got[lost], want)
+    others = [j for j in range(n) if j not in set(lost)]
+    assert np.array_equal(got[others], c_host[others])
+    assert host(st).tolist()[:2] == [int(ok.all()), int(len(lost) - ok.sum())]
+    if disks == 3 and not erase:
+        _, ok1 = codec.repair_conventional(G, c_host, er, lost)
+        assert ok.all() and ok1.sum() < ok.sum()
+
+
+def test_precoded_repair_rejects_bad_ids_without_writing():
+    import paper_1702_07409_amd as fs
+    b, k, n, t = 925, 1036, 2180, 64
+    g, G = graphs(k=k, n=n, dist="raptor", seed=1)
+    pc = fs.fs_precode_build(b, k)
+    c_host = codec.encode(G, precode.encode(b, k, gen.payload(0, 8, b, t)))
+    for lost in ([3, n], [5, 9, 5]):
+        c = dev(c_host)
+        rep, st = empty_u8(len(lost)), empty_i32(3)
+        ws = fs.workspace(g, fs.FS_OP_REPAIR_PRECODED, t, len(lost))
+        fs.fs_repair_precoded(g, pc, c, None, dev(np.array(lost, np.uint32)), len(lost), rep, st, t, ws)
+        assert np.array_equal(host(c), c_host) and not host(rep).any()
+        assert host(st).tolist()[:2] == [0, len(lost)]
