@@ -390,7 +390,7 @@ FS_API fs_status fs_checks_export(const fs_checks *ch, int32_t *c3_ptr, int32_t 
 FS_API void fs_checks_free(fs_checks *ch);
 
 /*
- * The check data file (§2.8): one integer array.  A check #2 equation is the
+ * The check data file (§2.7; read back as §2.8 describes): one integer array.  A check #2 equation is the
  * record 1, input, L, then the L coded blocks whose XOR is that input; a
  * check #3 group is the record 0, L, then its L coded blocks.
  *
@@ -426,7 +426,7 @@ FS_API fs_status fs_checks_load(const fs_graph *g, const int32_t *data, uint64_t
                                 fs_checks **out);
 
 /*
- * Local-group repair, the repair engine's fast path (§2.7, §2.8, §4): BP
+ * Local-group repair, the repair engine's fast path (§2.3, §2.8, §4): BP
  * over the check #3 groups.  At each level every lost coded row s still
  * unknown is rebuilt in place in c as the XOR of the other members of the
  * first (smallest) group holding s whose other members are all known:

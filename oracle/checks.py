@@ -25,7 +25,7 @@ Functions and the passage each follows
   with_extra_groups  the groups held with them: new ones that are empty or
                  equal to a held group are skipped, then all are ordered by
                  cardinality (held ones first on ties).
-  check_data     §2.8: the integer array of the check data file.  A check #2
+  check_data     §2.7: the integer array of the check data file.  A check #2
                  equation is the record 1, input, L, then the L coded blocks
                  whose XOR is that input; a check #3 group is 0, L, then its
                  L coded blocks.
@@ -33,7 +33,7 @@ Functions and the passage each follows
   from_check_data   what the repair engine keeps from it: the first check #2
                  record per input, and the check #3 groups ordered by
                  cardinality (ties in file order), members as sets.
-  local_repair   the repair engine's fast path (§2.7, §2.8, §4): BP over the
+  local_repair   the repair engine's fast path (§2.3, §2.8, §4): BP over the
                  check #3 groups.  At each level every lost coded block
                  still unknown is rebuilt as the XOR of the other members of
                  the first (smallest) group holding it whose other members

@@ -138,7 +138,7 @@ def test_local_repair_rejects_bad_ids_without_writing():
 
 @pytest.mark.parametrize("k,n,dist", [(64, 96, "rsd"), (200, 400, "raptor")])
 def test_check_data_equals_the_oracle_and_loads_back(k, n, dist):
-    # the library's check data array equals the oracle's (§2.8 records), and
+    # the library's check data array equals the oracle's (§2.7 records), and
     # loading it back gives the same equations
     import paper_1702_07409_amd as fs
     g, G = graphs(k=k, n=n, dist=dist)
@@ -152,7 +152,7 @@ def test_check_data_equals_the_oracle_and_loads_back(k, n, dist):
 
 
 def test_check_data_of_the_paper_example_loads():
-    # §2.8's example array on a code with at least 89 coded and 20 data blocks
+    # §2.7's example array on a code with at least 89 coded and 20 data blocks
     import json
     import os
     import paper_1702_07409_amd as fs

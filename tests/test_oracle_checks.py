@@ -152,7 +152,7 @@ def test_local_repair_closure_is_order_independent():
 
 
 def test_check_data_reads_the_papers_example():
-    # §2.8's example array: #3{13, 56, 17, 66}, #2(19; 11, 13), #3{39, 88}
+    # §2.7's example array: #3{13, 56, 17, 66}, #2(19; 11, 13), #3{39, 88}
     with open(os.path.join(GOLDEN, "paper_check_data.json")) as fh:
         g = json.load(fh)
     c2, c3 = checks.parse_check_data(g["array"])
@@ -163,7 +163,7 @@ def test_check_data_reads_the_papers_example():
 
 
 def test_check_data_size_formula_and_round_trip():
-    # a converged run stores N = sum L_c + k + 2n integers (§2.8): k check #2
+    # a converged run stores N = sum L_c + k + 2n integers (§2.7): k check #2
     # records of L + 3 and n - k check #3 records of L + 2
     G = graph.from_rows(2, [[0], [1], [0, 1]])
     check2, check3 = checks.split(*checks.cga(G)[:2])
