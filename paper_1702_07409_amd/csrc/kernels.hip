@@ -30,6 +30,11 @@ constexpr int kPlanThreads = 1024;
 
 __device__ __forceinline__ v4u ld16(const uint8_t *p) { return *reinterpret_cast<const v4u *>(p); }
 
+// a load of data read once (marked to leave the caches first)
+__device__ __forceinline__ v4u ld16_once(const uint8_t *p) {
+  return __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+}
+
 template <bool NT>
 __device__ __forceinline__ void st16(uint8_t *p, v4u v) {
   if constexpr (NT)
@@ -1106,6 +1111,10 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
   // ahead (two levels ahead measured no faster than one)
   constexpr int MP = LPS >= 32 ? 4 : 2;
   constexpr int PD = 1;
+  // Each coded block is read once, so its loads are non-temporal: the caches
+  // keep the decoded inputs that later pairs read instead (replay of the
+  // 4096 x 64 KiB stripe: 0.208 -> 0.182 ms).  Marking decoded inputs that
+  // no later pair reads non-temporal as well measured no faster.
   constexpr uint32_t W = LPS * 16;
   const uint32_t lane = threadIdx.x % LPS, sym = threadIdx.x / LPS;
   const uint32_t k = J.k;
@@ -1122,7 +1131,7 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
       for (int m = 0; m < MP; ++m) {
         const int q = q0 + (int)sym + m * NS;
         const uint32_t g = q < q1 ? (uint32_t)pg[q] : 0xffffffffu;
-        dst[m] = (live && g < J.n) ? ld16(J.c + (uint64_t)g * J.t + off) : zero;
+        dst[m] = (live && g < J.n) ? ld16_once(J.c + (uint64_t)g * J.t + off) : zero;
       }
     };
 #pragma unroll
@@ -1161,7 +1170,7 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
       for (int q = q0 + (int)sym + MP * NS; q < q1; q += NS) {
         const uint32_t f = (uint32_t)pf[q], g = (uint32_t)pg[q];
         if (!live || f >= k || g >= J.n) continue;
-        v4u acc = ld16(J.c + (uint64_t)g * J.t + off);
+        v4u acc = ld16_once(J.c + (uint64_t)g * J.t + off);
         const int o1 = (int)poff[q + 1];
         for (int o = (int)poff[q]; o < o1; ++o) acc ^= ld16(J.x + (uint64_t)pidx[o] * J.t + off);
         *reinterpret_cast<v4u *>(J.x + (uint64_t)f * J.t + off) = acc;
