@@ -188,6 +188,7 @@ struct LocalBufs {
   int32_t *chosen, *level, *pos, *item_ptr, *item_col, *item_dst, *lvl_ptr, *meta, *flag;
   unsigned long long *gacc;
   int32_t *rof, *best, *fa, *fb;
+  uint32_t *unk;
 };
 
 // the XOR lists are bounded by n blocks per lost row
@@ -208,6 +209,7 @@ void carve_local(Carver &cv, const fs_graph *g, uint32_t n_lost, LocalBufs &b) {
   b.best = cv.take<int32_t>((size_t)g->n + 1);
   b.fa = cv.take<int32_t>(4ull * g->n + 2);
   b.fb = cv.take<int32_t>(4ull * g->n + 2);
+  b.unk = cv.take<uint32_t>(((size_t)g->n + 31) / 32);
 }
 
 struct PrecodeBufs {
@@ -1524,6 +1526,7 @@ fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const
   pj.best = b.best;
   pj.fa = b.fa;
   pj.fb = b.fb;
+  pj.unk = b.unk;
   if ((uint64_t)pj.n_groups > 2ull * g->n) return fail(FS_ERR_UNSUPPORTED, "more than 2n check #3 groups");
   FS_TRY(launch_local_plan(pj, stream));
   if (n_lost == 0) return FS_OK;

@@ -11,7 +11,7 @@
 //                      j is the only one that changes while it is processed,
 //                      so this visits the same (j, i) pairs as the sequential
 //                      loops and takes the same steps.
-//   local_plan_kernel  BP over the check #3 groups: level by level, each lost
+//   local_*_kernel     BP over the check #3 groups: level by level, each lost
 //                      coded block still unknown takes the first group
 //                      holding it whose other members are all known; writes
 //                      the XOR lists in level order
@@ -193,38 +193,38 @@ __device__ uint32_t block_inclusive_scan(uint32_t v, uint32_t *sh) {
   return sh[tid];
 }
 
-// BP over the check #3 groups, run as a peel over them.  The unknown blocks
-// (erased or lost) are a bitset in LDS.  Every group carries (unknown
-// members << 40 | sum of their ids), so a group with one unknown names it.
-// A level takes the frontier of such groups; each lost block still unknown
-// that one of them names keeps the smallest such group index (the first
-// group in the stored order whose other members are all known).  After a
-// barrier the blocks taken become known and every group holding one loses
-// it; a group left with one unknown joins the next frontier.  The loop ends
-// at a level that takes none.  The items are then laid out level by level
-// (blocks in lost order within a level, the unrebuilt ones last with no
-// sources).
+// BP over the check #3 groups, run as a peel over them, in four launches.
+//   local_prep_kernel   (one workgroup) checks the lost ids and builds the
+//                       bitset of unknown blocks (erased or lost)
+//   local_count_kernel  (the device) gives every group (unknown members << 40
+//                       | sum of their ids), so a group with one unknown
+//                       names it, and lists those groups: the first frontier
+//   local_plan_kernel   (one workgroup) runs the levels.  A level takes the
+//                       frontier; each lost block still unknown that one of
+//                       its groups names keeps the smallest such group index
+//                       (the first group in the stored order whose other
+//                       members are all known).  After a barrier the blocks
+//                       taken become known and every group holding one loses
+//                       it; a group left with one unknown joins the next
+//                       frontier.  The loop ends at a level that takes none.
+//                       The items are then laid out level by level (blocks in
+//                       lost order within a level, the unrebuilt ones last
+//                       with no sources).  The group counters sit in LDS when
+//                       they fit.
+//   local_fill_kernel   (the device) writes each item's sources: its group
+//                       without the block it rebuilds
 constexpr unsigned long long kGrpOne = 1ull << 40;
 
-__global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J) {
+__device__ __forceinline__ bool local_failed(const LocalPlanJob &J) { return J.flag[0] != 0; }
+
+__global__ __launch_bounds__(kCgaThreads) void local_prep_kernel(LocalPlanJob J) {
   extern __shared__ uint32_t lds[];
   uint32_t *down = lds;                                // [ceil(n / 32)] unknown blocks
-  uint32_t *took = lds + (J.n + 31) / 32;              // [ceil(n / 32)] taken at this level
-  __shared__ uint32_t s_bad, s_fail, s_nA, s_nB, s_nT;
-  __shared__ uint32_t scan_sh[kCgaThreads];
+  __shared__ uint32_t s_bad;
   const uint32_t tid = threadIdx.x, nt = blockDim.x;
-  const uint32_t nw = (J.n + 31) / 32, m = J.n_lost, ng = J.n_groups;
-  if (tid == 0) {
-    s_bad = 0;
-    s_fail = 0;
-    s_nA = 0;
-    s_nB = 0;
-    s_nT = 0;
-  }
-  for (uint32_t w = tid; w < nw; w += nt) {
-    down[w] = 0;
-    took[w] = 0;
-  }
+  const uint32_t nw = (J.n + 31) / 32, m = J.n_lost;
+  if (tid == 0) s_bad = 0;
+  for (uint32_t w = tid; w < nw; w += nt) down[w] = 0;
   __syncthreads();
   for (uint32_t r = tid; r < m; r += nt) {
     const uint32_t s = J.lost[r];
@@ -249,6 +249,7 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
     }
     return;
   }
+  for (uint32_t w = tid; w < nw; w += nt) J.unk[w] = down[w];
   // lost index of every block, smallest usable group per lost block
   for (uint32_t s = tid; s < J.n; s += nt) {
     J.rof[s] = -1;
@@ -260,20 +261,61 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
     J.level[r] = -1;
     J.rof[J.lost[r]] = (int32_t)r;
   }
-  // unknown members of every group; the groups with one form the first frontier
-  for (uint32_t q = tid; q < ng; q += nt) {
+  if (tid == 0) {
+    J.flag[0] = 0;
+    J.meta[1] = 0;
+  }
+}
+
+// one wave per group, its lanes splitting the members
+__global__ __launch_bounds__(256) void local_count_kernel(LocalPlanJob J) {
+  if (local_failed(J)) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t nwv = gridDim.x * 4u;
+  for (uint32_t q = blockIdx.x * 4u + (threadIdx.x >> 6); q < J.n_groups; q += nwv) {
     unsigned long long acc = 0;
-    for (int32_t e = J.grp_ptr[q]; e < J.grp_ptr[q + 1]; ++e) {
+    for (int32_t e = J.grp_ptr[q] + (int32_t)lane; e < J.grp_ptr[q + 1]; e += 64) {
       const uint32_t u = (uint32_t)J.grp_col[e];
-      if ((down[u >> 5] >> (u & 31)) & 1u) acc += kGrpOne | u;
+      if ((J.unk[u >> 5] >> (u & 31)) & 1u) acc += kGrpOne | u;
     }
-    J.gacc[q] = acc;
-    if ((acc >> 40) == 1ull) {
-      const uint32_t at = atomicAdd(&s_nA, 1u);
-      J.fa[2 * at] = (int32_t)q;
-      J.fa[2 * at + 1] = (int32_t)(acc & (kGrpOne - 1));
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (lane == 0) {
+      J.gacc[q] = acc;
+      if ((acc >> 40) == 1ull) {
+        const uint32_t at = (uint32_t)atomicAdd(&J.meta[1], 1);
+        J.fa[2 * at] = (int32_t)q;
+        J.fa[2 * at + 1] = (int32_t)(acc & (kGrpOne - 1));
+      }
     }
   }
+}
+
+template <bool LDSG>
+__global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char lsm[];
+  uint32_t *lds = reinterpret_cast<uint32_t *>(lsm);
+  const uint32_t nw = (J.n + 31) / 32, m = J.n_lost, ng = J.n_groups;
+  uint32_t *down = lds;                                // [nw] unknown blocks
+  uint32_t *took = lds + nw;                           // [nw] taken at this level
+  // group counters: LDS copy (8-byte aligned: 2 nw words precede it) or the workspace
+  unsigned long long *gacc = LDSG ? reinterpret_cast<unsigned long long *>(lds + 2 * nw) : J.gacc;
+  __shared__ uint32_t s_fail, s_nA, s_nB, s_nT;
+  __shared__ uint32_t scan_sh[kCgaThreads];
+  if (local_failed(J)) return;
+  const uint32_t tid = threadIdx.x, nt = blockDim.x;
+  if (tid == 0) {
+    s_fail = 0;
+    s_nA = (uint32_t)J.meta[1];
+    s_nB = 0;
+    s_nT = 0;
+  }
+  for (uint32_t w = tid; w < nw; w += nt) {
+    down[w] = J.unk[w];
+    took[w] = 0;
+  }
+  if (LDSG)
+    for (uint32_t q = tid; q < ng; q += nt) gacc[q] = J.gacc[q];
   __syncthreads();
   int32_t *cur = J.fa, *nxt = J.fb;
   int level = 0;
@@ -319,7 +361,7 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
       const unsigned long long dec = 0ull - (kGrpOne | u);
       for (int32_t e = J.sym_ptr[u] + (int32_t)lane; e < J.sym_ptr[u + 1]; e += 64) {
         const int32_t q = J.sym_grp[e];
-        const unsigned long long after = atomicAdd(&J.gacc[q], dec) + dec;
+        const unsigned long long after = atomicAdd(&gacc[q], dec) + dec;
         if ((after >> 40) == 1ull) {
           const uint32_t at = atomicAdd(&s_nB, 1u);
           nxt[2 * at] = q;
@@ -380,17 +422,7 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
     off += sz;
   }
   if (tid == nt - 1) J.item_ptr[m] = (int32_t)incl;
-  __syncthreads();
-  for (uint32_t r = r0; r < r1; ++r) {
-    const int32_t g = J.chosen[r];
-    if (g < 0) continue;
-    const uint32_t s = J.lost[r];
-    int32_t o = J.item_ptr[J.pos[r]];
-    for (int32_t q = J.grp_ptr[g]; q < J.grp_ptr[g + 1]; ++q)
-      if ((uint32_t)J.grp_col[q] != s) J.item_col[o++] = J.grp_col[q];
-  }
   if (tid == 0) {
-    J.flag[0] = 0;
     J.meta[0] = level;
     J.status[0] = s_fail == 0 ? 1 : 0;
     J.status[1] = (int32_t)s_fail;
@@ -398,20 +430,55 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
   }
 }
 
+// one wave per lost block rebuilt: its group's members but itself, in
+// order, at the item's offset (the ballot of the members kept gives each
+// lane its place)
+__global__ __launch_bounds__(256) void local_fill_kernel(LocalPlanJob J) {
+  if (local_failed(J)) return;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t nwv = gridDim.x * 4u;
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (uint32_t r = blockIdx.x * 4u + (threadIdx.x >> 6); r < J.n_lost; r += nwv) {
+    const int32_t g = J.chosen[r];
+    if (g < 0) continue;
+    const int32_t s = (int32_t)J.lost[r];
+    int32_t o = J.item_ptr[J.pos[r]];
+    const int32_t e1 = J.grp_ptr[g + 1];
+    for (int32_t e0 = J.grp_ptr[g]; e0 < e1; e0 += 64) {
+      const int32_t e = e0 + (int32_t)lane;
+      const int32_t col = e < e1 ? J.grp_col[e] : s;
+      const bool keep = col != s;
+      const unsigned long long mask = __ballot(keep);
+      if (keep) J.item_col[o + (int32_t)__popcll(mask & below)] = col;
+      o += (int32_t)__popcll(mask);
+    }
+  }
+}
+
 // One workgroup per slice of 16 LPS bytes of every block walks the levels:
 // 256 / LPS items at a time, LPS lanes each, XOR their sources and store the
 // result; a barrier between levels orders a level's stores before the next
 // level's loads (blocks rebuilt earlier are sources later).
+// Slice of workgroup b: workgroups go round-robin over the 8 XCDs (b % 8),
+// so XCD x takes the contiguous slices [start_x, start_x + count_x).  The
+// slices that share a 128-byte line then meet in one XCD's L2 instead of each
+// XCD fetching the whole line for its 16 bytes.
+__device__ __forceinline__ uint32_t slice_of_block(uint32_t b, uint32_t nwg) {
+  const uint32_t xcd = b & 7u, local = b >> 3;
+  const uint32_t per = nwg >> 3, rem = nwg & 7u;
+  return xcd * per + min(xcd, rem) + local;
+}
+
 template <int LPS>
-__global__ __launch_bounds__(256) void local_apply_kernel(LocalPlanJob J, uint8_t *c, uint64_t t) {
+__global__ __launch_bounds__(256) void local_apply_kernel(LocalPlanJob J, uint8_t *c, uint64_t t, int first) {
   if (J.flag[0]) return;
   constexpr int IPW = 256 / LPS;
   const int levels = J.meta[0];
   const uint32_t lane = threadIdx.x % LPS, it = threadIdx.x / LPS;
-  const uint64_t off = (uint64_t)blockIdx.x * (16u * LPS) + lane * 16u;
+  const uint64_t off = (uint64_t)slice_of_block(blockIdx.x, gridDim.x) * (16u * LPS) + lane * 16u;
   const bool live = off < t;
   const v4u zero = {0u, 0u, 0u, 0u};
-  for (int l = 0; l <= levels; ++l) {
+  for (int l = first; l <= levels; ++l) {
     const int p1 = J.lvl_ptr[l + 1];
     if (live)
       for (int p = J.lvl_ptr[l] + (int)it; p < p1; p += IPW) {
@@ -431,6 +498,44 @@ __global__ __launch_bounds__(256) void local_apply_kernel(LocalPlanJob J, uint8_
     __syncthreads();
   }
 }
+
+// One level of the rebuild, for blocks too short to give every CU two
+// workgroups of 128-byte slices: one wave per (item, 1 KiB chunk) of the
+// level, each lane 16 bytes, so every source load is a whole 1 KiB run of
+// one block.  Levels follow each other as launches on the stream.  The level
+// past the last rebuilt one holds the blocks no group rebuilds (no sources:
+// they are zeroed).
+constexpr uint64_t kLevelChunk = 1024;
+
+__global__ __launch_bounds__(256) void local_level_kernel(LocalPlanJob J, uint8_t *c, uint64_t t, int l) {
+  if (J.flag[0] || l > J.meta[0]) return;
+  const int p0 = J.lvl_ptr[l], p1 = J.lvl_ptr[l + 1];
+  if (p1 <= p0) return;
+  const uint64_t nch = (t + kLevelChunk - 1) / kLevelChunk;
+  const uint64_t nwork = (uint64_t)(p1 - p0) * nch;
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint64_t wstride = (uint64_t)gridDim.x * 4u;
+  const v4u zero = {0u, 0u, 0u, 0u};
+  for (uint64_t w = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6); w < nwork; w += wstride) {
+    const int p = p0 + (int)(w / nch);
+    const uint64_t off = (w % nch) * kLevelChunk + lane * 16u;
+    if (off >= t) continue;
+    v4u acc = zero;
+    const int e1 = J.item_ptr[p + 1];
+    int e = J.item_ptr[p];
+    for (; e + 4 <= e1; e += 4) {
+      const v4u a0 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
+      const v4u a1 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 1] * t + off);
+      const v4u a2 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 2] * t + off);
+      const v4u a3 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 3] * t + off);
+      acc ^= (a0 ^ a1) ^ (a2 ^ a3);
+    }
+    for (; e < e1; ++e) acc ^= *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
+    *reinterpret_cast<v4u *>(c + (uint64_t)(uint32_t)J.item_dst[p] * t + off) = acc;
+  }
+}
+
+constexpr int kLevelLaunches = 16;   // levels rebuilt by per-level launches
 
 fs_status ck_hip(hipError_t e, const char *what) {
   if (e == hipSuccess) return FS_OK;
@@ -455,11 +560,39 @@ fs_status run_cga(const CgaJob &job, hipStream_t s) {
 }
 
 fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s) {
-  const size_t lds = 8ull * ((job.n + 31) / 32);
-  const void *fn = reinterpret_cast<const void *>(&local_plan_kernel);
-  if (lds > 32 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  hipLaunchKernelGGL(local_plan_kernel, dim3(1), dim3(kCgaThreads), lds, s, job);
-  return ck_hip(hipGetLastError(), "local repair plan launch");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const int cu = device_info(dev).cu_count;
+  const size_t budget = (size_t)device_info(dev).max_lds_per_block;
+  const size_t bits = 4ull * ((job.n + 31) / 32);
+  const void *prep = reinterpret_cast<const void *>(&local_prep_kernel);
+  if (bits > 32 * 1024) (void)hipFuncSetAttribute(prep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bits);
+  hipLaunchKernelGGL(local_prep_kernel, dim3(1), dim3(kCgaThreads), bits, s, job);
+  fs_status st = ck_hip(hipGetLastError(), "local repair check launch");
+  if (st != FS_OK) return st;
+  const uint32_t cgrid = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(8ull * (uint64_t)cu, ((uint64_t)job.n_groups + 3) / 4));
+  hipLaunchKernelGGL(local_count_kernel, dim3(cgrid), dim3(256), 0, s, job);
+  st = ck_hip(hipGetLastError(), "local repair count launch");
+  if (st != FS_OK) return st;
+  // the group counters go to LDS when they fit beside the two bitsets
+  const size_t with_g = 2 * bits + 8ull * job.n_groups;
+  if (with_g <= budget) {
+    const void *fn = reinterpret_cast<const void *>(&local_plan_kernel<true>);
+    if (with_g > 32 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)with_g);
+    hipLaunchKernelGGL(local_plan_kernel<true>, dim3(1), dim3(kCgaThreads), with_g, s, job);
+  } else {
+    const void *fn = reinterpret_cast<const void *>(&local_plan_kernel<false>);
+    if (2 * bits > 32 * 1024) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * bits));
+    hipLaunchKernelGGL(local_plan_kernel<false>, dim3(1), dim3(kCgaThreads), 2 * bits, s, job);
+  }
+  st = ck_hip(hipGetLastError(), "local repair plan launch");
+  if (st != FS_OK) return st;
+  if (job.n_lost == 0) return FS_OK;
+  const uint32_t fgrid = (uint32_t)std::max<uint64_t>(
+      1, std::min<uint64_t>(8ull * (uint64_t)cu, ((uint64_t)job.n_lost + 3) / 4));
+  hipLaunchKernelGGL(local_fill_kernel, dim3(fgrid), dim3(256), 0, s, job);
+  return ck_hip(hipGetLastError(), "local repair fill launch");
 }
 
 fs_status launch_local_apply(const LocalPlanJob &plan, uint8_t *c, uint64_t t, hipStream_t s) {
@@ -473,12 +606,28 @@ fs_status launch_local_apply(const LocalPlanJob &plan, uint8_t *c, uint64_t t, h
   if (nslices == 0) return FS_OK;
   if (nslices > 0x7fffffffull) return fail(FS_ERR_UNSUPPORTED, "block too large for the local repair");
   const dim3 grid((uint32_t)nslices), block(256);
+  int first = 0;
+  if (lps < 8) {
+    // short blocks: the first levels as launches of their own (the levels
+    // are known on the device only; launches past the last one return at
+    // once), the rest, if any, by the slice walk below
+    const uint64_t nch = (t + kLevelChunk - 1) / kLevelChunk;
+    const uint64_t waves = (uint64_t)plan.n_lost * nch;
+    const uint32_t lgrid = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>(8ull * (uint64_t)device_info(dev).cu_count, (waves + 3) / 4));
+    for (int l = 0; l < kLevelLaunches; ++l) {
+      hipLaunchKernelGGL(local_level_kernel, dim3(lgrid), block, 0, s, plan, c, t, l);
+      const fs_status st = ck_hip(hipGetLastError(), "local repair level launch");
+      if (st != FS_OK) return st;
+    }
+    first = kLevelLaunches;
+  }
   switch (lps) {
-    case 16: hipLaunchKernelGGL(local_apply_kernel<16>, grid, block, 0, s, plan, c, t); break;
-    case 8: hipLaunchKernelGGL(local_apply_kernel<8>, grid, block, 0, s, plan, c, t); break;
-    case 4: hipLaunchKernelGGL(local_apply_kernel<4>, grid, block, 0, s, plan, c, t); break;
-    case 2: hipLaunchKernelGGL(local_apply_kernel<2>, grid, block, 0, s, plan, c, t); break;
-    default: hipLaunchKernelGGL(local_apply_kernel<1>, grid, block, 0, s, plan, c, t); break;
+    case 16: hipLaunchKernelGGL(local_apply_kernel<16>, grid, block, 0, s, plan, c, t, first); break;
+    case 8: hipLaunchKernelGGL(local_apply_kernel<8>, grid, block, 0, s, plan, c, t, first); break;
+    case 4: hipLaunchKernelGGL(local_apply_kernel<4>, grid, block, 0, s, plan, c, t, first); break;
+    case 2: hipLaunchKernelGGL(local_apply_kernel<2>, grid, block, 0, s, plan, c, t, first); break;
+    default: hipLaunchKernelGGL(local_apply_kernel<1>, grid, block, 0, s, plan, c, t, first); break;
   }
   return ck_hip(hipGetLastError(), "local repair launch");
 }

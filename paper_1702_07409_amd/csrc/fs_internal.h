@@ -303,6 +303,7 @@ struct LocalPlanJob {
   unsigned long long *gacc;  // ws: [2n]
   int32_t *rof, *best;       // ws: [n] each
   int32_t *fa, *fb;          // ws: [2 * 2n] each
+  uint32_t *unk;             // ws: [ceil(n / 32)] unknown blocks (bitset)
 };
 fs_status launch_local_plan(const LocalPlanJob &job, hipStream_t s);
 // the rebuild of the lost blocks in c, level by level, from a local plan

@@ -113,6 +113,29 @@ def test_local_repair_of_a_whole_disk_takes_several_levels(disk):
     assert levels >= 2 and ok.sum() > 0
 
 
+@pytest.mark.parametrize("t", [304, 32768, 65536])
+def test_local_repair_of_a_long_chain(t):
+    # groups {i, i+1} with blocks 0..39 lost: one block per level, 40 levels
+    # and the level of blocks no group rebuilds.  Short blocks run the first
+    # levels as launches of their own and the rest as a slice walk; 64 KiB
+    # blocks take the slice walk throughout.
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor")
+    arr = []
+    for i in range(40):
+        arr += [0, 2, i, i + 1]
+    ch = fs.fs_checks_load(g, arr)
+    _, c3 = ch.export()
+    assert c3 == [[i, i + 1] for i in range(40)]
+    ok, levels = local_case(g, G, ch, c3, list(range(40)), None, t, 5)
+    assert levels == 40 and ok.all()
+    # a block of the chain that stays unknown: the blocks below it are not rebuilt
+    er = np.zeros(400, np.uint8)
+    er[25] = 1
+    ok, levels = local_case(g, G, ch, c3, [i for i in range(40) if i != 25], er, t, 6)
+    assert levels == 14 and ok.sum() == 14
+
+
 def test_local_repair_nothing_lost():
     import paper_1702_07409_amd as fs
     g, G = graphs(k=200, n=400, dist="raptor")
