@@ -477,9 +477,16 @@ def run_checks(reps=10):
             n_acc, reads, fetched, levels = _local_reads(c3, lost_h.tolist())
             assert n_acc == n_loc and levels == st.cpu().tolist()[2]
             _progress("checks: k=%d n=%d %s: local repair %d/%d in %.3f ms" % (k, n, tag, n_loc, m, t_loc))
+            # rates: every source read with repetition (what the rebuild issues),
+            # and the compulsory bytes (each surviving source once, each rebuilt block
+            # written once), against the 8 TB/s HBM peak
+            src_gbps = reads * t / (t_loc * 1e6)
+            comp_gbps = (fetched + n_loc) * t / (t_loc * 1e6)
             return {"groups": ch.n_check3, "ms": round(t_loc, 4), "repaired": n_loc, "levels": levels, "exact": ok,
                     "bytes_read": reads * t, "bytes_transferred": fetched * t,
-                    "mean_group_read": round(reads / max(n_loc, 1), 2)}
+                    "mean_group_read": round(reads / max(n_loc, 1), 2),
+                    "source_reads_GBps": round(src_gbps, 1), "source_reads_hbm_frac": round(src_gbps / 8000.0, 4),
+                    "compulsory_GBps": round(comp_gbps, 1)}
 
         row = {"k": k, "n": n, "t": t, "b": b, "object_bytes": b * t, "generate_ms": round(gen_ms, 2),
                "sweeps": ch.sweeps, "check2": ch.n_check2, "check3": ch.n_check3, "disks_lost": disks,

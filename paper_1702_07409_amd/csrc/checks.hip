@@ -349,23 +349,50 @@ __global__ __launch_bounds__(kCgaThreads) void local_plan_kernel(LocalPlanJob J)
       took[w] = 0;
     }
     __syncthreads();
+    // a wave takes blocks wave, wave + nwave, ...: up to 64 at a time, one
+    // per lane, whose record and group-list bounds load in one round; it
+    // then walks them two at a time, the lanes loading both blocks' groups
+    // before lowering their counters
     const uint32_t nT = s_nT, lane = tid & 63u, wave = tid >> 6, nwave = nt >> 6;
-    for (uint32_t i = wave; i < nT; i += nwave) {
-      const uint32_t u = (uint32_t)J.pos[i];
-      if (lane == 0) {
+    for (uint32_t bb = 0; wave + nwave * bb < nT; bb += 64) {
+      const uint32_t i = wave + nwave * (bb + lane);
+      uint32_t u = 0;
+      int32_t a0 = 0, a1 = 0;
+      if (i < nT) {
+        u = (uint32_t)J.pos[i];
         const int32_t r = J.rof[u];
+        a0 = J.sym_ptr[u];
+        a1 = J.sym_ptr[u + 1];
         J.chosen[r] = atomicAdd(&J.best[u], 0);
         J.level[r] = level;
         atomicAnd(&down[u >> 5], ~(1u << (u & 31)));
       }
-      const unsigned long long dec = 0ull - (kGrpOne | u);
-      for (int32_t e = J.sym_ptr[u] + (int32_t)lane; e < J.sym_ptr[u + 1]; e += 64) {
-        const int32_t q = J.sym_grp[e];
-        const unsigned long long after = atomicAdd(&gacc[q], dec) + dec;
-        if ((after >> 40) == 1ull) {
-          const uint32_t at = atomicAdd(&s_nB, 1u);
-          nxt[2 * at] = q;
-          nxt[2 * at + 1] = (int32_t)(after & (kGrpOne - 1));
+      const uint32_t nb = (uint32_t)__popcll(__ballot(i < nT));   // lanes 0 .. nb-1 hold blocks
+      for (uint32_t j = 0; j < nb; j += 2) {
+        const uint32_t jb = min(j + 1, nb - 1);
+        const uint32_t u0 = (uint32_t)__shfl((int)u, (int)j, 64), u1 = (uint32_t)__shfl((int)u, (int)jb, 64);
+        const int32_t f0 = __shfl(a0, (int)j, 64), g0 = __shfl(a1, (int)j, 64);
+        const int32_t f1 = __shfl(a0, (int)jb, 64), g1 = j + 1 < nb ? __shfl(a1, (int)jb, 64) : f1;
+        const unsigned long long d0 = 0ull - (kGrpOne | u0), d1 = 0ull - (kGrpOne | u1);
+        const int32_t span = max(g0 - f0, g1 - f1);
+        for (int32_t o = 0; o < span; o += 128) {
+          int32_t q[4];
+          const int32_t e0 = f0 + o + (int32_t)lane, e1 = f1 + o + (int32_t)lane;
+          q[0] = e0 < g0 ? J.sym_grp[e0] : -1;
+          q[1] = e0 + 64 < g0 ? J.sym_grp[e0 + 64] : -1;
+          q[2] = e1 < g1 ? J.sym_grp[e1] : -1;
+          q[3] = e1 + 64 < g1 ? J.sym_grp[e1 + 64] : -1;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            if (q[v] < 0) continue;
+            const unsigned long long dec = v < 2 ? d0 : d1;
+            const unsigned long long after = atomicAdd(&gacc[q[v]], dec) + dec;
+            if ((after >> 40) == 1ull) {
+              const uint32_t at = atomicAdd(&s_nB, 1u);
+              nxt[2 * at] = q[v];
+              nxt[2 * at + 1] = (int32_t)(after & (kGrpOne - 1));
+            }
+          }
         }
       }
     }
@@ -500,38 +527,48 @@ __global__ __launch_bounds__(256) void local_apply_kernel(LocalPlanJob J, uint8_
 }
 
 // One level of the rebuild, for blocks too short to give every CU two
-// workgroups of 128-byte slices: one wave per (item, 1 KiB chunk) of the
-// level, each lane 16 bytes, so every source load is a whole 1 KiB run of
-// one block.  Levels follow each other as launches on the stream.  The level
-// past the last rebuilt one holds the blocks no group rebuilds (no sources:
-// they are zeroed).
+// workgroups of 128-byte slices: one workgroup per (item, 1 KiB chunk) of the
+// level.  Its four waves take a quarter of the item's sources each, every
+// lane 16 bytes of the chunk, eight loads in flight, so every source load is
+// a whole 1 KiB run of one block; the four partial XORs meet in LDS.  Levels
+// follow each other as launches on the stream.  The level past the last
+// rebuilt one holds the blocks no group rebuilds (no sources: they are
+// zeroed).
 constexpr uint64_t kLevelChunk = 1024;
 
 __global__ __launch_bounds__(256) void local_level_kernel(LocalPlanJob J, uint8_t *c, uint64_t t, int l) {
+  __shared__ v4u part[4][64];
   if (J.flag[0] || l > J.meta[0]) return;
   const int p0 = J.lvl_ptr[l], p1 = J.lvl_ptr[l + 1];
   if (p1 <= p0) return;
   const uint64_t nch = (t + kLevelChunk - 1) / kLevelChunk;
   const uint64_t nwork = (uint64_t)(p1 - p0) * nch;
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint64_t wstride = (uint64_t)gridDim.x * 4u;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
   const v4u zero = {0u, 0u, 0u, 0u};
-  for (uint64_t w = (uint64_t)blockIdx.x * 4u + (threadIdx.x >> 6); w < nwork; w += wstride) {
+  for (uint64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
     const int p = p0 + (int)(w / nch);
     const uint64_t off = (w % nch) * kLevelChunk + lane * 16u;
-    if (off >= t) continue;
+    const int b0 = J.item_ptr[p], b1 = J.item_ptr[p + 1];
+    const int e1 = b0 + (int)(((int64_t)(b1 - b0) * (wv + 1)) / 4);
+    int e = b0 + (int)(((int64_t)(b1 - b0) * wv) / 4);
     v4u acc = zero;
-    const int e1 = J.item_ptr[p + 1];
-    int e = J.item_ptr[p];
-    for (; e + 4 <= e1; e += 4) {
-      const v4u a0 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
-      const v4u a1 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 1] * t + off);
-      const v4u a2 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 2] * t + off);
-      const v4u a3 = *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e + 3] * t + off);
-      acc ^= (a0 ^ a1) ^ (a2 ^ a3);
+    if (off < t) {
+      const uint8_t *src = c + off;
+      for (; e + 8 <= e1; e += 8) {
+        v4u a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          a[u] = *reinterpret_cast<const v4u *>(src + (uint64_t)(uint32_t)J.item_col[e + u] * t);
+        acc ^= ((a[0] ^ a[1]) ^ (a[2] ^ a[3])) ^ ((a[4] ^ a[5]) ^ (a[6] ^ a[7]));
+      }
+      for (; e < e1; ++e) acc ^= *reinterpret_cast<const v4u *>(src + (uint64_t)(uint32_t)J.item_col[e] * t);
     }
-    for (; e < e1; ++e) acc ^= *reinterpret_cast<const v4u *>(c + (uint64_t)(uint32_t)J.item_col[e] * t + off);
-    *reinterpret_cast<v4u *>(c + (uint64_t)(uint32_t)J.item_dst[p] * t + off) = acc;
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && off < t)
+      *reinterpret_cast<v4u *>(c + (uint64_t)(uint32_t)J.item_dst[p] * t + off) =
+          (part[0][lane] ^ part[1][lane]) ^ (part[2][lane] ^ part[3][lane]);
+    __syncthreads();   // the parts are read before the next item overwrites them
   }
 }
 
@@ -612,9 +649,9 @@ fs_status launch_local_apply(const LocalPlanJob &plan, uint8_t *c, uint64_t t, h
     // are known on the device only; launches past the last one return at
     // once), the rest, if any, by the slice walk below
     const uint64_t nch = (t + kLevelChunk - 1) / kLevelChunk;
-    const uint64_t waves = (uint64_t)plan.n_lost * nch;
+    const uint64_t units = (uint64_t)plan.n_lost * nch;
     const uint32_t lgrid = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>(8ull * (uint64_t)device_info(dev).cu_count, (waves + 3) / 4));
+        1, std::min<uint64_t>(8ull * (uint64_t)device_info(dev).cu_count, units));
     for (int l = 0; l < kLevelLaunches; ++l) {
       hipLaunchKernelGGL(local_level_kernel, dim3(lgrid), block, 0, s, plan, c, t, l);
       const fs_status st = ck_hip(hipGetLastError(), "local repair level launch");
