@@ -136,6 +136,21 @@ def test_local_repair_of_a_long_chain(t):
     assert levels == 14 and ok.sum() == 14
 
 
+def test_local_repair_with_group_counters_in_global_memory():
+    # 20000 groups: 8 bytes each no longer fit LDS beside the two bitsets, so
+    # the level loop lowers the counters in the workspace
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=25000, dist="raptor")
+    arr = []
+    for i in range(20000):
+        arr += [0, 2, i, i + 1]
+    ch = fs.fs_checks_load(g, arr)
+    _, c3 = ch.export()
+    assert len(c3) == 20000
+    ok, levels = local_case(g, G, ch, c3, list(range(40)), None, 304, 7)
+    assert levels == 40 and ok.all()
+
+
 def test_local_repair_nothing_lost():
     import paper_1702_07409_amd as fs
     g, G = graphs(k=200, n=400, dist="raptor")
