@@ -151,6 +151,22 @@ def test_local_repair_with_group_counters_in_global_memory():
     assert levels == 40 and ok.all()
 
 
+@pytest.mark.parametrize("lost", [[0], [0, 1], [1, 0, 7]])
+def test_local_repair_of_a_block_in_many_groups(lost):
+    # block 0 sits in 300 groups {0, j}: removing it from them takes the
+    # lanes of a wave several passes; with block 1 lost too, group {0, 1}
+    # waits a level for block 0
+    import paper_1702_07409_amd as fs
+    g, G = graphs(k=200, n=400, dist="raptor")
+    arr = []
+    for j in range(1, 301):
+        arr += [0, 2, 0, j]
+    ch = fs.fs_checks_load(g, arr)
+    _, c3 = ch.export()
+    ok, levels = local_case(g, G, ch, c3, lost, None, 304, 8)
+    assert ok.all() and levels == (1 if lost == [0] else 2)
+
+
 def test_local_repair_nothing_lost():
     import paper_1702_07409_amd as fs
     g, G = graphs(k=200, n=400, dist="raptor")
