@@ -1933,16 +1933,26 @@ fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStrea
   } else if (use_lookahead(job, *prog)) {
     e = run_replay_la<8>(job, *prog, budget, dev, cu, s);
   } else {
-    // large k: wide slices in global memory, about two workgroups per CU
+    // large k: wide slices in global memory, about two workgroups per CU;
+    // blocks too short to give every CU a 128-byte slice take the widest of
+    // 64, 32 or 16 bytes that does (successive slices share an XCD, so their
+    // 128-byte lines meet in one L2)
     const uint64_t per = (job.t + 2ull * cu - 1) / (2ull * cu);
+    const uint64_t cus = (uint64_t)cu;
     if (per >= 1024)
       e = run_replay_wide<64>(job, *prog, budget, dev, cu, s);
     else if (per >= 512)
       e = run_replay_wide<32>(job, *prog, budget, dev, cu, s);
     else if (per >= 256)
       e = run_replay_wide<16>(job, *prog, budget, dev, cu, s);
-    else
+    else if (job.t >= 128 * cus)
       e = run_replay_wide<8>(job, *prog, budget, dev, cu, s);
+    else if (job.t >= 64 * cus)
+      e = run_replay_wide<4>(job, *prog, budget, dev, cu, s);
+    else if (job.t >= 32 * cus)
+      e = run_replay_wide<2>(job, *prog, budget, dev, cu, s);
+    else
+      e = run_replay_wide<1>(job, *prog, budget, dev, cu, s);
   }
   return hip_check(e, "replay launch");
 }

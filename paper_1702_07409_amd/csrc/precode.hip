@@ -13,9 +13,11 @@
 //                          check at count one, claims it once, and lowers the
 //                          counts of the checks on it.  It writes the
 //                          (block, check) pairs of each level.
-//   precode_replay_kernel  one workgroup per 1 KiB byte slice of every block
-//                          replays the levels: block = XOR of the other
-//                          members of its check.
+//   precode_level_kernel   replays one level: block = XOR of the other
+//                          members of its check, one workgroup per (pair,
+//                          1 KiB chunk) of the level
+//   precode_replay_kernel  replays the later levels, one workgroup per 1 KiB
+//                          byte slice of every block
 
 #include <hip/hip_runtime.h>
 
@@ -122,13 +124,13 @@ __global__ __launch_bounds__(kPcThreads) void precode_peel_kernel(PrecodePeelJob
   }
 }
 
-__global__ __launch_bounds__(kPcReplayThreads) void precode_replay_kernel(PrecodeReplayJob J) {
+__global__ __launch_bounds__(kPcReplayThreads) void precode_replay_kernel(PrecodeReplayJob J, int first) {
   const int levels = J.meta[0];
-  if (levels <= 0) return;
+  if (levels <= first) return;
   const uint64_t off0 = (uint64_t)blockIdx.x * kPcSlice;
   if (off0 >= J.t) return;
   const uint32_t chunks = (uint32_t)(min<uint64_t>(kPcSlice, J.t - off0) / 16);
-  for (int l = 0; l < levels; ++l) {
+  for (int l = first; l < levels; ++l) {
     const int lo = J.level_ptr[l], hi = J.level_ptr[l + 1];
     const uint32_t items = (uint32_t)(hi - lo) * chunks;
     for (uint32_t it = threadIdx.x; it < items; it += kPcReplayThreads) {
@@ -145,6 +147,56 @@ __global__ __launch_bounds__(kPcReplayThreads) void precode_replay_kernel(Precod
     }
     // the next level reads blocks this workgroup wrote
     __syncthreads();
+  }
+}
+
+// One level of the second pass as a launch of its own: one workgroup per
+// (pair, 1 KiB chunk) of the level.  Its four waves take a quarter of the
+// check's members each, every lane 16 bytes of the chunk, eight loads in
+// flight; the four partial XORs meet in LDS.  The per-slice walk above
+// takes the levels past the ones launched this way.
+constexpr int kPcLevelLaunches = 4;
+
+__global__ __launch_bounds__(kPcReplayThreads) void precode_level_kernel(PrecodeReplayJob J, int l) {
+  __shared__ v4u part[4][64];
+  if (l >= J.meta[0]) return;
+  const int lo = J.level_ptr[l], hi = J.level_ptr[l + 1];
+  if (hi <= lo) return;
+  const uint64_t nch = (J.t + kPcSlice - 1) / kPcSlice;
+  const uint64_t nwork = (uint64_t)(hi - lo) * nch;
+  const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+  const v4u zero = {0u, 0u, 0u, 0u};
+  for (uint64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int q = lo + (int)(w / nch);
+    const uint64_t off = (w % nch) * kPcSlice + lane * 16u;
+    const uint32_t f = (uint32_t)J.pair_sym[q];
+    const int32_t r = J.pair_chk[q];
+    const int32_t b0 = J.chk_ptr[r], b1 = J.chk_ptr[r + 1];
+    const int32_t e1 = b0 + (int32_t)(((int64_t)(b1 - b0) * (wv + 1)) / 4);
+    int32_t e = b0 + (int32_t)(((int64_t)(b1 - b0) * wv) / 4);
+    v4u acc = zero;
+    if (off < J.t) {
+      const uint8_t *src = J.x + off;
+      for (; e + 8 <= e1; e += 8) {
+        uint32_t sv[8];
+        v4u a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sv[u] = (uint32_t)J.chk_col[e + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = sv[u] != f ? *reinterpret_cast<const v4u *>(src + (uint64_t)sv[u] * J.t) : zero;
+        acc ^= ((a[0] ^ a[1]) ^ (a[2] ^ a[3])) ^ ((a[4] ^ a[5]) ^ (a[6] ^ a[7]));
+      }
+      for (; e < e1; ++e) {
+        const uint32_t sv = (uint32_t)J.chk_col[e];
+        if (sv != f) acc ^= *reinterpret_cast<const v4u *>(src + (uint64_t)sv * J.t);
+      }
+    }
+    part[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && off < J.t)
+      *reinterpret_cast<v4u *>(J.x + (uint64_t)f * J.t + off) =
+          (part[0][lane] ^ part[1][lane]) ^ (part[2][lane] ^ part[3][lane]);
+    __syncthreads();   // the parts are read before the next pair overwrites them
   }
 }
 
@@ -251,7 +303,19 @@ fs_status launch_precode_replay(const PrecodeReplayJob &job, hipStream_t s) {
   const uint64_t slices = (job.t + kPcSlice - 1) / kPcSlice;
   if (slices == 0) return FS_OK;
   if (slices > 0x7fffffffull) return fail(FS_ERR_INVALID, "t too large");
-  hipLaunchKernelGGL(precode_replay_kernel, dim3((uint32_t)slices), dim3(kPcReplayThreads), 0, s, job);
+  // the first levels as launches of their own (the level count is known on
+  // the device only: launches past the last level return at once), the rest
+  // by the slice walk
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const uint32_t lgrid = 8u * (uint32_t)device_info(dev).cu_count;
+  for (int l = 0; l < kPcLevelLaunches; ++l) {
+    hipLaunchKernelGGL(precode_level_kernel, dim3(lgrid), dim3(kPcReplayThreads), 0, s, job, l);
+    const fs_status st = pc_hip(hipGetLastError(), "precode level launch");
+    if (st != FS_OK) return st;
+  }
+  hipLaunchKernelGGL(precode_replay_kernel, dim3((uint32_t)slices), dim3(kPcReplayThreads), 0, s, job,
+                     kPcLevelLaunches);
   return pc_hip(hipGetLastError(), "precode replay launch");
 }
 
