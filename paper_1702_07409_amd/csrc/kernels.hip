@@ -1933,23 +1933,29 @@ fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStrea
   } else if (use_lookahead(job, *prog)) {
     e = run_replay_la<8>(job, *prog, budget, dev, cu, s);
   } else {
-    // large k: wide slices in global memory, about two workgroups per CU;
-    // blocks too short to give every CU a 128-byte slice take the widest of
-    // 64, 32 or 16 bytes that does (successive slices share an XCD, so their
-    // 128-byte lines meet in one L2)
+    // large k: wide slices in global memory, about two workgroups per CU.
+    // Blocks too short for that take the widest of 128, 64, 32 or 16 bytes
+    // that still gives three quarters of the workgroups that fit at once (one
+    // or two per CU, by the program's LDS) a slice: one round of workgroups
+    // beats two rounds of narrower ones.  Successive slices share an XCD, so
+    // their 128-byte lines meet in one L2.
     const uint64_t per = (job.t + 2ull * cu - 1) / (2ull * cu);
-    const uint64_t cus = (uint64_t)cu;
+    const uint64_t lds_w = std::max<uint64_t>(
+        1, std::min<uint64_t>((uint64_t)budget, replay_prog_lds_bound(job.k, prog->pidx_cap)));
+    const uint64_t fit = std::min<uint64_t>(2, std::max<uint64_t>(1, (uint64_t)budget / lds_w));
+    const uint64_t want = (3ull * (uint64_t)cu * fit) / 4;
+    auto slices = [&](uint64_t w) { return (job.t + w - 1) / w; };
     if (per >= 1024)
       e = run_replay_wide<64>(job, *prog, budget, dev, cu, s);
     else if (per >= 512)
       e = run_replay_wide<32>(job, *prog, budget, dev, cu, s);
     else if (per >= 256)
       e = run_replay_wide<16>(job, *prog, budget, dev, cu, s);
-    else if (job.t >= 128 * cus)
+    else if (per >= 128 || slices(128) >= want)
       e = run_replay_wide<8>(job, *prog, budget, dev, cu, s);
-    else if (job.t >= 64 * cus)
+    else if (slices(64) >= want)
       e = run_replay_wide<4>(job, *prog, budget, dev, cu, s);
-    else if (job.t >= 32 * cus)
+    else if (slices(32) >= want)
       e = run_replay_wide<2>(job, *prog, budget, dev, cu, s);
     else
       e = run_replay_wide<1>(job, *prog, budget, dev, cu, s);

@@ -292,11 +292,12 @@ LOOKAHEAD_CASES = {
                         finite_w=tuple([0.3] + list(FIN16[1:])), stripe_key=5, n_erased=100),
     # 342 slab inputs: 128-byte slices
     "rsd": dict(stripe=7, k=2500, n=3000, t=4096 + 48, dist="rsd", stripe_key=6, n_erased=60),
-    # the wide replay of blocks too short for a 128-byte slice per CU: 32-byte
-    # slices (257 and a ragged 16 bytes), then 64-byte slices (256 and 16 bytes)
-    "short_32": dict(stripe=8, k=1500, n=1800, t=8192 + 48, dist="finite", finite_w=FIN16, stripe_key=7,
+    # the wide replay of blocks too short for enough 128-byte slices: 32-byte
+    # slices (513, the last one 16 bytes), then 64-byte slices (513, the last
+    # one 48 bytes)
+    "short_32": dict(stripe=8, k=1500, n=1800, t=16384 + 16, dist="finite", finite_w=FIN16, stripe_key=7,
                      n_erased=40),
-    "short_64": dict(stripe=8, k=1500, n=1800, t=16384 + 16, dist="rsd", stripe_key=8, n_erased=40),
+    "short_64": dict(stripe=8, k=1500, n=1800, t=32768 + 48, dist="rsd", stripe_key=8, n_erased=40),
     # 3619 slab inputs and 15203 program entries: 16-byte slices, a level of
     # 3339 pairs, no erasures
     "degree_one_heavy": dict(stripe=4, k=4000, n=16000, t=800, dist="finite",
