@@ -88,6 +88,16 @@ def test_encode_degree_k_rows_and_k1():
         assert np.array_equal(host(c), codec.encode(G, x))
 
 
+@pytest.mark.parametrize("k,n,dist,t", [(10246, 21800, "raptor", 7 * 1024 + 48), (12000, 13500, "finite", 2048 + 16)])
+def test_encode_sparse_graph_beyond_8192_inputs(k, n, dist, t):
+    # sparse graphs of more than 8192 inputs take 512-byte slices by default:
+    # several slices per block and a ragged tail
+    w = workloads.finite16_weights() if dist == "finite" else ()
+    sp = workloads.StripeSpec(stripe=0, k=k, n=n, t=t, dist=dist, finite_w=w, stripe_key=3, n_erased=0)
+    g, G, x, xd, c = encode_case(sp)
+    assert np.array_equal(host(c), codec.encode(G, x))
+
+
 def test_encode_tiles_beyond_the_lds_edge_stage():
     # 16-row tiles of degree-200 rows hold 3200 edges: read from global memory
     import paper_1702_07409_amd as fs
