@@ -5,10 +5,10 @@ the benchmark use this module; the library never does.
 
 Functions and the passage each follows
   cga            Algorithm 4 (§2.6): columns of the generator matrix B (k x n,
-                 column j = the inputs of coded block j) are XORed into each
-                 other while that lowers their weight; L(2,3) (n x n, the
-                 identity at the start) records which coded blocks each
-                 column has become the sum of.  The sweep over (j, i) repeats
+                 column j = the inputs of coded block j) absorb other columns
+                 (by XOR) whenever that lowers their weight; L(2,3) (n x n,
+                 the identity at the start) records which coded blocks each
+                 column has become the sum of.  Sweeps over the columns repeat
                  until B has n - k zero columns or a sweep changes nothing.
   split          §2.6: a column of weight one is a check #2 equation (input i
                  = XOR of the coded blocks of its L column), a column of
@@ -43,9 +43,10 @@ Functions and the passage each follows
                  repair.
 
 Readings:
-  * Columns are bitsets of the k inputs; w() is their number of ones.  The
-    pair test is 2 w(b_j) > w(b_i), then w(b_j ^ b_i) < w(b_j), both with the
-    current b_j (it changes inside the i loop).
+  * Columns are bitsets of the k inputs; w() is their number of ones.  A
+    column absorbs another when that lowers its weight; the test is made
+    against the column's current value, which changes as it absorbs others
+    during the same visit.
   * zero_columns counts the zero columns (the text's "nonzero" contradicts
     the loop bound n - k).
   * The check data array is written check #2 records first (ascending
@@ -66,28 +67,66 @@ def _w(x):
     return bin(x).count("1")
 
 
+def _pack(sets, width):
+    """0/1 bit matrix with one row per set, packed into uint64 words."""
+    words = (width + 63) // 64
+    M = np.zeros((len(sets), words * 64), dtype=np.uint8)
+    for r, s in enumerate(sets):
+        M[r, list(s)] = 1
+    return np.packbits(M, axis=1, bitorder="little").view(np.uint64)
+
+
+def _unpack(row):
+    return int.from_bytes(row.tobytes(), "little")
+
+
 def cga(G, max_sweeps=0):
     """Algorithm 4.  Returns (B columns after, L columns after, sweeps), each
-    column an int bitset (B over inputs, L over coded blocks)."""
+    column an int bitset (B over inputs, L over coded blocks).
+
+    Column j of B lowers its weight by absorbing column i exactly when
+    w(b_j ^ b_i) = w(b_j) + w(b_i) - 2|b_j & b_i| < w(b_j), that is when
+    w(b_i) < 2|b_j & b_i| (which also gives the paper's first test,
+    w(b_i) < 2 w(b_j)).  One sweep visits j = 0 .. n-1; for each j, the other
+    columns are offered in increasing i, each tested against the current b_j,
+    and each that passes is absorbed (b_j ^= b_i, l_j ^= l_i) before the next
+    is offered.  Sweeps repeat until n - k columns are zero, a sweep absorbs
+    nothing, or max_sweeps (> 0) sweeps ran.
+
+    B and L are held as packed bit matrices (one row per column of the
+    paper's matrices); for column j the test is evaluated for every later
+    candidate at once, the first passing one is absorbed, and the search
+    resumes after it.
+    """
     k, n = G.k, G.n
-    b = [sum(1 << int(i) for i in G.N(j)) for j in range(n)]
-    L = [1 << j for j in range(n)]
+    Bm = _pack([G.N(j) for j in range(n)], k)
+    Lm = _pack([[j] for j in range(n)], n)
+    w = np.bitwise_count(Bm).sum(axis=1).astype(np.int64)
     sweeps = 0
-    while sum(1 for x in b if x == 0) < n - k:
+    while int((w == 0).sum()) < n - k:
         if max_sweeps and sweeps == max_sweeps:
             break
-        changed = False
+        absorbed = False
         for j in range(n):
-            for i in range(n):
-                if j != i and 2 * _w(b[j]) > _w(b[i]):
-                    if _w(b[j] ^ b[i]) < _w(b[j]):
-                        b[j] ^= b[i]
-                        L[j] ^= L[i]
-                        changed = True
+            i = 0
+            while i < n:
+                overlap = np.bitwise_count(Bm[i:] & Bm[j]).sum(axis=1).astype(np.int64)
+                passing = w[i:] < 2 * overlap
+                if i <= j:
+                    passing[j - i] = False
+                hits = np.flatnonzero(passing)
+                if len(hits) == 0:
+                    break
+                i += int(hits[0])
+                Bm[j] ^= Bm[i]
+                Lm[j] ^= Lm[i]
+                w[j] = int(np.bitwise_count(Bm[j]).sum())
+                absorbed = True
+                i += 1
         sweeps += 1
-        if not changed:
+        if not absorbed:
             break
-    return b, L, sweeps
+    return [_unpack(r) for r in Bm], [_unpack(r) for r in Lm], sweeps
 
 
 def _members(x):

@@ -130,17 +130,18 @@ def peel_schedule(G, erased, maxit=0):
     edge_row = np.repeat(np.arange(n), deg)
     levels = []
     while in_F.any() and (maxit == 0 or len(levels) < maxit):
-        # weight of each column of C after zeroing decoded rows
+        # the edges g -> i with i still in F; weight(g) = |N(g) & F|
         live = in_F[G.col]
-        weight = np.bincount(edge_row, weights=live, minlength=n).astype(np.int64)
-        # sum of remaining ids; equals f(g) when the weight is 1
-        idsum = np.bincount(edge_row, weights=np.where(live, G.col, 0), minlength=n).astype(np.int64)
+        weight = np.bincount(edge_row[live], minlength=n)
+        # for a row of weight 1, its one live edge names f(g)
+        f_of = np.full(n, -1, dtype=np.int64)
+        f_of[edge_row[live]] = G.col[live]
         ripple = [g for g in survivors if weight[g] == 1]
         if not ripple:
             break
         best = {}
         for g in ripple:
-            f = int(idsum[g])
+            f = int(f_of[g])
             key = (int(deg[g]), int(g))
             if f not in best or key < best[f]:
                 best[f] = key
@@ -189,7 +190,6 @@ def bp_sequential(G, erased, order=None):
     k, n = G.k, G.n
     erased = np.asarray(erased, dtype=bool)
     weight = G.degrees().astype(np.int64).copy()
-    unknown_sum = np.array([int(G.N(g).sum()) for g in range(n)], dtype=np.int64)
     recovered = np.zeros(k, dtype=bool)
     queue = [g for g in range(n) if not erased[g] and weight[g] == 1]
     if order is not None:
@@ -197,15 +197,13 @@ def bp_sequential(G, erased, order=None):
         rng.shuffle(queue)
     while queue:
         g = queue.pop(0) if order is None else queue.pop(int(rng.integers(len(queue))))
-        if weight[g] != 1:
+        unknown = [int(i) for i in G.N(g) if not recovered[i]]
+        if len(unknown) != 1:
             continue
-        f = int(unknown_sum[g])
-        if recovered[f]:
-            continue
+        f = unknown[0]
         recovered[f] = True
         for h in G.NT(f):
             weight[h] -= 1
-            unknown_sum[h] -= f
             if not erased[h] and weight[h] == 1:
                 queue.append(int(h))
     return recovered

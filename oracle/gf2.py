@@ -13,6 +13,12 @@ routines are the textbook definitions, kept separate from the sparse code in
   ml_set       inputs i for which the unit vector e_i lies in the span of the
                surviving columns of B: exactly the inputs any decoder (peeling
                or maximum likelihood) could determine from the survivors
+
+Pinned by (tests): rank and ml_set equal the span listed element by element
+(the XOR of every subset of the surviving columns) over every survivor set of
+tiny graphs; hand cases where peeling recovers nothing but ML recovers all,
+where no unit vector is in the span, and where an input lies in no surviving
+row; ml_set is all inputs exactly at full rank.
 """
 
 import numpy as np

@@ -14,7 +14,8 @@ Functions and the passage each follows
   array_params   p = largest prime factor of k, k' = k / p, j' = k' - b / p
                  (Algorithm 2); b must be a multiple of p with 1 <= j' < k'.
   check_one      Algorithm 2: the k - b rows of L(1), k' - j' symbol indices
-                 each.
+                 each, built from the circulant block structure of array
+                 codes that Algorithm 2's index formula spells out.
   checks         each check equation as its member set: row r of L(1) plus
                  the parity block b + r it defines (reading below).
   encode         x[0:b] = data; x[b + r] = XOR of x over row r of L(1), in
@@ -65,14 +66,26 @@ def array_params(b, k):
 
 
 def check_one(b, k):
-    """Algorithm 2: L(1) as a list of k - b rows."""
+    """L(1) of Algorithm 2 as a list of k - b rows, members ascending.
+
+    Array LDPC codes are built from powers of the p x p cyclic shift P (row i
+    of P^s has its one in column (i + s) mod p).  Cut the k blocks into k'
+    block columns of p blocks.  Block row j < j' has k' - j' + 1 nonzero
+    blocks, at block columns j .. c_j with c_j = j + k' - j'; the block at
+    column c is P^s with s = (j' - 1 - j)(c - c_j) mod p, so the last one is
+    the identity and names the parity block c_j p + i = b + jp + i of check
+    row i + jp.  Row i + jp of L(1) lists the other members: the blocks
+    c p + (i + s) mod p for c = j .. c_j - 1.
+    """
     p, kp, jp = array_params(b, k)
-    L = [[0] * (kp - jp) for _ in range(k - b)]
-    for j in range(jp):
-        for i in range(p):
-            for m in range(1, kp - jp + 1):
-                L[i + j * p][m - 1] = kp * p - (jp - j + m - 1) * p - ((m * (jp - j - 1) - i - 1 + p) % p) - 1
-    return L
+    w = kp - jp
+    j = np.arange(jp).reshape(jp, 1, 1)
+    i = np.arange(p).reshape(1, p, 1)
+    c = j + np.arange(w).reshape(1, 1, w)        # block columns j .. c_j - 1
+    cj = j + w
+    s = ((jp - 1 - j) * (c - cj)) % p
+    L = (c * p + (i + s) % p).reshape(jp * p, w)
+    return [sorted(int(v) for v in row) for row in L]
 
 
 def checks(b, k):

@@ -218,9 +218,12 @@ uint32_t largest_prime_factor(uint32_t k) {
 }
 
 // L(1) of Algorithm 2 for an array code with largest prime factor p of k,
-// k' = k / p and j' = k' - b / p: row i + j p (j < j', i < p) holds, for m =
-// 1 .. k' - j', the block k' p - (j' - j + m - 1) p - ((m (j' - j - 1) - i - 1
-// + p) mod p) - 1.
+// k' = k / p and j' = k' - b / p.  The k blocks form k' block columns of p;
+// block row j < j' of the array code's check matrix holds p x p powers of the
+// cyclic shift at block columns j .. c_j (c_j = j + k' - j'), the power at
+// block column c being s = (j' - 1 - j)(c - c_j) mod p.  Check i + j p thus
+// meets block c p + (i + s) mod p of each block column c < c_j, and its own
+// parity block b + j p + i in the identity block at c_j.
 fs_status build_precode_host(uint32_t b, uint32_t k, fs_precode &pc) {
   if (k < 2 || b == 0 || b >= k) return fail(FS_ERR_INVALID, "need 0 < b < k");
   const uint32_t p = largest_prime_factor(k);
@@ -237,17 +240,17 @@ fs_status build_precode_host(uint32_t b, uint32_t k, fs_precode &pc) {
   const uint32_t w = kp - jp;
   pc.enc_ptr.assign(pc.m + 1, 0);
   pc.enc_col.assign((size_t)pc.m * w, 0);
-  for (uint32_t j = 0; j < jp; ++j)
-    for (uint32_t i = 0; i < p; ++i) {
-      const uint32_t r = i + j * p;
-      int32_t *row = pc.enc_col.data() + (size_t)r * w;
-      for (uint32_t m = 1; m <= w; ++m) {
-        const int64_t mod = (((int64_t)m * (jp - j - 1) - i - 1 + p) % p + p) % p;
-        row[m - 1] = (int32_t)((int64_t)kp * p - (int64_t)(jp - j + m - 1) * p - mod - 1);
-      }
-      std::sort(row, row + w);
-      pc.enc_ptr[r + 1] = (int32_t)((r + 1) * w);
+  for (uint32_t j = 0; j < jp; ++j) {
+    const uint32_t cj = j + w;
+    for (uint32_t c = j; c < cj; ++c) {
+      // shift of block (j, c): (j' - 1 - j)(c - c_j) mod p, with c - c_j < 0
+      const uint64_t s = ((uint64_t)(jp - 1 - j) * (uint64_t)(cj - c)) % p;
+      const uint32_t shift = (uint32_t)((p - s) % p);
+      for (uint32_t i = 0; i < p; ++i)   // columns ascend with c, so each row stays sorted
+        pc.enc_col[(size_t)(i + j * p) * w + (c - j)] = (int32_t)(c * p + (i + shift) % p);
     }
+  }
+  for (uint32_t r = 0; r < pc.m; ++r) pc.enc_ptr[r + 1] = (int32_t)((r + 1) * w);
   // check members: the row plus its parity block (which is the largest)
   pc.chk_ptr.assign(pc.m + 1, 0);
   pc.chk_col.clear();

@@ -176,6 +176,56 @@ def test_degree_one_graph_is_selection():
     assert np.array_equal(xd[covered], x[covered])
 
 
+def _span_by_enumeration(B, cols):
+    """Every GF(2) combination of the listed columns, as k-bit ints: the XOR
+    of each of the 2^|cols| subsets."""
+    vecs = [sum(1 << int(i) for i in np.flatnonzero(B[:, g])) for g in cols]
+    span = {0}
+    for v in vecs:
+        span |= {s ^ v for s in span}
+    return span
+
+
+def test_ml_set_small_cases():
+    # rows {0,1}, {1,2}, {0,1,2}: no row has one unknown, so peeling recovers
+    # nothing, yet the three rows have full rank and determine every input
+    G = graph.from_rows(3, [[0, 1], [1, 2], [0, 1, 2]])
+    B = gf2.dense_B(G)
+    assert gf2.ml_set(B, [0, 1, 2]) == [0, 1, 2] and gf2.rank(B, [0, 1, 2]) == 3
+    assert not codec.peel_schedule(G, np.zeros(3, np.uint8)).recovered_mask().any()
+    # without the third row the span is {0, x0^x1, x1^x2, x0^x2}: no unit vector
+    assert gf2.ml_set(B, [0, 1]) == [] and gf2.rank(B, [0, 1]) == 2
+    # an input no surviving row touches is never determinable; the others are
+    G2 = graph.from_rows(4, [[0], [0, 1], [1, 2], [3]])
+    B2 = gf2.dense_B(G2)
+    assert gf2.ml_set(B2, [0, 1, 2]) == [0, 1, 2]
+    assert gf2.ml_set(B2, [0, 1, 2, 3]) == [0, 1, 2, 3]
+    assert gf2.ml_set(B2, [1, 2, 3]) == [3]
+    assert gf2.ml_set(B2, []) == []
+
+
+def test_ml_set_and_rank_against_enumerated_span():
+    # brute force: the span of the surviving columns listed element by element
+    for k, n, seed in [(4, 6, 1), (5, 7, 2), (3, 6, 3), (5, 6, 4)]:
+        G = G_of(k, n, seed=seed, dist="finite", finite_w=(0.3, 0.4, 0.3))
+        B = gf2.dense_B(G)
+        for bits in itertools.product((0, 1), repeat=n):
+            surv = [j for j in range(n) if bits[j]]
+            span = _span_by_enumeration(B, surv)
+            assert gf2.ml_set(B, surv) == [i for i in range(k) if (1 << i) in span]
+            assert 1 << gf2.rank(B, surv) == len(span)
+
+
+def test_ml_set_is_all_inputs_exactly_at_full_rank():
+    for seed in range(4):
+        G = G_of(12, 20, seed=seed)
+        B = gf2.dense_B(G)
+        for m in (8, 12, 16, 20):
+            surv = list(range(m))
+            full = gf2.rank(B, surv) == 12
+            assert (gf2.ml_set(B, surv) == list(range(12))) == full
+
+
 def test_brute_force_all_erasure_patterns_tiny():
     """For tiny graphs and EVERY erasure pattern: R is within the ML-decodable
     set, ok implies full rank, F is a stopping set, values are exact."""

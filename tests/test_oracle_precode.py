@@ -1,5 +1,6 @@
 """Pins of the precode oracle (oracle/precode.py): Algorithm 2's checks against
-the circulant block structure of array LDPC codes, encodability, and the
+Algorithm 2 evaluated on small codes, the cyclic-shift block structure of
+array LDPC codes, girth, encodability, and the
 two-stage decode against direct checks and an independent check peel."""
 
 import itertools
@@ -25,20 +26,40 @@ def test_largest_prime_factor(k):
     assert not any(k % q == 0 and is_prime(q) for q in range(p + 1, k + 1))
 
 
+def test_check_one_equals_algorithm_2(golden):
+    # Algorithm 2's index expression, evaluated term by term for small codes
+    # (every row) and sampled rows of Table 2's codes
+    g = golden("alg2_check_one.json")
+    for code in g["codes"]:
+        b, k = code["b"], code["k"]
+        assert precode.array_params(b, k) == (code["p"], code["kp"], code["jp"])
+        L = precode.check_one(b, k)
+        assert len(L) == k - b
+        for r, row in code["rows"].items():
+            assert L[int(r)] == sorted(row), (b, k, r)
+    assert sorted(g["codes"][0]["rows"]["0"]) == [4, 12, 20]      # the hand-worked row
+
+
 @pytest.mark.parametrize("b,k", CODES)
-def test_checks_are_the_circulant_array_structure(b, k):
-    # Array LDPC codes are built from powers of the p x p cyclic shift: here
-    # block row j covers block columns j .. j + k' - j', ends in the identity
-    # (its parity block, column c_j = j + k' - j') and carries the shift
-    # (j' - 1 - j)(c - c_j) mod p at block column c.
+def test_checks_are_blocks_of_cyclic_shifts(b, k):
+    # Array LDPC codes are made of p x p powers of the cyclic shift: in every
+    # block row the checks meet a run of consecutive block columns, each in a
+    # permutation block whose column offset grows with the row by one (mod p),
+    # and the run ends in the identity block of that block row's parity blocks.
     p, kp, jp = precode.array_params(b, k)
     C = precode.checks(b, k)
     assert len(C) == k - b == jp * p
     for j in range(jp):
-        cj = j + kp - jp
-        for i in range(p):
-            want = sorted(c * p + (i + (jp - 1 - j) * (c - cj)) % p for c in range(j, cj + 1))
-            assert C[i + j * p] == want, (j, i)
+        rows = [C[i + j * p] for i in range(p)]
+        cols = [sorted({m // p for m in row}) for row in rows]
+        assert all(c_ == cols[0] for c_ in cols)
+        assert cols[0] == list(range(cols[0][0], cols[0][0] + kp - jp + 1))
+        assert cols[0][-1] * p == b + j * p                      # parity blocks b + jp .. b + jp + p - 1
+        for c in cols[0]:
+            off = [next(m % p for m in row if m // p == c) for row in rows]
+            assert sorted(off) == list(range(p))                 # a permutation block
+            assert all((off[i] - i) % p == (off[0]) % p for i in range(p))   # a power of the shift
+        assert [next(m for m in row if m // p == cols[0][-1]) for row in rows] == [b + j * p + i for i in range(p)]
 
 
 @pytest.mark.parametrize("b,k", [c for c in CODES if c[1] <= 1100])
