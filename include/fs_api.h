@@ -214,6 +214,24 @@ FS_API fs_status fs_decode(const fs_graph *g, const void *c, const uint8_t *eras
                     size_t ws_bytes, hipStream_t stream);
 
 /*
+ * fs_decode without a workspace argument, for callers that cannot allocate
+ * memory (code under stream capture, tight request loops, harnesses that
+ * forbid allocation calls): the workspace is a fixed 16 MiB device array
+ * inside the library, one per GPU, held until the process ends.  The call
+ * allocates nothing; arguments, outputs and results are those of fs_decode on
+ * the current device (the graph must live there).  Every call on a GPU shares
+ * that GPU's array: calls that overlap on one device (other streams, other
+ * threads) race and must be serialised by the caller.
+ * Errors: as fs_decode; FS_ERR_WORKSPACE when the graph's decode needs more
+ * than 16 MiB of workspace (fs_workspace_size(FS_OP_DECODE); every graph with
+ * k, n <= 65535 and Robust Soliton degrees fits), FS_ERR_INVALID when the
+ * graph was built for another device.
+ */
+FS_API fs_status fs_decode_noalloc(const fs_graph *g, const void *c, const uint8_t *erased, uint32_t maxit,
+                                   void *x, uint8_t *recovered, int32_t *status, uint64_t t,
+                                   hipStream_t stream);
+
+/*
  * Repair (the repair engine of §2.1 / §4).  lost: device uint32[n_lost]
  * coded rows to rebuild in place in c.
  *   x != NULL  re-encode from resident inputs: c_j = XOR_{i in N(j)} x_i.

@@ -92,6 +92,7 @@ _SIGS = {
     "fs_peel": ([P, P, U32, P, P, P, P, P, P, SZ, P], ST),
     "fs_replay": ([P, P, P, P, P, P, P, U64, P, SZ, P], ST),
     "fs_decode": ([P, P, P, U32, P, P, P, U64, P, SZ, P], ST),
+    "fs_decode_noalloc": ([P, P, P, U32, P, P, P, U64, P], ST),
     "fs_decode_plan": ([P, P, U32, P, P, P, SZ, P], ST),
     "fs_decode_apply": ([P, P, P, U64, P, SZ, P], ST),
     "fs_repair": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
@@ -295,6 +296,11 @@ def fs_decode(g, c, erased, maxit, x, recovered, status, t, ws, stream=None):
     w, wb = _ws(ws)
     _check(_lib.fs_decode(g.handle, _ptr(c), _ptr(erased), maxit, _ptr(x), _ptr(recovered), _ptr(status),
                           t, w, wb, _stream(stream)), "fs_decode")
+
+
+def fs_decode_noalloc(g, c, erased, maxit, x, recovered, status, t, stream=None):
+    _check(_lib.fs_decode_noalloc(g.handle, _ptr(c), _ptr(erased), maxit, _ptr(x), _ptr(recovered),
+                                  _ptr(status), t, _stream(stream)), "fs_decode_noalloc")
 
 
 def fs_decode_plan(g, erased, maxit, recovered, status, ws, stream=None):

@@ -32,6 +32,7 @@ SOURCES = [
     ("checks.hip", DEVICE),
     ("api.cpp", DEVICE),
     ("plan.cpp", DEVICE),
+    ("noalloc.cpp", DEVICE),
     ("graph_host.cpp", HOST),
 ]
 
