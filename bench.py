@@ -35,8 +35,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBPS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "large_stripe_traffic.json")
+PROFILE_COUNTERS = os.path.join(ROOT, "profiles", "large_stripe_counters.json")
 CSRC = os.path.join(ROOT, "paper_1702_07409_amd", "csrc")
+# what the traffic counters count: requests that leave the L2 for the data
+# fabric, which the Infinity Cache (MALL) may serve without touching HBM
+TRAFFIC_KIND = "L2-to-fabric bytes per launch from rocprofv3 request counters (128/64/32-byte reads, " \
+               "64/32-byte writes); includes Infinity Cache hits, so it bounds HBM traffic from above"
 
 
 def kernel_source_hash():
@@ -52,7 +56,7 @@ def kernel_source_hash():
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
@@ -69,6 +73,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--batch-stripes", type=int, default=512)
     ap.add_argument("--resident-stripes", type=int, default=256)
+    ap.add_argument("--reps", type=int, default=20,
+                    help="timed repetitions of each batched plan and plain loop (batch512, resident256)")
     ap.add_argument("--mode", choices=["step", "counters"], default="step",
                     help="counters: only K encode launches plus one plain copy of the same "
                          "output size, for rocprofv3 --pmc runs")
@@ -94,25 +100,108 @@ def counters_run(args, fs, torch, g, x, c, t, decode):
                       "copy_bytes_each_way": int(src.numel())}), flush=True)
 
 
+# state the forked oracle workers read: the graph, the schedule and the
+# payload arrays (c and the decoded x in shared anonymous maps, so each
+# worker writes its own byte columns of the parent's arrays)
+_POOL = {}
+
+
+def _shared_u8(shape):
+    import mmap
+    import numpy as np
+    buf = mmap.mmap(-1, int(shape[0]) * int(shape[1]))
+    return np.frombuffer(buf, dtype=np.uint8).reshape(shape)
+
+
+def _slice_encode(ab):
+    from oracle import codec
+    a, b = ab
+    _POOL["c"][:, a:b] = codec.encode(_POOL["G"], _POOL["x"][:, a:b])
+    return b - a
+
+
+def _slice_replay(ab):
+    from oracle import codec
+    a, b = ab
+    _POOL["xd"][:, a:b] = codec.replay(_POOL["G"], _POOL["c"][:, a:b], _POOL["sched"])
+    return b - a
+
+
 def cpu_baseline(spec, seconds):
-    """The oracle (numpy, one core) on the same stripe, repeated for ~seconds."""
+    """The oracle on the same stripe, timed on the host's cores.
+
+    Only the payload phases are timed, encode (codec.encode) and the decode's
+    XOR replay (codec.replay), as the paper times its compute stage; the
+    symbolic peel (codec.peel_schedule) is timed on its own and reported
+    beside them.  Two legs of about ``seconds`` each: the oracle as one numpy
+    process, and one forked process per core, each running the same oracle
+    calls on its own byte columns of every block (the code is bytewise, so
+    the columns are independent).  Must run before the GPU is initialised:
+    the workers are forked."""
+    import multiprocessing as mp
+    import numpy as np
     from oracle import codec, graph
     G = graph.build(graph.GraphParams(**spec.graph_kwargs()))
     x = spec.x()
     er = spec.erased_mask()
-    reps, total, nR = 0, 0.0, 0
-    while reps == 0 or total < seconds:
+    k, t = spec.k, spec.t
+    tp = time.perf_counter()
+    sched = codec.peel_schedule(G, er)
+    peel_s = time.perf_counter() - tp
+    nR = int(sched.recovered_mask().sum())
+    user = (k + nR) * t
+
+    # one core: encode XOR then replay XOR of the whole stripe
+    reps, enc_s, rep_s = 0, 0.0, 0.0
+    while reps == 0 or enc_s + rep_s < seconds:
         t0 = time.perf_counter()
         c = codec.encode(G, x)
-        _, rec, _, _ = codec.decode(G, c, er)
-        total += time.perf_counter() - t0
-        nR = int(rec.sum())
+        t1 = time.perf_counter()
+        codec.replay(G, c, sched)
+        t2 = time.perf_counter()
+        enc_s += t1 - t0
+        rep_s += t2 - t1
         reps += 1
-    user = (spec.k + nR) * spec.t
-    return {"value": round(user * reps / total / 1e9, 4), "unit": "GB/s", "cores": 1,
+    one = {"value": round(user * reps / (enc_s + rep_s) / 1e9, 4), "unit": "GB/s", "cores": 1,
+           "encode_s_per_rep": round(enc_s / reps, 4), "replay_s_per_rep": round(rep_s / reps, 4),
+           "reps": reps}
+
+    # all cores: byte columns of every block, one forked worker per core
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    parts = cores
+    step = max(8, (t // parts + 7) // 8 * 8)
+    slices = [(a, min(t, a + step)) for a in range(0, t, step)]
+    _POOL.update(G=G, x=x, sched=sched, c=_shared_u8((spec.n, t)), xd=_shared_u8((k, t)))
+    ctx = mp.get_context("fork")
+    reps_p, enc_p, rep_p = 0, 0.0, 0.0
+    with ctx.Pool(cores) as pool:
+        pool.map(_slice_encode, slices)          # workers started and warm
+        while reps_p == 0 or enc_p + rep_p < seconds:
+            t0 = time.perf_counter()
+            pool.map(_slice_encode, slices)
+            t1 = time.perf_counter()
+            pool.map(_slice_replay, slices)
+            t2 = time.perf_counter()
+            enc_p += t1 - t0
+            rep_p += t2 - t1
+            reps_p += 1
+    # the forked workers' output is the oracle's: check it against the one-core run
+    x_ref = codec.replay(G, c, sched)
+    assert np.array_equal(_POOL["c"], c) and np.array_equal(_POOL["xd"], x_ref)
+    _POOL.clear()
+    return {"value": round(user * reps_p / (enc_p + rep_p) / 1e9, 4), "unit": "GB/s", "cores": cores,
             "kind": "oracle",
-            "sample": "full stripe (k=%d, n=%d, t=%d), oracle encode+decode repeated %d times, %.1f s; "
-                      "numpy single thread" % (spec.k, spec.n, spec.t, reps, total)}
+            "sample": "full stripe (k=%d, n=%d, t=%d, %d erased): oracle encode + decode replay, %d "
+                      "forked numpy processes over %d byte columns of every block, repeated %d times "
+                      "(%.1f s); symbolic peel timed apart" % (spec.k, spec.n, spec.t, spec.n_erased, cores,
+                                                               len(slices), reps_p, enc_p + rep_p),
+            "encode_s_per_rep": round(enc_p / reps_p, 4), "replay_s_per_rep": round(rep_p / reps_p, 4),
+            "peel_s": round(peel_s, 4), "recovered": nR,
+            "one_core": one}
+
+
+def _progress_line(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def main():
@@ -122,9 +211,16 @@ def main():
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np
+    from synth import workloads
+
+    cpu = None
+    if args.workload in ("large_stripe", "all") and args.mode == "step" and not args.no_cpu:
+        # the oracle's pool is forked, so it runs before anything touches the GPU
+        cpu = cpu_baseline(workloads.large_stripe(), args.cpu_seconds)
+        _progress_line("cpu_baseline: %.3f GB/s on %d cores (one core %.3f GB/s)"
+                       % (cpu["value"], cpu["cores"], cpu["one_core"]["value"]))
     import torch
     import paper_1702_07409_amd as fs
-    from synth import workloads
 
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
@@ -141,9 +237,9 @@ def main():
         elif args.workload == "simdisk":
             res = bench_batch.run_simdisk()
         elif args.workload == "batch512":
-            res = bench_batch.run_batch512(args.batch_stripes)
+            res = bench_batch.run_batch512(args.batch_stripes, reps=args.reps, counters=args.mode == "counters")
         elif args.workload == "resident256":
-            res = bench_batch.run_resident256(args.resident_stripes)
+            res = bench_batch.run_resident256(args.resident_stripes, reps=args.reps)
         else:
             res = bench_batch.run_serve(args.serve_rate, args.serve_seconds)
         print(json.dumps(res), flush=True)
@@ -198,12 +294,17 @@ def main():
     torch.cuda.synchronize()
     # timed region: exactly K steps, inputs resident in HBM
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    begin = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    begin.record(stream)
     for i in range(args.steps):
         step(i, evs[i])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    # per-step intervals: from one step's replay end to the next (the first from the start)
+    ends = [begin] + [e[2] for e in evs]
+    step_ms = [ends[i].elapsed_time(ends[i + 1]) for i in range(args.steps)]
     enc_ms = [e[0].elapsed_time(e[1]) for e in evs]
     apply_ms = [e[5].elapsed_time(e[2]) for e in evs]
     plan_ms = [e[3].elapsed_time(e[4]) for e in evs]
@@ -235,6 +336,21 @@ def main():
         rep_ms.append(e[1].elapsed_time(e[2]))
         dec_ms.append(e[2].elapsed_time(e[3]))
 
+    # measured streaming ceiling: a plain device copy of 512 MiB (read + write bytes)
+    cp_src = torch.empty(1 << 29, dtype=torch.uint8, device="cuda")
+    cp_dst = torch.empty_like(cp_src)
+    cp_src.fill_(1)
+    cp_ms = []
+    for r in range(23):
+        e[0].record(stream)
+        cp_dst.copy_(cp_src)
+        e[1].record(stream)
+        torch.cuda.synchronize()
+        if r >= 3:
+            cp_ms.append(e[0].elapsed_time(e[1]))
+    copy_GBps = 2 * cp_src.numel() / (float(np.median(cp_ms)) * 1e-3) / 1e9
+    del cp_src, cp_dst
+
     ms_per_step = elapsed * 1e3 / args.steps
     user_bytes = (k + nR) * t
     value = user_bytes / (ms_per_step * 1e-3) / 1e9
@@ -251,12 +367,16 @@ def main():
     rep_avg_ms = float(np.mean(apply_ms))
     rep_achieved = rep_alg / (rep_avg_ms * 1e-3) / 1e9
     traffic = {"replay": None, "encode": None}
-    if os.path.exists(PROFILE_TRAFFIC):
-        with open(PROFILE_TRAFFIC) as f:
+    if os.path.exists(PROFILE_COUNTERS):
+        with open(PROFILE_COUNTERS) as f:
             prof = json.load(f)
+        # counters taken on other kernel sources are not reported
         if prof.get("kernel_source_sha256_16") == kernel_source_hash():
-            traffic = {"replay": prof.get("replay", {}).get("bytes_per_launch"),
-                       "encode": prof.get("encode", {}).get("bytes_per_launch")}
+            for key, pat in (("encode", "gather_kernel"), ("replay", "replay_wide_kernel")):
+                for name, rec in prof.get("kernels", {}).items():
+                    d = rec.get("derived", {})
+                    if pat in name and "read_bytes" in d and "write_bytes" in d:
+                        traffic[key] = int(d["read_bytes"] + d["write_bytes"])
     dec_avg_ms = float(np.median(dec_ms))
     out = {
         "metric": "encode+decode GB/s user data (% HBM peak), plain one-stripe path",
@@ -277,13 +397,23 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(rep_achieved, 2), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(rep_achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": traffic["replay"], "kernel": "replay_wide_kernel (fs_decode_apply)",
+                     "traffic": traffic["replay"], "traffic_kind": TRAFFIC_KIND,
+                     "kernel": "replay_wide_kernel (fs_decode_apply)",
                      "algorithmic_bytes_per_launch": rep_alg},
         "encode_roofline": {"bound": "hbm", "achieved": round(enc_achieved, 2), "peak": HBM_PEAK_GBPS,
                             "unit": "GB/s", "frac": round(enc_achieved / HBM_PEAK_GBPS, 4),
-                            "traffic": traffic["encode"], "kernel": "gather_kernel (fs_encode)",
+                            "traffic": traffic["encode"], "traffic_kind": TRAFFIC_KIND,
+                            "kernel": "gather_kernel (fs_encode)",
                             "algorithmic_bytes_per_launch": enc_alg},
+        "step_ms_median": round(float(np.median(step_ms)), 4),
+        "step_ms_p99": round(float(np.percentile(step_ms, 99)), 4),
+        "copy_ceiling": {"GBps": round(copy_GBps, 1), "frac_of_peak": round(copy_GBps / HBM_PEAK_GBPS, 4),
+                         "what": "plain device copy of 512 MiB, read + write bytes over its median time"},
         "encode_ms": round(enc_avg_ms, 4),
+        "encode_ms_median": round(float(np.median(enc_ms)), 4),
+        "encode_ms_p99": round(float(np.percentile(enc_ms, 99)), 4),
+        "apply_ms_median": round(float(np.median(apply_ms)), 4),
+        "apply_ms_p99": round(float(np.percentile(apply_ms, 99)), 4),
         "plan_ms": round(float(np.mean(plan_ms)), 4),
         "apply_ms": round(float(np.mean(apply_ms)), 4),
         "decode_one_stream_ms": round(dec_avg_ms, 4),
@@ -303,8 +433,8 @@ def main():
         # a failure there is reported in its field, the headline stands
         import bench_batch
         del x, c, xd, ws, wss, rws, pws
-        for key, run in (("batched", lambda: bench_batch.run_batch512(args.batch_stripes)),
-                         ("resident", lambda: bench_batch.run_resident256(args.resident_stripes)),
+        for key, run in (("batched", lambda: bench_batch.run_batch512(args.batch_stripes, reps=args.reps)),
+                         ("resident", lambda: bench_batch.run_resident256(args.resident_stripes, reps=args.reps)),
                          ("serve", lambda: bench_batch.run_serve(args.serve_rate, args.serve_seconds))):
             torch.cuda.empty_cache()
             try:
@@ -312,8 +442,8 @@ def main():
             except Exception as exc:  # noqa: BLE001 - recorded, not hidden
                 out[key] = {"error": "%s: %s" % (type(exc).__name__, exc)}
         torch.cuda.empty_cache()
-    if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(spec, args.cpu_seconds)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -51,12 +51,36 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
+def _time_reps(fn, reps, warm=2):
+    """Per-repetition times (ms) of fn, each bracketed by its own events,
+    run back to back after ``warm`` untimed calls."""
+    import torch
+    evs = [(_ev(), _ev()) for _ in range(reps)]
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record()
+        fn()
+        b.record()
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in evs]
+
+
+def _stats(ms):
+    return {"median_ms": round(float(np.median(ms)), 4), "p99_ms": round(float(np.percentile(ms, 99)), 4),
+            "reps": len(ms)}
+
+
 def _compulsory_encode(g, t):
     _, col, _, _ = g.export()
     return (len(np.unique(col)) + g.n) * t
 
 
-def run_batch512(count=512, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
+def run_batch512(count=512, reps=20, tune_cache="/tmp/fs_tune_cache.txt", counters=False):
+    """counters: the first wave only, one launch of its encode plan and one of
+    its decode plan (tuned from the cache, else by the default rule), for
+    rocprofv3 --pmc runs."""
     import torch
     import paper_1702_07409_amd as fs
     import synth.gpu as sg
@@ -91,12 +115,30 @@ def run_batch512(count=512, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
             st = torch.empty(3, dtype=torch.int32, device="cuda")
             bufs.append((sp, g, x, c, xd, er, rec, st))
         enc = fs.Plan([fs.work("encode", g, sp.t, x=x, c=c) for sp, g, x, c, xd, er, rec, st in bufs],
-                      tune_cache=tune_cache, autotune=True)
+                      tune_cache=tune_cache, autotune=not counters)
         dec = fs.Plan([fs.work("decode", g, sp.t, x=xd, c=c, erased=er, recovered=rec, status=st)
                        for sp, g, x, c, xd, er, rec, st in bufs])
+        if counters:
+            torch.cuda.synchronize()
+            enc.launch()
+            torch.cuda.synchronize()
+            dec.launch()
+            torch.cuda.synchronize()
+            return {"mode": "counters", "workload": "batch512", "stripes": len(wave),
+                    "input_bytes": sum(sp.k * sp.t for sp, *_ in bufs),
+                    "compulsory_encode_bytes": sum(_compulsory_encode(g, sp.t) for sp, g, *_ in bufs),
+                    "tune": enc.info()["tune"], "gather_jobs": enc.info()["gather_jobs"]}
         tune = enc.info()["tune"]
-        t_enc = _time(enc.launch, reps)
-        t_dec = _time(dec.launch, reps)
+        enc_ms = _time_reps(enc.launch, reps)
+        dec_ms = _time_reps(dec.launch, reps)
+        t_enc = float(np.median(enc_ms))
+        t_dec = float(np.median(dec_ms))
+        # check: the batched coded blocks equal the plain path's, stripe by stripe
+        for sp, g, x, c, xd, er, rec, st in bufs:
+            cref = torch.empty_like(c)
+            fs.fs_encode(g, x, cref, sp.t)
+            assert torch.equal(cref, c), "batched encode differs from the plain encode"
+            del cref
         # check: every recovered block equals its input (sampled rows)
         nrec = 0
         for sp, g, x, c, xd, er, rec, st in bufs:
@@ -113,7 +155,11 @@ def run_batch512(count=512, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
                 fs.fs_encode(g, x, c, sp.t)
                 fs.fs_decode(g, c, er, 0, xd, rec, st, sp.t, wss[id(g)])
 
-        t_plain = _time(plain, max(1, reps - 1))
+        plain_ms = _time_reps(plain, reps, warm=1)
+        t_plain = float(np.median(plain_ms))
+        for key, v in (("enc", enc_ms), ("dec", dec_ms), ("plain", plain_ms)):
+            tot.setdefault("p99_" + key, 0.0)
+            tot["p99_" + key] += float(np.percentile(v, 99))
         tot["enc_user"] += sum(sp.k * sp.t for sp, *_ in bufs)
         tot["dec_user"] += sum(int(b[6].sum().item()) * b[0].t for b in bufs)
         tot["comp"] += sum(_compulsory_encode(g, sp.t) + (int(rec.sum().item()) + sp.k) * sp.t
@@ -139,11 +185,14 @@ def run_batch512(count=512, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
         "batched_hbm_frac_effective": round(tot["comp"] / (tot["t_batch"] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "recovered_fraction": round(tot["recovered"] / tot["k"], 4),
         "batched_ms": round(tot["t_batch"], 3), "plain_ms": round(tot["t_plain"], 3),
+        "timing": "per wave: %d timed launches of the encode plan, the decode plan and the plain loop, each "
+                  "bracketed by its own events; *_ms sum the per-wave medians, *_p99_ms the per-wave p99s" % reps,
+        "batched_p99_ms": round(tot["p99_enc"] + tot["p99_dec"], 3), "plain_p99_ms": round(tot["p99_plain"], 3),
         "tune": tune, "setup_s": round(time.perf_counter() - t_setup, 1),
     }
 
 
-def run_resident256(count=256, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
+def run_resident256(count=256, reps=20, tune_cache="/tmp/fs_tune_cache.txt"):
     import torch
     import paper_1702_07409_amd as fs
     import synth.gpu as sg
@@ -177,9 +226,10 @@ def run_resident256(count=256, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
                   tune_cache=tune_cache, autotune=True)
     upd = fs.Plan([fs.work("update", d["g"], d["sp"].t, x=d["x"], c=d["c"], ids=d["ids"], n_ids=d["nu"],
                            new_blocks=d["new"], status=d["ust"]) for d in st_])
-    t_rep = _time(rep.launch, reps)
+    rep_ms = _time_reps(rep.launch, reps)
     # the first update applies the new blocks; repeats carry zero deltas but the same traffic
-    t_upd = _time(upd.launch, reps)
+    upd_ms = _time_reps(upd.launch, reps)
+    t_rep, t_upd = float(np.median(rep_ms)), float(np.median(upd_ms))
     assert all(d["rst"].cpu().tolist() == [1, 0, 0] for d in st_)
     ws = {}
     for d in st_:
@@ -195,8 +245,9 @@ def run_resident256(count=256, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
         for d in st_:
             fs.fs_update(d["g"], d["x"], d["c"], d["ids"], d["nu"], d["new"], d["ust"], d["sp"].t, ws[id(d)][1])
 
-    tp_rep = _time(plain_rep, reps)
-    tp_upd = _time(plain_upd, reps)
+    prep_ms = _time_reps(plain_rep, reps)
+    pupd_ms = _time_reps(plain_upd, reps)
+    tp_rep, tp_upd = float(np.median(prep_ms)), float(np.median(pupd_ms))
     # bytes: repair rebuilds |lost| blocks; update rewrites |U| inputs
     t = specs[0].t
     rep_user = sum(d["nl"] for d in st_) * t
@@ -223,6 +274,8 @@ def run_resident256(count=256, reps=3, tune_cache="/tmp/fs_tune_cache.txt"):
         "update_batched_ms": round(t_upd, 3), "update_plain_ms": round(tp_upd, 3),
         "update_batched_GBps_user": round(upd_user / (t_upd * 1e-3) / 1e9, 1),
         "update_hbm_frac_effective": round(upd_comp / (t_upd * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "repair_batched": _stats(rep_ms), "repair_plain": _stats(prep_ms),
+        "update_batched": _stats(upd_ms), "update_plain": _stats(pupd_ms),
         "repair_tune": rep.info()["tune"], "setup_s": round(time.perf_counter() - t0, 1),
     }
 

@@ -5,15 +5,11 @@
       per-kernel durations from the *kernel_stats.csv under DIR (a
       `rocprofv3 --kernel-trace --stats` run), as a markdown table
 
-  python bench_profile.py traffic FETCH_DIR WRITE_DIR COPY_BYTES OUT_JSON OUT_MD CMD_FETCH CMD_WRITE
-      HBM traffic per launch of the large-stripe encode and replay kernels
-      from two `rocprofv3 --pmc` passes over `bench.py --mode counters`
-      (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch).  Each counter is
-      scaled by the bytes a plain device copy of COPY_BYTES moves over what
-      the counter reports for that copy, summed over the dispatches the
-      runtime splits it into.  The JSON records the hash of the
-      library sources, so bench.py reports the traffic only while the kernels
-      are the ones measured.
+  python bench_profile.py counters OUT_JSON OUT_MD TITLE NOTE DIR1 CMD1 [DIR2 CMD2 ...]
+      per-kernel means of every counter of several `rocprofv3 --pmc` passes,
+      with read / write bytes at the L2-to-fabric interface (from the
+      request-size counters), the L2 hit rate and the DRAM share of reads
+      (OUT_JSON "-" writes the markdown only)
 """
 
 import csv
@@ -54,66 +50,85 @@ def stats(d, title, command):
     print("\n".join(out))
 
 
-def _counter(d, counter, total=False):
-    """kernel name -> mean counter value per dispatch (KiB), or with total the
-    sum over the kernel's dispatches."""
+def _all_counters(d):
+    """kernel name -> ({counter: mean value per dispatch}, dispatches) over one --pmc run."""
     acc = {}
     for path in _find(d, "counter_collection.csv"):
         with open(path) as f:
             for r in csv.DictReader(f):
-                if r.get("Counter_Name") != counter:
-                    continue
-                key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id", "")))
+                key = (r["Kernel_Name"], r.get("Dispatch_Id", r.get("Correlation_Id", "")), r["Counter_Name"])
                 acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
     per = {}
-    for (name, _), v in acc.items():
-        per.setdefault(name, []).append(v)
-    return {k: (sum(v) if total else sum(v) / len(v)) for k, v in per.items()}
+    for (name, _, cname), v in acc.items():
+        per.setdefault(name, {}).setdefault(cname, []).append(v)
+    return {k: ({c: sum(v) / len(v) for c, v in cs.items()}, max(len(v) for v in cs.values()))
+            for k, cs in per.items()}
 
 
-def traffic(fetch_dir, write_dir, copy_bytes, out_json, out_md, cmd_fetch, cmd_write):
+def _derived(cs):
+    """Bytes and rates from the raw counters of one kernel (None where a
+    counter was not taken)."""
+    g = cs.get
+    out = {}
+    if all(g(c) is not None for c in ("TCC_EA0_RDREQ_128B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_32B_sum")):
+        out["read_bytes"] = 128 * g("TCC_EA0_RDREQ_128B_sum") + 64 * g("TCC_EA0_RDREQ_64B_sum") \
+            + 32 * g("TCC_EA0_RDREQ_32B_sum")
+    if g("TCC_EA0_WRREQ_sum") is not None and g("TCC_EA0_WRREQ_64B_sum") is not None:
+        out["write_bytes"] = 64 * g("TCC_EA0_WRREQ_64B_sum") + 32 * (g("TCC_EA0_WRREQ_sum") - g("TCC_EA0_WRREQ_64B_sum"))
+    if g("TCC_HIT_sum") is not None and g("TCC_MISS_sum") is not None and g("TCC_HIT_sum") + g("TCC_MISS_sum") > 0:
+        out["l2_hit_rate"] = g("TCC_HIT_sum") / (g("TCC_HIT_sum") + g("TCC_MISS_sum"))
+    if g("TCC_EA0_RDREQ_DRAM_sum") is not None and g("TCC_EA0_RDREQ_sum"):
+        out["dram_share_of_read_requests"] = g("TCC_EA0_RDREQ_DRAM_sum") / g("TCC_EA0_RDREQ_sum")
+    return out
+
+
+def counters(out_json, out_md, title, note, runs):
+    """Merge several --pmc runs (DIR, COMMAND pairs) into per-kernel counter
+    means and the bytes derived from them."""
     from bench import kernel_source_hash
-    fetch = _counter(fetch_dir, "FETCH_SIZE")
-    write = _counter(write_dir, "WRITE_SIZE")
-    # the runtime splits the plain copy into several dispatches: its counters
-    # are summed over all of them
-    fetch_tot = _counter(fetch_dir, "FETCH_SIZE", total=True)
-    write_tot = _counter(write_dir, "WRITE_SIZE", total=True)
-    copy = [k for k in fetch_tot if "copyBuffer" in k]
-    if not copy:
-        raise SystemExit("no plain copy kernel in the counter runs")
-    ff = copy_bytes / (fetch_tot[copy[0]] * 1024.0)
-    wf = copy_bytes / (write_tot[copy[0]] * 1024.0)
-    res = {"workload": "large_stripe (k=4096, n=4506, t=65536)", "copy_bytes_each_way": copy_bytes,
-           "fetch_factor": round(ff, 4), "write_factor": round(wf, 4),
-           "kernel_source_sha256_16": kernel_source_hash(), "commands": [cmd_fetch, cmd_write]}
-    for key, pat in (("encode", "gather_kernel"), ("replay", "replay_")):
-        names = [k for k in fetch if pat in k and k in write]
-        if not names:
-            continue
-        name = max(names, key=lambda k: fetch[k])
-        fb, wb = fetch[name] * 1024.0 * ff, write[name] * 1024.0 * wf
-        res[key] = {"kernel": _short(name), "fetch_KiB_raw": round(fetch[name], 1),
-                    "write_KiB_raw": round(write[name], 1), "fetch_bytes_per_launch": int(fb),
-                    "write_bytes_per_launch": int(wb), "bytes_per_launch": int(fb + wb)}
-    with open(out_json, "w") as f:
-        json.dump(res, f, indent=1)
-    md = ["# HBM traffic: encode and replay kernels of the large stripe", "",
-          "Commands (two passes, one counter each; bench.py --mode counters runs 5 encodes, 5 one-stream",
-          "decodes and one plain device copy of the coded-block size), summarised by",
-          "`python bench_profile.py traffic ...`:", "", "```", cmd_fetch, cmd_write, "```", "",
-          "Scale = bytes the plain copy moves / what the counter reports for it: FETCH %.4f, WRITE %.4f." % (ff, wf),
-          "", "| kernel | FETCH KiB raw | WRITE KiB raw | read bytes | write bytes | total per launch |",
-          "|---|---:|---:|---:|---:|---:|"]
-    for key in ("encode", "replay"):
-        if key in res:
-            r = res[key]
-            md.append("| `%s` | %.1f | %.1f | %d | %d | %d |" % (
-                r["kernel"], r["fetch_KiB_raw"], r["write_KiB_raw"], r["fetch_bytes_per_launch"],
-                r["write_bytes_per_launch"], r["bytes_per_launch"]))
-    md += ["", "Every kernel of the runs (raw KiB per dispatch):", ""]
-    for name in sorted(fetch):
-        md.append("- `%s`: FETCH %.1f, WRITE %.1f" % (_short(name), fetch[name], write.get(name, float("nan"))))
+    merged, calls = {}, {}
+    for d, _ in runs:
+        for k, (cs, n) in _all_counters(d).items():
+            merged.setdefault(k, {}).update(cs)
+            calls[k] = n
+    # kernels that move at least 0.1 % of the bytes of the largest one
+    def moved(k):
+        d = _derived(merged[k])
+        return (d.get("read_bytes", 0.0) + d.get("write_bytes", 0.0)) * calls[k]
+    top = max((moved(k) for k in merged), default=0.0)
+    names = sorted((k for k in merged if moved(k) >= 1e-3 * top), key=lambda k: -moved(k))
+    res = {"title": title, "kernel_source_sha256_16": kernel_source_hash(), "commands": [c for _, c in runs],
+           "kernels": {}}
+    for k in names:
+        cs = merged[k]
+        res["kernels"][_short(k)] = {"dispatches": calls[k],
+                                     "counters": {c: round(v, 1) for c, v in sorted(cs.items())},
+                                     "derived": {c: (round(v, 4) if isinstance(v, float) else v)
+                                                 for c, v in _derived(cs).items()}}
+    if out_json != "-":
+        with open(out_json, "w") as f:
+            json.dump(res, f, indent=1)
+    cols = sorted({c for cs in merged.values() for c in cs})
+    md = ["# Counters: %s" % title, "", note, "", "Commands (one rocprofv3 pass each, from /tmp on one MI355X):", "",
+          "```"] + [c for _, c in runs] + ["```", "",
+          "Mean per dispatch. Read bytes = 128 x RDREQ_128B + 64 x RDREQ_64B + 32 x RDREQ_32B; write bytes = "
+          "64 x WRREQ_64B + 32 x (WRREQ - WRREQ_64B).  These are requests from the L2 to the data fabric: the "
+          "Infinity Cache (MALL) may serve a read without HBM, so they bound HBM traffic from above.", "",
+          "| kernel | dispatches | GB moved, all dispatches | read bytes | write bytes | L2 hit rate | "
+          "DRAM share of read requests |",
+          "|---|---:|---:|---:|---:|---:|---:|"]
+    for k in names:
+        d = _derived(merged[k])
+        md.append("| `%s` | %d | %.2f | %s | %s | %s | %s |" % (
+            _short(k, 70), calls[k], moved(k) / 1e9, "%.0f" % d["read_bytes"] if "read_bytes" in d else "-",
+            "%.0f" % d["write_bytes"] if "write_bytes" in d else "-",
+            "%.3f" % d["l2_hit_rate"] if "l2_hit_rate" in d else "-",
+            "%.3f" % d["dram_share_of_read_requests"] if "dram_share_of_read_requests" in d else "-"))
+    md += ["", "Raw counters (mean per dispatch):", "", "| kernel | " + " | ".join(cols) + " |",
+           "|---|" + "---:|" * len(cols)]
+    for k in names:
+        md.append("| `%s` | " % _short(k, 70) + " | ".join(
+            "%.0f" % merged[k][c] if c in merged[k] else "-" for c in cols) + " |")
     with open(out_md, "w") as f:
         f.write("\n".join(md) + "\n")
 
@@ -121,8 +136,9 @@ def traffic(fetch_dir, write_dir, copy_bytes, out_json, out_md, cmd_fetch, cmd_w
 if __name__ == "__main__":
     if len(sys.argv) >= 5 and sys.argv[1] == "stats":
         stats(sys.argv[2], sys.argv[3], sys.argv[4])
-    elif len(sys.argv) >= 9 and sys.argv[1] == "traffic":
-        traffic(sys.argv[2], sys.argv[3], int(sys.argv[4]), sys.argv[5], sys.argv[6], sys.argv[7], sys.argv[8])
+    elif len(sys.argv) >= 8 and sys.argv[1] == "counters" and len(sys.argv) % 2 == 0:
+        counters(sys.argv[2], sys.argv[3], sys.argv[4], sys.argv[5],
+                 list(zip(sys.argv[6::2], sys.argv[7::2])))
     else:
         print(__doc__, file=sys.stderr)
         sys.exit(2)

@@ -510,6 +510,26 @@ typedef struct fs_tune {
 FS_API fs_status fs_set_tune(const fs_tune *tune);
 FS_API fs_status fs_get_tune(fs_tune *tune);
 
+/*
+ * Shape of the last single-stripe gather (fs_encode, fs_repair, fs_update,
+ * fs_extend, the precode encode) and the last decode replay that the calling
+ * thread launched, as chosen by the tuning and the per-graph rules above.
+ * For tests and tuning tools; plans report their own choices through
+ * fs_plan_get_info.  Fields are 0 until the first launch of that kind.
+ */
+typedef struct fs_launch_info {
+  uint32_t gather_kind;          /* 1 gather kernel, 2 LDS-slab encode           */
+  uint32_t gather_lanes_per_row; /* lanes per coded row (slab: lanes per slice) */
+  uint32_t gather_chunks;        /* 16-byte chunks per lane (slab: 1)           */
+  uint32_t gather_slice_bytes;   /* bytes of each block one item covers         */
+  uint32_t replay_kind;          /* 1 LDS slab, 2 wide slices, 3 lookahead,
+                                    4 no program (global-memory replay)          */
+  uint32_t replay_slice_bytes;   /* bytes of each block one workgroup covers    */
+  uint32_t replay_workgroups;    /* grid of the replay launch                   */
+  uint32_t reserved;
+} fs_launch_info;
+FS_API fs_status fs_last_launch(fs_launch_info *info);
+
 /* ---------------------------------------------------------------------------
  * Batches: many stripes of uneven k and block size in one captured launch.
  *
@@ -525,6 +545,12 @@ FS_API fs_status fs_get_tune(fs_tune *tune);
  * fs_plan_launch replays the graph.  Items of one plan must be independent:
  * no item may write a buffer another item of the plan reads or writes.
  * Results are those of the single-stripe calls (bit for bit).
+ *
+ * Batching has no counterpart in the paper: it changes only how independent
+ * single-stripe operations are scheduled, never their arithmetic.  The
+ * nearest passages are the paper's processing of a file as independent
+ * partitions, each coded on its own (§2.2), and its dynamic thread
+ * scheduling over unevenly sized work in the decoder (§3.1).
  * ------------------------------------------------------------------------- */
 enum { FS_WORK_ENCODE = 0, FS_WORK_DECODE = 1, FS_WORK_REPAIR = 2, FS_WORK_UPDATE = 3 };
 
@@ -603,8 +629,12 @@ FS_API fs_status fs_plan_launch(fs_plan *plan, hipStream_t stream);
 /*
  * Point the plan at new buffers: same count and, item by item, the same op,
  * graph, t and n_ids (else FS_ERR_INVALID).  The descriptors are rewritten
- * in device memory on the stream; the captured graph is reused.  A launch
- * already enqueued on another stream must have completed.
+ * in device memory on the stream.  The captured graph is reused when every
+ * job of the plan runs inside the shared persistent kernels; a plan that
+ * also holds stripes large enough for launches of their own (their
+ * arguments are captured by value) is captured again, which costs a graph
+ * capture and instantiation on the host.  A launch already enqueued on
+ * another stream must have completed.
  */
 FS_API fs_status fs_plan_rebind(fs_plan *plan, const fs_work *items, uint32_t count, hipStream_t stream);
 FS_API fs_status fs_plan_get_info(const fs_plan *plan, fs_plan_info *info);

@@ -57,6 +57,13 @@ class fs_tune(ctypes.Structure):
                 ("replay_lookahead", ctypes.c_uint32)]
 
 
+class fs_launch_info(ctypes.Structure):
+    _fields_ = [("gather_kind", ctypes.c_uint32), ("gather_lanes_per_row", ctypes.c_uint32),
+                ("gather_chunks", ctypes.c_uint32), ("gather_slice_bytes", ctypes.c_uint32),
+                ("replay_kind", ctypes.c_uint32), ("replay_slice_bytes", ctypes.c_uint32),
+                ("replay_workgroups", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class fs_work(ctypes.Structure):
     _fields_ = [("op", ctypes.c_uint32), ("n_ids", ctypes.c_uint32), ("graph", ctypes.c_void_p),
                 ("t", ctypes.c_uint64), ("x", ctypes.c_void_p), ("c", ctypes.c_void_p),
@@ -126,6 +133,7 @@ _SIGS = {
     "fs_plan_free": ([P], None),
     "fs_set_tune": ([ctypes.POINTER(fs_tune)], ST),
     "fs_get_tune": ([ctypes.POINTER(fs_tune)], ST),
+    "fs_last_launch": ([ctypes.POINTER(fs_launch_info)], ST),
     "fs_status_string": ([I32], ctypes.c_char_p),
     "fs_last_error": ([], ctypes.c_char_p),
     "fs_version": ([], ctypes.c_char_p),
@@ -488,6 +496,13 @@ def fs_set_tune(lanes_per_row=0, chunks=0, xcd_remap=1, nt_store=1, replay_prog_
 
 def fs_reset_tune():
     _check(_lib.fs_set_tune(None), "fs_set_tune")
+
+
+def fs_last_launch():
+    """Shape of this thread's last single-stripe gather and replay launch."""
+    li = fs_launch_info()
+    _check(_lib.fs_last_launch(ctypes.byref(li)), "fs_last_launch")
+    return {f: getattr(li, f) for f, _ in fs_launch_info._fields_ if f != "reserved"}
 
 
 def fs_get_tune():

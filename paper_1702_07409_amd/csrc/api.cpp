@@ -384,6 +384,11 @@ ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, cons
 
 fs_tune tune_snapshot() { return current_tune(); }
 
+fs_launch_info &launch_record() {
+  static thread_local fs_launch_info rec = {};
+  return rec;
+}
+
 }  // namespace fs
 
 using namespace fs;
@@ -406,6 +411,13 @@ const char *fs_status_string(fs_status s) {
 }
 
 const char *fs_last_error(void) { return g_last_error.c_str(); }
+
+fs_status fs_last_launch(fs_launch_info *info) {
+  clear_error();
+  if (!info) return fail(FS_ERR_INVALID, "info must be non-null");
+  *info = launch_record();
+  return FS_OK;
+}
 
 fs_status fs_set_tune(const fs_tune *tune) {
   clear_error();

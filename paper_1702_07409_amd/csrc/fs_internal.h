@@ -80,6 +80,9 @@ const DeviceInfo &device_info(int dev);
 // the process-wide tuning (fs_set_tune)
 fs_tune tune_snapshot();
 
+// shape of the last single-stripe gather and replay of this thread (fs_last_launch)
+fs_launch_info &launch_record();
+
 // workspace carving: aligned sub-buffers of one caller workspace
 struct Carver {
   uint8_t *base;

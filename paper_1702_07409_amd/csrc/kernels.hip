@@ -404,6 +404,11 @@ bool try_slab_encode(const GatherJob &j, const fs_tune &tune, hipStream_t s, hip
   const uint64_t nslices = (j.t + w - 1) / w;
   if (nslices < (uint64_t)cu || nslices > 0xffffffffull) return false;
   const int grid = cu;
+  fs_launch_info &rec = launch_record();
+  rec.gather_kind = 2;
+  rec.gather_lanes_per_row = (uint32_t)lps;
+  rec.gather_chunks = 1;
+  rec.gather_slice_bytes = w;
   switch (lps) {
     case 64: e = run_slab_encode<64>(j, (uint32_t)nslices, grid, dev, s); break;
     case 32: e = run_slab_encode<32>(j, (uint32_t)nslices, grid, dev, s); break;
@@ -422,6 +427,11 @@ hipError_t run_gather(const GatherJob &j, uint32_t remap, hipStream_t s, int cu_
   // device-sized jobs use a bounded grid that strides over the live items
   const uint64_t cap = j.nrows_dev ? (uint64_t)cu_count * 8 : (uint64_t)1 << 30;
   uint64_t grid = nitems < cap ? nitems : cap;
+  fs_launch_info &rec = launch_record();
+  rec.gather_kind = 1;
+  rec.gather_lanes_per_row = LPR;
+  rec.gather_chunks = CH;
+  rec.gather_slice_bytes = W;
   if (grid == 0) return hipSuccess;
   hipLaunchKernelGGL((gather_kernel<LPR, CH, NT>), dim3((uint32_t)grid), dim3(kGatherThreads), 0, s,
                      j, nslices, remap);
@@ -1834,6 +1844,10 @@ static hipError_t run_replay_lds(const ReplayJob &job, const ProgJob &prog, uint
                                  int budget, int dev, hipStream_t s) {
   static bool done[64] = {false};
   set_max_lds(reinterpret_cast<const void *>(&replay_lds_kernel<LPS, M>), dev, budget, done);
+  fs_launch_info &rec = launch_record();
+  rec.replay_kind = 1;
+  rec.replay_slice_bytes = 16u * LPS;
+  rec.replay_workgroups = grid;
   hipLaunchKernelGGL((replay_lds_kernel<LPS, M>), dim3(grid), dim3(kReplayThreads), budget, s, job, prog,
                      nslices, (uint32_t)budget, tune_snapshot().replay_prog_global ? 0u : 1u);
   return hipGetLastError();
@@ -1850,6 +1864,10 @@ static hipError_t run_replay_wide(const ReplayJob &job, const ProgJob &prog, int
   // LDS for the 16-bit program: its largest possible size (the kernel checks
   // the actual one), so that two workgroups share a CU when it is small
   const int lds = (int)std::min<size_t>((size_t)budget, replay_prog_lds_bound(job.k, prog.pidx_cap));
+  fs_launch_info &rec = launch_record();
+  rec.replay_kind = 2;
+  rec.replay_slice_bytes = w;
+  rec.replay_workgroups = grid;
   hipLaunchKernelGGL(replay_wide_kernel<LPS>, dim3(grid), dim3(kReplayThreads), lds, s, job, prog, nslices,
                      (uint32_t)lds, tune_snapshot().replay_prog_global ? 0u : 1u);
   return hipGetLastError();
@@ -1882,6 +1900,10 @@ static hipError_t run_replay_la(const ReplayJob &job, const ProgJob &prog, int b
                                 hipStream_t s) {
   static bool done[64] = {false};
   set_max_lds(reinterpret_cast<const void *>(&replay_la_kernel<PD>), dev, budget, done);
+  fs_launch_info &rec = launch_record();
+  rec.replay_kind = 3;
+  rec.replay_slice_bytes = 0;  // chosen in the kernel from the slab it fits
+  rec.replay_workgroups = (uint32_t)cu;
   hipLaunchKernelGGL(replay_la_kernel<PD>, dim3(cu), dim3(kReplayThreads), budget, s, job, prog, (uint32_t)budget);
   return hipGetLastError();
 }
@@ -1907,11 +1929,17 @@ fs_status launch_replay_prog(const ReplayJob &job, const ProgJob *prog, hipStrea
   const int budget = device_info(dev).max_lds_per_block;
   if (!prog) {
     // no workspace for a program: the plain global-memory replay
+    fs_launch_info &rec = launch_record();
+    rec.replay_kind = 4;
     if (job.t >= 256ull * 512) {
       const uint32_t ns = (uint32_t)((job.t + 255) / 256);
+      rec.replay_slice_bytes = 256;
+      rec.replay_workgroups = ns;
       hipLaunchKernelGGL(replay_kernel<16>, dim3(ns), dim3(kReplayThreads), 0, s, job);
     } else {
       const uint32_t ns = (uint32_t)((job.t + 63) / 64);
+      rec.replay_slice_bytes = 64;
+      rec.replay_workgroups = ns;
       hipLaunchKernelGGL(replay_kernel<4>, dim3(ns), dim3(kReplayThreads), 0, s, job);
     }
     return hip_check(hipGetLastError(), "replay launch");

@@ -96,6 +96,9 @@ def test_encode_sparse_graph_beyond_8192_inputs(k, n, dist, t):
     sp = workloads.StripeSpec(stripe=0, k=k, n=n, t=t, dist=dist, finite_w=w, stripe_key=3, n_erased=0)
     g, G, x, xd, c = encode_case(sp)
     assert np.array_equal(host(c), codec.encode(G, x))
+    import paper_1702_07409_amd as fs
+    li = fs.fs_last_launch()
+    assert (li["gather_kind"], li["gather_slice_bytes"]) == (1, 512), li
 
 
 def test_encode_tiles_beyond_the_lds_edge_stage():
@@ -319,6 +322,12 @@ LOOKAHEAD_CASES = {
 }
 
 
+# slice width the wide replay must take for the short-block cases (the rule
+# depends on the CU count and on how many program workgroups fit a CU, so
+# the launch is checked, not assumed)
+WIDE_REPLAY_WIDTH = {"short_32": 32, "short_64": 64}
+
+
 @pytest.mark.parametrize("lookahead", [1, 0])
 @pytest.mark.parametrize("case", sorted(LOOKAHEAD_CASES))
 def test_decode_lookahead_replay(case, lookahead):
@@ -329,6 +338,12 @@ def test_decode_lookahead_replay(case, lookahead):
     fs.fs_set_tune(replay_lookahead=lookahead)
     try:
         decode_case(workloads.StripeSpec(**LOOKAHEAD_CASES[case]))
+        li = fs.fs_last_launch()
+        if lookahead == 0 and case in WIDE_REPLAY_WIDTH:
+            assert (li["replay_kind"], li["replay_slice_bytes"]) == (2, WIDE_REPLAY_WIDTH[case]), li
+        # with the lookahead tuning its kernel is launched (it falls back to
+        # wide slices inside when the slab does not fit); without, the wide one
+        assert li["replay_kind"] == (3 if lookahead else 2), li
     finally:
         fs.fs_reset_tune()
 
