@@ -65,8 +65,11 @@ enum {
 
 /* fs_graph_params.flags */
 enum {
-  FS_GRAPH_HOST_ONLY = 1   /* build the host arrays only (no device copy, no
+  FS_GRAPH_HOST_ONLY = 1,  /* build the host arrays only (no device copy, no
                               HIP call): for fs_graph_export on any machine  */
+  FS_GRAPH_ON_DEVICE = 2   /* build the graph with kernels on the current
+                              device (the same arrays, element for element);
+                              the host keeps no copy of the CSR/CSC          */
 };
 
 typedef struct fs_graph_params {
@@ -110,8 +113,15 @@ FS_API fs_status fs_degree_table(const fs_graph_params *params, uint64_t *T_out,
  * and the row is sorted ascending.  Rows do not depend on n.
  * Unless FS_GRAPH_HOST_ONLY, the CSR/CSC are copied to the current device on
  * `stream` and the call returns after the copy has completed.
+ * With FS_GRAPH_ON_DEVICE the rows are drawn by kernels on `stream` instead
+ * (one thread per row, a workgroup per row of more than 64 neighbours), the
+ * transpose and the encode segments likewise; the call synchronises the
+ * stream twice (for the sizes, then the heavy-row list) and returns with the
+ * graph complete.  fs_graph_export then copies from the device, and
+ * fs_graph_image_size / fs_graph_upload do not apply.
  * *out receives the graph (freed with fs_graph_free).
- * Errors: FS_ERR_INVALID (parameters, nnz >= 2^31), FS_ERR_NOMEM, FS_ERR_HIP.
+ * Errors: FS_ERR_INVALID (parameters, unknown or conflicting flags,
+ * nnz >= 2^31), FS_ERR_NOMEM, FS_ERR_HIP.
  */
 FS_API fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_graph **out);
 
@@ -158,7 +168,7 @@ FS_API fs_status fs_encode(const fs_graph *g, const void *x, void *c, uint64_t t
 enum { FS_OP_ENCODE = 0, FS_OP_PEEL = 1, FS_OP_DECODE = 2, FS_OP_REPAIR = 3,
        FS_OP_REPAIR_CONVENTIONAL = 4, FS_OP_UPDATE = 5, FS_OP_REPLAY = 6, FS_OP_EXTEND = 7,
        FS_OP_EXTEND_CONVENTIONAL = 8, FS_OP_SIM_DISKS = 9, FS_OP_DECODE_PRECODED = 10,
-       FS_OP_REPAIR_LOCAL = 11, FS_OP_REPAIR_PRECODED = 12 };
+       FS_OP_REPAIR_LOCAL = 11, FS_OP_REPAIR_PRECODED = 12, FS_OP_EXTEND_LOCAL = 13 };
 
 /*
  * Workspace bytes the operation needs for this graph and block size
@@ -283,6 +293,22 @@ FS_API fs_status fs_update(const fs_graph *g, void *x, void *c, const uint32_t *
 FS_API fs_status fs_extend(const fs_graph *g, uint32_t n_old, const void *x, void *c,
                     const uint8_t *erased, uint8_t *made, int32_t *status, uint64_t t,
                     void *ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Code extension through local groups, as §2.9 describes the update: the new
+ * coded rows n_old..n-1 of the longer graph g are made from existing coded
+ * blocks only, each as the XOR of the other members of a check #3 group of
+ * the longer code, smallest groups first (fs_repair_local with the new rows
+ * as the lost ones).  ch: the check #2/#3 equations of g (fs_checks_generate
+ * on the longer graph, or its check data loaded).  erased: device uint8[n_old]
+ * (the old rows that are unavailable) or NULL.  made: device
+ * uint8[n - n_old]; status: device int32[3] as fs_repair_local's.  Rows no
+ * local group reaches are left zero-filled (made 0) for fs_extend.
+ * ws: FS_OP_EXTEND_LOCAL bytes with n_items = n - n_old.
+ */
+FS_API fs_status fs_extend_local(const fs_graph *g, const fs_checks *ch, uint32_t n_old, void *c,
+                                 const uint8_t *erased, uint8_t *made, int32_t *status, uint64_t t,
+                                 void *ws, size_t ws_bytes, hipStream_t stream);
 
 /*
  * Disk-failure sweep, the simDisk utility (§2.1, §2.2): which combinations
@@ -480,9 +506,12 @@ FS_API fs_status fs_decode_apply(const fs_graph *g, const void *c, void *x, uint
 
 /* Tuning of the gather-XOR kernel family (encode, repair, update). */
 typedef struct fs_tune {
-  uint32_t lanes_per_row;  /* 16, 32 or 64 lanes share one coded row         */
+  uint32_t lanes_per_row;  /* 16, 32, 64, 128 or 256 lanes share one coded
+                              row (128 and 256: one or two rows per
+                              workgroup, for jobs of few rows)               */
   uint32_t chunks;         /* 16-byte chunks per lane per slice: 1, 2 or 4
-                              (both 0: chosen per graph, see fs_set_tune)    */
+                              (1 or 2 with 128 and 256 lanes; both 0: chosen
+                              per graph, see fs_set_tune)                    */
   uint32_t xcd_remap;      /* 1: keep each XCD on a contiguous slice range   */
   uint32_t nt_store;       /* 1: non-temporal stores for outputs             */
   uint32_t replay_prog_global; /* 1: keep decode replay programs in global
@@ -497,11 +526,14 @@ typedef struct fs_tune {
                               (16-128 bytes).  Off by default: on the
                               k = 4096 x 64 KiB stripe it takes 0.38 ms
                               against 0.21 ms for the wide-slice replay    */
+  uint32_t claim_chunk;    /* items a workgroup of the batched gather claims
+                              from its XCD's counter at a time, 1..1024
+                              (0: by the plan's item count and grid)        */
 } fs_tune;
 
 /*
  * Override (or with NULL restore) the gather tuning used by this process.
- * The default is {0, 0, 1, 1, 0, 1, 0}: the gather slice is chosen per graph
+ * The default is {0, 0, 1, 1, 0, 1, 0, 0}: the gather slice is chosen per graph
  * (4 KiB for graphs of mean degree <= 6, which read each neighbour block in
  * long runs; for denser graphs 2 MiB / k within [512 B, 4 KiB], so that one
  * slice of every input stays in an XCD's L2), the LDS-slab encode where it

@@ -33,6 +33,10 @@ Functions and the passage each follows
   from_check_data   what the repair engine keeps from it: the first check #2
                  record per input, and the check #3 groups ordered by
                  cardinality (ties in file order), members as sets.
+  extend_local   §2.9's update through local groups: the coded rows
+                 n_old..n-1 of a longer code made from the existing rows by
+                 local_repair over the longer code's check #3 groups, the
+                 new rows taking the place of lost ones.
   local_repair   the repair engine's fast path (§2.3, §2.8, §4): BP over the
                  check #3 groups.  At each level every lost coded block
                  still unknown is rebuilt as the XOR of the other members of
@@ -282,3 +286,20 @@ def local_repair(groups, c, lost, erased=None, max_levels=0):
             work[lost[r]] = out[r]
         levels += 1
     return out, ok, used, level_of, levels
+
+
+def extend_local(groups, c_old, n, erased=None):
+    """(rows[n - n_old, t], made[n - n_old], levels): the new coded rows of a
+    code grown from n_old = len(c_old) to n rows, rebuilt from the existing
+    rows through the check #3 groups of the n-row code.  erased: uint8[n_old]
+    (old rows that are unavailable) or None.  Rows no group reaches stay
+    zero with made 0."""
+    c_old = np.asarray(c_old, dtype=np.uint8)
+    n_old, t = c_old.shape
+    c = np.zeros((n, t), dtype=np.uint8)
+    c[:n_old] = c_old
+    er = np.zeros(n, dtype=np.uint8)
+    if erased is not None:
+        er[:n_old] = np.asarray(erased, dtype=np.uint8)
+    rows, made, _, _, levels = local_repair(groups, c, list(range(n_old, n)), er)
+    return rows, made, levels

@@ -14,7 +14,7 @@ then raises ImportError.
 _BINDING = (
     "EXPORTED", "FS_DEFAULT_SEED", "FS_OP_DECODE", "FS_OP_ENCODE", "FS_OP_PEEL", "FS_OP_REPAIR",
     "FS_OP_REPAIR_CONVENTIONAL", "FS_OP_REPLAY", "FS_OP_UPDATE", "FS_OP_EXTEND",
-    "FS_OP_EXTEND_CONVENTIONAL", "FS_OP_SIM_DISKS", "FS_OP_DECODE_PRECODED", "FS_OP_REPAIR_LOCAL", "FS_OP_REPAIR_PRECODED", "FsError",
+    "FS_OP_EXTEND_CONVENTIONAL", "FS_OP_SIM_DISKS", "FS_OP_DECODE_PRECODED", "FS_OP_REPAIR_LOCAL", "FS_OP_REPAIR_PRECODED", "FS_OP_EXTEND_LOCAL", "fs_extend_local", "FsError",
     "Graph", "Checks", "fs_checks_generate", "fs_checks_load", "fs_repair_local", "fs_repair_precoded", "fs_decode", "fs_decode_noalloc", "fs_decode_apply", "fs_decode_plan", "fs_degree_table", "fs_encode", "fs_get_tune", "fs_last_launch",
     "fs_graph_build", "fs_peel", "fs_repair", "fs_replay", "fs_reset_tune", "fs_set_tune",
     "fs_update", "fs_extend", "fs_sim_disks", "fs_sim_disks_precoded", "fs_precode_build",

@@ -35,9 +35,10 @@ FS_OK, FS_ERR_INVALID, FS_ERR_ALIGN, FS_ERR_NOMEM, FS_ERR_HIP, FS_ERR_UNSUPPORTE
 FS_DIST_RSD, FS_DIST_FINITE, FS_DIST_RAPTOR = 0, 1, 2
 FS_DEFAULT_SEED = 1389488782
 FS_GRAPH_HOST_ONLY = 1
+FS_GRAPH_ON_DEVICE = 2
 (FS_OP_ENCODE, FS_OP_PEEL, FS_OP_DECODE, FS_OP_REPAIR, FS_OP_REPAIR_CONVENTIONAL, FS_OP_UPDATE, FS_OP_REPLAY,
  FS_OP_EXTEND, FS_OP_EXTEND_CONVENTIONAL, FS_OP_SIM_DISKS, FS_OP_DECODE_PRECODED, FS_OP_REPAIR_LOCAL,
- FS_OP_REPAIR_PRECODED) = range(13)
+ FS_OP_REPAIR_PRECODED, FS_OP_EXTEND_LOCAL) = range(14)
 
 DIST_CODES = {"rsd": FS_DIST_RSD, "finite": FS_DIST_FINITE, "raptor": FS_DIST_RAPTOR}
 
@@ -54,7 +55,7 @@ class fs_tune(ctypes.Structure):
     _fields_ = [("lanes_per_row", ctypes.c_uint32), ("chunks", ctypes.c_uint32),
                 ("xcd_remap", ctypes.c_uint32), ("nt_store", ctypes.c_uint32),
                 ("replay_prog_global", ctypes.c_uint32), ("encode_slab", ctypes.c_uint32),
-                ("replay_lookahead", ctypes.c_uint32)]
+                ("replay_lookahead", ctypes.c_uint32), ("claim_chunk", ctypes.c_uint32)]
 
 
 class fs_launch_info(ctypes.Structure):
@@ -124,6 +125,7 @@ _SIGS = {
     "fs_checks_load": ([P, P, U64, P, ctypes.POINTER(P)], ST),
     "fs_checks_add_groups": ([P, P, P, P, ctypes.POINTER(U32)], ST),
     "fs_repair_local": ([P, P, P, P, P, U32, P, P, U64, P, SZ, P], ST),
+    "fs_extend_local": ([P, P, U32, P, P, P, P, U64, P, SZ, P], ST),
     "fs_plan_create": ([ctypes.POINTER(fs_work), U32, ctypes.c_char_p, U32, P, ctypes.POINTER(P)], ST),
     "fs_plan_launch": ([P, P], ST),
     "fs_plan_memory_size": ([ctypes.POINTER(fs_work), U32, ctypes.POINTER(SZ), ctypes.POINTER(SZ)], ST),
@@ -180,7 +182,7 @@ def _stream(stream):
 
 
 def make_params(k, n, dist="rsd", rsd_c=0.1, rsd_delta=0.05, finite_w=(), seed=FS_DEFAULT_SEED,
-                stripe_key=0, host_only=False):
+                stripe_key=0, host_only=False, on_device=False):
     p = fs_graph_params()
     p.k, p.n = k, n
     p.dist = DIST_CODES[dist]
@@ -189,7 +191,7 @@ def make_params(k, n, dist="rsd", rsd_c=0.1, rsd_delta=0.05, finite_w=(), seed=F
     p.finite_dmax = len(finite_w)
     p.finite_w = ctypes.cast(w, ctypes.POINTER(ctypes.c_double))
     p.seed, p.stripe_key = seed, stripe_key
-    p.flags = FS_GRAPH_HOST_ONLY if host_only else 0
+    p.flags = (FS_GRAPH_HOST_ONLY if host_only else 0) | (FS_GRAPH_ON_DEVICE if on_device else 0)
     p._keep = w
     return p
 
@@ -215,6 +217,14 @@ class Graph:
                                   ctypes.byref(md), ctypes.byref(mc)), "fs_graph_info")
         self.k, self.n, self.nnz = k.value, n.value, nnz.value
         self.max_degree, self.max_column_degree = md.value, mc.value
+
+    @property
+    def built_on_device(self):
+        return bool(self.params.flags & FS_GRAPH_ON_DEVICE)
+
+    def device_bytes(self):
+        """Device bytes of the graph's arrays (CSR, CSC, encode segments), about."""
+        return 4 * (3 * self.nnz + 3 * self.n + self.k) + 9 * 256
 
     def export(self):
         import numpy as np
@@ -255,8 +265,10 @@ class Graph:
 
 
 def fs_graph_build(k, n, dist="rsd", rsd_c=0.1, rsd_delta=0.05, finite_w=(), seed=FS_DEFAULT_SEED,
-                   stripe_key=0, host_only=False, stream=None):
-    p = make_params(k, n, dist, rsd_c, rsd_delta, finite_w, seed, stripe_key, host_only)
+                   stripe_key=0, host_only=False, on_device=False, stream=None):
+    """on_device: the rows, transpose and encode segments are built by
+    kernels on the current device (same arrays as the host build)."""
+    p = make_params(k, n, dist, rsd_c, rsd_delta, finite_w, seed, stripe_key, host_only, on_device)
     h = P()
     s = None if host_only else _stream(stream)
     _check(_lib.fs_graph_build(ctypes.byref(p), s, ctypes.byref(h)), "fs_graph_build")
@@ -470,6 +482,14 @@ def fs_repair_local(g, ch, c, erased, lost, n_lost, repaired, status, t, ws, str
                                 _ptr(status), t, w, wb, _stream(stream)), "fs_repair_local")
 
 
+def fs_extend_local(g, ch, n_old, c, erased, made, status, t, ws, stream=None):
+    """New coded rows n_old..n-1 from existing ones through the check #3
+    groups ch of the longer graph g (§2.9)."""
+    w, wb = _ws(ws)
+    _check(_lib.fs_extend_local(g.handle, ch.handle, n_old, _ptr(c), _ptr(erased), _ptr(made), _ptr(status),
+                                t, w, wb, _stream(stream)), "fs_extend_local")
+
+
 def fs_repair_precoded(g, pc, c, erased, lost, n_lost, repaired, status, t, ws, stream=None):
     w, wb = _ws(ws)
     _check(_lib.fs_repair_precoded(g.handle, pc.handle, _ptr(c), _ptr(erased), _ptr(lost), n_lost, _ptr(repaired),
@@ -489,8 +509,9 @@ def fs_sim_disks(g, s, f, first, count, maxit, result, ws, stream=None):
 
 
 def fs_set_tune(lanes_per_row=0, chunks=0, xcd_remap=1, nt_store=1, replay_prog_global=0, encode_slab=1,
-                replay_lookahead=0):
-    tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store, replay_prog_global, encode_slab, replay_lookahead)
+                replay_lookahead=0, claim_chunk=0):
+    tu = fs_tune(lanes_per_row, chunks, xcd_remap, nt_store, replay_prog_global, encode_slab, replay_lookahead,
+                 claim_chunk)
     _check(_lib.fs_set_tune(ctypes.byref(tu)), "fs_set_tune")
 
 
@@ -510,7 +531,7 @@ def fs_get_tune():
     _check(_lib.fs_get_tune(ctypes.byref(tu)), "fs_get_tune")
     return dict(lanes_per_row=tu.lanes_per_row, chunks=tu.chunks, xcd_remap=tu.xcd_remap,
                 nt_store=tu.nt_store, replay_prog_global=tu.replay_prog_global, encode_slab=tu.encode_slab,
-                replay_lookahead=tu.replay_lookahead)
+                replay_lookahead=tu.replay_lookahead, claim_chunk=tu.claim_chunk)
 
 
 FS_WORK_ENCODE, FS_WORK_DECODE, FS_WORK_REPAIR, FS_WORK_UPDATE = range(4)
@@ -582,7 +603,7 @@ class Plan:
         _check(_lib.fs_plan_get_info(self.handle, ctypes.byref(i)), "fs_plan_get_info")
         out = {f: getattr(i, f) for f, _ in fs_plan_info._fields_ if f != "tune"}
         out["tune"] = dict(lanes_per_row=i.tune.lanes_per_row, chunks=i.tune.chunks,
-                           xcd_remap=i.tune.xcd_remap, nt_store=i.tune.nt_store)
+                           xcd_remap=i.tune.xcd_remap, nt_store=i.tune.nt_store, claim_chunk=i.tune.claim_chunk)
         return out
 
     def free(self):

@@ -30,6 +30,7 @@ SOURCES = [
     ("simdisk.hip", DEVICE),
     ("precode.hip", DEVICE),
     ("checks.hip", DEVICE),
+    ("graph_dev.hip", DEVICE),
     ("api.cpp", DEVICE),
     ("plan.cpp", DEVICE),
     ("noalloc.cpp", DEVICE),

@@ -38,7 +38,7 @@ const DeviceInfo &device_info(int dev) {
 
 namespace {
 std::mutex g_tune_mu;
-fs_tune g_tune = {0, 0, 1, 1, 0, 1, 0};
+fs_tune g_tune = {0, 0, 1, 1, 0, 1, 0, 0};
 
 }  // namespace
 
@@ -81,29 +81,37 @@ fs_tune tile_for(const fs_tune &t, const fs_graph *g) {
 
 static bool tune_ok(const fs_tune &t) {
   const bool auto_tile = t.lanes_per_row == 0 && t.chunks == 0;
-  const bool lpr = auto_tile || t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64;
-  const bool ch = auto_tile || t.chunks == 1 || t.chunks == 2 || t.chunks == 4;
+  const bool lpr = auto_tile || t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64 ||
+                   t.lanes_per_row == 128 || t.lanes_per_row == 256;
+  // row-wide tilings (one or two rows per workgroup) take 1 or 2 chunks
+  const bool ch = auto_tile || t.chunks == 1 || t.chunks == 2 || (t.chunks == 4 && t.lanes_per_row <= 64);
   return lpr && ch && t.xcd_remap <= 1 && t.nt_store <= 1 && t.replay_prog_global <= 1 && t.encode_slab <= 1 &&
-         t.replay_lookahead <= 1;
+         t.replay_lookahead <= 1 && t.claim_chunk <= 1024;
 }
 
 // The device copy of a graph: nine arrays, each 256-byte aligned, in one buffer.
-void graph_image(const fs_graph &g, GraphImage &img) {
-  img.parts[0] = {g.row_ptr.data(), g.row_ptr.size() * 4, 0};
-  img.parts[1] = {g.col.data(), g.col.size() * 4, 0};
-  img.parts[2] = {g.col_ptr.data(), g.col_ptr.size() * 4, 0};
-  img.parts[3] = {g.rowidx.data(), g.rowidx.size() * 4, 0};
-  img.parts[4] = {g.seg_ptr.data(), g.seg_ptr.size() * 4, 0};
-  img.parts[5] = {g.seg_row.data(), g.seg_row.size() * 4, 0};
-  img.parts[6] = {g.heavy.data(), g.heavy.size() * 4, 0};
-  img.parts[7] = {g.seg_atomic.data(), g.seg_atomic.size(), 0};
-  img.parts[8] = {g.seg_col.data(), g.seg_col.size() * 4, 0};
+void graph_image_sized(uint32_t k, uint32_t n, uint64_t nnz, uint32_t nseg, uint32_t nheavy, GraphImage &img) {
+  const size_t bytes[9] = {((size_t)n + 1) * 4, nnz * 4,  ((size_t)k + 1) * 4,      nnz * 4, ((size_t)nseg + 1) * 4,
+                           (size_t)nseg * 4,    (size_t)nheavy * 4, (size_t)nseg, nnz * 4};
   size_t total = 0;
-  for (GraphImage::Part &pt : img.parts) {
-    pt.off = total;
-    total += (pt.bytes + 255) & ~size_t(255);
+  for (int i = 0; i < 9; ++i) {
+    img.parts[i] = {nullptr, bytes[i], total};
+    total += (bytes[i] + 255) & ~size_t(255);
   }
   img.total = total + 256;
+}
+
+void graph_image(const fs_graph &g, GraphImage &img) {
+  graph_image_sized(g.k, g.n, g.nnz, g.nseg, (uint32_t)g.heavy.size(), img);
+  img.parts[0].src = g.row_ptr.data();
+  img.parts[1].src = g.col.data();
+  img.parts[2].src = g.col_ptr.data();
+  img.parts[3].src = g.rowidx.data();
+  img.parts[4].src = g.seg_ptr.data();
+  img.parts[5].src = g.seg_row.data();
+  img.parts[6].src = g.heavy.data();
+  img.parts[7].src = g.seg_atomic.data();
+  img.parts[8].src = g.seg_col.data();
 }
 
 void bind_image(fs_graph &g, const GraphImage &img, void *base) {
@@ -294,6 +302,13 @@ size_t workspace_bytes(const fs_graph *g, int op, uint64_t t, uint32_t n_items) 
       carve_local(cv, g, n_items, b);
       return cv.size();
     }
+    case FS_OP_EXTEND_LOCAL: {
+      cv.take<uint32_t>(g->n);
+      cv.take<uint8_t>(g->n);
+      LocalBufs b;
+      carve_local(cv, g, n_items, b);
+      return cv.size();
+    }
     case FS_OP_DECODE_PRECODED: {
       cv.take<uint8_t>(workspace_bytes(g, FS_OP_DECODE, t, 0));
       PrecodeBufs b;
@@ -384,6 +399,124 @@ ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, cons
 
 fs_tune tune_snapshot() { return current_tune(); }
 
+namespace {
+// Scratch of the device graph builds, kept per device and grown when a build
+// needs more: a hipFree waits for the whole device, so builds made while
+// other work runs (a request loop) must not free memory.  Builds on one
+// process take the lock for their duration.
+struct BuildScratch {
+  std::mutex mu;
+  void *buf[64][2] = {};
+  size_t bytes[64][2] = {};
+};
+BuildScratch g_build_scratch;
+
+fs_status build_scratch(int dev, int slot, size_t need, void **out) {
+  if (dev < 0 || dev >= 64) return fail(FS_ERR_INVALID, "device index out of range");
+  if (g_build_scratch.bytes[dev][slot] < need) {
+    if (g_build_scratch.buf[dev][slot]) (void)hipFree(g_build_scratch.buf[dev][slot]);
+    g_build_scratch.buf[dev][slot] = nullptr;
+    g_build_scratch.bytes[dev][slot] = 0;
+    const size_t grow = std::max(need, (size_t)4 << 20);
+    if (hipMalloc(&g_build_scratch.buf[dev][slot], grow) != hipSuccess)
+      return fail(FS_ERR_NOMEM, "graph scratch allocation failed");
+    g_build_scratch.bytes[dev][slot] = grow;
+  }
+  *out = g_build_scratch.buf[dev][slot];
+  return FS_OK;
+}
+}  // namespace
+
+// Device construction (graph_dev.hip): thresholds on the host, then the
+// degree pass, one copy of the sizes back (nnz, segments, heavy rows), the
+// image allocated to fit, the rows, segments and transpose, and the heavy-row
+// list and largest column copied back.
+fs_status build_device_graph(const fs_graph_params &p, hipStream_t stream, fs_graph &g) {
+  if (p.k < 1 || p.n < 1) return fail(FS_ERR_INVALID, "k and n must be >= 1");
+  if (p.k > (1u << 20)) return fail(FS_ERR_INVALID, "k above 2^20 is not supported");
+  if (p.reserved != 0) return fail(FS_ERR_INVALID, "reserved field must be 0");
+  std::vector<double> w;
+  FS_TRY(degree_weights(p, w));
+  std::vector<uint64_t> T;
+  degree_thresholds(w, T);
+  g.k = p.k;
+  g.n = p.n;
+  g.params = p;
+  g.params.flags = p.flags;
+  if (p.dist == FS_DIST_FINITE) {
+    g.finite_w.assign(p.finite_w, p.finite_w + p.finite_dmax);
+    g.params.finite_w = g.finite_w.data();
+  } else {
+    g.params.finite_w = nullptr;
+  }
+  g.host_arrays = false;
+  if (const hipError_t e = hipGetDevice(&g.device); e != hipSuccess)
+    return fail(FS_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  DevGraphJob J{};
+  J.k = p.k;
+  J.n = p.n;
+  J.D = (uint32_t)T.size();
+  J.seed = p.seed;
+  J.stripe_key = p.stripe_key;
+  std::lock_guard<std::mutex> lock(g_build_scratch.mu);
+  Carver sz(nullptr);
+  dev_graph_carve(sz, J, J.k, J.n, J.D);
+  void *scratch = nullptr, *scratch2 = nullptr;
+  FS_TRY(build_scratch(g.device, 0, sz.size(), &scratch));
+  auto done = [&](fs_status st) { return st; };
+  Carver cv(scratch);
+  dev_graph_carve(cv, J, J.k, J.n, J.D);
+  int32_t *row_ptr_tmp = J.row_ptr;
+  hipError_t e = hipMemcpyAsync(const_cast<uint64_t *>(J.T), T.data(), T.size() * 8, hipMemcpyHostToDevice, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(J.scalars, 0, kScalarCount * 4, stream);
+  if (e == hipSuccess) e = hipMemsetAsync(J.edges, 0, 8, stream);
+  if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph setup: ") + hipGetErrorString(e)));
+  fs_status st = launch_dev_graph_degrees(J, stream);
+  if (st != FS_OK) return done(st);
+  int32_t sizes[kScalarCount] = {0, 0, 0, 0};
+  unsigned long long edges = 0;
+  e = hipMemcpyAsync(sizes, J.scalars, sizeof(sizes), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&edges, J.edges, 8, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph sizes: ") + hipGetErrorString(e)));
+  // row_ptr is int32 (its scan wraps past 2^31 edges)
+  if (edges >= (unsigned long long)INT32_MAX) return done(fail(FS_ERR_INVALID, "graph has 2^31 or more edges"));
+  g.nnz = edges;
+  g.max_deg = (uint32_t)sizes[kScalarMaxDeg];
+  g.nseg = (uint32_t)sizes[kScalarSegs];
+  const uint32_t nheavy = (uint32_t)sizes[kScalarHeavy];
+  GraphImage img;
+  graph_image_sized(g.k, g.n, g.nnz, g.nseg, nheavy, img);
+  if (hipMalloc(&g.d_base, img.total) != hipSuccess) return done(fail(FS_ERR_NOMEM, "device allocation for the graph failed"));
+  bind_image(g, img, g.d_base);
+  uint8_t *base = static_cast<uint8_t *>(g.d_base);
+  J.row_ptr = reinterpret_cast<int32_t *>(base + img.parts[0].off);
+  J.col = reinterpret_cast<int32_t *>(base + img.parts[1].off);
+  J.col_ptr = reinterpret_cast<int32_t *>(base + img.parts[2].off);
+  J.rowidx = reinterpret_cast<int32_t *>(base + img.parts[3].off);
+  J.seg_ptr = reinterpret_cast<int32_t *>(base + img.parts[4].off);
+  J.seg_row = reinterpret_cast<int32_t *>(base + img.parts[5].off);
+  J.heavy = reinterpret_cast<int32_t *>(base + img.parts[6].off);
+  J.seg_atomic = base + img.parts[7].off;
+  J.seg_col = reinterpret_cast<int32_t *>(base + img.parts[8].off);
+  Carver sz2(nullptr);
+  dev_graph_carve_rows(sz2, J, J.k, J.n, g.nseg);
+  FS_TRY(build_scratch(g.device, 1, sz2.size(), &scratch2));
+  Carver cv2(scratch2);
+  dev_graph_carve_rows(cv2, J, J.k, J.n, g.nseg);
+  e = hipMemcpyAsync(J.row_ptr, row_ptr_tmp, ((size_t)p.n + 1) * 4, hipMemcpyDeviceToDevice, stream);
+  if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph row_ptr: ") + hipGetErrorString(e)));
+  st = launch_dev_graph_rows(J, g.nseg, nheavy, stream);
+  if (st != FS_OK) return done(st);
+  g.heavy.assign(nheavy, 0);
+  if (nheavy) e = hipMemcpyAsync(g.heavy.data(), J.heavy, (size_t)nheavy * 4, hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(sizes, J.scalars, sizeof(sizes), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph build: ") + hipGetErrorString(e)));
+  g.max_cdeg = (uint32_t)sizes[kScalarMaxCdeg];
+  return done(FS_OK);
+}
+
 fs_launch_info &launch_record() {
   static thread_local fs_launch_info rec = {};
   return rec;
@@ -423,7 +556,7 @@ fs_status fs_set_tune(const fs_tune *tune) {
   clear_error();
   std::lock_guard<std::mutex> lock(g_tune_mu);
   if (!tune) {
-    g_tune = fs_tune{0, 0, 1, 1, 0, 1, 0};
+    g_tune = fs_tune{0, 0, 1, 1, 0, 1, 0, 0};
     return FS_OK;
   }
   if (!tune_ok(*tune)) return fail(FS_ERR_INVALID, "tuning out of range");
@@ -453,8 +586,21 @@ fs_status fs_degree_table(const fs_graph_params *params, uint64_t *T_out, uint32
 fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_graph **out) {
   clear_error();
   if (!params || !out) return fail(FS_ERR_INVALID, "params and out must be non-null");
+  if ((params->flags & FS_GRAPH_HOST_ONLY) && (params->flags & FS_GRAPH_ON_DEVICE))
+    return fail(FS_ERR_INVALID, "FS_GRAPH_HOST_ONLY and FS_GRAPH_ON_DEVICE exclude each other");
+  if (params->flags & ~3u) return fail(FS_ERR_INVALID, "unknown graph flags");
   fs_graph *g = new (std::nothrow) fs_graph();
   if (!g) return fail(FS_ERR_NOMEM, "host allocation failed");
+  if (params->flags & FS_GRAPH_ON_DEVICE) {
+    const fs_status st = build_device_graph(*params, stream, *g);
+    if (st != FS_OK) {
+      if (g->d_base) (void)hipFree(g->d_base);
+      delete g;
+      return st;
+    }
+    *out = g;
+    return FS_OK;
+  }
   fs_status st = build_host_graph(*params, *g);
   if (st != FS_OK) {
     delete g;
@@ -492,6 +638,7 @@ fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_g
 fs_status fs_graph_image_size(const fs_graph *g, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
+  if (!g->host_arrays) return fail(FS_ERR_INVALID, "graph was built on the device and has no host image");
   GraphImage img;
   graph_image(*g, img);
   *bytes = img.total;
@@ -542,6 +689,22 @@ fs_status fs_graph_info(const fs_graph *g, uint32_t *k, uint32_t *n, uint64_t *n
 fs_status fs_graph_export(const fs_graph *g, int32_t *row_ptr, int32_t *col, int32_t *col_ptr, int32_t *rowidx) {
   clear_error();
   if (!g) return fail(FS_ERR_INVALID, "graph is null");
+  if (!g->host_arrays) {
+    // built on the device: copy from the device image (synchronous)
+    const struct {
+      int32_t *dst;
+      const int32_t *src;
+      size_t count;
+    } parts[4] = {{row_ptr, g->d_row_ptr, (size_t)g->n + 1},
+                  {col, g->d_col, (size_t)g->nnz},
+                  {col_ptr, g->d_col_ptr, (size_t)g->k + 1},
+                  {rowidx, g->d_rowidx, (size_t)g->nnz}};
+    for (const auto &pt : parts)
+      if (pt.dst && pt.count)
+        if (const hipError_t e = hipMemcpy(pt.dst, pt.src, pt.count * 4, hipMemcpyDeviceToHost); e != hipSuccess)
+          return fail(FS_ERR_HIP, std::string("graph export: ") + hipGetErrorString(e));
+    return FS_OK;
+  }
   if (row_ptr) std::memcpy(row_ptr, g->row_ptr.data(), g->row_ptr.size() * 4);
   if (col) std::memcpy(col, g->col.data(), g->col.size() * 4);
   if (col_ptr) std::memcpy(col_ptr, g->col_ptr.data(), g->col_ptr.size() * 4);
@@ -558,7 +721,7 @@ void fs_graph_free(fs_graph *g) {
 fs_status fs_workspace_size(const fs_graph *g, int op, uint64_t t, uint32_t n_items, size_t *bytes) {
   clear_error();
   if (!g || !bytes) return fail(FS_ERR_INVALID, "graph and bytes must be non-null");
-  if (op < FS_OP_ENCODE || op > FS_OP_REPAIR_PRECODED) return fail(FS_ERR_INVALID, "unknown operation");
+  if (op < FS_OP_ENCODE || op > FS_OP_EXTEND_LOCAL) return fail(FS_ERR_INVALID, "unknown operation");
   if ((op == FS_OP_REPAIR_CONVENTIONAL || op == FS_OP_EXTEND_CONVENTIONAL || op == FS_OP_UPDATE ||
        op == FS_OP_REPAIR_PRECODED) &&
       (t == 0 || (t & 15)))
@@ -619,7 +782,7 @@ GatherJob encode_job(const fs_graph *g, const void *x, void *c, uint64_t t) {
   j.idx = g->d_seg_col;
   j.out_map = g->d_seg_row;
   j.seg_atomic = g->heavy.empty() ? nullptr : g->d_seg_atomic;
-  j.nrows = (uint32_t)g->seg_row.size();
+  j.nrows = g->nseg;
   j.csr_rows = j.nrows;
   j.t = t;
   j.slab_k = g->k;
@@ -1503,19 +1666,54 @@ void fs_checks_free(fs_checks *ch) {
   delete ch;
 }
 
-fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const uint8_t *erased, const uint32_t *lost,
-                          uint32_t n_lost, uint8_t *repaired, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
-                          hipStream_t stream) {
-  clear_error();
+static fs_status local_repair_impl(const fs_graph *g, const fs_checks *ch, void *c, const uint8_t *erased,
+                                   const uint32_t *lost, uint32_t n_lost, uint8_t *repaired, int32_t *status,
+                                   uint64_t t, Carver &cv, hipStream_t stream);
+
+static fs_status check_local(const fs_graph *g, const fs_checks *ch, void *c, uint64_t t) {
   FS_TRY(check_graph(g));
   if (!ch || !ch->d_base) return fail(FS_ERR_INVALID, "checks is null");
   if (ch->n != g->n || ch->k != g->k) return fail(FS_ERR_INVALID, "the checks belong to another graph shape");
   if (g->n > kLocalMaxN) return fail(FS_ERR_UNSUPPORTED, "local repair plans codes of at most 524288 blocks");
-  FS_TRY(check_payload(c, t, "c"));
+  return check_payload(c, t, "c");
+}
+
+fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const uint8_t *erased, const uint32_t *lost,
+                          uint32_t n_lost, uint8_t *repaired, int32_t *status, uint64_t t, void *ws, size_t ws_bytes,
+                          hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_local(g, ch, c, t));
   if ((n_lost && (!lost || !repaired)) || !status)
     return fail(FS_ERR_INVALID, "lost, repaired and status must be non-null");
   FS_TRY(check_ws(g, FS_OP_REPAIR_LOCAL, t, n_lost, ws, ws_bytes));
   Carver cv(ws);
+  return local_repair_impl(g, ch, c, erased, lost, n_lost, repaired, status, t, cv, stream);
+}
+
+fs_status fs_extend_local(const fs_graph *g, const fs_checks *ch, uint32_t n_old, void *c, const uint8_t *erased,
+                          uint8_t *made, int32_t *status, uint64_t t, void *ws, size_t ws_bytes, hipStream_t stream) {
+  clear_error();
+  FS_TRY(check_local(g, ch, c, t));
+  if (n_old > g->n) return fail(FS_ERR_INVALID, "n_old exceeds the rows of the graph");
+  const uint32_t n_new = g->n - n_old;
+  if ((n_new && !made) || !status) return fail(FS_ERR_INVALID, "made and status must be non-null");
+  FS_TRY(check_ws(g, FS_OP_EXTEND_LOCAL, t, n_new, ws, ws_bytes));
+  Carver cv(ws);
+  ExtendPrepJob ej{};
+  ej.n = g->n;
+  ej.n_old = n_old;
+  ej.erased = erased;
+  ej.ids = cv.take<uint32_t>(g->n);
+  ej.erased_full = cv.take<uint8_t>(g->n);
+  FS_TRY(launch_extend_prep(ej, stream));
+  return local_repair_impl(g, ch, c, ej.erased_full, ej.ids, n_new, made, status, t, cv, stream);
+}
+
+}  // extern "C"
+
+static fs_status local_repair_impl(const fs_graph *g, const fs_checks *ch, void *c, const uint8_t *erased,
+                                   const uint32_t *lost, uint32_t n_lost, uint8_t *repaired, int32_t *status,
+                                   uint64_t t, Carver &cv, hipStream_t stream) {
   LocalBufs b;
   carve_local(cv, g, n_lost, b);
   LocalPlanJob pj{};
@@ -1550,5 +1748,3 @@ fs_status fs_repair_local(const fs_graph *g, const fs_checks *ch, void *c, const
   if (n_lost == 0) return FS_OK;
   return launch_local_apply(pj, static_cast<uint8_t *>(c), t, stream);
 }
-
-}  // extern "C"

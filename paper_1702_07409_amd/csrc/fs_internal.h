@@ -25,6 +25,9 @@ struct fs_graph {
   // heavy lists those rows once.
   std::vector<int32_t> seg_ptr, seg_row, seg_col, heavy;
   std::vector<uint8_t> seg_atomic;
+  uint32_t nseg = 0;          // encode segments
+  bool host_arrays = true;    // false: built on the device (the host vectors
+                              // above are empty, except heavy)
   int device = -1;
   void *d_base = nullptr;
   const int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_col_ptr = nullptr,
@@ -69,6 +72,8 @@ void clear_error();
 fs_status degree_weights(const fs_graph_params &p, std::vector<double> &w);
 fs_status degree_thresholds(const std::vector<double> &w, std::vector<uint64_t> &T);
 fs_status build_host_graph(const fs_graph_params &p, fs_graph &g);
+// the same graph built by kernels on the current device (api.cpp, graph_dev.hip)
+fs_status build_device_graph(const fs_graph_params &p, hipStream_t stream, fs_graph &g);
 
 // device facts cached per device
 struct DeviceInfo {
@@ -354,6 +359,9 @@ struct UpdateDeltaJob {
 fs_status launch_update_delta(const UpdateDeltaJob &job, hipStream_t s);
 
 // ---- batched launches (one launch for many stripes) ----
+// the batched gather's per-XCD work counters lie kCounterStride words apart
+constexpr uint32_t kCounterStride = 32;
+
 struct ZeroEntry {
   uint8_t *base;
   uint64_t t;
@@ -428,6 +436,37 @@ struct GraphImage {
   size_t total;
 };
 void graph_image(const fs_graph &g, GraphImage &img);
+// the same layout from the array sizes alone (no host sources)
+void graph_image_sized(uint32_t k, uint32_t n, uint64_t nnz, uint32_t nseg, uint32_t nheavy, GraphImage &img);
+
+// ---- device graph construction (graph_dev.hip) ----
+enum { kScalarMaxDeg = 0, kScalarSegs = 1, kScalarHeavy = 2, kScalarMaxCdeg = 3, kScalarCount = 4 };
+struct DevGraphJob {
+  uint32_t k, n, D;
+  uint64_t seed, stripe_key;
+  // scratch
+  const uint64_t *T;       // degree thresholds (D)
+  int32_t *deg;            // degree of each row (n)
+  uint32_t *blk_hist;      // per block of rows: segment bucket counts, then offsets
+  int32_t *scalars;        // kScalar*
+  unsigned long long *edges;   // sum of the degrees (nnz) in 64 bits
+  uint32_t *sums;          // scan block sums
+  int32_t *ccnt, *cfill;   // column counts and fill cursors (k)
+  int32_t *seg_len, *seg_beg;   // per segment: edges and first edge (nseg)
+  // the graph image
+  int32_t *row_ptr, *col, *col_ptr, *rowidx, *seg_ptr, *seg_row, *heavy, *seg_col;
+  uint8_t *seg_atomic;
+};
+// scratch before the sizes are known: T, deg, a row_ptr copy, block
+// histograms, scalars and scan sums for n and k elements
+void dev_graph_carve(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n, uint32_t D);
+// scratch once the segment count is known: seg_len, seg_beg and scan sums
+// for max(n, k, nseg) elements
+void dev_graph_carve_rows(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n, uint32_t nseg);
+// degrees, row_ptr, segment and heavy-row counts (scalars)
+fs_status launch_dev_graph_degrees(const DevGraphJob &J, hipStream_t s);
+// neighbours, segments, heavy rows and the transpose (scalars: max_cdeg)
+fs_status launch_dev_graph_rows(const DevGraphJob &J, uint32_t nseg, uint32_t nheavy, hipStream_t s);
 void bind_image(fs_graph &g, const GraphImage &img, void *base);
 
 fs_tune current_tune();

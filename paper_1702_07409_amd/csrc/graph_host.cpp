@@ -246,6 +246,7 @@ fs_status build_host_graph(const fs_graph_params &p, fs_graph &g) {
       g.seg_atomic[at] = split ? 1 : 0;
     }
   }
+  g.nseg = (uint32_t)ns;
   g.seg_ptr.assign(ns + 1, 0);
   for (size_t i = 0; i < ns; ++i) g.seg_ptr[i + 1] = g.seg_ptr[i] + (int32_t)slen[i];
   g.seg_col.resize(g.nnz);

@@ -91,31 +91,32 @@ constexpr int kStageCap = 2048;   // edges of one row tile staged in LDS
 
 // XOR of the sources of one row into acc.  Neighbour ids come from idx (LDS
 // when the tile's edge list was staged, else global); loads are issued in
-// batches of four neighbours x CH chunks before any is consumed.
+// batches of U = 4 neighbours x CH chunks before any is consumed.  (Eight
+// neighbours in flight measured 5-10 % slower for one and two chunks on
+// finite-degree and Robust Soliton stripes: the extra loads in flight
+// thrash the L2 more than they hide latency.)
 template <int CH, uint32_t STEP, class IdxPtr>
 __device__ __forceinline__ void gather_row(v4u (&acc)[CH], const bool (&valid)[CH], IdxPtr idx, int e,
                                            const int e1, const uint8_t *src, const uint64_t stride) {
+  constexpr int U = 4;
   const v4u zero = {0u, 0u, 0u, 0u};
-  for (; e < e1; e += 4) {
+  for (; e < e1; e += U) {
     const int cnt = e1 - e;
-    const int32_t i0 = idx[e];
-    const int32_t i1 = cnt > 1 ? idx[e + 1] : 0;
-    const int32_t i2 = cnt > 2 ? idx[e + 2] : 0;
-    const int32_t i3 = cnt > 3 ? idx[e + 3] : 0;
-    const uint8_t *p0 = src + (uint64_t)i0 * stride;
-    const uint8_t *p1 = src + (uint64_t)i1 * stride;
-    const uint8_t *p2 = src + (uint64_t)i2 * stride;
-    const uint8_t *p3 = src + (uint64_t)i3 * stride;
-    v4u v0[CH], v1[CH], v2[CH], v3[CH];
+    const uint8_t *p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) p[u] = src + (uint64_t)(u < cnt ? idx[e + u] : 0) * stride;
+    v4u v[U][CH];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int c = 0; c < CH; ++c) v[u][c] = (valid[c] && u < cnt) ? ld16(p[u] + c * STEP) : zero;
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      v0[c] = valid[c] ? ld16(p0 + c * STEP) : zero;
-      v1[c] = (valid[c] && cnt > 1) ? ld16(p1 + c * STEP) : zero;
-      v2[c] = (valid[c] && cnt > 2) ? ld16(p2 + c * STEP) : zero;
-      v3[c] = (valid[c] && cnt > 3) ? ld16(p3 + c * STEP) : zero;
-    }
+      v4u x = v[0][c];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) acc[c] ^= (v0[c] ^ v1[c]) ^ (v2[c] ^ v3[c]);
+      for (int u = 1; u < U; ++u) x ^= v[u][c];
+      acc[c] ^= x;
+    }
   }
 }
 
@@ -226,7 +227,9 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(GatherJob j, uin
 // an XCD stay close together (same job, same slice: the slice's input slab
 // stays in that XCD's L2) while uneven stripes still balance dynamically.  A
 // workgroup whose partition is used up moves on to the next partitions.
-// counters[x] must start at the first item of partition x (reset kernel).
+// counters[x * kCounterStride] must start at the first item of partition x
+// (reset kernel); each counter has a 256-byte line of its own, so the claims
+// of different XCDs do not queue on one L2 channel.
 constexpr uint32_t kXcds = 8;
 
 template <int LPR, int CH, bool NT>
@@ -249,7 +252,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_batch_kernel(const Gath
     const unsigned long long hi = total * (part + 1) / kXcds;
     for (;;) {
       __syncthreads();   // everyone has read s_next
-      if (threadIdx.x == 0) s_next = atomicAdd(&counters[part], (unsigned long long)chunk);
+      if (threadIdx.x == 0) s_next = atomicAdd(&counters[part * kCounterStride], (unsigned long long)chunk);
       __syncthreads();
       const unsigned long long base = s_next;
       if (base >= hi) break;
@@ -280,7 +283,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_batch_kernel(const Gath
 // counter reset for the batched gather (a kernel, so it can sit in a graph):
 // partition x starts at total * x / 8
 __global__ void reset_counter_kernel(unsigned long long *counters, const unsigned long long *prefix, uint32_t njobs) {
-  if (threadIdx.x < kXcds) counters[threadIdx.x] = prefix[njobs] * threadIdx.x / kXcds;
+  if (threadIdx.x < kXcds) counters[threadIdx.x * kCounterStride] = prefix[njobs] * threadIdx.x / kXcds;
 }
 
 __global__ __launch_bounds__(256) void zero_rows_kernel(uint8_t *dst, const int32_t *rows, uint32_t nrows,
@@ -1684,6 +1687,10 @@ fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s
     case 641: e = run_gather_nt<64, 1>(job, tune, s, cu); break;
     case 642: e = run_gather_nt<64, 2>(job, tune, s, cu); break;
     case 644: e = run_gather_nt<64, 4>(job, tune, s, cu); break;
+    case 1281: e = run_gather_nt<128, 1>(job, tune, s, cu); break;
+    case 1282: e = run_gather_nt<128, 2>(job, tune, s, cu); break;
+    case 2561: e = run_gather_nt<256, 1>(job, tune, s, cu); break;
+    case 2562: e = run_gather_nt<256, 2>(job, tune, s, cu); break;
     default: return fail(FS_ERR_INVALID, "unsupported gather tuning");
   }
   return hip_check(e, "gather launch");
@@ -2047,7 +2054,9 @@ fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long 
                               uint64_t total_items, hipStream_t s) {
   if (njobs == 0 || grid == 0) return FS_OK;
   // small chunks keep the items in flight on an XCD close together
-  const uint32_t chunk = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(2, total_items / ((uint64_t)grid * 64)));
+  const uint32_t chunk = tune.claim_chunk ? tune.claim_chunk
+                                          : (uint32_t)std::min<uint64_t>(
+                                                16, std::max<uint64_t>(2, total_items / ((uint64_t)grid * 64)));
   const bool nt = tune.nt_store != 0;
   hipError_t e;
   switch (tune.lanes_per_row * 10 + tune.chunks) {
@@ -2060,6 +2069,10 @@ fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long 
     case 641: e = run_gather_batch<64, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
     case 642: e = run_gather_batch<64, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
     case 644: e = run_gather_batch<64, 4>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 1281: e = run_gather_batch<128, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 1282: e = run_gather_batch<128, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 2561: e = run_gather_batch<256, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 2562: e = run_gather_batch<256, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
     default: return fail(FS_ERR_INVALID, "unsupported gather tuning");
   }
   return hip_check(e, "batched gather launch");

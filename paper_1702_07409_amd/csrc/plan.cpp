@@ -81,7 +81,7 @@ struct fs_plan {
   GatherJob *d_tjobs = nullptr;
   unsigned long long *d_tprefix = nullptr;
   uint32_t n_tjobs = 0;
-  unsigned long long *d_counter = nullptr;   // 8 work counters (one per XCD) of the persistent gather
+  unsigned long long *d_counter = nullptr;   // 8 work counters (one per XCD, 256 bytes apart) of the persistent gather
 
   bool external = false;   // workspace and descriptors in caller memory
   hipGraph_t graph = nullptr;
@@ -424,7 +424,7 @@ fs_status upload_descriptors(fs_plan &P, hipStream_t s, bool allocate, void *sta
   P.d_zeros = place<ZeroEntry>(base, off, P.zeros.size());
   P.d_tjobs = place<GatherJob>(base, off, tjobs.size());
   P.d_tprefix = place<unsigned long long>(base, off, tprefix.size());
-  P.d_counter = place<unsigned long long>(base, off, 8);
+  P.d_counter = place<unsigned long long>(base, off, 8 * kCounterStride);
   P.n_tjobs = (uint32_t)tjobs.size();
   off = (off + 255) & ~size_t(255);
   if (allocate) {
@@ -539,7 +539,7 @@ fs_status capture(fs_plan &P) {
 std::string shape_key(const fs_plan &P) {
   // the plan's shape: per item op, k, n, nnz, t (arch first)
   std::ostringstream os;
-  os << "gfx950";
+  os << "gfx950.v2";   // v2: entries carry the claim chunk
   uint64_t h = 1469598103934665603ull;
   for (const fs_work &w : P.items) {
     const uint64_t v[5] = {w.op, w.graph->k, w.graph->n, w.graph->nnz, w.t};
@@ -556,16 +556,18 @@ bool cache_lookup(const char *path, const std::string &key, fs_tune &t) {
   if (!path) return false;
   std::ifstream f(path);
   std::string k;
-  uint32_t lpr, ch, rm, nt;
+  std::string line;
   bool found = false;
-  while (f >> k >> lpr >> ch >> rm >> nt) {
-    if (k == key) {
-      t.lanes_per_row = lpr;
-      t.chunks = ch;
-      t.xcd_remap = rm;
-      t.nt_store = nt;
-      found = true;   // the last entry wins
-    }
+  while (std::getline(f, line)) {
+    std::istringstream is(line);
+    uint32_t lpr, ch, rm, nt, cc;
+    if (!(is >> k >> lpr >> ch >> rm >> nt >> cc) || k != key) continue;
+    t.lanes_per_row = lpr;
+    t.chunks = ch;
+    t.xcd_remap = rm;
+    t.nt_store = nt;
+    t.claim_chunk = cc;
+    found = true;   // the last entry wins
   }
   return found;
 }
@@ -573,55 +575,100 @@ bool cache_lookup(const char *path, const std::string &key, fs_tune &t) {
 void cache_store(const char *path, const std::string &key, const fs_tune &t) {
   if (!path) return;
   std::ofstream f(path, std::ios::app);
-  f << key << " " << t.lanes_per_row << " " << t.chunks << " " << t.xcd_remap << " " << t.nt_store << "\n";
+  f << key << " " << t.lanes_per_row << " " << t.chunks << " " << t.xcd_remap << " " << t.nt_store << " "
+    << t.claim_chunk << "\n";
 }
 
-// Time the persistent gather (without the accumulating jobs) for a few
-// tilings and keep the fastest.
+// Time the plan's gathers (the persistent kernel and the large jobs' own
+// launches, without the accumulating update jobs) under candidate tunings
+// and keep the fastest:
+//   1. every tiling (lanes per row x chunks), and the per-graph rule (the
+//      persistent kernel at 16 x 2, each large job at its graph's tiling),
+//      with XCD remap and non-temporal stores on: one warm run, one timed;
+//   2. the three fastest again, median of five timed runs each;
+//   3. the winner with XCD remap off, then with plain stores, then with
+//      claim chunks of 1, 4 and 32 items: each kept when its median of five
+//      is faster.
 fs_status autotune(fs_plan &P, hipStream_t s) {
   size_t solo_tuned = 0;
   for (uint8_t a : P.solo_accumulate) solo_tuned += a == 0;
   if (P.n_tjobs == 0 && solo_tuned == 0) return FS_OK;
-  static const uint32_t cand[][2] = {{16, 2}, {32, 2}, {32, 4}, {64, 1}, {64, 2}, {64, 4}};
+  static const uint32_t cand[][2] = {{0, 0},  {16, 1}, {16, 2}, {16, 4}, {32, 1},  {32, 2},  {32, 4},
+                                     {64, 1}, {64, 2}, {64, 4}, {128, 2}, {256, 1}, {256, 2}};
   hipEvent_t e0, e1;
   PL_TRY(hip_ok(hipEventCreate(&e0), "event"));
   PL_TRY(hip_ok(hipEventCreate(&e1), "event"));
-  float best = 1e30f;
-  fs_tune best_t = P.tune;
   std::vector<GatherJob> tjobs;
   for (size_t i = 0; i < P.gjobs.size(); ++i)
     if (!P.gjob_accumulate[i]) tjobs.push_back(P.gjobs[i]);
+  // median time of `reps` timed runs (after one warm run) of the gathers under tuning t
+  auto measure = [&](const fs_tune &t, int reps, float &median) -> fs_status {
+    const fs_tune bt = batch_tune(t);
+    std::vector<unsigned long long> pre;
+    gather_prefix(tjobs, bt, pre);
+    PL_TRY(hip_ok(hipMemcpyAsync(P.d_tprefix, pre.data(), pre.size() * sizeof(unsigned long long),
+                                 hipMemcpyHostToDevice, s), "tune prefix"));
+    const uint32_t grid = gather_grid_for(pre.back());
+    auto run = [&]() -> fs_status {
+      PL_TRY(launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, P.d_counter, bt, grid, pre.back(), s));
+      for (size_t i = 0; i < P.solo.size(); ++i)
+        if (!P.solo_accumulate[i]) PL_TRY(launch_gather(P.solo[i], tile_for(t, P.solo_graph[i]), s));
+      return FS_OK;
+    };
+    PL_TRY(run());
+    std::vector<float> ms;
+    for (int r = 0; r < reps; ++r) {
+      PL_TRY(hip_ok(hipEventRecord(e0, s), "tune event"));
+      PL_TRY(run());
+      PL_TRY(hip_ok(hipEventRecord(e1, s), "tune event"));
+      PL_TRY(hip_ok(hipEventSynchronize(e1), "tune sync"));
+      float m = 0.0f;
+      (void)hipEventElapsedTime(&m, e0, e1);
+      ms.push_back(m);
+    }
+    std::sort(ms.begin(), ms.end());
+    median = ms[ms.size() / 2];
+    return FS_OK;
+  };
   fs_status st = FS_OK;
+  std::vector<std::pair<float, fs_tune>> first;
   for (const auto &c : cand) {
     fs_tune t = P.tune;
     t.lanes_per_row = c[0];
     t.chunks = c[1];
-    std::vector<unsigned long long> pre;
-    gather_prefix(tjobs, t, pre);
-    st = hip_ok(hipMemcpyAsync(P.d_tprefix, pre.data(), pre.size() * sizeof(unsigned long long),
-                               hipMemcpyHostToDevice, s), "tune prefix");
+    t.xcd_remap = 1;
+    t.nt_store = 1;
+    float m = 0.0f;
+    st = measure(t, 1, m);
     if (st != FS_OK) break;
-    const uint32_t grid = gather_grid_for(pre.back());
-    // the persistent kernel and the large jobs' own launches (without the
-    // accumulating ones): one warm run, then the timed one
-    auto run = [&]() -> fs_status {
-      PL_TRY(launch_gather_batch(P.d_tjobs, P.d_tprefix, P.n_tjobs, P.d_counter, t, grid, pre.back(), s));
-      for (size_t i = 0; i < P.solo.size(); ++i)
-        if (!P.solo_accumulate[i]) PL_TRY(launch_gather(P.solo[i], t, s));
-      return FS_OK;
-    };
-    st = run();
-    if (st != FS_OK) break;
-    (void)hipEventRecord(e0, s);
-    st = run();
-    if (st != FS_OK) break;
-    (void)hipEventRecord(e1, s);
-    st = hip_ok(hipEventSynchronize(e1), "tune sync");
-    if (st != FS_OK) break;
-    float ms = 0.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
-    if (ms < best) {
-      best = ms;
+    first.emplace_back(m, t);
+  }
+  float best = 1e30f;
+  fs_tune best_t = P.tune;
+  if (st == FS_OK) {
+    std::stable_sort(first.begin(), first.end(),
+                     [](const std::pair<float, fs_tune> &a, const std::pair<float, fs_tune> &b) {
+                       return a.first < b.first;
+                     });
+    for (size_t i = 0; i < first.size() && i < 3 && st == FS_OK; ++i) {
+      float m = 0.0f;
+      st = measure(first[i].second, 5, m);
+      if (st == FS_OK && m < best) {
+        best = m;
+        best_t = first[i].second;
+      }
+    }
+  }
+  for (int flip = 0; flip < 5 && st == FS_OK; ++flip) {
+    if (flip >= 2 && P.n_tjobs == 0) break;   // claim chunks apply to the persistent kernel only
+    fs_tune t = best_t;
+    if (flip == 0) t.xcd_remap = 0;
+    else if (flip == 1) t.nt_store = 0;
+    else t.claim_chunk = flip == 2 ? 1u : flip == 3 ? 4u : 32u;
+    float m = 0.0f;
+    st = measure(t, 5, m);
+    if (st == FS_OK && m < best) {
+      best = m;
       best_t = t;
     }
   }

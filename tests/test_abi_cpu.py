@@ -142,3 +142,24 @@ def test_precode_rejects_bad_parameters(b, k):
     import paper_1702_07409_amd as fs
     with pytest.raises(fs.FsError):
         fs.fs_precode_build(b, k, host_only=True)
+
+
+def test_graph_build_rejects_conflicting_flags():
+    # host-only and on-device builds exclude each other (checked before any HIP call)
+    import paper_1702_07409_amd as fs
+    with pytest.raises(fs.FsError) as e:
+        fs.fs_graph_build(k=64, n=96, host_only=True, on_device=True)
+    assert e.value.status == fs._lib.FS_ERR_INVALID
+
+
+def test_workspace_size_knows_every_operation():
+    # every FS_OP_* the header declares sizes a workspace (host-only graph, no GPU)
+    import paper_1702_07409_amd as fs
+    text = open(os.path.join(ROOT, "include", "fs_api.h")).read()
+    ops = re.findall(r"\b(FS_OP_[A-Z_]+)\s*=\s*(\d+)", text)
+    assert len(ops) >= 14
+    g = fs.fs_graph_build(k=64, n=96, host_only=True)
+    for name, code in ops:
+        assert getattr(fs, name) == int(code), name
+        # the encode needs none; every other operation some
+        assert (fs.fs_workspace_size(g, int(code), 4096, 4) > 0) == (name != "FS_OP_ENCODE"), name

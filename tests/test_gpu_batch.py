@@ -139,6 +139,11 @@ def test_plan_rebind_to_new_buffers():
     b.verify()
 
 
+# the autotuner's search space: tilings (0, 0 = the per-graph rule), XCD remap, store kind
+TUNED_TILINGS = {(0, 0), (16, 1), (16, 2), (16, 4), (32, 1), (32, 2), (32, 4), (64, 1), (64, 2), (64, 4),
+                 (128, 2), (256, 1), (256, 2)}
+
+
 def test_plan_autotune_and_cache():
     import paper_1702_07409_amd as fs
     with tempfile.TemporaryDirectory() as d:
@@ -147,6 +152,9 @@ def test_plan_autotune_and_cache():
         p1 = fs.Plan(b.items, tune_cache=path, autotune=True)
         i1 = p1.info()
         assert i1["tune_source"] == 1 and i1["tuned_ms"] > 0
+        tu = i1["tune"]
+        assert (tu["lanes_per_row"], tu["chunks"]) in TUNED_TILINGS
+        assert tu["xcd_remap"] in (0, 1) and tu["nt_store"] in (0, 1) and tu["claim_chunk"] in (0, 1, 4, 32)
         p1.launch()
         b.verify()
         b2 = Batch(data_seed=4)
@@ -155,6 +163,29 @@ def test_plan_autotune_and_cache():
         assert i2["tune_source"] == 2 and i2["tune"] == i1["tune"]
         p2.launch()
         b2.verify()
+
+
+@pytest.mark.parametrize("lpr,ch", [(128, 1), (128, 2), (256, 1), (256, 2)])
+def test_row_wide_tilings(lpr, ch):
+    # one or two rows per workgroup: plans (encode, repair, the update's
+    # accumulate pass) and a single-stripe encode with a ragged block
+    import paper_1702_07409_amd as fs
+    fs.fs_set_tune(lpr, ch, 1, 1)
+    try:
+        b = Batch(data_seed=6)
+        fs.Plan(b.items).launch()
+        b.verify()
+        sp = S(stripe=23, k=300, n=450, t=8192 + 48, dist="rsd", stripe_key=23)
+        g, G = graphs(**sp.graph_kwargs())
+        x = gen.payload(0, sp.stripe, sp.k, sp.t)
+        c = empty_u8(sp.n, sp.t)
+        fs.fs_set_tune(lpr, ch, 1, 1, encode_slab=0)
+        fs.fs_encode(g, dev(x), c, sp.t)
+        assert np.array_equal(host(c), codec.encode(G, x))
+        li = fs.fs_last_launch()
+        assert (li["gather_lanes_per_row"], li["gather_chunks"]) == (lpr, ch), li
+    finally:
+        fs.fs_reset_tune()
 
 
 def test_plan_rejects_bad_items():

@@ -105,3 +105,38 @@ def test_extend_large_stripe_full_size():
     sp = replace(base, n=gen.overhead_n(4096, 0.20))
     made, st = extend_case(sp, base.n, False, base.n_erased)
     assert made.sum() > 0
+
+
+@pytest.mark.parametrize("n_erased", [0, 12])
+def test_extend_through_local_groups(n_erased):
+    # §2.9: the new rows of a code grown from 360 to 400 rows, made from the
+    # existing rows through the longer code's check #3 groups; the same rows,
+    # made flags and status as the oracle, old rows untouched
+    import paper_1702_07409_amd as fs
+    from oracle import checks
+    g, G = graphs(k=200, n=400, dist="raptor", seed=2)
+    ch = fs.fs_checks_generate(g)
+    _, c3 = ch.export()
+    t, n_old = 1024 + 16, 360
+    x = gen.payload(4, 0, 200, t)
+    c_full = codec.encode(G, x)
+    er = gen.erasure_mask(2, 0, n_old, n_erased) if n_erased else None
+    rows, made_w, levels = checks.extend_local(c3, c_full[:n_old], 400, er)
+    c = dev(c_full)
+    c[n_old:] = 0x5A
+    old = c_full[:n_old].copy()
+    if er is not None:
+        # unavailable old rows hold garbage: the extension must not read them
+        ids = np.flatnonzero(er)
+        c[dev(ids.astype(np.int64))] = 0xC3
+        old[ids] = 0xC3
+    made, st = empty_u8(40), empty_i32(3)
+    ws = fs.workspace(g, fs.FS_OP_EXTEND_LOCAL, t, 40)
+    fs.fs_extend_local(g, ch, n_old, c, dev(er) if er is not None else None, made, st, t, ws)
+    got = host(c)
+    assert np.array_equal(got[:n_old], old)
+    assert np.array_equal(host(made), made_w)
+    assert np.array_equal(got[n_old:][made_w == 1], rows[made_w == 1])
+    assert np.array_equal(got[n_old:][made_w == 1], c_full[n_old:][made_w == 1])
+    assert host(st).tolist() == [int(made_w.all()), int(40 - made_w.sum()), levels]
+    assert made_w.sum() > 0

@@ -218,3 +218,37 @@ def test_extra_groups_hold_on_precoded_payloads():
     merged = checks.with_extra_groups(check3, extra)
     assert [len(gr) for gr in merged] == sorted(len(gr) for gr in merged)
     assert len({tuple(gr) for gr in merged}) == len(merged) >= len(check3)
+
+
+def test_extend_local_makes_the_encoded_rows():
+    # §2.9: a code grown from 140 to 160 rows; the new rows that local groups
+    # reach equal the encoding of the longer code's rows (the definition),
+    # the rest stay zero; with some old rows unavailable fewer are made
+    G = graph.build(graph.GraphParams(k=80, n=160, dist="raptor", seed=5))
+    x = gen.payload(3, 0, 80, 64)
+    c = codec.encode(G, x)
+    b, L, _ = checks.cga(G)
+    _, groups = checks.split(b, L)
+    rows, made, levels = checks.extend_local(groups, c[:140], 160)
+    assert made.sum() > 0 and levels >= 1
+    assert np.array_equal(rows[made == 1], c[140:][made == 1])
+    assert not rows[made == 0].any()
+    er = np.zeros(140, np.uint8)
+    er[::7] = 1
+    rows2, made2, _ = checks.extend_local(groups, c[:140], 160, er)
+    assert made2.sum() <= made.sum()
+    assert np.array_equal(rows2[made2 == 1], c[140:][made2 == 1])
+    # a new row is made exactly when some group of it has every other member
+    # known, directly or through rows made before: the closure, checked by brute force
+    known = np.ones(160, bool)
+    known[140:] = False
+    known[:140][er == 1] = False
+    changed = True
+    while changed:
+        changed = False
+        for grp in groups:
+            unk = [m for m in grp if not known[m]]
+            if len(unk) == 1 and unk[0] >= 140:
+                known[unk[0]] = True
+                changed = True
+    assert np.array_equal(made2.astype(bool), known[140:])
