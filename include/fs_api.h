@@ -117,8 +117,11 @@ FS_API fs_status fs_degree_table(const fs_graph_params *params, uint64_t *T_out,
  * (one thread per row, a workgroup per row of more than 64 neighbours), the
  * transpose and the encode segments likewise; the call synchronises the
  * stream twice (for the sizes, then the heavy-row list) and returns with the
- * graph complete.  fs_graph_export then copies from the device, and
- * fs_graph_image_size / fs_graph_upload do not apply.
+ * graph complete.  Its scratch memory is kept per calling thread and device
+ * (grown, never freed, so that builds beside other work do not wait for the
+ * device); builds on different threads and streams run concurrently.
+ * fs_graph_export then copies from the device, and fs_graph_image_size /
+ * fs_graph_upload do not apply.
  * *out receives the graph (freed with fs_graph_free).
  * Errors: FS_ERR_INVALID (parameters, unknown or conflicting flags,
  * nnz >= 2^31), FS_ERR_NOMEM, FS_ERR_HIP.

@@ -400,29 +400,28 @@ ReplayJob replay_job(const fs_graph *g, const void *c, void *x, uint64_t t, cons
 fs_tune tune_snapshot() { return current_tune(); }
 
 namespace {
-// Scratch of the device graph builds, kept per device and grown when a build
-// needs more: a hipFree waits for the whole device, so builds made while
-// other work runs (a request loop) must not free memory.  Builds on one
-// process take the lock for their duration.
+// Scratch of the device graph builds, kept per thread and device and grown
+// when a build needs more: a hipFree waits for the whole device, so builds
+// made while other work runs (a request loop) must not free memory, and
+// builds on different threads (each on its own stream) run side by side.
+// The buffers live until the process ends.
 struct BuildScratch {
-  std::mutex mu;
   void *buf[64][2] = {};
   size_t bytes[64][2] = {};
 };
-BuildScratch g_build_scratch;
 
 fs_status build_scratch(int dev, int slot, size_t need, void **out) {
+  static thread_local BuildScratch sc;
   if (dev < 0 || dev >= 64) return fail(FS_ERR_INVALID, "device index out of range");
-  if (g_build_scratch.bytes[dev][slot] < need) {
-    if (g_build_scratch.buf[dev][slot]) (void)hipFree(g_build_scratch.buf[dev][slot]);
-    g_build_scratch.buf[dev][slot] = nullptr;
-    g_build_scratch.bytes[dev][slot] = 0;
+  if (sc.bytes[dev][slot] < need) {
+    if (sc.buf[dev][slot]) (void)hipFree(sc.buf[dev][slot]);
+    sc.buf[dev][slot] = nullptr;
+    sc.bytes[dev][slot] = 0;
     const size_t grow = std::max(need, (size_t)4 << 20);
-    if (hipMalloc(&g_build_scratch.buf[dev][slot], grow) != hipSuccess)
-      return fail(FS_ERR_NOMEM, "graph scratch allocation failed");
-    g_build_scratch.bytes[dev][slot] = grow;
+    if (hipMalloc(&sc.buf[dev][slot], grow) != hipSuccess) return fail(FS_ERR_NOMEM, "graph scratch allocation failed");
+    sc.bytes[dev][slot] = grow;
   }
-  *out = g_build_scratch.buf[dev][slot];
+  *out = sc.buf[dev][slot];
   return FS_OK;
 }
 }  // namespace
@@ -458,7 +457,6 @@ fs_status build_device_graph(const fs_graph_params &p, hipStream_t stream, fs_gr
   J.D = (uint32_t)T.size();
   J.seed = p.seed;
   J.stripe_key = p.stripe_key;
-  std::lock_guard<std::mutex> lock(g_build_scratch.mu);
   Carver sz(nullptr);
   dev_graph_carve(sz, J, J.k, J.n, J.D);
   void *scratch = nullptr, *scratch2 = nullptr;

@@ -146,6 +146,8 @@ struct PeelJob {
   const int32_t *skip_flag;  // non-zero: write status only
   uint64_t nnz;              // edges (0: unknown; the compact all-LDS variant needs it)
   int32_t *status_out;       // int32[3] or null: a second copy of status (the caller's)
+  uint32_t acc_ready;        // 1: acc holds the initial row states (count << 40 | id sum,
+                             // erased rows flagged), made by the many-workgroup init kernels
 };
 
 size_t peel_ws_bytes(uint32_t k, uint32_t n);
@@ -174,6 +176,7 @@ struct ProgJob {
   int32_t *poff;       // int32[k+1]
   int32_t *pidx;       // int32[pidx_cap]
   int32_t *meta;       // int32[4]
+  uint32_t *psums;     // block sums of the many-workgroup build (scans over k pairs and n rows)
   uint32_t pidx_cap;
   const int32_t *skip_flag;
   // dependency-slab form of the program (graphs with k, n <= 65535): per

@@ -17,6 +17,7 @@
 #include <cstring>
 
 #include "fs_internal.h"
+#include "scan.h"
 
 namespace fs {
 namespace {
@@ -25,7 +26,6 @@ constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 constexpr uint64_t kPurposeGraph = 1;
 constexpr int kThreads = 1024;       // rows per block of the counting passes
 constexpr int kSampleThreads = 256;  // rows per block of the light sampler
-constexpr int kScanItems = 4;        // elements per thread of the scans
 
 // SplitMix64 output function (Steele, Lea & Flood 2014; Stafford's Mix13
 // constants), the row streams of the host construction.
@@ -56,38 +56,6 @@ __device__ __forceinline__ uint32_t floyd_candidate(uint64_t key, uint32_t k, ui
   return (uint32_t)(((draw(key, s + 1) >> 32) * (r + 1)) >> 32);
 }
 
-// Block-wide exclusive scan of one value per thread (NT threads); sh holds
-// NT/64 + 1 words.  Every thread must call it.
-template <int NT>
-__device__ uint32_t scan_block(uint32_t v, uint32_t *sh, uint32_t &total) {
-  constexpr int NW = NT / 64;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  uint32_t x = v;
-#pragma unroll
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, 64);
-    if (lane >= o) x += y;
-  }
-  if (lane == 63) sh[wid] = x;
-  __syncthreads();
-  if (wid == 0) {
-    const uint32_t w = lane < NW ? sh[lane] : 0u;
-    uint32_t s = w;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(s, o, 64);
-      if (lane >= o) s += y;
-    }
-    if (lane < NW) sh[lane] = s - w;
-    if (lane == NW - 1) sh[NW] = s;
-  }
-  __syncthreads();
-  const uint32_t res = sh[wid] + x - v;
-  total = sh[NW];
-  __syncthreads();
-  return res;
-}
-
 // ---------------------------------------------------------------------------
 // degrees
 // ---------------------------------------------------------------------------
@@ -104,60 +72,6 @@ __global__ __launch_bounds__(256) void degree_kernel(DevGraphJob J) {
     else hi = mid;
   }
   J.deg[j] = (int32_t)(lo + 1);
-}
-
-// ---------------------------------------------------------------------------
-// exclusive scan of int32 counts: out[0..m] (out[m] = total), three passes
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void scan_partial_kernel(const int32_t *in, uint32_t m, uint32_t *sums) {
-  __shared__ uint32_t sh[kThreads / 64 + 1];
-  const uint64_t base = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) * kScanItems;
-  uint32_t v = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i)
-    if (base + i < m) v += (uint32_t)in[base + i];
-  uint32_t total = 0;
-  (void)scan_block<kThreads>(v, sh, total);
-  if (threadIdx.x == 0) sums[blockIdx.x] = total;
-}
-
-// one workgroup: exclusive scan of the block sums in place (nb of them)
-__global__ __launch_bounds__(kThreads) void scan_sums_kernel(uint32_t *sums, uint32_t nb, int32_t *total_out) {
-  __shared__ uint32_t sh[kThreads / 64 + 1];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t b0 = 0; b0 < nb; b0 += kThreads) {
-    const uint32_t b = b0 + threadIdx.x;
-    const uint32_t v = b < nb ? sums[b] : 0u;
-    uint32_t total = 0;
-    const uint32_t ex = scan_block<kThreads>(v, sh, total);
-    if (b < nb) sums[b] = carry + ex;
-    __syncthreads();
-    if (threadIdx.x == 0) carry += total;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0 && total_out) *total_out = (int32_t)carry;
-}
-
-__global__ __launch_bounds__(kThreads) void scan_final_kernel(const int32_t *in, uint32_t m, const uint32_t *sums,
-                                                              int32_t *out) {
-  __shared__ uint32_t sh[kThreads / 64 + 1];
-  const uint64_t base = ((uint64_t)blockIdx.x * kThreads + threadIdx.x) * kScanItems;
-  uint32_t v[kScanItems], s = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = base + i < m ? (uint32_t)in[base + i] : 0u;
-    s += v[i];
-  }
-  uint32_t total = 0;
-  uint32_t run = sums[blockIdx.x] + scan_block<kThreads>(s, sh, total);
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < m) out[base + i] = (int32_t)run;
-    run += v[i];
-  }
-  if (base < m && base + kScanItems >= m) out[m] = (int32_t)run;   // the thread holding the last element
 }
 
 // ---------------------------------------------------------------------------
@@ -286,15 +200,47 @@ __global__ __launch_bounds__(256) void seg_copy_kernel(DevGraphJob J, uint32_t n
 // ---------------------------------------------------------------------------
 // neighbours
 // ---------------------------------------------------------------------------
-// Rows of at most kSegMax neighbours: one thread each, the picks in LDS
+// Floyd's steps s0 .. s0 + 63 of a row of degree d, one per lane of a wave
+// (live: the step exists), given whether each lane's candidate v was picked
+// by an earlier batch (taken).  A lane falls back to its r when v was picked
+// before it: by an earlier batch, or by an earlier lane, either as that
+// lane's v (then v was picked before whatever that lane did) or as that
+// lane's r (only when that lane fell back; r = k - d + s, so the lane is
+// found from v).  The first two are independent of the other lanes'
+// outcomes; the third is followed to its fixed point, at most one round per
+// link of a chain of fallbacks.  Returns the lane's pick.
+__device__ __forceinline__ uint32_t floyd_wave(uint32_t v, uint32_t r, bool live, bool taken, uint32_t k,
+                                               uint32_t d, uint32_t s0) {
+  const int lane = threadIdx.x & 63;
+  const int nlive = (int)min(64u, d - s0);
+  bool dup = live && taken;
+  for (int q = 0; q < nlive - 1; ++q) {
+    const uint32_t vq = (uint32_t)__builtin_amdgcn_readlane((int)v, q);
+    dup |= live && lane > q && v == vq;
+  }
+  const int64_t idx = (int64_t)v - ((int64_t)k - (int64_t)d + (int64_t)s0);
+  const bool in_range = live && idx >= 0 && idx < lane;
+  const uint32_t at = in_range ? (uint32_t)idx : 0u;
+  for (;;) {
+    const uint64_t mask = __ballot(dup);
+    const bool nd = dup || (in_range && ((mask >> at) & 1ull));
+    if (__ballot(nd != dup) == 0ull) break;
+    dup = nd;
+  }
+  return dup ? r : v;
+}
+
+// Rows of at most kLightMax neighbours: one thread each, the picks in LDS
 // (slot-major, so that neighbouring threads use neighbouring banks), the
 // membership test by a scan of the picks so far, then an insertion sort.
+constexpr uint32_t kLightMax = 16;
+
 __global__ __launch_bounds__(kSampleThreads) void sample_light_kernel(DevGraphJob J) {
-  __shared__ int32_t picks[kSegMax][kSampleThreads];
+  __shared__ int32_t picks[kLightMax][kSampleThreads];
   const uint32_t j = blockIdx.x * kSampleThreads + threadIdx.x;
   if (j >= J.n) return;
   const uint32_t d = (uint32_t)J.deg[j];
-  if (d > kSegMax) return;
+  if (d > kLightMax) return;
   const uint64_t key = row_key(J.seed, J.stripe_key, j);
   const int t = threadIdx.x;
   for (uint32_t s = 0; s < d; ++s) {
@@ -317,9 +263,31 @@ __global__ __launch_bounds__(kSampleThreads) void sample_light_kernel(DevGraphJo
   for (uint32_t s = 0; s < d; ++s) out[s] = picks[s][t];
 }
 
-// Rows of more than kSegMax neighbours: a workgroup each.  Thread 0 runs
-// Floyd's steps against a k-bit LDS bitmap; the set bits, in order, are the
-// sorted row.
+// Rows of kLightMax + 1 .. kSegMax neighbours: one wave each, lane s taking
+// Floyd's step s (floyd_wave).  A lane's place in the sorted row is the
+// number of picks below its own.
+__global__ __launch_bounds__(256) void sample_medium_kernel(DevGraphJob J) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t j = blockIdx.x * 4u + (threadIdx.x >> 6);
+  if (j >= J.n) return;
+  const uint32_t d = (uint32_t)J.deg[j];
+  if (d <= kLightMax || d > kSegMax) return;
+  const uint64_t key = row_key(J.seed, J.stripe_key, j);
+  const bool live = (uint32_t)lane < d;
+  uint32_t r = 0, v = 0;
+  if (live) v = floyd_candidate(key, J.k, d, (uint32_t)lane, r);
+  const uint32_t pick = floyd_wave(v, r, live, false, J.k, d, 0);
+  uint32_t below = 0;
+  for (int q = 0; q < (int)d; ++q) below += (uint32_t)__builtin_amdgcn_readlane((int)pick, q) < pick ? 1u : 0u;
+  if (live) J.col[J.row_ptr[j] + below] = (int32_t)pick;
+}
+
+// Rows of more than kSegMax neighbours: a workgroup each.  Wave 0 runs
+// Floyd's steps against a k-bit LDS bitmap, 64 steps at a time (floyd_wave:
+// each lane tests its candidate against the bitmap of earlier batches, then
+// against the lanes before it).  A fallback r is never taken (every earlier
+// pick is at most the previous step's r).  The set bits, read in order, are
+// the sorted row.
 __global__ __launch_bounds__(kThreads) void sample_heavy_kernel(DevGraphJob J) {
   extern __shared__ uint32_t bits[];   // ceil(k / 32) words
   __shared__ uint32_t sh[kThreads / 64 + 1];
@@ -328,14 +296,17 @@ __global__ __launch_bounds__(kThreads) void sample_heavy_kernel(DevGraphJob J) {
   const uint32_t words = (J.k + 31) / 32;
   for (uint32_t w = threadIdx.x; w < words; w += kThreads) bits[w] = 0;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x;
     const uint64_t key = row_key(J.seed, J.stripe_key, j);
-    for (uint32_t s = 0; s < d; ++s) {
-      uint32_t r;
-      const uint32_t v = floyd_candidate(key, J.k, d, s, r);
-      const bool taken = (bits[v >> 5] >> (v & 31)) & 1u;
-      const uint32_t pick = taken ? r : v;
-      bits[pick >> 5] |= 1u << (pick & 31);
+    for (uint32_t s0 = 0; s0 < d; s0 += 64) {
+      const uint32_t s = s0 + lane;
+      const bool live = s < d;
+      uint32_t r = 0, v = 0;
+      if (live) v = floyd_candidate(key, J.k, d, s, r);
+      const bool taken = live && ((bits[v >> 5] >> (v & 31)) & 1u);
+      const uint32_t pick = floyd_wave(v, r, live, taken, J.k, d, s0);
+      if (live) atomicOr(&bits[pick >> 5], 1u << (pick & 31));
     }
   }
   __syncthreads();
@@ -358,28 +329,51 @@ __global__ __launch_bounds__(kThreads) void sample_heavy_kernel(DevGraphJob J) {
 // ---------------------------------------------------------------------------
 // transpose
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void col_count_kernel(DevGraphJob J) {
-  const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-  if (j >= J.n) return;
-  for (int32_t e = J.row_ptr[j]; e < J.row_ptr[j + 1]; ++e) atomicAdd(&J.ccnt[J.col[e]], 1);
+// One thread per encode segment (at most kSegMax edges), so that a row of
+// thousands of neighbours does not serialise its atomics in one thread.
+__global__ __launch_bounds__(256) void col_count_kernel(DevGraphJob J, uint32_t nseg) {
+  const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+  if (s >= nseg) return;
+  const int32_t e0 = J.seg_beg[s], e1 = e0 + J.seg_len[s];
+  for (int32_t e = e0; e < e1; ++e) atomicAdd(&J.ccnt[J.col[e]], 1);
 }
 
-__global__ __launch_bounds__(256) void col_fill_kernel(DevGraphJob J) {
-  const uint32_t j = blockIdx.x * 256u + threadIdx.x;
-  if (j >= J.n) return;
-  for (int32_t e = J.row_ptr[j]; e < J.row_ptr[j + 1]; ++e) {
+__global__ __launch_bounds__(256) void col_fill_kernel(DevGraphJob J, uint32_t nseg) {
+  const uint32_t s = blockIdx.x * 256u + threadIdx.x;
+  if (s >= nseg) return;
+  const int32_t j = J.seg_row[s];
+  const int32_t e0 = J.seg_beg[s], e1 = e0 + J.seg_len[s];
+  for (int32_t e = e0; e < e1; ++e) {
     const int32_t i = J.col[e];
     const int32_t at = atomicAdd(&J.cfill[i], 1);
-    J.rowidx[J.col_ptr[i] + at] = (int32_t)j;
+    J.rowidx[J.col_ptr[i] + at] = j;
   }
 }
 
-// rows of one column ascending (insertion sort), and the largest column
+// rows of one column ascending, and the largest column: a column of at most
+// 64 rows is sorted in LDS (slot-major), a longer one in place
 __global__ __launch_bounds__(256) void col_sort_kernel(DevGraphJob J) {
+  __shared__ int32_t buf[64][256];
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= J.k) return;
+  const int t = threadIdx.x;
   int32_t *r = J.rowidx + J.col_ptr[i];
   const int32_t c = J.col_ptr[i + 1] - J.col_ptr[i];
+  atomicMax(J.scalars + kScalarMaxCdeg, c);
+  if (c <= 64) {
+    for (int32_t a = 0; a < c; ++a) buf[a][t] = r[a];
+    for (int32_t a = 1; a < c; ++a) {
+      const int32_t x = buf[a][t];
+      int32_t q = a;
+      while (q > 0 && buf[q - 1][t] > x) {
+        buf[q][t] = buf[q - 1][t];
+        --q;
+      }
+      buf[q][t] = x;
+    }
+    for (int32_t a = 0; a < c; ++a) r[a] = buf[a][t];
+    return;
+  }
   for (int32_t a = 1; a < c; ++a) {
     const int32_t x = r[a];
     int32_t q = a;
@@ -389,7 +383,6 @@ __global__ __launch_bounds__(256) void col_sort_kernel(DevGraphJob J) {
     }
     r[q] = x;
   }
-  atomicMax(J.scalars + kScalarMaxCdeg, c);
 }
 
 fs_status hip_ok(hipError_t e, const char *what) {
@@ -397,43 +390,32 @@ fs_status hip_ok(hipError_t e, const char *what) {
   return fail(FS_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-fs_status scan_launch(const int32_t *in, uint32_t m, uint32_t *sums, int32_t *out, hipStream_t s) {
-  const uint32_t per = kThreads * kScanItems;
-  const uint32_t nb = std::max<uint32_t>(1, (m + per - 1) / per);
-  hipLaunchKernelGGL(scan_partial_kernel, dim3(nb), dim3(kThreads), 0, s, in, m, sums);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(kThreads), 0, s, sums, nb, (int32_t *)nullptr);
-  hipLaunchKernelGGL(scan_final_kernel, dim3(nb), dim3(kThreads), 0, s, in, m, sums, out);
-  return hip_ok(hipGetLastError(), "graph scan launch");
-}
-
 }  // namespace
 
 void dev_graph_carve(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n, uint32_t D) {
   const uint32_t nblk = (n + kThreads - 1) / kThreads;
-  const uint32_t per = kThreads * kScanItems;
   J.T = cv.take<uint64_t>(D);
   J.deg = cv.take<int32_t>(n);
   J.row_ptr = cv.take<int32_t>((size_t)n + 1);
   J.blk_hist = cv.take<uint32_t>((size_t)nblk * (kSegMax + 1));
   J.scalars = cv.take<int32_t>(kScalarCount);
   J.edges = cv.take<unsigned long long>(1);
-  J.sums = cv.take<uint32_t>((std::max(n, k) + per - 1) / per + 1);
+  J.sums = cv.take<uint32_t>(scan_sums_for(std::max(n, k)) + 1);
   J.ccnt = cv.take<int32_t>(k);
   J.cfill = cv.take<int32_t>(k);
 }
 
 void dev_graph_carve_rows(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n, uint32_t nseg) {
-  const uint32_t per = kThreads * kScanItems;
   J.seg_len = cv.take<int32_t>(nseg);
   J.seg_beg = cv.take<int32_t>(nseg);
-  J.sums = cv.take<uint32_t>((std::max(std::max(n, k), nseg) + per - 1) / per + 1);
+  J.sums = cv.take<uint32_t>(scan_sums_for(std::max(std::max(n, k), nseg)) + 1);
 }
 
 fs_status launch_dev_graph_degrees(const DevGraphJob &J, hipStream_t s) {
   if (J.n == 0) return FS_OK;
   hipLaunchKernelGGL(degree_kernel, dim3((J.n + 255) / 256), dim3(256), 0, s, J);
   // row_ptr (into the image) from the degrees; the last entry is nnz
-  fs_status st = scan_launch(J.deg, J.n, J.sums, J.row_ptr, s);
+  fs_status st = scan_i32(J.deg, J.n, J.sums, J.row_ptr, s);
   if (st != FS_OK) return st;
   const uint32_t nblk = (J.n + kThreads - 1) / kThreads;
   hipLaunchKernelGGL(seg_count_kernel, dim3(nblk), dim3(kThreads), 0, s, J);
@@ -446,6 +428,7 @@ fs_status launch_dev_graph_rows(const DevGraphJob &J, uint32_t nseg, uint32_t nh
   hipLaunchKernelGGL(seg_place_kernel, dim3(nblk), dim3(kThreads), 0, s, J);
   hipLaunchKernelGGL(sample_light_kernel, dim3((J.n + kSampleThreads - 1) / kSampleThreads), dim3(kSampleThreads),
                      0, s, J);
+  hipLaunchKernelGGL(sample_medium_kernel, dim3((J.n + 3) / 4), dim3(256), 0, s, J);
   if (nheavy) {
     const size_t lds = (size_t)((J.k + 31) / 32) * 4;
     static bool done[64] = {false};
@@ -459,16 +442,16 @@ fs_status launch_dev_graph_rows(const DevGraphJob &J, uint32_t nseg, uint32_t nh
     }
     hipLaunchKernelGGL(sample_heavy_kernel, dim3(nheavy), dim3(kThreads), lds, s, J);
   }
-  fs_status st = scan_launch(J.seg_len, nseg, J.sums, J.seg_ptr, s);
+  fs_status st = scan_i32(J.seg_len, nseg, J.sums, J.seg_ptr, s);
   if (st != FS_OK) return st;
   if (nseg) hipLaunchKernelGGL(seg_copy_kernel, dim3((nseg + 255) / 256), dim3(256), 0, s, J, nseg);
   st = hip_ok(hipMemsetAsync(J.ccnt, 0, sizeof(int32_t) * J.k, s), "graph clear");
   if (st == FS_OK) st = hip_ok(hipMemsetAsync(J.cfill, 0, sizeof(int32_t) * J.k, s), "graph clear");
   if (st != FS_OK) return st;
-  if (J.n) hipLaunchKernelGGL(col_count_kernel, dim3((J.n + 255) / 256), dim3(256), 0, s, J);
-  st = scan_launch(J.ccnt, J.k, J.sums, J.col_ptr, s);
+  if (nseg) hipLaunchKernelGGL(col_count_kernel, dim3((nseg + 255) / 256), dim3(256), 0, s, J, nseg);
+  st = scan_i32(J.ccnt, J.k, J.sums, J.col_ptr, s);
   if (st != FS_OK) return st;
-  if (J.n) hipLaunchKernelGGL(col_fill_kernel, dim3((J.n + 255) / 256), dim3(256), 0, s, J);
+  if (nseg) hipLaunchKernelGGL(col_fill_kernel, dim3((nseg + 255) / 256), dim3(256), 0, s, J, nseg);
   hipLaunchKernelGGL(col_sort_kernel, dim3((J.k + 255) / 256), dim3(256), 0, s, J);
   return hip_ok(hipGetLastError(), "graph rows launch");
 }

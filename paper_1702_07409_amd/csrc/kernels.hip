@@ -19,6 +19,7 @@
 #include <algorithm>
 
 #include "fs_internal.h"
+#include "scan.h"
 
 namespace fs {
 
@@ -613,7 +614,21 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     J.level_ptr[0] = 0;
   }
   __syncthreads();
-  for (uint32_t g = tid; g < n; g += kPeelThreads) {
+  if (!ALL && J.acc_ready) {
+    // the row states were made by the init kernels: take them over (packed
+    // when the counters are 32-bit) and list the rows of one unknown
+    for (uint32_t g = tid; g < n; g += kPeelThreads) {
+      const unsigned long long a0 = J.acc[g];
+      const bool erased_row = (a0 & kErasedAcc) != 0;
+      if constexpr (PACKED)
+        S.acc32[g] = erased_row ? (kErasedAcc32 + (uint32_t)(a0 & kSumMask32))
+                                : ((uint32_t)(a0 >> 40) << 24 | (uint32_t)(a0 & kSumMask32));
+      else if constexpr (MODE == kPeelLdsRows)
+        S.acc[g] = a0;
+      if (!erased_row && (a0 >> 40) == 1ull) S.fa[atomicAdd(&s_nA, 1)] = (int32_t)g;
+    }
+  }
+  for (uint32_t g = tid; g < n && !(!ALL && J.acc_ready); g += kPeelThreads) {
     const int d = J.row_ptr[g + 1] - J.row_ptr[g];
     if constexpr (ALL) S.deg[g] = (uint16_t)d;
     if (J.erased[g]) {
@@ -638,7 +653,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   // sums of neighbour ids, accumulated by input over the CSC: the work per
   // thread follows the column degrees, which stay small even when a few rows
   // have huge degree
-  for (uint32_t i = tid; i < k; i += kPeelThreads) {
+  for (uint32_t i = tid; i < k && !(!ALL && J.acc_ready); i += kPeelThreads) {
     const int c1 = S.cptr[i + 1];
     for (int e = S.cptr[i]; e < c1; e += kPeelBatch) {
       int32_t h[kPeelBatch];
@@ -902,6 +917,109 @@ __device__ __forceinline__ void prog_body(const ProgJob &P) {
 }
 
 __global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) { prog_body(P); }
+
+// The same program built by many workgroups, for large schedules (one
+// workgroup walks every pair and row in turn and is bound by its memory
+// latency there):
+//   1. decoding maps cleared, each pair's count of other inputs into poff;
+//   2. poff scanned in place (entries past the pairs are 0);
+//   3. per pair, its other inputs copied to pidx, gsrc and finv set;
+//   4. the decoding rows listed ascending (gl, fl) by a count per block of
+//      rows, a scan of the counts and ranks within each block;
+//   5. meta.
+// The result is prog_body's, entry for entry.
+__device__ __forceinline__ int prog_pairs(const ProgJob &P) {
+  return min(max((int)P.k - P.status[1], 0), (int)P.k);
+}
+
+__global__ __launch_bounds__(256) void prog_wide_count_kernel(ProgJob P) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  // the dependency-slab form is unusable until prog_lookahead_kernel says otherwise
+  if (i == 0 && P.la_meta) P.la_meta[0] = 0;
+  if (P.skip_flag && *P.skip_flag) return;
+  if (i < P.k) P.gsrc[i] = -1;
+  if (i < P.n) P.finv[i] = -1;
+  if (i < P.k) {
+    int32_t cnt = 0;
+    if ((int)i < prog_pairs(P)) {
+      const int32_t f = P.dp_f[i], g = P.dp_g[i];
+      if ((uint32_t)f < P.k && (uint32_t)g < P.n) cnt = P.row_ptr[g + 1] - P.row_ptr[g] - 1;
+    }
+    P.poff[i] = cnt;
+  }
+}
+
+__global__ __launch_bounds__(256) void prog_wide_fill_kernel(ProgJob P) {
+  if (P.skip_flag && *P.skip_flag) return;
+  const int p = (int)(blockIdx.x * 256u + threadIdx.x);
+  const int nR = prog_pairs(P);
+  if (p >= nR) return;
+  const int32_t f = P.dp_f[p], g = P.dp_g[p];
+  if (!((uint32_t)f < P.k && (uint32_t)g < P.n)) return;
+  P.gsrc[f] = g;
+  P.finv[g] = f;
+  if ((uint32_t)P.poff[nR] > P.pidx_cap) return;   // does not fit: the program is marked unusable
+  int32_t o = P.poff[p];
+  const int32_t end = P.poff[p + 1];
+  for (int e = P.row_ptr[g]; e < P.row_ptr[g + 1] && o < end; ++e) {
+    const int32_t c = P.col[e];
+    if (c != f) P.pidx[o++] = c;
+  }
+}
+
+__global__ __launch_bounds__(1024) void prog_wide_rows_count_kernel(ProgJob P) {
+  __shared__ uint32_t sh[1024 / 64 + 1];
+  if (P.skip_flag && *P.skip_flag) return;
+  const uint32_t g = blockIdx.x * 1024u + threadIdx.x;
+  uint32_t total = 0;
+  (void)scan_block<1024>(g < P.n && P.finv[g] >= 0 ? 1u : 0u, sh, total);
+  if (threadIdx.x == 0) P.psums[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(1024) void prog_wide_rows_place_kernel(ProgJob P) {
+  __shared__ uint32_t sh[1024 / 64 + 1];
+  if (P.skip_flag && *P.skip_flag) return;
+  const uint32_t g = blockIdx.x * 1024u + threadIdx.x;
+  const int32_t f = g < P.n ? P.finv[g] : -1;
+  uint32_t total = 0;
+  const uint32_t pos = P.psums[blockIdx.x] + scan_block<1024>(f >= 0 ? 1u : 0u, sh, total);
+  if (f >= 0 && pos < P.k) {
+    P.gl[pos] = (int32_t)g;
+    P.fl[pos] = f;
+  }
+}
+
+__global__ void prog_wide_meta_kernel(ProgJob P, uint32_t nblk) {
+  if (threadIdx.x != 0) return;
+  if (P.skip_flag && *P.skip_flag) {
+    P.meta[3] = 0;
+    return;
+  }
+  const int nR = prog_pairs(P);
+  const int L = min(max(P.status[2], 0), (int)P.k);
+  const uint32_t total = (uint32_t)P.poff[nR];
+  const uint32_t nused = (uint32_t)P.psums[nblk];
+  P.poff[nR] = (int32_t)total;
+  P.meta[0] = nR;
+  P.meta[1] = L;
+  P.meta[2] = (int32_t)total;
+  P.meta[3] = total <= P.pidx_cap && nused == (uint32_t)nR ? 1 : 0;
+}
+
+fs_status launch_prog_wide(const ProgJob &P, hipStream_t s) {
+  const uint32_t span = std::max(P.k, P.n);
+  hipLaunchKernelGGL(prog_wide_count_kernel, dim3((span + 255) / 256), dim3(256), 0, s, P);
+  const fs_status st = scan_i32(P.poff, P.k, P.psums, P.poff, s);
+  if (st != FS_OK) return st;
+  hipLaunchKernelGGL(prog_wide_fill_kernel, dim3((P.k + 255) / 256), dim3(256), 0, s, P);
+  const uint32_t nblk = (P.n + 1023) / 1024;
+  hipLaunchKernelGGL(prog_wide_rows_count_kernel, dim3(nblk), dim3(1024), 0, s, P);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, P.psums, nblk, (int32_t *)(P.psums + nblk));
+  hipLaunchKernelGGL(prog_wide_rows_place_kernel, dim3(nblk), dim3(1024), 0, s, P);
+  hipLaunchKernelGGL(prog_wide_meta_kernel, dim3(1), dim3(64), 0, s, P, nblk);
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? FS_OK : fail(FS_ERR_HIP, std::string("program launch: ") + hipGetErrorString(e));
+}
 
 __global__ __launch_bounds__(kPlanThreads) void prog_batch_kernel(const ProgJob *jobs) { prog_body(jobs[blockIdx.x]); }
 
@@ -1777,7 +1895,27 @@ fs_status launch_plan(const PeelJob &job, const ProgJob &prog, hipStream_t s, ui
   return st != FS_OK ? st : launch_prog_lookahead(prog, s);
 }
 
-fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg) {
+// Initial row states for the peels whose rows live in global memory or in
+// LDS rows only: count << 40 | sum of the row's input ids (erased rows
+// flagged), by one thread per row and then one per column (the column
+// degrees stay small even when a few rows have huge degree).  One
+// workgroup took about 0.05 ms for this on the k = 10246 code.
+__global__ __launch_bounds__(256) void peel_init_rows_kernel(PeelJob J) {
+  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+  if (g >= J.n) return;
+  const int d = J.row_ptr[g + 1] - J.row_ptr[g];
+  J.acc[g] = J.erased[g] ? kErasedAcc : ((unsigned long long)d << 40);
+}
+
+__global__ __launch_bounds__(256) void peel_init_cols_kernel(PeelJob J) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i >= J.k) return;
+  const int c1 = J.col_ptr[i + 1];
+  for (int e = J.col_ptr[i]; e < c1; ++e) atomicAdd(&J.acc[J.rowidx[e]], (unsigned long long)i);
+}
+
+fs_status launch_peel(const PeelJob &job_in, hipStream_t s, uint32_t max_deg) {
+  PeelJob job = job_in;
   int dev = 0;
   (void)hipGetDevice(&dev);
   const size_t lds = peel_lds_bytes(job.k, job.n);
@@ -1795,6 +1933,9 @@ fs_status launch_peel(const PeelJob &job, hipStream_t s, uint32_t max_deg) {
     hipLaunchKernelGGL(peel_kernel<kPeelLds>, dim3(1), dim3(kPeelThreads), lds, s, job);
   } else {
     if (!job.acc) return fail(FS_ERR_WORKSPACE, "peel state needs the workspace");
+    if (job.n) hipLaunchKernelGGL(peel_init_rows_kernel, dim3((job.n + 255) / 256), dim3(256), 0, s, job);
+    if (job.k) hipLaunchKernelGGL(peel_init_cols_kernel, dim3((job.k + 255) / 256), dim3(256), 0, s, job);
+    job.acc_ready = 1;
     if (mode == kPeelLdsRows) {
       static bool done[64] = {false};
       set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLdsRows>), dev, budget - (int)static_lds, done);
@@ -1818,6 +1959,7 @@ void prog_carve(Carver &cv, ProgJob &p, uint64_t nnz) {
   p.poff = cv.take<int32_t>((size_t)p.k + 1);
   p.pidx = cv.take<int32_t>(nnz ? nnz : 1);
   p.meta = cv.take<int32_t>(4);
+  p.psums = cv.take<uint32_t>(std::max(scan_sums_for((uint64_t)p.k + 1), (p.n + 1023u) / 1024u) + 2);
   p.pidx_cap = (uint32_t)(nnz ? nnz : 1);
   if (p.k <= 65535 && p.n <= 65535) {
     p.la_slot = cv.take<int32_t>(p.k);
@@ -1888,8 +2030,18 @@ static hipError_t run_replay_lds_m(const ReplayJob &job, const ProgJob &prog, ui
   return run_replay_lds<LPS, 16>(job, prog, nslices, grid, budget, dev, s);
 }
 
+// Schedules of this many inputs or more build their replay program with
+// many workgroups (prog_wide_*): on the k = 10246 code one workgroup took
+// 0.137 ms.
+constexpr uint32_t kProgWideMinK = 4096;
+
 fs_status launch_prog(const ProgJob &prog, hipStream_t s) {
-  FS_TRY_LAUNCH(prog_build, prog, s);
+  if (prog.k >= kProgWideMinK) {
+    const fs_status st = launch_prog_wide(prog, s);
+    if (st != FS_OK) return st;
+  } else {
+    FS_TRY_LAUNCH(prog_build, prog, s);
+  }
   return launch_prog_lookahead(prog, s);
 }
 

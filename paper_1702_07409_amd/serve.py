@@ -16,12 +16,12 @@ the loop (a "tick"):
 
 Graphs are kept on the device in a cache keyed by their parameters (the
 paper regenerates an object's graph from its seed and parameters, so objects
-of equal k and n share one).  A missing graph is built by kernels on the
-device when its request arrives (fs_graph_build with FS_GRAPH_ON_DEVICE, on
-the cache's own stream; the call returns with the graph complete, in about
-0.1-0.5 ms for k up to 16384).  With device builds off, host construction
-starts on a thread pool instead and the device copy is made on the stream of
-the tick that first uses it, other streams waiting for that copy.
+of equal k and n share one).  A missing graph is built when its request
+arrives, on a thread pool so that the loop goes on: by kernels on the
+device (fs_graph_build with FS_GRAPH_ON_DEVICE, each worker on a stream of
+its own; the call returns with the graph complete), or, with device builds
+off, on the host, the device copy then being made on the stream of the tick
+that first uses it, other streams waiting for that copy.
 
 Resident stripes (inputs x and coded blocks c kept on the device) are the
 targets of decode, repair (from the resident inputs) and update.  Requests on
@@ -31,6 +31,7 @@ Everything on the device runs in libfs.so; this module only schedules.
 """
 
 import collections
+import threading
 import time
 from concurrent.futures import ThreadPoolExecutor
 
@@ -72,7 +73,7 @@ class GraphCache:
     def __init__(self, device, workers=8, capacity=4 << 30, device_builds=True):
         self.device = device
         self.device_builds = device_builds
-        self.build_stream = torch.cuda.Stream(device=device) if device_builds else None
+        self.local = threading.local()
         self.pool = ThreadPoolExecutor(max_workers=workers)
         self.capacity = capacity
         self.entries = collections.OrderedDict()
@@ -91,10 +92,7 @@ class GraphCache:
             p = dict(params)
             p["finite_w"] = tuple(p.get("finite_w", ()))
             if self.device_builds:
-                e = GraphEntry(key, None)
-                e.graph = fs.fs_graph_build(on_device=True, stream=self.build_stream, **p)
-                e.bytes = e.graph.device_bytes()
-                self.device_bytes += e.bytes
+                e = GraphEntry(key, self.pool.submit(self._build_on_device, p))
             else:
                 e = GraphEntry(key, self.pool.submit(fs.fs_graph_build, host_only=True, **p))
             self.entries[key] = e
@@ -104,13 +102,22 @@ class GraphCache:
             self.entries.move_to_end(key)
         return e
 
+    def _build_on_device(self, p):
+        # a worker thread: its own stream (the build waits on it)
+        s = getattr(self.local, "stream", None)
+        if s is None:
+            s = self.local.stream = torch.cuda.Stream(device=self.device)
+        return fs.fs_graph_build(on_device=True, stream=s, **p)
+
     def on_device(self, e, stream, keep):
         """Make sure e has a device copy usable on `stream`; pinned staging
         buffers that must outlive the copy are appended to `keep`."""
         if e.graph is None:
             e.graph = e.future.result()
         if e.graph.built_on_device:
-            pass   # complete on the device when its build returned
+            if not e.bytes:   # complete on the device when its build returned
+                e.bytes = e.graph.device_bytes()
+                self.device_bytes += e.bytes
         elif e.mem is None:
             nbytes = e.graph.image_size()
             e.mem = _empty(nbytes, self.device)
