@@ -114,12 +114,16 @@ FS_API fs_status fs_degree_table(const fs_graph_params *params, uint64_t *T_out,
  * Unless FS_GRAPH_HOST_ONLY, the CSR/CSC are copied to the current device on
  * `stream` and the call returns after the copy has completed.
  * With FS_GRAPH_ON_DEVICE the rows are drawn by kernels on `stream` instead
- * (one thread per row, a workgroup per row of more than 64 neighbours), the
- * transpose and the encode segments likewise; the call synchronises the
- * stream twice (for the sizes, then the heavy-row list) and returns with the
- * graph complete.  Its scratch memory is kept per calling thread and device
+ * (16 lanes per row of at most 16 neighbours, a wave per row of up to 64, a
+ * workgroup per longer row), the transpose and the encode segments likewise;
+ * the call synchronises the stream twice (for the sizes, then the heavy-row
+ * list) and returns with the graph complete.  The degree thresholds of the
+ * last distribution built on a thread stay on the device for its next build.
+ * Its scratch memory is kept per calling thread and device
  * (grown, never freed, so that builds beside other work do not wait for the
- * device); builds on different threads and streams run concurrently.
+ * device); builds on different threads and streams run concurrently.  The
+ * graph's device memory comes from a memory pool per device that keeps
+ * freed memory for later builds (hipMalloc when no pool can be made).
  * fs_graph_export then copies from the device, and fs_graph_image_size /
  * fs_graph_upload do not apply.
  * *out receives the graph (freed with fs_graph_free).
@@ -140,6 +144,8 @@ FS_API fs_status fs_graph_info(const fs_graph *g, uint32_t *k, uint32_t *n, uint
 FS_API fs_status fs_graph_export(const fs_graph *g, int32_t *row_ptr, int32_t *col,
                           int32_t *col_ptr, int32_t *rowidx);
 
+/* Release a graph and its device memory.  Like hipFree, it waits for all
+ * work on the graph's device first. */
 FS_API void fs_graph_free(fs_graph *g);
 
 /*
@@ -509,7 +515,7 @@ FS_API fs_status fs_decode_apply(const fs_graph *g, const void *c, void *x, uint
 
 /* Tuning of the gather-XOR kernel family (encode, repair, update). */
 typedef struct fs_tune {
-  uint32_t lanes_per_row;  /* 16, 32, 64, 128 or 256 lanes share one coded
+  uint32_t lanes_per_row;  /* 8, 16, 32, 64, 128 or 256 lanes share one coded
                               row (128 and 256: one or two rows per
                               workgroup, for jobs of few rows)               */
   uint32_t chunks;         /* 16-byte chunks per lane per slice: 1, 2 or 4

@@ -81,7 +81,8 @@ fs_tune tile_for(const fs_tune &t, const fs_graph *g) {
 
 static bool tune_ok(const fs_tune &t) {
   const bool auto_tile = t.lanes_per_row == 0 && t.chunks == 0;
-  const bool lpr = auto_tile || t.lanes_per_row == 16 || t.lanes_per_row == 32 || t.lanes_per_row == 64 ||
+  const bool lpr = auto_tile || t.lanes_per_row == 8 || t.lanes_per_row == 16 || t.lanes_per_row == 32 ||
+                   t.lanes_per_row == 64 ||
                    t.lanes_per_row == 128 || t.lanes_per_row == 256;
   // row-wide tilings (one or two rows per workgroup) take 1 or 2 chunks
   const bool ch = auto_tile || t.chunks == 1 || t.chunks == 2 || (t.chunks == 4 && t.lanes_per_row <= 64);
@@ -406,8 +407,8 @@ namespace {
 // builds on different threads (each on its own stream) run side by side.
 // The buffers live until the process ends.
 struct BuildScratch {
-  void *buf[64][2] = {};
-  size_t bytes[64][2] = {};
+  void *buf[64][3] = {};     // slots: before the sizes, after them, thresholds
+  size_t bytes[64][3] = {};
 };
 
 fs_status build_scratch(int dev, int slot, size_t need, void **out) {
@@ -424,9 +425,99 @@ fs_status build_scratch(int dev, int slot, size_t need, void **out) {
   *out = sc.buf[dev][slot];
   return FS_OK;
 }
+
+// Images of device-built graphs come from one memory pool per device that
+// keeps freed memory for reuse, so that a build does not wait on the mapping
+// of new memory (a request loop builds graphs while other work runs).  Null
+// when the pool cannot be made; builds then use hipMalloc.
+hipMemPool_t graph_pool(int dev) {
+  static std::mutex mu;
+  static hipMemPool_t pools[64] = {};
+  static bool tried[64] = {};
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!tried[dev]) {
+    tried[dev] = true;
+    hipMemPoolProps props = {};
+    props.allocType = hipMemAllocationTypePinned;
+    props.handleTypes = hipMemHandleTypeNone;
+    props.location.type = hipMemLocationTypeDevice;
+    props.location.id = dev;
+    hipMemPool_t pool = nullptr;
+    if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+      uint64_t keep = UINT64_MAX;
+      if (hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep) == hipSuccess) pools[dev] = pool;
+      else (void)hipMemPoolDestroy(pool);
+    }
+    (void)hipGetLastError();
+  }
+  return pools[dev];
+}
+
+// The degree thresholds of the last distribution a thread built with, on
+// the host and in its threshold scratch: a request loop builds many graphs
+// of one distribution, and RSD has k thresholds.
+struct ThresholdCache {
+  bool valid = false;
+  uint32_t dist = 0, k = 0;
+  double c = 0.0, delta = 0.0;
+  std::vector<double> finite;
+  std::vector<uint64_t> T;
+  void *dev = nullptr;
+};
+
+fs_status device_thresholds(const fs_graph_params &p, int dev, hipStream_t stream, const uint64_t **T_dev,
+                            uint32_t *D) {
+  static thread_local ThresholdCache cache[64];
+  ThresholdCache &tc = cache[dev];
+  bool same = tc.valid && tc.dist == p.dist && tc.k == p.k;
+  if (same && p.dist == FS_DIST_RSD) same = tc.c == p.rsd_c && tc.delta == p.rsd_delta;
+  if (same && p.dist == FS_DIST_FINITE)
+    same = tc.finite.size() == p.finite_dmax && p.finite_w &&
+           std::equal(tc.finite.begin(), tc.finite.end(), p.finite_w);
+  if (!same) {
+    tc.valid = false;
+    std::vector<double> w;
+    FS_TRY(degree_weights(p, w));
+    degree_thresholds(w, tc.T);
+    tc.dist = p.dist;
+    tc.k = p.k;
+    tc.c = p.rsd_c;
+    tc.delta = p.rsd_delta;
+    if (p.dist == FS_DIST_FINITE) tc.finite.assign(p.finite_w, p.finite_w + p.finite_dmax);
+    else tc.finite.clear();
+  }
+  void *buf = nullptr;
+  FS_TRY(build_scratch(dev, 2, tc.T.size() * sizeof(uint64_t), &buf));
+  if (!same || buf != tc.dev) {
+    // tc.T stays unchanged until the build that uses it has synchronised
+    const hipError_t e = hipMemcpyAsync(buf, tc.T.data(), tc.T.size() * sizeof(uint64_t), hipMemcpyHostToDevice, stream);
+    if (e != hipSuccess) return fail(FS_ERR_HIP, std::string("graph thresholds: ") + hipGetErrorString(e));
+    tc.dev = buf;
+  }
+  tc.valid = true;
+  *T_dev = static_cast<const uint64_t *>(buf);
+  *D = (uint32_t)tc.T.size();
+  return FS_OK;
+}
+
+void free_graph_memory(fs_graph &g) {
+  if (!g.d_base) return;
+  if (g.pooled) {
+    // work on any stream may still read the image: wait for the device, as
+    // hipFree does, then hand the memory back to the pool
+    (void)hipDeviceSynchronize();
+    (void)hipFreeAsync(g.d_base, nullptr);
+    (void)hipStreamSynchronize(nullptr);
+  } else {
+    (void)hipFree(g.d_base);
+  }
+  g.d_base = nullptr;
+}
 }  // namespace
 
-// Device construction (graph_dev.hip): thresholds on the host, then the
+// Device construction (graph_dev.hip): thresholds on the host (kept for the
+// next build of the same distribution), then the
 // degree pass, one copy of the sizes back (nnz, segments, heavy rows), the
 // image allocated to fit, the rows, segments and transpose, and the heavy-row
 // list and largest column copied back.
@@ -434,10 +525,6 @@ fs_status build_device_graph(const fs_graph_params &p, hipStream_t stream, fs_gr
   if (p.k < 1 || p.n < 1) return fail(FS_ERR_INVALID, "k and n must be >= 1");
   if (p.k > (1u << 20)) return fail(FS_ERR_INVALID, "k above 2^20 is not supported");
   if (p.reserved != 0) return fail(FS_ERR_INVALID, "reserved field must be 0");
-  std::vector<double> w;
-  FS_TRY(degree_weights(p, w));
-  std::vector<uint64_t> T;
-  degree_thresholds(w, T);
   g.k = p.k;
   g.n = p.n;
   g.params = p;
@@ -454,38 +541,46 @@ fs_status build_device_graph(const fs_graph_params &p, hipStream_t stream, fs_gr
   DevGraphJob J{};
   J.k = p.k;
   J.n = p.n;
-  J.D = (uint32_t)T.size();
+  FS_TRY(device_thresholds(p, g.device, stream, &J.T, &J.D));
   J.seed = p.seed;
   J.stripe_key = p.stripe_key;
   Carver sz(nullptr);
-  dev_graph_carve(sz, J, J.k, J.n, J.D);
+  dev_graph_carve(sz, J, J.k, J.n);
   void *scratch = nullptr, *scratch2 = nullptr;
   FS_TRY(build_scratch(g.device, 0, sz.size(), &scratch));
   auto done = [&](fs_status st) { return st; };
   Carver cv(scratch);
-  dev_graph_carve(cv, J, J.k, J.n, J.D);
+  dev_graph_carve(cv, J, J.k, J.n);
   int32_t *row_ptr_tmp = J.row_ptr;
-  hipError_t e = hipMemcpyAsync(const_cast<uint64_t *>(J.T), T.data(), T.size() * 8, hipMemcpyHostToDevice, stream);
-  if (e == hipSuccess) e = hipMemsetAsync(J.scalars, 0, kScalarCount * 4, stream);
-  if (e == hipSuccess) e = hipMemsetAsync(J.edges, 0, 8, stream);
-  if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph setup: ") + hipGetErrorString(e)));
+  // the degree pass clears the scalars and the edge count itself
   fs_status st = launch_dev_graph_degrees(J, stream);
   if (st != FS_OK) return done(st);
-  int32_t sizes[kScalarCount] = {0, 0, 0, 0};
-  unsigned long long edges = 0;
-  e = hipMemcpyAsync(sizes, J.scalars, sizeof(sizes), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(&edges, J.edges, 8, hipMemcpyDeviceToHost, stream);
+  int32_t sizes[kScalarWords] = {};
+  hipError_t e = hipMemcpyAsync(sizes, J.scalars, sizeof(sizes), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  unsigned long long edges = 0;
+  std::memcpy(&edges, sizes + kScalarCount, sizeof(edges));
   if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph sizes: ") + hipGetErrorString(e)));
   // row_ptr is int32 (its scan wraps past 2^31 edges)
   if (edges >= (unsigned long long)INT32_MAX) return done(fail(FS_ERR_INVALID, "graph has 2^31 or more edges"));
   g.nnz = edges;
+  J.nnz = (uint32_t)edges;
   g.max_deg = (uint32_t)sizes[kScalarMaxDeg];
   g.nseg = (uint32_t)sizes[kScalarSegs];
   const uint32_t nheavy = (uint32_t)sizes[kScalarHeavy];
   GraphImage img;
   graph_image_sized(g.k, g.n, g.nnz, g.nseg, nheavy, img);
-  if (hipMalloc(&g.d_base, img.total) != hipSuccess) return done(fail(FS_ERR_NOMEM, "device allocation for the graph failed"));
+  if (hipMemPool_t pool = graph_pool(g.device)) {
+    g.pooled = hipMallocFromPoolAsync(&g.d_base, img.total, pool, stream) == hipSuccess;
+    if (!g.pooled) {
+      g.d_base = nullptr;
+      (void)hipGetLastError();
+    }
+  }
+  if (!g.d_base && hipMalloc(&g.d_base, img.total) != hipSuccess) {
+    g.d_base = nullptr;
+    return done(fail(FS_ERR_NOMEM, "device allocation for the graph failed"));
+  }
   bind_image(g, img, g.d_base);
   uint8_t *base = static_cast<uint8_t *>(g.d_base);
   J.row_ptr = reinterpret_cast<int32_t *>(base + img.parts[0].off);
@@ -498,20 +593,20 @@ fs_status build_device_graph(const fs_graph_params &p, hipStream_t stream, fs_gr
   J.seg_atomic = base + img.parts[7].off;
   J.seg_col = reinterpret_cast<int32_t *>(base + img.parts[8].off);
   Carver sz2(nullptr);
-  dev_graph_carve_rows(sz2, J, J.k, J.n, g.nseg);
+  dev_graph_carve_rows(sz2, J, J.k, J.n, g.nseg, g.nnz);
   FS_TRY(build_scratch(g.device, 1, sz2.size(), &scratch2));
   Carver cv2(scratch2);
-  dev_graph_carve_rows(cv2, J, J.k, J.n, g.nseg);
-  e = hipMemcpyAsync(J.row_ptr, row_ptr_tmp, ((size_t)p.n + 1) * 4, hipMemcpyDeviceToDevice, stream);
-  if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph row_ptr: ") + hipGetErrorString(e)));
+  dev_graph_carve_rows(cv2, J, J.k, J.n, g.nseg, g.nnz);
+  J.row_src = row_ptr_tmp;   // copied into the image by the first kernel
   st = launch_dev_graph_rows(J, g.nseg, nheavy, stream);
   if (st != FS_OK) return done(st);
-  g.heavy.assign(nheavy, 0);
-  if (nheavy) e = hipMemcpyAsync(g.heavy.data(), J.heavy, (size_t)nheavy * 4, hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipMemcpyAsync(sizes, J.scalars, sizeof(sizes), hipMemcpyDeviceToHost, stream);
+  // the scalars and, after them, the heavy-row list in one copy
+  std::vector<int32_t> tail((size_t)kScalarWords + nheavy);
+  e = hipMemcpyAsync(tail.data(), J.scalars, tail.size() * sizeof(int32_t), hipMemcpyDeviceToHost, stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) return done(fail(FS_ERR_HIP, std::string("graph build: ") + hipGetErrorString(e)));
-  g.max_cdeg = (uint32_t)sizes[kScalarMaxCdeg];
+  g.heavy.assign(tail.begin() + kScalarWords, tail.end());
+  g.max_cdeg = (uint32_t)tail[kScalarMaxCdeg];
   return done(FS_OK);
 }
 
@@ -592,7 +687,7 @@ fs_status fs_graph_build(const fs_graph_params *params, hipStream_t stream, fs_g
   if (params->flags & FS_GRAPH_ON_DEVICE) {
     const fs_status st = build_device_graph(*params, stream, *g);
     if (st != FS_OK) {
-      if (g->d_base) (void)hipFree(g->d_base);
+      free_graph_memory(*g);
       delete g;
       return st;
     }
@@ -712,7 +807,7 @@ fs_status fs_graph_export(const fs_graph *g, int32_t *row_ptr, int32_t *col, int
 
 void fs_graph_free(fs_graph *g) {
   if (!g) return;
-  if (g->d_base) hipFree(g->d_base);
+  free_graph_memory(*g);
   delete g;
 }
 

@@ -30,6 +30,7 @@ struct fs_graph {
                               // above are empty, except heavy)
   int device = -1;
   void *d_base = nullptr;
+  bool pooled = false;        // d_base came from the graph memory pool
   const int32_t *d_row_ptr = nullptr, *d_col = nullptr, *d_col_ptr = nullptr,
                 *d_rowidx = nullptr;
   const int32_t *d_seg_ptr = nullptr, *d_seg_row = nullptr, *d_seg_col = nullptr, *d_heavy = nullptr;
@@ -443,29 +444,45 @@ void graph_image(const fs_graph &g, GraphImage &img);
 void graph_image_sized(uint32_t k, uint32_t n, uint64_t nnz, uint32_t nseg, uint32_t nheavy, GraphImage &img);
 
 // ---- device graph construction (graph_dev.hip) ----
-enum { kScalarMaxDeg = 0, kScalarSegs = 1, kScalarHeavy = 2, kScalarMaxCdeg = 3, kScalarCount = 4 };
+enum {
+  kScalarMaxDeg = 0,
+  kScalarSegs = 1,
+  kScalarHeavy = 2,
+  kScalarMaxCdeg = 3,
+  kScalarMidCols = 4,    // columns of 65 .. 1024 rows
+  kScalarLongCols = 5,   // longer columns
+  kScalarCount = 6,
+  kScalarWords = 8       // the scalars, then the 64-bit edge count
+};
 struct DevGraphJob {
   uint32_t k, n, D;
+  uint32_t nnz;            // known once the degrees are
   uint64_t seed, stripe_key;
   // scratch
   const uint64_t *T;       // degree thresholds (D)
   int32_t *deg;            // degree of each row (n)
   uint32_t *blk_hist;      // per block of rows: segment bucket counts, then offsets
-  int32_t *scalars;        // kScalar*
+  uint32_t *blk_max, *blk_sum;   // per block of rows: largest degree, degree sum
+  int32_t *bucket;         // per segment bucket: first segment, then first edge
+  int32_t *scalars;        // kScalar*, the edge count, then the heavy rows
   unsigned long long *edges;   // sum of the degrees (nnz) in 64 bits
   uint32_t *sums;          // scan block sums
   int32_t *ccnt, *cfill;   // column counts and fill cursors (k)
   int32_t *seg_len, *seg_beg;   // per segment: edges and first edge (nseg)
+  int32_t *unsorted;       // each column's rows before its sort (nnz)
+  int32_t *col_list;       // columns of more than 64 rows (k)
+  const int32_t *row_src;  // row_ptr as the degree pass left it (n + 1)
   // the graph image
   int32_t *row_ptr, *col, *col_ptr, *rowidx, *seg_ptr, *seg_row, *heavy, *seg_col;
   uint8_t *seg_atomic;
 };
-// scratch before the sizes are known: T, deg, a row_ptr copy, block
-// histograms, scalars and scan sums for n and k elements
-void dev_graph_carve(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n, uint32_t D);
-// scratch once the segment count is known: seg_len, seg_beg and scan sums
-// for max(n, k, nseg) elements
-void dev_graph_carve_rows(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n, uint32_t nseg);
+// scratch before the sizes are known: deg, a row_ptr copy, block
+// histograms and totals, bucket starts, scalars (with room for n heavy rows)
+// and scan sums for n and k elements (T is set apart)
+void dev_graph_carve(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n);
+// scratch once the sizes are known: seg_len, seg_beg, the unsorted columns,
+// the long-column list and scan sums for max(n, k) elements
+void dev_graph_carve_rows(Carver &cv, DevGraphJob &J, uint32_t k, uint32_t n, uint32_t nseg, uint64_t nnz);
 // degrees, row_ptr, segment and heavy-row counts (scalars)
 fs_status launch_dev_graph_degrees(const DevGraphJob &J, hipStream_t s);
 // neighbours, segments, heavy rows and the transpose (scalars: max_cdeg)

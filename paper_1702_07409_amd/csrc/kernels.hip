@@ -1796,6 +1796,9 @@ fs_status launch_gather(const GatherJob &job, const fs_tune &tune, hipStream_t s
   (void)hipGetDevice(&dev);
   const int cu = device_info(dev).cu_count;
   switch (tune.lanes_per_row * 10 + tune.chunks) {
+    case 81: e = run_gather_nt<8, 1>(job, tune, s, cu); break;
+    case 82: e = run_gather_nt<8, 2>(job, tune, s, cu); break;
+    case 84: e = run_gather_nt<8, 4>(job, tune, s, cu); break;
     case 161: e = run_gather_nt<16, 1>(job, tune, s, cu); break;
     case 162: e = run_gather_nt<16, 2>(job, tune, s, cu); break;
     case 164: e = run_gather_nt<16, 4>(job, tune, s, cu); break;
@@ -2212,6 +2215,9 @@ fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long 
   const bool nt = tune.nt_store != 0;
   hipError_t e;
   switch (tune.lanes_per_row * 10 + tune.chunks) {
+    case 81: e = run_gather_batch<8, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 82: e = run_gather_batch<8, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
+    case 84: e = run_gather_batch<8, 4>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
     case 161: e = run_gather_batch<16, 1>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
     case 162: e = run_gather_batch<16, 2>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;
     case 164: e = run_gather_batch<16, 4>(d_jobs, d_prefix, njobs, d_counter, nt, grid, chunk, s); break;

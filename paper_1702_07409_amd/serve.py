@@ -23,6 +23,13 @@ its own; the call returns with the graph complete), or, with device builds
 off, on the host, the device copy then being made on the stream of the tick
 that first uses it, other streams waiting for that copy.
 
+The loop and the build threads share the interpreter lock: the loop polls
+without blocking, and a thread that waits for the lock gets it only when
+the holder has run for the interpreter's switch interval (5 ms by default).
+run() therefore shortens the switch interval (switch_interval, 50 us) for
+its duration, so that a build starts and finishes without waiting on the
+loop.
+
 Resident stripes (inputs x and coded blocks c kept on the device) are the
 targets of decode, repair (from the resident inputs) and update.  Requests on
 one stripe run one at a time in arrival order.
@@ -31,6 +38,7 @@ Everything on the device runs in libfs.so; this module only schedules.
 """
 
 import collections
+import sys
 import threading
 import time
 from concurrent.futures import ThreadPoolExecutor
@@ -272,8 +280,10 @@ class Server:
     """
 
     def __init__(self, budget=32 << 30, streams=3, max_inflight=4, max_items=64, workers=8,
-                 graph_cache_bytes=4 << 30, keep_outputs=False, device="cuda", device_graph_builds=True):
+                 graph_cache_bytes=4 << 30, keep_outputs=False, device="cuda", device_graph_builds=True,
+                 switch_interval=50e-6):
         self.device = torch.device(device)
+        self.switch_interval = switch_interval
         self.budget = budget
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.next_stream = 0
@@ -451,7 +461,18 @@ class Server:
     def run(self, requests, time_scale=1.0):
         """Serve `requests` (sorted by .arrival, seconds from the start);
         each is submitted once the wall clock passes its arrival time scaled
-        by time_scale.  Returns the statistics of the run."""
+        by time_scale.  Returns the statistics of the run.  The interpreter's
+        thread switch interval is switch_interval while it runs (None: left
+        as it is)."""
+        prev = sys.getswitchinterval()
+        if self.switch_interval:
+            sys.setswitchinterval(self.switch_interval)
+        try:
+            return self._run(requests, time_scale)
+        finally:
+            sys.setswitchinterval(prev)
+
+    def _run(self, requests, time_scale):
         torch.cuda.synchronize(self.device)
         self.ref = torch.cuda.Event(enable_timing=True)
         self.ref.record(self.streams[0])

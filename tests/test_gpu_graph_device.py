@@ -34,6 +34,15 @@ CASES = {
     "rsd_heavy": dict(k=8192, n=8847, dist="rsd", rsd_c=0.05, rsd_delta=0.01, seed=1, stripe_key=11),
     "raptor": dict(k=10246, n=21800, dist="raptor", seed=SEED),
     "rsd_16k": dict(k=16384, n=18022, dist="rsd", seed=7, stripe_key=3),
+    # rows of k - 8 of k neighbours: Floyd batches full of fallback chains
+    "nearly_full_rows": dict(k=2048, n=6, dist="finite", finite_w=(0,) * 2039 + (1.0,), seed=5),
+    "full_rows_16k": dict(k=16384, n=3, dist="finite", finite_w=(0,) * 15999 + (1.0,), seed=6),
+    # columns of ~31 and ~62 rows: one-wave column sorts, and columns of 65 and more rows
+    "columns_31": dict(k=2048, n=8000, dist="finite", finite_w=(0,) * 7 + (1.0,), seed=7),
+    "columns_62": dict(k=512, n=4000, dist="finite", finite_w=(0,) * 7 + (1.0,), seed=8),
+    # columns of thousands of rows, then of more rows than one LDS bitmap covers
+    "long_columns": dict(k=16, n=5000, dist="finite", finite_w=(0,) * 7 + (1.0,), seed=9),
+    "long_columns_two_passes": dict(k=8, n=600000, dist="finite", finite_w=(0, 0, 0, 1.0), seed=10),
 }
 
 
@@ -47,7 +56,7 @@ def test_device_graph_equals_host_and_oracle(case):
         (gh.k, gh.n, gh.nnz, gh.max_degree, gh.max_column_degree)
     for a, b in zip(gd.export(), gh.export()):
         assert np.array_equal(a, b)
-    if kw["k"] <= 4096:
+    if kw["k"] <= 4096 and kw["n"] <= 30000:
         G = graph.build(graph.GraphParams(**kw))
         rp, col, cp, ri = gd.export()
         assert np.array_equal(rp, G.row_ptr) and np.array_equal(col, G.col)
