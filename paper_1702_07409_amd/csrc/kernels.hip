@@ -470,7 +470,8 @@ __device__ __forceinline__ uint32_t words_of(uint32_t k) { return (k + 31) / 32;
 
 struct PeelState {
   unsigned long long *acc, *best;
-  uint32_t *acc32;    // packed row state (kPeelLdsRows32, kPeelLds16)
+  uint32_t *acc32;    // packed row state (kPeelLdsRows32, kPeelLdsRows32B, kPeelLds16)
+  uint32_t *best32;   // decoding row per input as degree << 24 | row (kPeelLdsRows32B), else null
   int32_t *fa, *fb, *dl;
   uint16_t *fa16, *fb16, *dl16, *ridx;   // kPeelLds16: 16-bit frontiers, list and column rows
   uint32_t *mask, *decm;
@@ -520,7 +521,7 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
       if (FLIST) {
         J.dp_g[pos] = -1;
       } else {
-        J.dp_g[pos] = (int32_t)(uint32_t)(S.best[f] & 0xffffffffull);
+        J.dp_g[pos] = S.best32 ? (int32_t)(S.best32[f] & 0xffffffu) : (int32_t)(uint32_t)(S.best[f] & 0xffffffffull);
         J.recovered[f] = 1;
       }
       ++pos;
@@ -534,12 +535,21 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
 // only the per-row counters (the one array every edge updates atomically;
 // for stripes whose full state does not fit), kPeelLdsRows32 the counters
 // packed in 32 bits (for stripes whose 64-bit counters do not fit either),
-// kPeelGlobal none of it.
+// kPeelGlobal none of it.  kPeelLdsRows32B keeps, beside the packed
+// counters, the decoding row of each input (32 bits: degree << 24 | row) and
+// the input masks in LDS, so that a level's atomics stay on the CU (for
+// stripes too large for kPeelLds16, such as the k = 10246 code).
 // kPeelLds16 keeps everything in LDS in compact form (k, n <= 65535, degrees
 // <= 127): packed 32-bit counters, 16-bit frontiers and input list, and the
 // graph's column lists as 16-bit row ids, so a level touches no global
 // memory but the schedule it writes.
-constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2, kPeelLdsRows32 = 3, kPeelLds16 = 4;
+constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2, kPeelLdsRows32 = 3, kPeelLds16 = 4,
+              kPeelLdsRows32B = 5;
+
+// LDS of kPeelLdsRows32B: counters (n), best rows (k), input masks (2 x k bits)
+__host__ __device__ inline size_t peel_rows32b_bytes(uint32_t k, uint32_t n) {
+  return 4ull * n + 4ull * k + 8ull * ((k + 31) / 32);
+}
 
 __host__ __device__ inline size_t peel_lds16_bytes(uint32_t k, uint32_t n, uint64_t nnz) {
   const size_t kw = (k + 31) / 32;
@@ -557,7 +567,8 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
   const uint32_t k = J.k, n = J.n, kw = words_of(k);
   const int tid = threadIdx.x;
   const int wid = tid >> 6;
-  constexpr bool PACKED = MODE == kPeelLdsRows32 || MODE == kPeelLds16;   // 32-bit counters
+  constexpr bool PACKED = MODE == kPeelLdsRows32 || MODE == kPeelLds16 || MODE == kPeelLdsRows32B;   // 32-bit counters
+  constexpr bool BEST32 = MODE == kPeelLdsRows32B;                         // 32-bit best rows in LDS
   constexpr bool ALL = MODE == kPeelLds || MODE == kPeelLds16;             // degrees, column pointers in LDS
   constexpr bool SHORT = MODE == kPeelLds16;                               // 16-bit lists
   PeelState S;
@@ -574,6 +585,18 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.deg = reinterpret_cast<uint16_t *>(p); p += 2ull * n;
     S.ridx = reinterpret_cast<uint16_t *>(p);
     S.acc = nullptr; S.fa = S.fb = S.dl = nullptr;
+    S.best32 = nullptr;
+  } else if constexpr (MODE == kPeelLdsRows32B) {
+    unsigned char *p = smem;
+    S.acc32 = reinterpret_cast<uint32_t *>(p); p += 4ull * n;
+    S.best32 = reinterpret_cast<uint32_t *>(p); p += 4ull * k;
+    S.mask = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
+    S.decm = reinterpret_cast<uint32_t *>(p);
+    S.acc = nullptr; S.best = nullptr;
+    S.fa = J.front_a; S.fb = J.front_b; S.dl = J.dlist;
+    S.fa16 = S.fb16 = S.dl16 = S.ridx = nullptr;
+    S.cptr = const_cast<int32_t *>(J.col_ptr);
+    S.deg = nullptr;
   } else if constexpr (MODE == kPeelLds) {
     unsigned char *p = smem;
     S.acc = reinterpret_cast<unsigned long long *>(p); p += 8ull * n;
@@ -585,6 +608,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.decm = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
     S.cptr = reinterpret_cast<int32_t *>(p); p += 4ull * (k + 1);
     S.deg = reinterpret_cast<uint16_t *>(p);
+    S.best32 = nullptr;
   } else {
     S.acc = MODE == kPeelLdsRows ? reinterpret_cast<unsigned long long *>(smem) : J.acc;
     S.acc32 = MODE == kPeelLdsRows32 ? reinterpret_cast<uint32_t *>(smem) : nullptr;
@@ -592,9 +616,13 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.mask = J.mask; S.decm = J.decmask;
     S.cptr = const_cast<int32_t *>(J.col_ptr);
     S.deg = nullptr;
+    S.best32 = nullptr;
   }
   for (uint32_t f = tid; f < k; f += kPeelThreads) {
-    S.best[f] = ~0ull;
+    if constexpr (BEST32)
+      S.best32[f] = ~0u;
+    else
+      S.best[f] = ~0ull;
     J.recovered[f] = 0;
   }
   for (uint32_t w = tid; w < kw; w += kPeelThreads) {
@@ -705,7 +733,10 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
         d = S.deg[g];
       else
         d = (uint32_t)(J.row_ptr[g + 1] - J.row_ptr[g]);
-      atomicMin(&S.best[f], ((unsigned long long)d << 32) | (uint32_t)g);
+      if constexpr (BEST32)
+        atomicMin(&S.best32[f], (d << 24) | (uint32_t)g);
+      else
+        atomicMin(&S.best[f], ((unsigned long long)d << 32) | (uint32_t)g);
       const uint32_t bit = 1u << (f & 31);
       const uint32_t old = atomicOr(&S.mask[f >> 5], bit);
       if (!(old & bit)) {
@@ -1864,7 +1895,7 @@ int peel_mode(uint32_t k, uint32_t n, uint32_t max_deg) {
   if (max_deg < 65536 && peel_lds_bytes(k, n) <= budget) return kPeelLds;
   if (8ull * n <= budget) return kPeelLdsRows;
   if (4ull * n <= budget && max_deg <= 127 && (uint64_t)max_deg * (k ? k - 1 : 0) < (1ull << 24))
-    return kPeelLdsRows32;
+    return peel_rows32b_bytes(k, n) <= budget && n < (1u << 24) ? kPeelLdsRows32B : kPeelLdsRows32;
   return kPeelGlobal;
 }
 
@@ -1943,6 +1974,11 @@ fs_status launch_peel(const PeelJob &job_in, hipStream_t s, uint32_t max_deg) {
       static bool done[64] = {false};
       set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLdsRows>), dev, budget - (int)static_lds, done);
       hipLaunchKernelGGL(peel_kernel<kPeelLdsRows>, dim3(1), dim3(kPeelThreads), 8ull * job.n, s, job);
+    } else if (mode == kPeelLdsRows32B) {
+      static bool done[64] = {false};
+      set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLdsRows32B>), dev, budget - (int)static_lds, done);
+      hipLaunchKernelGGL(peel_kernel<kPeelLdsRows32B>, dim3(1), dim3(kPeelThreads), peel_rows32b_bytes(job.k, job.n),
+                         s, job);
     } else if (mode == kPeelLdsRows32) {
       static bool done[64] = {false};
       set_max_lds(reinterpret_cast<const void *>(&peel_kernel<kPeelLdsRows32>), dev, budget - (int)static_lds, done);

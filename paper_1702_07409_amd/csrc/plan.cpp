@@ -254,7 +254,8 @@ void build_descriptors(fs_plan &P) {
         } else if (mode == 1) {
           P.peel_rows_bytes = std::max<size_t>(P.peel_rows_bytes, 8ull * g->n);
           P.peels_rows.push_back(pj);
-        } else if (mode == 3) {
+        } else if (mode == 3 || mode == 5) {
+          // (the batched peel keeps only the packed counters in LDS)
           P.peel_rows32_bytes = std::max<size_t>(P.peel_rows32_bytes, 4ull * g->n);
           P.peels_rows32.push_back(pj);
         } else {

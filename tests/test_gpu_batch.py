@@ -165,10 +165,11 @@ def test_plan_autotune_and_cache():
         b2.verify()
 
 
-@pytest.mark.parametrize("lpr,ch", [(128, 1), (128, 2), (256, 1), (256, 2)])
-def test_row_wide_tilings(lpr, ch):
-    # one or two rows per workgroup: plans (encode, repair, the update's
-    # accumulate pass) and a single-stripe encode with a ragged block
+@pytest.mark.parametrize("lpr,ch", [(8, 1), (8, 2), (8, 4), (128, 1), (128, 2), (256, 1), (256, 2)])
+def test_narrow_and_row_wide_tilings(lpr, ch):
+    # 8 lanes per row (128-512 byte slices), and one or two rows per
+    # workgroup: plans (encode, repair, the update's accumulate pass) and a
+    # single-stripe encode with a ragged block
     import paper_1702_07409_amd as fs
     fs.fs_set_tune(lpr, ch, 1, 1)
     try:

@@ -256,7 +256,8 @@ def test_peel_state_beyond_lds_uses_workspace(k, n, dist):
     # k = 16384: the full peel state does not fit LDS, its per-row counters
     # (8 n bytes) do; n = 22000 Robust Soliton: not even those, everything
     # stays in the workspace; n = 21800 and 32000 with degrees <= 65 or 16:
-    # the counters fit packed in 32 bits
+    # the counters fit packed in 32 bits, and at n = 21800 the decoding row
+    # of each input and the input masks as well
     w = workloads.finite16_weights() if dist == "finite" else ()
     sp = workloads.StripeSpec(stripe=0, k=k, n=n, t=16, dist=dist, finite_w=w, stripe_key=1,
                               n_erased=round(0.05 * n))
