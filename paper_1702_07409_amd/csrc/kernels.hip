@@ -472,7 +472,6 @@ struct PeelState {
   unsigned long long *acc, *best;
   uint32_t *acc32;    // packed row state (kPeelLdsRows32, kPeelLdsRows32B, kPeelLds16)
   uint32_t *best32;   // decoding row per input as degree << 24 | row (kPeelLdsRows32B), else null
-  uint8_t *deg8;      // row degrees (kPeelLdsRows32B)
   int32_t *fa, *fb, *dl;
   uint16_t *fa16, *fb16, *dl16, *ridx;   // kPeelLds16: 16-bit frontiers, list and column rows
   uint32_t *mask, *decm;
@@ -537,9 +536,8 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
 // for stripes whose full state does not fit), kPeelLdsRows32 the counters
 // packed in 32 bits (for stripes whose 64-bit counters do not fit either),
 // kPeelGlobal none of it.  kPeelLdsRows32B keeps, beside the packed
-// counters, the decoding row of each input (32 bits: degree << 24 | row),
-// the input masks and the row degrees (8 bits) in LDS, so that a level's
-// atomics stay on the CU and its frontier rows need no degree lookups (for
+// counters, the decoding row of each input (32 bits: degree << 24 | row) and
+// the input masks in LDS, so that a level's atomics stay on the CU (for
 // stripes too large for kPeelLds16, such as the k = 10246 code).
 // kPeelLds16 keeps everything in LDS in compact form (k, n <= 65535, degrees
 // <= 127): packed 32-bit counters, 16-bit frontiers and input list, and the
@@ -548,10 +546,9 @@ __device__ __forceinline__ uint32_t wave0_list(const PeelState &S, const PeelJob
 constexpr int kPeelGlobal = 0, kPeelLdsRows = 1, kPeelLds = 2, kPeelLdsRows32 = 3, kPeelLds16 = 4,
               kPeelLdsRows32B = 5;
 
-// LDS of kPeelLdsRows32B: counters (n), best rows (k), input masks (2 x k
-// bits), row degrees (n bytes)
+// LDS of kPeelLdsRows32B: counters (n), best rows (k), input masks (2 x k bits)
 __host__ __device__ inline size_t peel_rows32b_bytes(uint32_t k, uint32_t n) {
-  return 4ull * n + 4ull * k + 8ull * ((k + 31) / 32) + n;
+  return 4ull * n + 4ull * k + 8ull * ((k + 31) / 32);
 }
 
 __host__ __device__ inline size_t peel_lds16_bytes(uint32_t k, uint32_t n, uint64_t nnz) {
@@ -594,8 +591,7 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     S.acc32 = reinterpret_cast<uint32_t *>(p); p += 4ull * n;
     S.best32 = reinterpret_cast<uint32_t *>(p); p += 4ull * k;
     S.mask = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
-    S.decm = reinterpret_cast<uint32_t *>(p); p += 4ull * kw;
-    S.deg8 = reinterpret_cast<uint8_t *>(p);
+    S.decm = reinterpret_cast<uint32_t *>(p);
     S.acc = nullptr; S.best = nullptr;
     S.fa = J.front_a; S.fb = J.front_b; S.dl = J.dlist;
     S.fa16 = S.fb16 = S.dl16 = S.ridx = nullptr;
@@ -628,9 +624,6 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
     else
       S.best[f] = ~0ull;
     J.recovered[f] = 0;
-  }
-  if constexpr (BEST32) {
-    for (uint32_t g = tid; g < n; g += kPeelThreads) S.deg8[g] = (uint8_t)(J.row_ptr[g + 1] - J.row_ptr[g]);
   }
   for (uint32_t w = tid; w < kw; w += kPeelThreads) {
     S.mask[w] = 0;
@@ -738,8 +731,6 @@ __device__ __forceinline__ void peel_body(const PeelJob &J) {
       uint32_t d;
       if constexpr (ALL)
         d = S.deg[g];
-      else if constexpr (BEST32)
-        d = S.deg8[g];
       else
         d = (uint32_t)(J.row_ptr[g + 1] - J.row_ptr[g]);
       if constexpr (BEST32)
