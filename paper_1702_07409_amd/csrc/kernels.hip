@@ -955,9 +955,8 @@ __global__ __launch_bounds__(kPlanThreads) void prog_build_kernel(ProgJob P) { p
 //   1. decoding maps cleared, each pair's count of other inputs into poff;
 //   2. poff scanned in place (entries past the pairs are 0);
 //   3. per pair, its other inputs copied to pidx, gsrc and finv set;
-//   4. the decoding rows listed ascending (gl, fl) by a count per block of
-//      rows, a scan of the counts and ranks within each block;
-//   5. meta.
+//   4. the decoding rows listed ascending (gl, fl) by one workgroup with a
+//      running count, and meta.
 // The result is prog_body's, entry for entry.
 __device__ __forceinline__ int prog_pairs(const ProgJob &P) {
   return min(max((int)P.k - P.status[1], 0), (int)P.k);
@@ -992,49 +991,63 @@ __global__ __launch_bounds__(256) void prog_wide_fill_kernel(ProgJob P) {
   if ((uint32_t)P.poff[nR] > P.pidx_cap) return;   // does not fit: the program is marked unusable
   int32_t o = P.poff[p];
   const int32_t end = P.poff[p + 1];
-  for (int e = P.row_ptr[g]; e < P.row_ptr[g + 1] && o < end; ++e) {
-    const int32_t c = P.col[e];
-    if (c != f) P.pidx[o++] = c;
+  const int e1 = P.row_ptr[g + 1];
+  // the row's entries eight at a time, loaded before any is stored (the
+  // longest rows set the launch's time)
+  for (int e = P.row_ptr[g]; e < e1 && o < end; e += 8) {
+    int32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = e + u < e1 ? P.col[e + u] : f;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (c[u] != f && o < end) P.pidx[o++] = c[u];
   }
 }
 
-__global__ __launch_bounds__(1024) void prog_wide_rows_count_kernel(ProgJob P) {
-  __shared__ uint32_t sh[1024 / 64 + 1];
-  if (P.skip_flag && *P.skip_flag) return;
-  const uint32_t g = blockIdx.x * 1024u + threadIdx.x;
-  uint32_t total = 0;
-  (void)scan_block<1024>(g < P.n && P.finv[g] >= 0 ? 1u : 0u, sh, total);
-  if (threadIdx.x == 0) P.psums[blockIdx.x] = total;
-}
+// The decoding rows ascending (gl, fl) in one workgroup: chunks of 16 rows
+// per thread with a running count, then meta.
+constexpr int kRowsItems = 16;
 
-__global__ __launch_bounds__(1024) void prog_wide_rows_place_kernel(ProgJob P) {
+__global__ __launch_bounds__(1024) void prog_wide_rows_kernel(ProgJob P) {
   __shared__ uint32_t sh[1024 / 64 + 1];
-  if (P.skip_flag && *P.skip_flag) return;
-  const uint32_t g = blockIdx.x * 1024u + threadIdx.x;
-  const int32_t f = g < P.n ? P.finv[g] : -1;
-  uint32_t total = 0;
-  const uint32_t pos = P.psums[blockIdx.x] + scan_block<1024>(f >= 0 ? 1u : 0u, sh, total);
-  if (f >= 0 && pos < P.k) {
-    P.gl[pos] = (int32_t)g;
-    P.fl[pos] = f;
-  }
-}
-
-__global__ void prog_wide_meta_kernel(ProgJob P, uint32_t nblk) {
-  if (threadIdx.x != 0) return;
   if (P.skip_flag && *P.skip_flag) {
-    P.meta[3] = 0;
+    if (threadIdx.x == 0) P.meta[3] = 0;
     return;
   }
-  const int nR = prog_pairs(P);
-  const int L = min(max(P.status[2], 0), (int)P.k);
-  const uint32_t total = (uint32_t)P.poff[nR];
-  const uint32_t nused = (uint32_t)P.psums[nblk];
-  P.poff[nR] = (int32_t)total;
-  P.meta[0] = nR;
-  P.meta[1] = L;
-  P.meta[2] = (int32_t)total;
-  P.meta[3] = total <= P.pidx_cap && nused == (uint32_t)nR ? 1 : 0;
+  constexpr uint32_t kChunk = 1024u * kRowsItems;
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < P.n; c0 += kChunk) {
+    const uint32_t base = c0 + threadIdx.x * kRowsItems;
+    int32_t f[kRowsItems];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int i = 0; i < kRowsItems; ++i) {
+      f[i] = base + i < P.n ? P.finv[base + i] : -1;
+      cnt += f[i] >= 0 ? 1u : 0u;
+    }
+    uint32_t total = 0;
+    uint32_t pos = carry + scan_block<1024>(cnt, sh, total);
+#pragma unroll
+    for (int i = 0; i < kRowsItems; ++i) {
+      if (f[i] < 0) continue;
+      if (pos < P.k) {
+        P.gl[pos] = (int32_t)(base + i);
+        P.fl[pos] = f[i];
+      }
+      ++pos;
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) {
+    const int nR = prog_pairs(P);
+    const int L = min(max(P.status[2], 0), (int)P.k);
+    const uint32_t total = (uint32_t)P.poff[nR];
+    P.poff[nR] = (int32_t)total;
+    P.meta[0] = nR;
+    P.meta[1] = L;
+    P.meta[2] = (int32_t)total;
+    P.meta[3] = total <= P.pidx_cap && carry == (uint32_t)nR ? 1 : 0;
+  }
 }
 
 fs_status launch_prog_wide(const ProgJob &P, hipStream_t s) {
@@ -1043,11 +1056,7 @@ fs_status launch_prog_wide(const ProgJob &P, hipStream_t s) {
   const fs_status st = scan_i32(P.poff, P.k, P.psums, P.poff, s);
   if (st != FS_OK) return st;
   hipLaunchKernelGGL(prog_wide_fill_kernel, dim3((P.k + 255) / 256), dim3(256), 0, s, P);
-  const uint32_t nblk = (P.n + 1023) / 1024;
-  hipLaunchKernelGGL(prog_wide_rows_count_kernel, dim3(nblk), dim3(1024), 0, s, P);
-  hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(1024), 0, s, P.psums, nblk, (int32_t *)(P.psums + nblk));
-  hipLaunchKernelGGL(prog_wide_rows_place_kernel, dim3(nblk), dim3(1024), 0, s, P);
-  hipLaunchKernelGGL(prog_wide_meta_kernel, dim3(1), dim3(64), 0, s, P, nblk);
+  hipLaunchKernelGGL(prog_wide_rows_kernel, dim3(1), dim3(1024), 0, s, P);
   const hipError_t e = hipGetLastError();
   return e == hipSuccess ? FS_OK : fail(FS_ERR_HIP, std::string("program launch: ") + hipGetErrorString(e));
 }
@@ -1941,6 +1950,23 @@ __global__ __launch_bounds__(256) void peel_init_rows_kernel(PeelJob J) {
   J.acc[g] = J.erased[g] ? kErasedAcc : ((unsigned long long)d << 40);
 }
 
+// rows of bounded degree: the sum of the row's ids read from the CSR, eight
+// entries at a time, in the same launch
+__global__ __launch_bounds__(256) void peel_init_rowsum_kernel(PeelJob J) {
+  const uint32_t g = blockIdx.x * 256u + threadIdx.x;
+  if (g >= J.n) return;
+  const int e0 = J.row_ptr[g], e1 = J.row_ptr[g + 1];
+  unsigned long long sum = 0;
+  for (int e = e0; e < e1; e += 8) {
+    int32_t c[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) c[u] = e + u < e1 ? J.col[e + u] : 0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += (uint32_t)c[u];
+  }
+  J.acc[g] = (J.erased[g] ? kErasedAcc : ((unsigned long long)(e1 - e0) << 40)) + sum;
+}
+
 __global__ __launch_bounds__(256) void peel_init_cols_kernel(PeelJob J) {
   const uint32_t i = blockIdx.x * 256u + threadIdx.x;
   if (i >= J.k) return;
@@ -1967,8 +1993,12 @@ fs_status launch_peel(const PeelJob &job_in, hipStream_t s, uint32_t max_deg) {
     hipLaunchKernelGGL(peel_kernel<kPeelLds>, dim3(1), dim3(kPeelThreads), lds, s, job);
   } else {
     if (!job.acc) return fail(FS_ERR_WORKSPACE, "peel state needs the workspace");
-    if (job.n) hipLaunchKernelGGL(peel_init_rows_kernel, dim3((job.n + 255) / 256), dim3(256), 0, s, job);
-    if (job.k) hipLaunchKernelGGL(peel_init_cols_kernel, dim3((job.k + 255) / 256), dim3(256), 0, s, job);
+    if (max_deg <= 128) {
+      if (job.n) hipLaunchKernelGGL(peel_init_rowsum_kernel, dim3((job.n + 255) / 256), dim3(256), 0, s, job);
+    } else {
+      if (job.n) hipLaunchKernelGGL(peel_init_rows_kernel, dim3((job.n + 255) / 256), dim3(256), 0, s, job);
+      if (job.k) hipLaunchKernelGGL(peel_init_cols_kernel, dim3((job.k + 255) / 256), dim3(256), 0, s, job);
+    }
     job.acc_ready = 1;
     if (mode == kPeelLdsRows) {
       static bool done[64] = {false};
