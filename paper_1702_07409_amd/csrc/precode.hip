@@ -48,13 +48,15 @@ __global__ __launch_bounds__(kPcThreads) void precode_peel_kernel(PrecodePeelJob
     s_missing = 0;
     s_tail = 0;
   }
-  for (uint32_t w = tid; w < kw; w += nt) {
-    uint32_t bits = 0;
-    for (uint32_t i = 0; i < 32; ++i) {
-      const uint32_t s = 32 * w + i;
-      if (s < J.k && J.recovered[s]) bits |= 1u << i;
+  // the recovered flags as a bitmap: a wave reads 64 consecutive flags and
+  // ballots them into two words (blockDim is a multiple of 64)
+  for (uint32_t s0 = (tid & ~63u) * 1u; s0 < 32 * kw; s0 += nt) {
+    const uint32_t s = s0 + (tid & 63);
+    const uint64_t m = __ballot(s < J.k && J.recovered[s] != 0);
+    if ((tid & 63) == 0) {
+      known[s0 >> 5] = (uint32_t)m;
+      if ((s0 >> 5) + 1 < kw) known[(s0 >> 5) + 1] = (uint32_t)(m >> 32);
     }
-    known[w] = bits;
   }
   __syncthreads();
   uint32_t miss = 0;
@@ -66,11 +68,20 @@ __global__ __launch_bounds__(kPcThreads) void precode_peel_kernel(PrecodePeelJob
     // the second pass runs only when data blocks are still missing
     for (uint32_t r = tid; r < J.m; r += nt) {
       uint32_t c = 0, x = 0;
-      for (int32_t e = J.chk_ptr[r]; e < J.chk_ptr[r + 1]; ++e) {
-        const uint32_t s = (uint32_t)J.chk_col[e];
-        if (!((known[s >> 5] >> (s & 31)) & 1u)) {
-          ++c;
-          x ^= s;
+      const int32_t e1 = J.chk_ptr[r + 1];
+      // the check's entries eight at a time, loaded before any is tested
+      for (int32_t e = J.chk_ptr[r]; e < e1; e += 8) {
+        int32_t sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) sv[u] = e + u < e1 ? J.chk_col[e + u] : -1;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          if (sv[u] < 0) continue;
+          const uint32_t sym = (uint32_t)sv[u];
+          if (!((known[sym >> 5] >> (sym & 31)) & 1u)) {
+            ++c;
+            x ^= sym;
+          }
         }
       }
       cnt[r] = c;
