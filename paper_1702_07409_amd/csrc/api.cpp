@@ -164,6 +164,19 @@ void carve_sched(Carver &cv, uint32_t k, SchedBufs &s, bool with_recovered) {
 void carve_repair(Carver &cv, const fs_graph *g, uint64_t t, bool conventional, RepairBufs &b) {
   b.seen = cv.take<uint32_t>((g->n + 31) / 32);
   b.flag = cv.take<int32_t>(4);
+  b.sptr = b.sidx = b.roff = b.sout = b.nseg = nullptr;
+  b.satomic = nullptr;
+  b.seg_cap = 0;
+  if (!conventional && g->max_deg > kSegMax) {
+    // every row of the graph in pieces of at most 64 edges: its encode segments
+    b.seg_cap = std::max<uint32_t>(g->nseg, 1);
+    b.sptr = cv.take<int32_t>((size_t)b.seg_cap + 1);
+    b.sidx = cv.take<int32_t>(std::max<uint64_t>(g->nnz, 1));
+    b.roff = cv.take<int32_t>(g->n);
+    b.sout = cv.take<int32_t>(b.seg_cap);
+    b.satomic = cv.take<uint8_t>(b.seg_cap);
+    b.nseg = cv.take<int32_t>(1);
+  }
   b.erased2 = nullptr;
   b.x = nullptr;
   b.sched = SchedBufs{};
@@ -610,6 +623,42 @@ fs_status build_device_graph(const fs_graph_params &p, hipStream_t stream, fs_gr
   return done(FS_OK);
 }
 
+void repair_pieces_prep(RepairPrepJob &pj, const fs_graph *g, const RepairBufs &b, void *c, uint64_t t) {
+  pj.row_ptr = g->d_row_ptr;
+  pj.col = g->d_col;
+  pj.sptr = b.sptr;
+  pj.sidx = b.sidx;
+  pj.roff = b.roff;
+  pj.sout = b.sout;
+  pj.satomic = b.satomic;
+  pj.nseg = b.nseg;
+  pj.seg_cap = b.seg_cap;
+  pj.c = static_cast<uint8_t *>(c);
+  pj.t = t;
+}
+
+GatherJob repair_pieces_job(const fs_graph *g, const RepairBufs &b, uint32_t n_lost, const void *x, void *c,
+                            uint64_t t) {
+  GatherJob gj{};
+  gj.src = static_cast<const uint8_t *>(x);
+  gj.src_stride = t;
+  gj.dst = static_cast<uint8_t *>(c);
+  gj.dst_stride = t;
+  gj.ptr = b.sptr;
+  gj.idx = b.sidx;
+  gj.out_map = b.sout;
+  gj.seg_atomic = b.satomic;
+  gj.skip_flag = b.flag;
+  // the pieces are counted on the device; at most n_lost rows of the
+  // largest degree
+  const uint64_t per = ((uint64_t)std::max<uint32_t>(g->max_deg, 1) + kSegMax - 1) / kSegMax;
+  gj.nrows = (uint32_t)std::min<uint64_t>(b.seg_cap, (uint64_t)n_lost * per);
+  gj.nrows_dev = b.nseg;
+  gj.csr_rows = b.seg_cap;
+  gj.t = t;
+  return gj;
+}
+
 fs_launch_info &launch_record() {
   static thread_local fs_launch_info rec = {};
   return rec;
@@ -1046,8 +1095,12 @@ static fs_status repair_impl(const fs_graph *g, const void *x, void *c, const ui
   pj.flag = b.flag;
   pj.repaired = repaired;
   pj.status = status;
+  // graphs with rows of more than 64 edges repair through pieces
+  const bool pieces = !conventional && b.sptr;
+  if (pieces) repair_pieces_prep(pj, g, b, c, t);
   FS_TRY(launch_repair_prep(pj, stream));
   if (n_lost == 0) return FS_OK;
+  if (pieces) return launch_gather(repair_pieces_job(g, b, n_lost, x, c, t), tile_for(current_tune(), g), stream);
 
   GatherJob gj{};
   gj.src_stride = t;

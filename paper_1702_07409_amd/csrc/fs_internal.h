@@ -213,8 +213,30 @@ struct RepairPrepJob {
   int32_t *flag;           // out: 0 ok, FS_ERR_INVALID bad ids
   uint8_t *repaired;       // out: default value
   int32_t *status;         // out
+  // Repair from inputs: the lost rows' edges copied into one compact CSR of
+  // pieces of at most 64 edges for the gather (sptr null: not made).  Rows
+  // of several pieces are zeroed here; their pieces XOR into them
+  // atomically.
+  const int32_t *row_ptr, *col;
+  int32_t *sptr;           // [seg_cap + 1]: first edge of each piece in sidx
+  int32_t *sidx;           // [nnz]: the lost rows' edges, row after row
+  int32_t *roff;           // [n]: first edge of each lost row in sidx
+  int32_t *sout;           // [seg_cap]: row of each piece
+  uint8_t *satomic;        // [seg_cap]: 1 when the row has several pieces
+  int32_t *nseg;           // out: pieces
+  uint32_t seg_cap;
+  uint8_t *c;              // coded blocks (rows of several pieces zeroed)
+  uint64_t t;
 };
 fs_status launch_repair_prep(const RepairPrepJob &job, hipStream_t s);
+struct RepairBufs;
+struct GatherJob;
+// A repair from inputs: the prep job's piece fields, and the gather over the
+// pieces (rows of more than 64 edges no longer hold one workgroup per slice
+// for their whole length).
+void repair_pieces_prep(RepairPrepJob &pj, const struct fs_graph *g, const RepairBufs &b, void *c, uint64_t t);
+GatherJob repair_pieces_job(const struct fs_graph *g, const RepairBufs &b, uint32_t n_lost, const void *x, void *c,
+                            uint64_t t);
 
 // Lost-row list and erasure vector of a code extension: ids[i] = n_old + i
 // for i < n - n_old; erased_full (if non-null) = erased on [0, n_old), 0 above.
@@ -417,6 +439,10 @@ struct DecodeBufs {
 struct RepairBufs {
   uint32_t *seen;
   int32_t *flag;
+  // repair from inputs: the pieces of the lost rows (RepairPrepJob)
+  int32_t *sptr, *sidx, *roff, *sout, *nseg;
+  uint8_t *satomic;
+  uint32_t seg_cap;
   uint8_t *erased2;
   SchedBufs sched;
   PeelJob peel;

@@ -1640,6 +1640,63 @@ __device__ __forceinline__ void repair_prep_body(const RepairPrepJob &J, int def
     J.status[1] = bad ? (int32_t)J.n_lost : 0;
     J.status[2] = bad ? FS_ERR_INVALID : 0;
   }
+  if (!J.sptr) return;
+  // the lost rows' edges, row after row, cut into pieces of at most kSegMax
+  // edges (the ids are valid and distinct here, or the gather is skipped).
+  // A row of at most kSegMax edges is copied by its thread; longer rows by
+  // the whole workgroup, which also zeroes them (their pieces XOR into them).
+  __shared__ uint32_t sh[kPlanThreads / 64 + 1];
+  __shared__ uint32_t s_heavy[kPlanThreads];
+  __shared__ uint32_t s_nheavy;
+  uint32_t carry = 0, ecarry = 0;
+  for (uint32_t m0 = 0; !bad && m0 < J.n_lost; m0 += kPlanThreads) {
+    const uint32_t m = m0 + tid;
+    int32_t e0 = 0, e1 = 0;
+    if (m < J.n_lost) {
+      const uint32_t j = J.lost[m];
+      e0 = J.row_ptr[j];
+      e1 = J.row_ptr[j + 1];
+    }
+    const uint32_t d = (uint32_t)(e1 - e0);
+    const uint32_t pieces = m < J.n_lost ? max(1u, (d + kSegMax - 1) / kSegMax) : 0u;
+    uint32_t total = 0, etotal = 0;
+    const uint32_t first = carry + scan_block<kPlanThreads>(pieces, sh, total);
+    const uint32_t off = ecarry + scan_block<kPlanThreads>(d, sh, etotal);
+    if (tid == 0) s_nheavy = 0;
+    if (m < J.n_lost) {
+      J.roff[m] = (int32_t)off;
+      for (uint32_t p = 0; p < pieces; ++p) {
+        const uint32_t sg = first + p;
+        if (sg >= J.seg_cap) break;
+        J.sptr[sg] = (int32_t)(off + p * kSegMax);
+        J.sout[sg] = (int32_t)J.lost[m];
+        J.satomic[sg] = pieces > 1 ? 1 : 0;
+      }
+      if (d <= kSegMax)
+        for (uint32_t e = 0; e < d; ++e) J.sidx[off + e] = J.col[e0 + (int32_t)e];
+    }
+    __syncthreads();
+    if (m < J.n_lost && d > kSegMax) s_heavy[atomicAdd(&s_nheavy, 1u)] = m;
+    __syncthreads();
+    const uint32_t nh = s_nheavy;
+    for (uint32_t h = 0; h < nh; ++h) {
+      const uint32_t mh = s_heavy[h], j = J.lost[mh];
+      const int32_t h0 = J.row_ptr[j], hd = J.row_ptr[j + 1] - h0;
+      int32_t *dst = J.sidx + J.roff[mh];
+      for (int32_t e = (int32_t)tid; e < hd; e += kPlanThreads) dst[e] = J.col[h0 + e];
+      uint8_t *row = J.c + (uint64_t)j * J.t;
+      for (uint64_t o = (uint64_t)tid * 16; o < J.t; o += (uint64_t)kPlanThreads * 16)
+        *reinterpret_cast<v4u *>(row + o) = v4u{0u, 0u, 0u, 0u};
+    }
+    __syncthreads();
+    carry += total;
+    ecarry += etotal;
+  }
+  if (tid == 0) {
+    const uint32_t ns = min(carry, J.seg_cap);
+    *J.nseg = bad ? 0 : (int32_t)ns;
+    J.sptr[ns] = (int32_t)ecarry;
+  }
 }
 
 __global__ __launch_bounds__(kPlanThreads) void repair_prep_kernel(RepairPrepJob J, int default_ok) {

@@ -37,7 +37,11 @@ DEC = [S(stripe=30, k=64, n=96, t=4096, dist="rsd", stripe_key=30, n_erased=16),
        S(stripe=31, k=500, n=1000, t=512 + 32, dist="rsd", stripe_key=31, n_erased=100),
        S(stripe=32, k=3000, n=3300, t=2048, dist="finite", finite_w=workloads.finite16_weights(),
          stripe_key=32, n_erased=165)]
-REP = [S(stripe=40, k=1024, n=1126, t=4096, dist="rsd", stripe_key=40)]
+# repair stripes and their lost rows: short rows, and rows of hundreds of
+# inputs (cut into 64-edge pieces that XOR into the zeroed row)
+REP = [(S(stripe=40, k=1024, n=1126, t=4096, dist="rsd", stripe_key=40), lambda G: [5, 77, 1100]),
+       (S(stripe=41, k=2000, n=2200, t=1024 + 48, dist="rsd", rsd_c=0.05, rsd_delta=0.01, stripe_key=41),
+        lambda G: [int(j) for j in np.argsort(-G.degrees())[:2]] + [3])]
 UPD = [S(stripe=50, k=1024, n=1126, t=2048, dist="rsd", stripe_key=50)]
 
 
@@ -69,11 +73,11 @@ class Batch:
             self.checks.append(lambda xo=xo, rec=rec, st=st, xw=xw, recw=recw, stw=stw:
                                np.array_equal(host(xo), xw) and np.array_equal(host(rec), recw)
                                and host(st).tolist() == list(stw))
-        for sp in REP:
+        for sp, lost_of in REP:
             g, G = graphs(**sp.graph_kwargs())
             x = gen.payload(data_seed, sp.stripe, sp.k, sp.t)
             c_host = codec.encode(G, x)
-            lost = [5, 77, 1100]
+            lost = lost_of(G)
             c = dev(c_host)
             c[lost] = 0
             rep, st = empty_u8(len(lost)), empty_i32(3)

@@ -461,6 +461,38 @@ def test_repair_from_inputs():
     assert host(rep).tolist() == [1] * len(lost) and host(st).tolist() == [1, 0, 0]
 
 
+@pytest.mark.parametrize("tile", [(0, 0), (16, 2), (256, 1)])
+def test_repair_from_inputs_long_rows(tile):
+    # lost rows of hundreds of inputs are cut into 64-edge pieces that XOR
+    # into the zeroed row (with a row of exactly 64, one of 65 and short ones
+    # beside them); the row-wide and default tilings and a ragged block
+    import paper_1702_07409_amd as fs
+    sp = workloads.StripeSpec(stripe=11, k=2000, n=2200, t=1024 + 48, dist="rsd", rsd_c=0.05, rsd_delta=0.01,
+                              stripe_key=11)
+    g, G = spec_graphs(sp)
+    deg = G.degrees()
+    heavy = [int(j) for j in np.argsort(-deg)[:3]]
+    assert deg[heavy[0]] > 200
+    lost = heavy + [int(j) for j in np.flatnonzero(deg == 1)[:2]]
+    for d in (64, 65, 128):
+        rows = np.flatnonzero(deg == d)
+        if len(rows):
+            lost.append(int(rows[0]))
+    x = sp.x()
+    c_host = codec.encode(G, x)
+    c = dev(c_host)
+    c[lost] = 0x5a
+    rep, st = empty_u8(len(lost)), empty_i32(3)
+    ws = fs.workspace(g, fs.FS_OP_REPAIR, sp.t, len(lost))
+    fs.fs_set_tune(tile[0], tile[1], 1, 1)
+    try:
+        fs.fs_repair(g, dev(x), c, None, dev(np.array(lost, np.uint32)), len(lost), rep, st, sp.t, ws)
+    finally:
+        fs.fs_reset_tune()
+    assert np.array_equal(host(c), c_host)
+    assert host(rep).tolist() == [1] * len(lost) and host(st).tolist() == [1, 0, 0]
+
+
 def test_repair_conventional():
     import paper_1702_07409_amd as fs
     sp = workloads.StripeSpec(stripe=2, k=64, n=96, t=512, dist="rsd", graph_seed=2, n_erased=4)
