@@ -395,7 +395,7 @@ struct ZeroEntry {
 };
 // device arrays of job descriptors; see kernels.hip for the item spaces
 // d_counter: a device word the launch resets and then uses to hand out items
-fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long *d_prefix, uint32_t njobs,
+fs_status launch_gather_batch(const GatherJob *d_jobs, unsigned long long *d_prefix, uint32_t njobs,
                               unsigned long long *d_counter, const fs_tune &tune, uint32_t grid,
                               uint64_t total_items, hipStream_t s);
 // mode: where the peel keeps its state (peel_mode); lds_bytes: dynamic LDS

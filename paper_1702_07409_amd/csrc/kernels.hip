@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_batch_kernel(const Gath
           jcur = jb;
           skip = j.skip_flag && *j.skip_flag;
           nrows = live_rows(j);
-          ntiles = (j.nrows + RPB - 1) / RPB;   // the decomposition uses the bound
+          ntiles = (nrows + RPB - 1) / RPB;   // live rows, as batch_start_kernel counted them
         }
         if (!skip) gather_item<LPR, CH, NT>(j, nrows, ntiles, item - prefix[jb], s_ptr, s_idx);
       }
@@ -281,9 +281,51 @@ __global__ __launch_bounds__(kGatherThreads) void gather_batch_kernel(const Gath
   }
 }
 
-// counter reset for the batched gather (a kernel, so it can sit in a graph):
-// partition x starts at total * x / 8
-__global__ void reset_counter_kernel(unsigned long long *counters, const unsigned long long *prefix, uint32_t njobs) {
+// Start of a batched gather (a kernel, so it can sit in a graph): every
+// job's (slice, tile) item count from its live rows (jobs sized on the
+// device count only their live tiles; skipped jobs none) into prefix, then
+// partition x's counter at total * x / 8.  One workgroup, 1024 jobs a pass.
+__global__ __launch_bounds__(1024) void batch_start_kernel(const GatherJob *jobs, unsigned long long *prefix,
+                                                          uint32_t njobs, unsigned long long *counters, uint32_t rpb,
+                                                          uint32_t w) {
+  __shared__ unsigned long long wsum[16];
+  __shared__ unsigned long long s_carry;
+  const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    s_carry = 0;
+    prefix[0] = 0;
+  }
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < njobs; b0 += 1024) {
+    const uint32_t i = b0 + threadIdx.x;
+    unsigned long long v = 0;
+    if (i < njobs) {
+      const GatherJob &j = jobs[i];
+      uint32_t rows = live_rows(j);
+      if (j.skip_flag && *j.skip_flag) rows = 0;
+      v = (unsigned long long)((j.t + w - 1) / w) * ((rows + rpb - 1) / rpb);
+    }
+    unsigned long long x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const unsigned long long y = __shfl_up(x, o, 64);
+      if ((int)lane >= o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long run = s_carry;
+      for (int q = 0; q < 16; ++q) {
+        const unsigned long long t = wsum[q];
+        wsum[q] = run;
+        run += t;
+      }
+      s_carry = run;
+    }
+    __syncthreads();
+    if (i < njobs) prefix[i + 1] = wsum[wid] + x;
+    __syncthreads();
+  }
   if (threadIdx.x < kXcds) counters[threadIdx.x * kCounterStride] = prefix[njobs] * threadIdx.x / kXcds;
 }
 
@@ -2314,10 +2356,11 @@ fs_status launch_update_delta(const UpdateDeltaJob &job, hipStream_t s) {
 namespace fs {
 
 template <int LPR, int CH>
-static hipError_t run_gather_batch(const GatherJob *jobs, const unsigned long long *prefix, uint32_t njobs,
+static hipError_t run_gather_batch(const GatherJob *jobs, unsigned long long *prefix, uint32_t njobs,
                                    unsigned long long *counter, bool nt, uint32_t grid, uint32_t chunk,
                                    hipStream_t s) {
-  hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(64), 0, s, counter, prefix, njobs);
+  hipLaunchKernelGGL(batch_start_kernel, dim3(1), dim3(1024), 0, s, jobs, prefix, njobs, counter,
+                     (uint32_t)(kGatherThreads / LPR), (uint32_t)(16 * LPR * CH));
   if (nt)
     hipLaunchKernelGGL((gather_batch_kernel<LPR, CH, true>), dim3(grid), dim3(kGatherThreads), 0, s, jobs, prefix,
                        njobs, counter, chunk);
@@ -2327,7 +2370,7 @@ static hipError_t run_gather_batch(const GatherJob *jobs, const unsigned long lo
   return hipGetLastError();
 }
 
-fs_status launch_gather_batch(const GatherJob *d_jobs, const unsigned long long *d_prefix, uint32_t njobs,
+fs_status launch_gather_batch(const GatherJob *d_jobs, unsigned long long *d_prefix, uint32_t njobs,
                               unsigned long long *d_counter, const fs_tune &tune, uint32_t grid,
                               uint64_t total_items, hipStream_t s) {
   if (njobs == 0 || grid == 0) return FS_OK;

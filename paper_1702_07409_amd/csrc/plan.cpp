@@ -556,7 +556,7 @@ fs_status capture(fs_plan &P) {
 std::string shape_key(const fs_plan &P) {
   // the plan's shape: per item op, k, n, nnz, t (arch first)
   std::ostringstream os;
-  os << "gfx950.v2";   // v2: entries carry the claim chunk
+  os << "gfx950.v3";   // v2: entries carry the claim chunk
   uint64_t h = 1469598103934665603ull;
   for (const fs_work &w : P.items) {
     const uint64_t v[5] = {w.op, w.graph->k, w.graph->n, w.graph->nnz, w.t};
@@ -600,8 +600,9 @@ void cache_store(const char *path, const std::string &key, const fs_tune &t) {
 // launches, without the accumulating update jobs) under candidate tunings
 // and keep the fastest:
 //   1. every tiling (lanes per row x chunks), and the per-graph rule (the
-//      persistent kernel at 16 x 2, each large job at its graph's tiling),
-//      with XCD remap and non-temporal stores on: one warm run, one timed;
+//      persistent kernel by its jobs' blocks, each large job at its graph's
+//      tiling), with XCD remap and non-temporal stores on: one warm run,
+//      median of three timed;
 //   2. the three fastest again, median of five timed runs each;
 //   3. the winner with XCD remap off, then with plain stores, then with
 //      claim chunks of 1, 4 and 32 items: each kept when its median of five
@@ -618,6 +619,10 @@ fs_status autotune(fs_plan &P, hipStream_t s) {
   std::vector<GatherJob> tjobs;
   for (size_t i = 0; i < P.gjobs.size(); ++i)
     if (!P.gjob_accumulate[i]) tjobs.push_back(P.gjobs[i]);
+  // the repairs' pieces are counted by their prep kernel: without it the
+  // timed gathers would find no live rows (it writes only the plan's
+  // workspace, the items' status outputs and lost rows of c)
+  PL_TRY(launch_repair_prep_batch(P.d_rpreps, (uint32_t)P.rpreps.size(), s));
   // median time of `reps` timed runs (after one warm run) of the gathers under tuning t
   auto measure = [&](const fs_tune &t, int reps, float &median) -> fs_status {
     const fs_tune bt = batch_tune(t, min_block(P.gjobs));
@@ -656,7 +661,7 @@ fs_status autotune(fs_plan &P, hipStream_t s) {
     t.xcd_remap = 1;
     t.nt_store = 1;
     float m = 0.0f;
-    st = measure(t, 1, m);
+    st = measure(t, 3, m);
     if (st != FS_OK) break;
     first.emplace_back(m, t);
   }
