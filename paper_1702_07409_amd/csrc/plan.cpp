@@ -556,7 +556,7 @@ fs_status capture(fs_plan &P) {
 std::string shape_key(const fs_plan &P) {
   // the plan's shape: per item op, k, n, nnz, t (arch first)
   std::ostringstream os;
-  os << "gfx950.v3";   // v2: entries carry the claim chunk
+  os << "gfx950.v3";   // v3: tuned with live row counts (entries carry the claim chunk)
   uint64_t h = 1469598103934665603ull;
   for (const fs_work &w : P.items) {
     const uint64_t v[5] = {w.op, w.graph->k, w.graph->n, w.graph->nnz, w.t};
