@@ -59,14 +59,25 @@ fs_status degree_weights(const fs_graph_params &p, std::vector<double> &w) {
     double mf = std::floor((double)k / R);
     uint64_t M = mf < 1.0 ? 1 : (mf > (double)k ? k : (uint64_t)mf);
     w.assign((size_t)k + 1, 0.0);
-    for (uint64_t i = 1; i <= k; ++i) {
-      const double rho = (i == 1) ? 1.0 / (double)k : 1.0 / (double)(i * (i - 1));
-      double tau = 0.0;
-      if (i < M)
-        tau = R / (double)(i * (uint64_t)k);
-      else if (i == M)
-        tau = R * std::log(R / delta) / (double)k;
-      w[i] = rho + tau;
+    // rho(i) + tau(i).  The products i (i - 1) and i k are below 2^41, so
+    // forming them in doubles is exact and the branch-free range loops give
+    // the same quotients as integer products would (and vectorise).
+    const double dk = (double)k;
+    auto tau_at = [&](uint64_t i) {
+      if (i < M) return R / ((double)i * dk);
+      if (i == M) return R * std::log(R / delta) / dk;
+      return 0.0;
+    };
+    w[1] = 1.0 / dk + tau_at(1);
+    const uint64_t lo_end = std::min<uint64_t>(M, (uint64_t)k + 1);   // i < M: both terms
+    for (uint64_t i = 2; i < lo_end; ++i) {
+      const double di = (double)i;
+      w[i] = 1.0 / (di * (di - 1.0)) + R / (di * dk);
+    }
+    if (M >= 2 && M <= k) w[M] = 1.0 / ((double)M * ((double)M - 1.0)) + tau_at(M);
+    for (uint64_t i = std::max<uint64_t>(M + 1, 2); i <= k; ++i) {
+      const double di = (double)i;
+      w[i] = 1.0 / (di * (di - 1.0)) + 0.0;
     }
     return FS_OK;
   }
@@ -99,16 +110,17 @@ fs_status degree_thresholds(const std::vector<double> &w, std::vector<uint64_t> 
   double W = 0.0;
   for (size_t d = 1; d <= D; ++d) W += w[d];
   T.assign(D, 0);
+  // the quotients first (independent, so they vectorise), then the running
+  // sum in order; C * 2^53 is never negative, so truncation is the floor
+  std::vector<double> q(D + 1);
+  for (size_t d = 1; d <= D; ++d) q[d] = w[d] / W;
   double C = 0.0;
-  for (size_t d = 1; d <= D; ++d) {
-    C += w[d] / W;
-    if (d < D) {
-      const double v = std::floor(C * (double)kTwo53);
-      T[d - 1] = v >= (double)kTwo53 ? kTwo53 : (uint64_t)v;
-    } else {
-      T[d - 1] = kTwo53;
-    }
+  for (size_t d = 1; d < D; ++d) {
+    C += q[d];
+    const double v = C * (double)kTwo53;
+    T[d - 1] = v >= (double)kTwo53 ? kTwo53 : (uint64_t)v;
   }
+  if (D) T[D - 1] = kTwo53;
   return FS_OK;
 }
 
