@@ -33,6 +33,18 @@ def _short(name, width=90):
     return name if len(name) <= width else name[:width]
 
 
+def _dispatch_durations(d):
+    """kernel name -> sorted dispatch durations in µs, from the kernel trace
+    (empty when the run wrote none)."""
+    per = {}
+    for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                per.setdefault(r["Kernel_Name"], []).append(
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    return {k: sorted(v) for k, v in per.items()}
+
+
 def stats(d, title, command):
     rows = []
     for path in _find(d, "kernel_stats.csv"):
@@ -40,13 +52,17 @@ def stats(d, title, command):
             for r in csv.DictReader(f):
                 rows.append(r)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    durs = _dispatch_durations(d)
     out = ["# Kernel trace: %s" % title, "", "Command (from the repository root, on one MI355X):", "", "```",
-           command, "```", "", "Per-kernel durations (`--stats`):", "",
-           "| kernel | calls | avg µs | total ms | % |", "|---|---:|---:|---:|---:|"]
+           command, "```", "", "Per-kernel durations (`--stats`; median, min and max from the dispatch trace):", "",
+           "| kernel | calls | avg µs | median µs | min µs | max µs | total ms | % |",
+           "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for r in rows:
-        out.append("| `%s` | %s | %.2f | %.3f | %.1f |" % (
-            _short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, float(r["TotalDurationNs"]) / 1e6,
-            float(r["Percentage"])))
+        v = durs.get(r["Name"], [])
+        med, lo, hi = (("%.2f" % v[len(v) // 2], "%.2f" % v[0], "%.2f" % v[-1]) if v else ("-", "-", "-"))
+        out.append("| `%s` | %s | %.2f | %s | %s | %s | %.3f | %.1f |" % (
+            _short(r["Name"]), r["Calls"], float(r["AverageNs"]) / 1e3, med, lo, hi,
+            float(r["TotalDurationNs"]) / 1e6, float(r["Percentage"])))
     print("\n".join(out))
 
 
