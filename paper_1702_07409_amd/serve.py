@@ -28,7 +28,10 @@ without blocking, and a thread that waits for the lock gets it only when
 the holder has run for the interpreter's switch interval (5 ms by default).
 run() therefore shortens the switch interval (switch_interval, 50 us) for
 its duration, so that a build starts and finishes without waiting on the
-loop.
+loop.  It also turns off the interpreter's cyclic garbage collector for its
+duration (pause_gc): a collection of the young generations stops every
+thread for 0.5-1 ms, about the device time of a large request, and the
+loop's objects are freed by reference counting anyway.
 
 Resident stripes (inputs x and coded blocks c kept on the device) are the
 targets of decode, repair (from the resident inputs) and update.  Requests on
@@ -38,6 +41,7 @@ Everything on the device runs in libfs.so; this module only schedules.
 """
 
 import collections
+import gc
 import sys
 import threading
 import time
@@ -281,9 +285,10 @@ class Server:
 
     def __init__(self, budget=32 << 30, streams=3, max_inflight=4, max_items=64, workers=8,
                  graph_cache_bytes=4 << 30, keep_outputs=False, device="cuda", device_graph_builds=True,
-                 switch_interval=50e-6):
+                 switch_interval=50e-6, pause_gc=True):
         self.device = torch.device(device)
         self.switch_interval = switch_interval
+        self.pause_gc = pause_gc
         self.budget = budget
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.next_stream = 0
@@ -463,14 +468,19 @@ class Server:
         each is submitted once the wall clock passes its arrival time scaled
         by time_scale.  Returns the statistics of the run.  The interpreter's
         thread switch interval is switch_interval while it runs (None: left
-        as it is)."""
+        as it is), and the cyclic garbage collector is off if pause_gc."""
         prev = sys.getswitchinterval()
         if self.switch_interval:
             sys.setswitchinterval(self.switch_interval)
+        gc_was = gc.isenabled()
+        if self.pause_gc:
+            gc.disable()
         try:
             return self._run(requests, time_scale)
         finally:
             sys.setswitchinterval(prev)
+            if gc_was:
+                gc.enable()
 
     def _run(self, requests, time_scale):
         torch.cuda.synchronize(self.device)
