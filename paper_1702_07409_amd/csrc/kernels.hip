@@ -885,11 +885,12 @@ constexpr int kReplayThreads = 1024;
 // inputs of its decoding row other than f, at pidx[poff[p] .. poff[p+1]);
 // gsrc[f] is the decoding row of f (-1 for unrecovered inputs).  Pairs that
 // do not fit the graph are dropped; meta = {nR, L, entries, usable}.
-// Loads are hoisted in groups of eight pairs so each thread keeps several
-// dependent chains (row -> row pointer -> neighbour ids) in flight.
+// Loads are hoisted in groups of G pairs so each thread keeps several
+// dependent chains (row -> row pointer -> neighbour ids) in flight (G = 4
+// where the registers are capped at 64 per lane, so that nothing spills).
+template <int G = 8>
 __device__ __forceinline__ void prog_body(const ProgJob &P) {
   __shared__ uint32_t scan_sh[kPlanThreads / 64 + 1];
-  constexpr int G = 8;
   const int tid = threadIdx.x;
   const int k = (int)P.k;
   // the dependency-slab form is unusable until prog_lookahead_kernel says otherwise
@@ -1117,7 +1118,7 @@ __global__ __launch_bounds__(kPeelThreads) __attribute__((amdgpu_waves_per_eu(8)
 void plan_kernel(PeelJob J, ProgJob P) {
   peel_body<MODE>(J);
   __syncthreads();
-  prog_body(P);
+  prog_body<4>(P);
 }
 
 // Dependency-slab form of a replay program (one workgroup, after
