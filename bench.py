@@ -207,7 +207,7 @@ def _progress_line(msg):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)"
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (--gpus %d refused)"
               % args.gpus, file=sys.stderr)
         sys.exit(2)
     import numpy as np

@@ -46,7 +46,7 @@ typedef enum fs_status {
   FS_ERR_ALIGN = 2,       /* t % 16 != 0 or a payload base not 16-B aligned */
   FS_ERR_NOMEM = 3,       /* host or device allocation failed (build/plan)  */
   FS_ERR_HIP = 4,         /* a HIP runtime call failed; see fs_last_error   */
-  FS_ERR_UNSUPPORTED = 5, /* valid request this build does not handle       */
+  FS_ERR_UNSUPPORTED = 5, /* valid request the library does not handle       */
   FS_ERR_WORKSPACE = 6    /* workspace pointer null or smaller than needed  */
 } fs_status;
 
