@@ -51,20 +51,21 @@ fs_tune current_tune() {
 // 0).  Sparse graphs (mean degree <= 6) with k <= 8192 read each neighbour
 // block in 4 KiB runs; denser ones (the Robust Soliton graphs), and sparse
 // ones of more inputs, re-read every input about d times from slices too
-// large to stay on chip, so the slice narrows until one slice of every
-// input block (k x W bytes) fits about half an XCD's L2: W = 2 MiB / k,
-// within [512 B, 4 KiB].  Measured on k = 4096 and 8192 RSD stripes:
-// 512-byte slices 14-18 % faster than 4 KiB ones; on the k = 4096
-// finite-degree stripe 4 KiB slices 14 % faster than 512-byte ones; on the
-// k = 10246 Raptor code (mean degree 5.7, 7 KiB blocks) 512-byte slices
-// 0.082 ms against 0.25 ms.
+// large to stay on chip, so the slice narrows as k grows: W = 4 MiB / k
+// (one slice of every input block, k x W bytes, about one XCD's L2),
+// within [512 B, 4 KiB].  Measured with the inputs out of the caches, on
+// Robust Soliton stripes of 1024 x 256 KiB, 2048 x 128 KiB, 4096 x 64 KiB
+// and 8192 x 32 KiB: this width within 0-4 % of the best of 512 B - 4 KiB,
+// where 2 MiB / k was up to 16 % slower; on the k = 4096 finite-degree stripe
+// 4 KiB slices 14 % faster than 512-byte ones; on the k = 10246 Raptor code
+// (mean degree 5.7, 7 KiB blocks) 512-byte slices 0.082 ms against 0.25 ms.
 fs_tune tile_for(const fs_tune &t, const fs_graph *g) {
   if (t.lanes_per_row != 0) return t;
   fs_tune r = t;
   const double dbar = g->n ? (double)g->nnz / (double)g->n : 1.0;
   uint64_t w = 4096;
   if (dbar > 6.0 || g->k > 8192) {
-    w = (2ull << 20) / std::max<uint32_t>(g->k, 1);
+    w = (4ull << 20) / std::max<uint32_t>(g->k, 1);
     w = std::min<uint64_t>(4096, std::max<uint64_t>(512, w));
   }
   if (w >= 4096) {
