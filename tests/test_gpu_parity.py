@@ -101,6 +101,20 @@ def test_encode_sparse_graph_beyond_8192_inputs(k, n, dist, t):
     assert (li["gather_kind"], li["gather_slice_bytes"]) == (1, 512), li
 
 
+@pytest.mark.parametrize("k,width", [(1024, 4096), (2048, 2048), (4096, 1024), (8192, 512)])
+def test_encode_rsd_default_slice_width(k, width):
+    # Robust Soliton graphs take W = 4 MiB / k slices by default (within
+    # [512 B, 4 KiB]); blocks of two slices and a ragged 16-byte tail
+    t = 2 * width + 16
+    sp = workloads.StripeSpec(stripe=0, k=k, n=round(1.08 * k), t=t, dist="rsd", rsd_c=0.05, rsd_delta=0.01,
+                              stripe_key=7, n_erased=0)
+    g, G, x, xd, c = encode_case(sp)
+    import paper_1702_07409_amd as fs
+    li = fs.fs_last_launch()
+    assert (li["gather_kind"], li["gather_slice_bytes"]) == (1, width), li
+    assert np.array_equal(host(c), codec.encode(G, x))
+
+
 def test_encode_tiles_beyond_the_lds_edge_stage():
     # 16-row tiles of degree-200 rows hold 3200 edges: read from global memory
     import paper_1702_07409_amd as fs
