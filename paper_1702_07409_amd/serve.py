@@ -31,7 +31,12 @@ its duration, so that a build starts and finishes without waiting on the
 loop.  It also turns off the interpreter's cyclic garbage collector for its
 duration (pause_gc): a collection of the young generations stops every
 thread for 0.5-1 ms, about the device time of a large request, and the
-loop's objects are freed by reference counting anyway.
+loop's objects are freed by reference counting anyway.  Before it starts,
+run() takes the in-flight budget from torch's caching allocator once and
+gives it back (reserve), so that the outputs and plans of the requests are
+carved from memory the allocator already holds instead of new device
+allocations in the middle of the run (a first run without it showed stalls
+of several milliseconds).
 
 Resident stripes (inputs x and coded blocks c kept on the device) are the
 targets of decode, repair (from the resident inputs) and update.  Requests on
@@ -285,10 +290,11 @@ class Server:
 
     def __init__(self, budget=32 << 30, streams=3, max_inflight=4, max_items=64, workers=8,
                  graph_cache_bytes=4 << 30, keep_outputs=False, device="cuda", device_graph_builds=True,
-                 switch_interval=50e-6, pause_gc=True):
+                 switch_interval=50e-6, pause_gc=True, reserve=True):
         self.device = torch.device(device)
         self.switch_interval = switch_interval
         self.pause_gc = pause_gc
+        self.reserve = reserve
         self.budget = budget
         self.streams = [torch.cuda.Stream(device=self.device) for _ in range(streams)]
         self.next_stream = 0
@@ -468,7 +474,11 @@ class Server:
         each is submitted once the wall clock passes its arrival time scaled
         by time_scale.  Returns the statistics of the run.  The interpreter's
         thread switch interval is switch_interval while it runs (None: left
-        as it is), and the cyclic garbage collector is off if pause_gc."""
+        as it is), and the cyclic garbage collector is off if pause_gc.  With
+        reserve, the budget is first taken from torch's caching allocator and
+        given back."""
+        if self.reserve:
+            self._reserve()
         prev = sys.getswitchinterval()
         if self.switch_interval:
             sys.setswitchinterval(self.switch_interval)
@@ -481,6 +491,15 @@ class Server:
             sys.setswitchinterval(prev)
             if gc_was:
                 gc.enable()
+
+    def _reserve(self):
+        """Hold the budget in torch's caching allocator (best effort: skipped
+        when the device cannot spare it)."""
+        try:
+            block = torch.empty(max(int(self.budget), 1), dtype=torch.uint8, device=self.device)
+        except torch.OutOfMemoryError:
+            return
+        del block
 
     def _run(self, requests, time_scale):
         torch.cuda.synchronize(self.device)
