@@ -25,6 +25,7 @@ large_stripe gives the headline alone.
 """
 
 import argparse
+import gc
 import hashlib
 import json
 import os
@@ -433,9 +434,10 @@ def main():
         # a failure there is reported in its field, the headline stands
         import bench_batch
         del x, c, xd, ws, wss, rws, pws
-        for key, run in (("batched", lambda: bench_batch.run_batch512(args.batch_stripes, reps=args.reps)),
-                         ("resident", lambda: bench_batch.run_resident256(args.resident_stripes, reps=args.reps)),
-                         ("serve", lambda: bench_batch.run_serve(args.serve_rate, args.serve_seconds))):
+        for key, run in (("serve", lambda: bench_batch.run_serve(args.serve_rate, args.serve_seconds)),
+                         ("batched", lambda: bench_batch.run_batch512(args.batch_stripes, reps=args.reps)),
+                         ("resident", lambda: bench_batch.run_resident256(args.resident_stripes, reps=args.reps))):
+            gc.collect()   # device tensors of the previous workload held in reference cycles
             torch.cuda.empty_cache()
             try:
                 out[key] = run()
