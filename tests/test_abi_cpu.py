@@ -163,3 +163,36 @@ def test_workspace_size_knows_every_operation():
         assert getattr(fs, name) == int(code), name
         # the encode needs none; every other operation some
         assert (fs.fs_workspace_size(g, int(code), 4096, 4) > 0) == (name != "FS_OP_ENCODE"), name
+
+
+def test_graph_and_table_reject_out_of_range_parameters():
+    # checked on the host before any HIP call
+    import ctypes
+    from paper_1702_07409_amd import _lib as L
+    # more inputs than the builds support, a reserved field, unknown flags and distribution
+    p = L.make_params(k=(1 << 20) + 1, n=5, host_only=True)
+    h = L.P()
+    assert L._lib.fs_graph_build(ctypes.byref(p), None, ctypes.byref(h)) == L.FS_ERR_INVALID
+    p = L.make_params(k=10, n=5, host_only=True)
+    p.reserved = 1
+    assert L._lib.fs_graph_build(ctypes.byref(p), None, ctypes.byref(h)) == L.FS_ERR_INVALID
+    p = L.make_params(k=10, n=5, host_only=True)
+    p.flags |= 8
+    assert L._lib.fs_graph_build(ctypes.byref(p), None, ctypes.byref(h)) == L.FS_ERR_INVALID
+    p = L.make_params(k=10, n=5, host_only=True)
+    p.dist = 7
+    assert L._lib.fs_graph_build(ctypes.byref(p), None, ctypes.byref(h)) == L.FS_ERR_INVALID
+    # the threshold table: a buffer shorter than D is refused, D is still reported
+    p = L.make_params(k=100, n=1)
+    D = L.U32()
+    assert L._lib.fs_degree_table(ctypes.byref(p), None, 0, ctypes.byref(D)) == 0 and D.value == 100
+    buf = (ctypes.c_uint64 * 10)()
+    assert L._lib.fs_degree_table(ctypes.byref(p), buf, 10, ctypes.byref(D)) == L.FS_ERR_INVALID
+    assert "threshold" in L._lib.fs_last_error().decode()
+
+
+def test_status_strings_name_every_status():
+    from paper_1702_07409_amd import _lib as L
+    names = {L._lib.fs_status_string(s).decode() for s in range(7)}
+    assert len(names) == 7 and "unknown status" not in names
+    assert L._lib.fs_status_string(99).decode() == "unknown status"
