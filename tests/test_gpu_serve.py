@@ -162,3 +162,20 @@ def test_request_larger_than_budget_is_served_alone():
         _check_same(srv, reqs, outs, xs, cs)
     finally:
         srv.close()
+
+
+def test_budget_beyond_device_memory_skips_the_reservation():
+    # run() reserves the budget in torch's caching allocator first; a budget
+    # larger than the device is left unreserved and the requests are served
+    from paper_1702_07409_amd.serve import Request, Server
+    srv = Server(budget=1 << 50, streams=2, max_inflight=2, max_items=8, workers=2, keep_outputs=True)
+    try:
+        pool = serving.build_pool(srv, 4, hi=HI)
+        trace = workloads.serving_trace(rate=20000.0, duration=0.001, pool_size=4, hi=HI)
+        reqs = serving.build_requests(trace, pool, Request, hi=HI)
+        stats = srv.run(reqs)
+        assert stats["requests"] == len(reqs) and all(r.t_done is not None for r in reqs)
+        outs, xs, cs = _alone(pool, reqs)
+        _check_same(srv, reqs, outs, xs, cs)
+    finally:
+        srv.close()
