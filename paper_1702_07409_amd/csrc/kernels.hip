@@ -1316,14 +1316,13 @@ __global__ __launch_bounds__(kReplayThreads) void replay_lds_kernel(ReplayJob J,
 // program (pairs, decoding rows, other inputs) sits in LDS as 16-bit indices
 // when it fits, so a level costs one round trip to memory: every load of a
 // pair (its coded block and the other inputs) is issued before any is used.
-template <int LPS, class IT>
+template <int LPS, class IT, int MP = (LPS >= 32 ? 4 : 2)>
 __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT *lp, const IT *pf, const IT *pg,
                                                    const IT *poff, const IT *pidx, int L, int nR,
                                                    uint32_t nslices, uint32_t vb, uint32_t stride) {
   constexpr int NS = kReplayThreads / LPS;
-  // pairs per thread whose coded block is prefetched, and how many levels
-  // ahead (two levels ahead measured no faster than one)
-  constexpr int MP = LPS >= 32 ? 4 : 2;
+  // MP: pairs per thread whose coded block is prefetched; PD: how many
+  // levels ahead (two levels ahead measured no faster than one)
   constexpr int PD = 1;
   // Each coded block is read once, so its loads are non-temporal: the caches
   // keep the decoded inputs that later pairs read instead (replay of the
@@ -1400,7 +1399,7 @@ __device__ __forceinline__ void replay_wide_slices(const ReplayJob &J, const IT 
   }
 }
 
-template <int LPS>
+template <int LPS, int MP = (LPS >= 32 ? 4 : 2)>
 __device__ __forceinline__ void replay_wide_body(const ReplayJob &J, const ProgJob &P, uint32_t nslices,
                                                  uint32_t lds_bytes, uint32_t prog_lds, uint32_t vb,
                                                  uint32_t stride) {
@@ -1425,9 +1424,10 @@ __device__ __forceinline__ void replay_wide_body(const ReplayJob &J, const ProgJ
     for (int i = threadIdx.x; i <= nR; i += kReplayThreads) poff[i] = (uint16_t)P.poff[i];
     for (int i = threadIdx.x; i < total; i += kReplayThreads) pidx[i] = (uint16_t)P.pidx[i];
     __syncthreads();
-    replay_wide_slices<LPS, uint16_t>(J, lp, pf, pg, poff, pidx, L, nR, nslices, vb, stride);
+    replay_wide_slices<LPS, uint16_t, MP>(J, lp, pf, pg, poff, pidx, L, nR, nslices, vb, stride);
   } else {
-    replay_wide_slices<LPS, int32_t>(J, J.level_ptr, J.dp_f, J.dp_g, P.poff, P.pidx, L, nR, nslices, vb, stride);
+    replay_wide_slices<LPS, int32_t, MP>(J, J.level_ptr, J.dp_f, J.dp_g, P.poff, P.pidx, L, nR, nslices, vb,
+                                         stride);
   }
 }
 
@@ -1437,6 +1437,16 @@ template <int LPS>
 __global__ __launch_bounds__(kReplayThreads) __attribute__((amdgpu_waves_per_eu(LPS <= 16 ? 8 : 1)))
 void replay_wide_kernel(ReplayJob J, ProgJob P, uint32_t nslices, uint32_t lds_bytes, uint32_t prog_lds) {
   replay_wide_body<LPS>(J, P, nslices, lds_bytes, prog_lds, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
+}
+
+// The same for narrow slices when the program's LDS leaves one workgroup per
+// CU anyway: the registers of four waves per SIMD, and four pairs per thread
+// prefetched a level ahead (levels of up to 4 x 1024 / LPS pairs load no
+// coded block inside the level).
+template <int LPS>
+__global__ __launch_bounds__(kReplayThreads) __attribute__((amdgpu_waves_per_eu(4)))
+void replay_wide_one_kernel(ReplayJob J, ProgJob P, uint32_t nslices, uint32_t lds_bytes, uint32_t prog_lds) {
+  replay_wide_body<LPS, 4>(J, P, nslices, lds_bytes, prog_lds, xcd_remap(blockIdx.x, gridDim.x), gridDim.x);
 }
 
 // Lookahead replay with a dependency slab.  One workgroup per CU walks byte
@@ -2186,8 +2196,16 @@ static hipError_t run_replay_wide(const ReplayJob &job, const ProgJob &prog, int
   rec.replay_kind = 2;
   rec.replay_slice_bytes = w;
   rec.replay_workgroups = grid;
+  const uint32_t prog_lds = tune_snapshot().replay_prog_global ? 0u : 1u;
+  if (LPS <= 4 && 2 * lds > budget) {
+    static bool done_one[64] = {false};
+    set_max_lds(reinterpret_cast<const void *>(&replay_wide_one_kernel<LPS <= 4 ? LPS : 4>), dev, budget, done_one);
+    hipLaunchKernelGGL(replay_wide_one_kernel<LPS <= 4 ? LPS : 4>, dim3(grid), dim3(kReplayThreads), lds, s, job,
+                       prog, nslices, (uint32_t)lds, prog_lds);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL(replay_wide_kernel<LPS>, dim3(grid), dim3(kReplayThreads), lds, s, job, prog, nslices,
-                     (uint32_t)lds, tune_snapshot().replay_prog_global ? 0u : 1u);
+                     (uint32_t)lds, prog_lds);
   return hipGetLastError();
 }
 
