@@ -201,6 +201,25 @@ def cpu_baseline(spec, seconds):
             "one_core": one}
 
 
+def _child_workload(args, workload):
+    """One workload of the full line, run as ``bench.py --workload <workload>``
+    in a child process; returns its JSON line, or the failure as a field."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--workload", workload, "--no-cpu",
+           "--serve-rate", str(args.serve_rate), "--serve-seconds", str(args.serve_seconds),
+           "--batch-stripes", str(args.batch_stripes), "--resident-stripes", str(args.resident_stripes),
+           "--reps", str(args.reps)]
+    _progress_line("%s: in a process of its own" % workload)
+    try:
+        p = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=900)
+    except subprocess.TimeoutExpired:
+        return {"error": "%s timed out after 900 s" % workload}
+    lines = [ln for ln in p.stdout.splitlines() if ln.startswith("{")]
+    if p.returncode != 0 or not lines:
+        return {"error": "%s ended with exit status %d" % (workload, p.returncode)}
+    return json.loads(lines[-1])
+
+
 def _progress_line(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -220,6 +239,13 @@ def main():
         cpu = cpu_baseline(workloads.large_stripe(), args.cpu_seconds)
         _progress_line("cpu_baseline: %.3f GB/s on %d cores (one core %.3f GB/s)"
                        % (cpu["value"], cpu["cores"], cpu["one_core"]["value"]))
+    extra = {}
+    if args.workload == "all" and args.mode == "step":
+        # serving, batched and resident workloads each run in a process of
+        # their own, started before this one touches the GPU, so that each
+        # begins from a clean device (allocator, queues, caches) as it would alone
+        for key, wl in (("serve", "serve"), ("batched", "batch512"), ("resident", "resident256")):
+            extra[key] = _child_workload(args, wl)
     import torch
     import paper_1702_07409_amd as fs
 
@@ -457,21 +483,9 @@ def main():
         "paper_cpu_context": "Table 2: encode 2722 MB/s, decode 3291/2852/2340 MB/s (2-4 disks lost), "
                              "k=1036 n=2180 t=1024, 2x Xeon E5-2620 with 12 threads",
     }
-    if args.workload == "all":
-        # the rest of the metric: batched vs the plain loop, and serving latency;
-        # a failure there is reported in its field, the headline stands
-        import bench_batch
-        del x, c, xd, ws, wss, rws, pws
-        for key, run in (("serve", lambda: bench_batch.run_serve(args.serve_rate, args.serve_seconds)),
-                         ("batched", lambda: bench_batch.run_batch512(args.batch_stripes, reps=args.reps)),
-                         ("resident", lambda: bench_batch.run_resident256(args.resident_stripes, reps=args.reps))):
-            gc.collect()   # device tensors of the previous workload held in reference cycles
-            torch.cuda.empty_cache()
-            try:
-                out[key] = run()
-            except Exception as exc:  # noqa: BLE001 - recorded, not hidden
-                out[key] = {"error": "%s: %s" % (type(exc).__name__, exc)}
-        torch.cuda.empty_cache()
+    # the rest of the metric (batched vs the plain loop, serving latency), run
+    # before this process touched the GPU; a failure there is in its field
+    out.update(extra)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
