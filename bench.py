@@ -206,6 +206,7 @@ def _child_workload(args, workload):
     in a child process; returns its JSON line, or the failure as a field."""
     import subprocess
     cmd = [sys.executable, os.path.abspath(__file__), "--workload", workload, "--no-cpu",
+           "--steps", str(args.steps), "--warmup", str(args.warmup),
            "--serve-rate", str(args.serve_rate), "--serve-seconds", str(args.serve_seconds),
            "--batch-stripes", str(args.batch_stripes), "--resident-stripes", str(args.resident_stripes),
            "--reps", str(args.reps)]
@@ -239,13 +240,20 @@ def main():
         cpu = cpu_baseline(workloads.large_stripe(), args.cpu_seconds)
         _progress_line("cpu_baseline: %.3f GB/s on %d cores (one core %.3f GB/s)"
                        % (cpu["value"], cpu["cores"], cpu["one_core"]["value"]))
-    extra = {}
     if args.workload == "all" and args.mode == "step":
-        # serving, batched and resident workloads each run in a process of
-        # their own, started before this one touches the GPU, so that each
-        # begins from a clean device (allocator, queues, caches) as it would alone
+        # every workload of the full line runs in a process of its own, the
+        # headline first, so that each begins from a clean device (allocator,
+        # queues, caches) as it would alone; this process never touches the GPU
+        out = _child_workload(args, "large_stripe")
+        if "error" in out:
+            print(json.dumps(out), flush=True)
+            sys.exit(1)
         for key, wl in (("serve", "serve"), ("batched", "batch512"), ("resident", "resident256")):
-            extra[key] = _child_workload(args, wl)
+            out[key] = _child_workload(args, wl)   # a failure there is in its field
+        if cpu is not None:
+            out["cpu_baseline"] = cpu
+        print(json.dumps(out), flush=True)
+        return
     import torch
     import paper_1702_07409_amd as fs
 
@@ -483,9 +491,6 @@ def main():
         "paper_cpu_context": "Table 2: encode 2722 MB/s, decode 3291/2852/2340 MB/s (2-4 disks lost), "
                              "k=1036 n=2180 t=1024, 2x Xeon E5-2620 with 12 threads",
     }
-    # the rest of the metric (batched vs the plain loop, serving latency), run
-    # before this process touched the GPU; a failure there is in its field
-    out.update(extra)
     if cpu is not None:
         out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
