@@ -18,8 +18,9 @@ they were taken on the current kernel source, and the CPU oracle timed on
 the host.  By default (--workload all) the line also carries the rest of the
 metric: 512 batched stripes against the plain loop over them ("batched"),
 batched repair and update on 256 resident stripes ("resident"), and the
-serving loop's p50/p99 latency on a Poisson mix ("serve"); --workload
-large_stripe gives the headline alone.
+serving loop's p50/p99 latency on a Poisson mix ("serve"), each workload
+run by this script in a child process of its own, the headline first;
+--workload large_stripe gives the headline alone.
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload W]
 """
